@@ -1,0 +1,29 @@
+"""Plain FP64 CPU oracle for the EnVar forward ensemble and its anomaly gradient.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import this package:
+only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` use it. It shares no code with the HIP library (its own geometry,
+its own operators, a sparse direct Poisson solve instead of multigrid, a
+two-pass cost instead of shifted running sums, an SVD least squares instead of
+a Gram/Cholesky solve).
+
+What it computes, and where the paper defines it:
+
+* ``ns``      forced incompressible Navier-Stokes, eq. (forced_NS), in the
+              semi-discrete form L dq/dt + N(q) = P f of eq. (discrete_NS),
+              discretised on a uniform MAC grid with an explicit
+              Adams-Bashforth-2 predictor and a Chorin projection.
+* ``cost``    J(f) = observation term + penalty, eq. (Envarcost); the
+              observation term is the time-integrated fluctuation energy of
+              eq. (kinenergy) over the whole fluid domain.
+* ``envar``   the N+1 forward evaluations of Sec. 3.3.1 (eq. fdapprox) and the
+              least-squares reduction of {delta f_i, J_i} to a gradient in
+              span of the perturbations (eq. gradient_EnVar, scalar-J form),
+              plus the fixed-ensemble descent loop of Fig. (envar_loop).
+
+Pins (tests/test_oracle_*.py): Taylor-Green linear AB2 recurrence and O(h^2)
+nonlinear decay, energy conservation of the advection operator, the discrete
+Poiseuille profile, divergence after projection, projection idempotence,
+two-pass vs brute-force cost, closed-form gradients on quadratic costs, and
+central finite differences of the Navier-Stokes cost.
+"""
