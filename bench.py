@@ -1,0 +1,248 @@
+"""Benchmark: ensemble cell-steps/s of the batched EnVar forward + anomaly gradient on one MI355X.
+
+Workload (one "step" = one full pass of the hot path): the h = 1/128 open
+cavity (512 x 128 channel + 128 x 128 cavity = 81,920 fluid cells), Re = 7500,
+dt = 5e-4, a centre run plus 64 GRF-perturbed forcings (m = 65,536, length
+0.05, std 5e-3) integrated for 20,000 steps from a 2,000-step spin-up, then
+the anomaly Gram / least-squares / projection to the gradient. `value` is the
+batched mixed-precision path (FP32 stencil tendencies and V-cycles inside
+FP64 iterative refinement to max|div u| <= 1e-10); the plain FP64 batched and
+FP64 one-member-at-a-time paths are measured beside it on a shorter horizon.
+All inputs are synthetic and seeded; nothing is read from disk.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--horizon H]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+N_MEMBERS = 64
+INV_H, RE, SPINUP = 128, 7500.0, 2000
+ELL, SIGMA = 0.05, 5e-3
+
+# algorithmic bytes per fluid cell and launch (ideal fusion, halos re-read from cache)
+BYTES_PER_CELL = {
+    # u, v (16) + T^{n-1} (16 | 8) + forcing on 2/5 of the cells (6.4) -> u*, v* (16) + T^n (16 | 8) + b (8)
+    ("predictor", "fp64"): 78.4, ("predictor", "mixed"): 62.4,
+    # phi in/out (8 + 8) + b (8) + coarse rhs (8/4)              | mixed, zero guess: r (4) + e (4) + coarse (1)
+    ("pre", "fp64"): 26.0, ("pre", "mixed"): 9.0,
+    # phi in/out (8 + 8) + b (8) + coarse correction (8/4)       | mixed: e (4) + r (4) + coarse (1) + phi64 in/out (16)
+    ("post", "fp64"): 26.0, ("post", "mixed"): 25.0,
+    # phi64 (8) + b64 (8) -> r32 (4)
+    ("resid", "mixed"): 20.0,
+    # u*, v* (16) + phi (8) -> u, v (16) + cost sums S1 in/out (32)
+    ("project", "fp64"): 72.0, ("project", "mixed"): 72.0,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_inputs(torch, E, inputs):
+    p64 = E.Problem(inv_h=INV_H, Re=RE, precision=E.FP64)
+    u0, v0 = inputs.initial_field(INV_H, amp=1e-3)
+    state = E.state_init(p64, u0, v0)
+    t = time.time()
+    st = E.spinup(p64, state, SPINUP)
+    torch.cuda.synchronize()
+    log(f"spin-up {SPINUP} steps: {time.time() - t:.2f}s, mean cycles {st['mean_cycles']:.2f}")
+    m = E.control_dim(p64)
+    pert = inputs.grf_perturbations(N_MEMBERS, INV_H, ELL, SIGMA)
+    rows = np.vstack([np.zeros(m), pert])
+    return state, torch.tensor(rows, dtype=torch.float64, device="cuda"), m
+
+
+def one_pass(E, p, state, ctrl, horizon, ws, J, gws, g, stats=False):
+    J, _, st = E.forward(p, state, ctrl, horizon, ws=ws, J=J, stats=stats)
+    E.gradient(ctrl, J, p.precision, ws=gws, g=g)
+    return st
+
+
+def roofline(st, prec, ncells, members):
+    cyc = st["mean_cycles"]
+    per_step = {
+        "predictor": st["predictor_us"],
+        "project": st["project_us"],
+        "pre": st["pre_us"] * cyc,
+        "post": st["post_us"] * cyc,
+    }
+    if prec == "mixed":
+        per_step["resid"] = st["resid_us"] * (cyc + 1)
+    name = max(per_step, key=per_step.get)
+    avg_us = {"predictor": st["predictor_us"], "project": st["project_us"], "pre": st["pre_us"],
+              "post": st["post_us"], "resid": st["resid_us"]}[name]
+    nbytes = BYTES_PER_CELL[(name, prec)] * ncells * members
+    achieved = nbytes / (avg_us * 1e-6) / 1e9
+    return {
+        "kernel": {"predictor": "k_predictor", "project": "k_project_cost", "pre": "k_mg_pre (finest level)",
+                   "post": "k_mg_post (finest level)", "resid": "k_resid64"}[name],
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+        "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2),
+        "per_step_us": {k: round(v, 1) for k, v in per_step.items()},
+    }
+
+
+def cpu_baseline(state_host, rows, steps, procs):
+    """The oracle (plain FP64 numpy/scipy) on a bounded sample: every member for `steps` steps."""
+    from oracle import envar as OE
+
+    op = OE.Problem(inv_h=INV_H, Re=RE)
+    op.poisson()  # factorise once, shared by the forked workers
+    u, v, tu, tv = state_host
+    from oracle import ns
+
+    base = ns.State(u, v, tu, tv)
+    t = time.time()
+    OE.forward(op, base, rows, steps, processes=procs)
+    dt = time.time() - t
+    ncells = op.grid().ncells
+    return ncells * steps * rows.shape[0] / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--horizon", type=int, default=20000)
+    ap.add_argument("--baseline-horizon", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-baselines", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the ensemble members of one MI355X "
+              "(multi-GPU member sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2605_23812_amd import envar as E
+    from paper_2605_23812_amd import inputs
+
+    E.lib()
+    torch.cuda.init()
+    state, ctrl, m = build_inputs(torch, E, inputs)
+    nrows = ctrl.shape[0]
+    pm = E.Problem(inv_h=INV_H, Re=RE, precision=E.MIXED, flags=E.FLAG_TIME_KERNELS)
+    p64 = E.Problem(inv_h=INV_H, Re=RE, precision=E.FP64, flags=E.FLAG_TIME_KERNELS)
+    ncells = E.cell_count(pm)
+    ws = E._bytes_tensor(E.workspace_bytes(pm, nrows))
+    gws = E._bytes_tensor(E.gradient_bytes(nrows - 1, m, E.MIXED))
+    J = torch.empty(nrows, dtype=torch.float64, device="cuda")
+    g = torch.empty(m, dtype=torch.float64, device="cuda")
+
+    for w in range(args.warmup):
+        t = time.time()
+        one_pass(E, pm, state, ctrl, args.horizon, ws, J, gws, g)
+        torch.cuda.synchronize()
+        log(f"warmup pass {w}: {time.time() - t:.2f}s")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    st = None
+    for k in range(args.steps):
+        st = one_pass(E, pm, state, ctrl, args.horizon, ws, J, gws, g, stats=(k == args.steps - 1))
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    cell_steps = ncells * nrows * args.horizon * args.steps
+    value = cell_steps / elapsed
+    log(f"timed {args.steps} pass(es): {elapsed:.2f}s -> {value:.4g} cell-steps/s; stats {st}")
+    J_mixed_long = J.cpu().numpy().copy()
+
+    extra = {}
+    if not args.no_baselines:
+        hb = args.baseline_horizon
+        ws64 = E._bytes_tensor(E.workspace_bytes(p64, nrows))
+        Jm, _, stm = E.forward(pm, state, ctrl, hb, ws=ws)
+        torch.cuda.synchronize()
+        t = time.time()
+        Jm, _, stm = E.forward(pm, state, ctrl, hb, ws=ws)
+        torch.cuda.synchronize()
+        tm = time.time() - t
+        J64 = torch.empty_like(J)
+        E.forward(p64, state, ctrl, hb, ws=ws64, J=J64)
+        torch.cuda.synchronize()
+        t = time.time()
+        J64, _, st64 = E.forward(p64, state, ctrl, hb, ws=ws64, J=J64)
+        torch.cuda.synchronize()
+        t64 = time.time() - t
+        # plain FP64 one member at a time (same kernels, n_rows = 1), on a subset of members
+        ws1 = E._bytes_tensor(E.workspace_bytes(p64, 1))
+        sub = [0, 1, 2, 3]
+        E.forward(p64, state, ctrl[0:1].contiguous(), hb, ws=ws1)
+        torch.cuda.synchronize()
+        t = time.time()
+        for i in sub:
+            E.forward(p64, state, ctrl[i:i + 1].contiguous(), hb, ws=ws1)
+        torch.cuda.synchronize()
+        t1 = time.time() - t
+        rate_m = ncells * nrows * hb / tm
+        rate_64 = ncells * nrows * hb / t64
+        rate_1 = ncells * len(sub) * hb / t1
+        jm, j64 = Jm.cpu().numpy(), J64.cpu().numpy()
+        extra = {
+            "baselines_horizon": hb,
+            "mixed_batched_cell_steps_per_s": round(rate_m, 1),
+            "fp64_batched_cell_steps_per_s": round(rate_64, 1),
+            "fp64_one_at_a_time_cell_steps_per_s": round(rate_1, 1),
+            "speedup_mixed_batched_vs_fp64_one_at_a_time": round(rate_m / rate_1, 2),
+            "speedup_fp64_batched_vs_fp64_one_at_a_time": round(rate_64 / rate_1, 2),
+            "J_rel_err_mixed_vs_fp64_max": float(np.max(np.abs(jm - j64) / np.abs(j64))),
+            "fp64_mean_vcycles_per_step": round(st64["mean_cycles"], 3),
+            "fp64_roofline": roofline(st64, "fp64", ncells, nrows),
+        }
+        log("baselines", extra)
+
+    cpu = None
+    if not args.no_cpu:
+        u, v, tu, tv, _ = E.state_read(E.Problem(inv_h=INV_H, Re=RE), state)
+        procs = min(16, os.cpu_count() or 1)
+        rows = ctrl.cpu().numpy()
+        rate, secs = cpu_baseline((u, v, tu, tv), rows, args.cpu_steps, procs)
+        cpu = {"value": round(rate, 1), "unit": "cell-steps/s", "cores": procs, "kind": "oracle",
+               "sample": f"all {nrows} members x {args.cpu_steps} steps of the same h=1/128 workload "
+                         f"from the same base state ({secs:.1f}s wall, one process per member)"}
+        log("cpu baseline", cpu)
+
+    out = {
+        "metric": "ensemble cell-steps/s, batched FP32 vs plain FP64 at J err<=1e-4; p50/p99 solve latency",
+        "value": round(value, 1),
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64",
+        "data": "synthetic",
+        "config": {
+            "workload": "open-cavity EnVar forward ensemble + anomaly gradient, h=1/128 (81,920 cells), "
+                        "Re=7500, dt=5e-4, centre + 64 GRF members, m=65,536, batched mixed precision",
+            "members": nrows, "horizon": args.horizon, "inv_h": INV_H, "Re": RE,
+            "spinup_steps": SPINUP, "precision": "fp32 stencil/V-cycle + fp64 refinement",
+            "div_tol": 1e-10,
+        },
+        "mean_refinement_passes_per_step": round(st["mean_cycles"], 3),
+        "max_div": st["max_div"],
+        "J_finite": bool(np.all(np.isfinite(J_mixed_long))),
+        "roofline": roofline(st, "mixed", ncells, nrows),
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

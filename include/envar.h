@@ -1,0 +1,212 @@
+/* envar.h -- C ABI of the MI355X EnVar forward-ensemble library.
+ *
+ * The library integrates N independent 2D incompressible Navier-Stokes
+ * open-cavity simulations in one batch, each driven by its own steady
+ * forcing row f_i (eq. forced_NS with f_u(x) steady, Sec. 2), accumulates
+ * each member's cost J_i on the fly (eq. Envarcost with the fluctuation
+ * energy of eq. kinenergy as observation term), and reduces the control
+ * anomalies and costs to a gradient estimate (eq. gradient_EnVar in its
+ * scalar-J form, with the finite differences of eq. fdapprox).
+ *
+ * Conventions shared by every entry point
+ *  - The caller owns all memory. Device buffers are plain device pointers
+ *    (any allocator); the library never allocates device memory. Sizes come
+ *    from envar_state_bytes / envar_workspace_bytes / envar_gradient_bytes.
+ *  - Every call is stream ordered on `stream` (a hipStream_t passed as void*,
+ *    NULL = the default stream) and asynchronous unless stated otherwise.
+ *  - Arrays are row-major FP64. A control row has m = 2 * n_ctrl entries:
+ *    f_x over the control cells in row-major cell order, then f_y over the
+ *    same cells. The gradient is the Euclidean dJ/df_k (no mass-matrix
+ *    scaling).
+ *  - Return value: ENVAR_OK or an error code; envar_last_error() returns a
+ *    thread-local message for the last failing call on this thread. No C++
+ *    exception crosses the ABI. Calls on distinct workspaces are thread safe.
+ *
+ * Grid (cavity geometry): channel [0, 4] x [0, 1] over a square cavity
+ * [x_cav, x_cav + 1] x [-1, 0], uniform spacing h = 1 / inv_h, MAC
+ * staggering; bounding box NX = 4 inv_h by NY = 2 inv_h cells. Host field
+ * layouts ("oracle layout") are dense row-major: u (NY, NX + 1), v (NY + 1,
+ * NX), cell fields (NY, NX). The channel geometry drops the cavity (NY = inv_h).
+ */
+#ifndef ENVAR_H
+#define ENVAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ENVAR_OK = 0,
+  ENVAR_EINVAL = 1,      /* bad argument: shape, size, NULL pointer, NaN input */
+  ENVAR_ENOMEM = 2,      /* a buffer is smaller than the size the library needs */
+  ENVAR_EDIVERGED = 3,   /* >= 1 member produced a non-finite cost; its J is NaN, others are valid */
+  ENVAR_EDEVICE = 4,     /* a HIP runtime call failed */
+  ENVAR_EBUSY = 5,       /* serving queue is full */
+  ENVAR_ECANCELLED = 6,  /* request cancelled before completion */
+  ENVAR_ETIMEOUT = 7     /* envar_wait timed out */
+};
+
+enum { ENVAR_CAVITY = 0, ENVAR_CHANNEL = 1 };
+/* Control regions (cells whose centre lies inside):
+ *  COLUMN: x in [x_cav, x_cav + 1], all y (cavity + channel column above it), 2 / h^2 cells
+ *  CAVITY: the cavity cells only, 1 / h^2 cells
+ *  BOX:    fluid cells with centre in [box[0], box[1]] x [box[2], box[3]] (Sec. 4.1 actuation window) */
+enum { ENVAR_REGION_COLUMN = 0, ENVAR_REGION_CAVITY = 1, ENVAR_REGION_BOX = 2 };
+/* FP64: every kernel in FP64. MIXED: stencil tendencies and the multigrid
+ * V-cycle in FP32, wrapped in FP64 iterative refinement of the pressure; the
+ * state, the coarse solve, the cost sums and the least squares stay FP64. */
+enum { ENVAR_FP64 = 0, ENVAR_MIXED = 1 };
+
+/* One forward problem, passed by value-pointer; fields <= 0 take defaults. */
+typedef struct {
+  int32_t inv_h;       /* 1/h; a multiple of 16 (cavity aligned down to h = 1/4) */
+  int32_t geometry;    /* ENVAR_CAVITY | ENVAR_CHANNEL */
+  int32_t region;      /* ENVAR_REGION_* */
+  int32_t precision;   /* ENVAR_FP64 | ENVAR_MIXED */
+  double Re;           /* U D / nu with U = inflow centreline speed, D = cavity depth (Sec. 2) */
+  double dt;           /* <= 0: 0.064 h */
+  double x_cav;        /* <= 0: 1.25 */
+  double box[4];       /* x0, x1, y0, y1 for ENVAR_REGION_BOX */
+  double penalty;      /* lambda of the penalty lambda h^2 |f|^2; < 0: 1e-3 */
+  double div_tol;      /* pressure solve stops when dt * max|b - L phi| <= div_tol; <= 0: 1e-12 FP64, 1e-10 MIXED */
+  int32_t max_cycles;  /* cap on V-cycles (FP64) or refinement passes (MIXED) per step; <= 0: 30 */
+  int32_t flags;       /* ENVAR_FLAG_* bits, 0 = none */
+} envar_problem;
+
+/* envar_problem.flags */
+enum {
+  /* Record HIP events on the call's stream around the predictor, the first
+   * full cycle's finest-level multigrid launches and the projection of a
+   * uniform sample of steps (at most ~256), filling the *_us fields of
+   * envar_stats (requires stats != NULL). */
+  ENVAR_FLAG_TIME_KERNELS = 1
+};
+
+/* Per-call statistics (filled only when a non-NULL pointer is passed; then the
+ * call synchronises its stream before returning). */
+typedef struct {
+  double max_resid;        /* max over members and steps of dt * max|b - L phi| after the last cycle */
+  double max_div;          /* max over members and steps of max |div_h u^{n+1}| measured after projection */
+  double mean_cycles;      /* V-cycles (FP64) or refinement passes (MIXED) per member-step */
+  int32_t max_cycles_used; /* largest per-step count */
+  int32_t unconverged;     /* member-steps that reached max_cycles without meeting div_tol */
+  int32_t diverged;        /* members with a non-finite cost */
+  int32_t steps;           /* time steps integrated */
+  double cell_steps;       /* fluid cells x steps x members */
+  /* ENVAR_FLAG_TIME_KERNELS: mean device time per launch (microseconds) over
+   * the sampled steps, and the number of sampled steps */
+  double predictor_us;     /* fused predictor */
+  double pre_us;           /* finest-level pre-smoothing + restriction */
+  double post_us;          /* finest-level prolongation + post-smoothing (+ residual norm) */
+  double resid_us;         /* FP64 refinement residual (MIXED) */
+  double project_us;       /* projection + cost accumulator */
+  double vcycle_us;        /* one full V-cycle (FP64) or refinement pass (MIXED) */
+  int32_t timed_steps;
+  int32_t timed_members;   /* members active in the timed cycle (all, unless converged before it) */
+} envar_stats;
+
+/* Number of control entries m = 2 * n_ctrl for this problem. */
+int envar_control_dim(const envar_problem* p, int64_t* m);
+
+/* Fluid cells of the flow grid. */
+int envar_cell_count(const envar_problem* p, int64_t* ncells);
+
+/* Device bytes of a resident base state (flow fields, AB2 history, warm-start
+ * pressure, cost shift, control map, coarse-grid inverse). */
+size_t envar_state_bytes(const envar_problem* p);
+
+/* Device bytes of the workspace of a forward over n_rows members (all member
+ * fields and the multigrid hierarchy). The admission footprint of a request. */
+size_t envar_workspace_bytes(const envar_problem* p, int32_t n_rows);
+
+/* Build a base state in caller memory `state_dev` (envar_state_bytes) from host
+ * arrays in oracle layout: u (NY, NX+1), v (NY+1, NX) and optionally the
+ * previous tendencies tu_prev, tv_prev (same shapes; NULL = cold start, the
+ * first step then uses T^{-1} = T^0) and a warm-start pressure phi (NY, NX)
+ * (NULL = 0). Boundary values are imposed (walls 0, inflow 4y(1-y)).
+ * Synchronous (returns after the upload completed). */
+int envar_state_init(const envar_problem* p, const double* u, const double* v,
+                     const double* tu_prev, const double* tv_prev, const double* phi,
+                     void* state_dev, void* stream);
+
+/* Copy a base state back to host arrays in oracle layout (any pointer may be
+ * NULL). Synchronous. */
+int envar_state_read(const envar_problem* p, const void* state_dev, double* u, double* v,
+                     double* tu_prev, double* tv_prev, double* phi);
+
+/* Advance a base state in place by `steps` unforced steps (spin-up). Uses a
+ * workspace sized for n_rows = 1. */
+int envar_spinup(const envar_problem* p, void* state_dev, int32_t steps, void* ws_dev,
+                 size_t ws_bytes, envar_stats* stats, void* stream);
+
+/* The N+1 forward evaluations (Sec. 3.3.1, eq. fdapprox): every row i of
+ * controls_dev [n_rows][m] (device, FP64) drives one member from the base state
+ * for `horizon` steps; J_dev[i] (device, FP64) receives
+ *   J_i = dt h^2 sum_{n=1..K} sum_c |u_c^n - ubar_c|^2 + lambda h^2 |f_i|^2
+ * with ubar_c the member's time mean over its K = horizon samples.
+ * fields_dev (optional, device, may be NULL): [n_rows][NY*(NX+1) + (NY+1)*NX]
+ * receives each member's final u then v in oracle layout.
+ * Errors: EINVAL (shape, m mismatch, horizon < 1), ENOMEM (ws_bytes too small),
+ * EDIVERGED (only when stats != NULL and a cost is non-finite). */
+int envar_forward(const envar_problem* p, const void* state_dev, const double* controls_dev,
+                  int32_t n_rows, int64_t m, int32_t horizon, void* ws_dev, size_t ws_bytes,
+                  double* J_dev, double* fields_dev, envar_stats* stats, void* stream);
+
+/* Device bytes of the workspace of envar_gradient. */
+size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
+
+/* Anomaly reduction {delta f_i, J_i} -> g (eq. gradient_EnVar, scalar-J form):
+ * rows 1..n of controls_dev [n+1][m] are the perturbed controls and row 0 the
+ * centre; X_i = f_i - f_0, dJ_i = J_i - J_0 (J_dev [n+1], device);
+ * g_dev [m] (device) receives the minimum-norm least-squares solution
+ * g = X^+ dJ = X^T (X X^T)^{-1} dJ (n <= m; n > m uses (X^T X)^{-1} X^T dJ).
+ * The Gram X X^T runs on the matrix cores (FP64 MFMA, or FP32 MFMA with
+ * precision = ENVAR_MIXED); the n x n solve is an FP64 Cholesky with a
+ * relative ridge 1e-12 tr(G)/n. Errors: EINVAL (n < 1, m < 1), ENOMEM. */
+int envar_gradient(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
+                   int32_t precision, void* ws_dev, size_t ws_bytes, double* g_dev, void* stream);
+
+/* Line search and iteration parameters of envar_iterate (Armijo, eq. update_BFGS). */
+typedef struct {
+  int32_t iters;          /* descent iterations */
+  int32_t max_trials;     /* Armijo backtracking trials per search; <= 0: 8 */
+  double c1;              /* sufficient-decrease constant; <= 0: 1e-4 */
+  double shrink;          /* step reduction per trial; <= 0: 0.5 */
+  double alpha0;          /* first trial step; <= 0: max|perturb| / max|g| */
+  int32_t search_every;   /* 0: search at the first iteration only and reuse that step */
+  int32_t reserved;
+} envar_ls_params;
+
+/* Per-iteration record of envar_iterate. */
+typedef struct {
+  double J0;       /* centre cost at the start of the iteration */
+  double gnorm;    /* |g| */
+  double alpha;    /* accepted step (0 = line search failed, loop stopped) */
+  double J_trial;  /* cost at the accepted trial (NaN when the step was reused without a trial) */
+} envar_iter_record;
+
+/* Fixed-ensemble descent (Fig. envar_loop, Sec. 3.3.3): each iteration runs
+ * the N+1 forwards of f and f + perturb_i, forms g, and moves f <- f - alpha g.
+ * f_dev [m] (device, in/out), perturb_dev [n][m] (device, held fixed).
+ * ws_dev must hold envar_iterate_bytes. records (host, `iters` entries) may be
+ * NULL. Synchronous (the step decisions read costs on the host). */
+size_t envar_iterate_bytes(const envar_problem* p, int32_t n, int64_t m);
+int envar_iterate(const envar_problem* p, const void* state_dev, double* f_dev,
+                  const double* perturb_dev, int32_t n, int64_t m, int32_t horizon,
+                  const envar_ls_params* ls, void* ws_dev, size_t ws_bytes,
+                  envar_iter_record* records, void* stream);
+
+/* Thread-local message of the last failing call. */
+const char* envar_last_error(void);
+
+/* Library version string. */
+const char* envar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENVAR_H */

@@ -96,21 +96,31 @@ def forward_member(p, base, f, horizon, return_state=False):
     return (J, st) if return_state else J
 
 
-def _member_job(args):
-    p, base, f, horizon = args
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    return forward_member(p, base, f, horizon)
+_SHARED = {}
+
+
+def _member_job(i):
+    p, base, controls, horizon = _SHARED["job"]
+    return forward_member(p, base, controls[i], horizon)
 
 
 def forward(p, base, controls, horizon, processes=1):
-    """J_i for every control row (one independent run per row, Sec. 5.3's ensemble parallelism)."""
+    """J_i for every control row (one independent run per row, Sec. 5.3's ensemble parallelism).
+
+    With processes > 1 the rows run in forked worker processes that inherit
+    the problem (and its one sparse LU factorisation) from the parent.
+    """
     controls = np.asarray(controls, dtype=np.float64)
-    jobs = [(Problem(**{k: getattr(p, k) for k in p.__dataclass_fields__ if k != "_cache"}),
-             base, controls[i], horizon) for i in range(controls.shape[0])]
+    n = controls.shape[0]
     if processes <= 1:
-        return np.array([forward_member(p, base, controls[i], horizon) for i in range(len(jobs))])
-    with get_context("fork").Pool(processes) as pool:
-        return np.array(pool.map(_member_job, jobs))
+        return np.array([forward_member(p, base, controls[i], horizon) for i in range(n)])
+    p.poisson()
+    _SHARED["job"] = (p, base, controls, horizon)
+    try:
+        with get_context("fork").Pool(processes) as pool:
+            return np.array(pool.map(_member_job, range(n), chunksize=1))
+    finally:
+        _SHARED.clear()
 
 
 def gradient(controls, J, rcond=1e-12):

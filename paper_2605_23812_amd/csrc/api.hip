@@ -1,0 +1,1103 @@
+// C ABI of the EnVar library: problem setup (geometry, control map, coarse
+// operator inverse), memory layout of the caller-owned state and workspace,
+// the time loop with adaptive per-step cycle caps, the anomaly reduction and
+// the fixed-ensemble descent loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/envar.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace envar {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(ENVAR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------- problem plan
+struct Plan {
+  envar_problem p;
+  int n;
+  int mixed;
+  double dt, nu, tol, penalty;
+  int cap_max;
+  int nlev_grid;        // levels run by the tiled kernels (inv_h > 16)
+  int ncoarse;          // levels run by the LDS kernel (top inv_h <= 16 .. 4)
+  Geo lev[MAX_LEVELS];  // lev[nlev_grid] is the top of the LDS part
+  Tiling mg_tl[MAX_LEVELS];
+  int mg_tiles[MAX_LEVELS];
+  Tiling st_tl;
+  int st_tiles;
+  long cplane;  // nx * ny
+  int ncells;
+  std::vector<int> ctrl_cells;  // dense cell index (i + j nx) of each control cell, row-major
+  long m;
+  int nc;  // coarsest unknowns
+  int norm_slots;
+  // state layout
+  size_t s_meta, s_u, s_v, s_tu, s_tv, s_phi, s_shu, s_shv, s_cmap, s_ainv, s_aidx, s_total;
+};
+
+static Geo make_geo(int n, int geometry, double x_cav) {
+  Geo g;
+  g.n = n;
+  g.nx = 4 * n;
+  g.h = 1.0 / n;
+  if (geometry == ENVAR_CAVITY) {
+    g.ny = 2 * n;
+    g.jc = n;
+    g.ic0 = (int)std::lround(x_cav * n);
+    g.ic1 = g.ic0 + n;
+  } else {
+    g.ny = n;
+    g.jc = 0;
+    g.ic0 = g.ic1 = 0;
+  }
+  g.pitch = ((g.nx + 1 + 15) / 16) * 16;
+  g.rows = g.ny + 1;
+  return g;
+}
+
+static int make_plan(const envar_problem* pin, Plan& P) {
+  if (!pin) return fail(ENVAR_EINVAL, "problem is NULL");
+  P.p = *pin;
+  envar_problem& p = P.p;
+  if (p.inv_h < 16 || p.inv_h % 16 != 0 || p.inv_h > 2048)
+    return fail(ENVAR_EINVAL, "inv_h must be a multiple of 16 in [16, 2048], got %d", p.inv_h);
+  if (p.geometry != ENVAR_CAVITY && p.geometry != ENVAR_CHANNEL)
+    return fail(ENVAR_EINVAL, "unknown geometry %d", p.geometry);
+  if (p.precision != ENVAR_FP64 && p.precision != ENVAR_MIXED)
+    return fail(ENVAR_EINVAL, "unknown precision %d", p.precision);
+  if (!(p.Re > 0.0) || !std::isfinite(p.Re)) return fail(ENVAR_EINVAL, "Re must be positive");
+  if (p.x_cav <= 0.0) p.x_cav = 1.25;
+  if (std::fabs(p.x_cav * 4.0 - std::round(p.x_cav * 4.0)) > 1e-12 || p.x_cav + 1.0 > 4.0)
+    return fail(ENVAR_EINVAL, "x_cav must be a multiple of 1/4 with the cavity inside [0, 4]");
+  P.n = p.inv_h;
+  P.mixed = p.precision == ENVAR_MIXED;
+  P.dt = p.dt > 0.0 ? p.dt : 0.064 / p.inv_h;
+  P.nu = 1.0 / p.Re;
+  P.penalty = p.penalty < 0.0 ? 1e-3 : p.penalty;
+  P.tol = p.div_tol > 0.0 ? p.div_tol : (P.mixed ? 1e-10 : 1e-12);
+  P.cap_max = p.max_cycles > 0 ? std::min(p.max_cycles, 200) : 30;
+  P.norm_slots = P.cap_max + 2;
+  // levels
+  int nl = 0;
+  for (int n = P.n; n > 16; n /= 2) ++nl;
+  P.nlev_grid = nl;
+  P.lev[0] = make_geo(P.n, p.geometry, p.x_cav);
+  for (int l = 1; l <= nl; ++l) P.lev[l] = P.lev[l - 1].coarser();
+  const int ntop = P.lev[nl].n;  // 16
+  P.ncoarse = 0;
+  for (int n = ntop; n >= 4; n /= 2) ++P.ncoarse;
+  for (int l = 0; l < nl; ++l) {
+    P.mg_tl[l] = Tiling::make(P.lev[l], MG_TH);
+    P.mg_tiles[l] = P.mg_tl[l].count();
+  }
+  const Geo& g = P.lev[0];
+  P.st_tl = Tiling::make(g, STEP_TH);
+  P.st_tiles = P.st_tl.count();
+  P.cplane = (long)g.nx * g.ny;
+  P.ncells = 0;
+  for (int j = 0; j < g.ny; ++j)
+    for (int i = 0; i < g.nx; ++i) P.ncells += g.fluid(i, j);
+  // control region, row-major over fluid cells whose centre lies inside
+  P.ctrl_cells.clear();
+  for (int j = 0; j < g.ny; ++j)
+    for (int i = 0; i < g.nx; ++i) {
+      if (!g.fluid(i, j)) continue;
+      const double x = (i + 0.5) * g.h;
+      const double y = (p.geometry == ENVAR_CAVITY ? -1.0 : 0.0) + (j + 0.5) * g.h;
+      bool in = false;
+      if (p.region == ENVAR_REGION_COLUMN)
+        in = x > p.x_cav && x < p.x_cav + 1.0;
+      else if (p.region == ENVAR_REGION_CAVITY)
+        in = x > p.x_cav && x < p.x_cav + 1.0 && y < 0.0;
+      else if (p.region == ENVAR_REGION_BOX)
+        in = x >= p.box[0] && x <= p.box[1] && y >= p.box[2] && y <= p.box[3];
+      else
+        return fail(ENVAR_EINVAL, "unknown region %d", p.region);
+      if (in) P.ctrl_cells.push_back(j * g.nx + i);
+    }
+  P.m = 2 * (long)P.ctrl_cells.size();
+  // coarsest level
+  Geo gc = P.lev[nl];
+  for (int l = 1; l < P.ncoarse; ++l) gc = gc.coarser();
+  P.nc = 0;
+  for (int j = 0; j < gc.ny; ++j)
+    for (int i = 0; i < gc.nx; ++i) P.nc += gc.fluid(i, j);
+  if (P.nc > MAX_COARSE_UNKNOWNS) return fail(ENVAR_EINVAL, "coarsest level too large (%d unknowns)", P.nc);
+  // state layout
+  const long pl = g.plane();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  P.s_meta = take(256);
+  P.s_u = take(pl * 8);
+  P.s_v = take(pl * 8);
+  P.s_tu = take(pl * 8);
+  P.s_tv = take(pl * 8);
+  P.s_phi = take(pl * 8);
+  P.s_shu = take(P.cplane * 8);
+  P.s_shv = take(P.cplane * 8);
+  P.s_cmap = take(pl * 4);
+  P.s_ainv = take((size_t)P.nc * P.nc * 8);
+  P.s_aidx = take((size_t)P.nc * 4);
+  P.s_total = o;
+  return ENVAR_OK;
+}
+
+// workspace layout of a forward over nmem members
+struct WS {
+  size_t u, v, us, vs, tuA, tvA, tuB, tvB, phiA, phiB, b0, e0, r0;
+  size_t lphiA[MAX_LEVELS], lphiB[MAX_LEVELS], lb[MAX_LEVELS];
+  size_t s1u, s1v, s2part, norms, stats, divmax;
+  size_t total;
+};
+
+static WS make_ws(const Plan& P, int nmem) {
+  WS w;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const long pl = P.lev[0].plane();
+  const size_t tsz = P.mixed ? 4 : 8;  // tendency storage
+  const size_t vsz = P.mixed ? 4 : 8;  // V-cycle storage
+  w.u = take(nmem * pl * 8);
+  w.v = take(nmem * pl * 8);
+  w.us = take(nmem * pl * 8);
+  w.vs = take(nmem * pl * 8);
+  w.tuA = take(nmem * pl * tsz);
+  w.tvA = take(nmem * pl * tsz);
+  w.tuB = take(nmem * pl * tsz);
+  w.tvB = take(nmem * pl * tsz);
+  w.phiA = take(nmem * pl * 8);
+  w.phiB = P.mixed ? 0 : take(nmem * pl * 8);
+  w.b0 = take(nmem * pl * 8);
+  w.e0 = P.mixed ? take(nmem * pl * 4) : 0;
+  w.r0 = P.mixed ? take(nmem * pl * 4) : 0;
+  for (int l = 1; l <= P.nlev_grid; ++l) {
+    const long lp = P.lev[l].plane();
+    w.lphiA[l] = take(nmem * lp * vsz);
+    w.lphiB[l] = (l < P.nlev_grid) ? take(nmem * lp * vsz) : 0;
+    w.lb[l] = take(nmem * lp * vsz);
+  }
+  w.s1u = take(nmem * P.cplane * 8);
+  w.s1v = take(nmem * P.cplane * 8);
+  w.s2part = take((size_t)nmem * P.st_tiles * 8);
+  w.norms = take((size_t)nmem * P.norm_slots * 8);
+  w.stats = take((size_t)nmem * STATS_STRIDE * 8);
+  w.divmax = take((size_t)nmem * 8);
+  w.total = o;
+  return w;
+}
+
+// dense inverse of the coarsest operator (Gauss-Jordan with partial pivoting)
+static void coarse_inverse(const Geo& g, std::vector<double>& inv, std::vector<int>& idx) {
+  idx.clear();
+  std::vector<int> id(g.nx * g.ny, -1);
+  for (int j = 0; j < g.ny; ++j)
+    for (int i = 0; i < g.nx; ++i)
+      if (g.fluid(i, j)) {
+        id[j * g.nx + i] = (int)idx.size();
+        idx.push_back(j * g.nx + i);
+      }
+  const int nc = (int)idx.size();
+  std::vector<double> A((size_t)nc * nc, 0.0);
+  const double ih2 = 1.0 / (g.h * g.h);
+  for (int q = 0; q < nc; ++q) {
+    const int i = idx[q] % g.nx, j = idx[q] / g.nx;
+    A[(size_t)q * nc + q] = -(double)g.diag_count(i, j) * ih2;
+    const int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+    for (auto& c : nb)
+      if (g.fluid(c[0], c[1])) A[(size_t)q * nc + id[c[1] * g.nx + c[0]]] = ih2;
+  }
+  inv.assign((size_t)nc * nc, 0.0);
+  for (int q = 0; q < nc; ++q) inv[(size_t)q * nc + q] = 1.0;
+  for (int c = 0; c < nc; ++c) {
+    int pr = c;
+    for (int r = c + 1; r < nc; ++r)
+      if (std::fabs(A[(size_t)r * nc + c]) > std::fabs(A[(size_t)pr * nc + c])) pr = r;
+    if (pr != c)
+      for (int k = 0; k < nc; ++k) {
+        std::swap(A[(size_t)pr * nc + k], A[(size_t)c * nc + k]);
+        std::swap(inv[(size_t)pr * nc + k], inv[(size_t)c * nc + k]);
+      }
+    const double d = 1.0 / A[(size_t)c * nc + c];
+    for (int k = 0; k < nc; ++k) {
+      A[(size_t)c * nc + k] *= d;
+      inv[(size_t)c * nc + k] *= d;
+    }
+    for (int r = 0; r < nc; ++r) {
+      if (r == c) continue;
+      const double f = A[(size_t)r * nc + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < nc; ++k) {
+        A[(size_t)r * nc + k] -= f * A[(size_t)c * nc + k];
+        inv[(size_t)r * nc + k] -= f * inv[(size_t)c * nc + k];
+      }
+    }
+  }
+}
+
+template <typename T>
+static T* at(void* base, size_t off) {
+  return (T*)((char*)base + off);
+}
+template <typename T>
+static const T* at(const void* base, size_t off) {
+  return (const T*)((const char*)base + off);
+}
+
+// pinned host staging for the asynchronous cycle-cap monitor
+struct Pinned {
+  double* p = nullptr;
+  size_t n = 0;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+  double* get(size_t need) {
+    if (need > n) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      n = 0;
+      if (hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
+      n = need;
+    }
+    return p;
+  }
+};
+static thread_local Pinned g_pinned;
+
+// HIP-event sampling of the main kernels on the call's stream
+enum { TM_PRED = 0, TM_PRE = 1, TM_POST = 2, TM_RESID = 3, TM_PROJ = 4, TM_CYCLE = 5, TM_N = 6 };
+struct Timer {
+  bool on = false;
+  int every = 1, max_samples = 256;
+  std::vector<hipEvent_t> ev;  // [sample][TM_N][2]
+  std::vector<unsigned char> rec;  // [sample][TM_N] both edges recorded
+  int samples = 0;
+  int cur = -1;  // sample index of the current step, -1 = not sampled
+  int begin_step(int s, int steps) {
+    cur = -1;
+    if (!on || s == 0) return 0;
+    if ((s - 1) % every != 0 || samples >= max_samples) return 0;
+    cur = samples++;
+    const size_t need = (size_t)samples * TM_N * 2;
+    while (ev.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      ev.push_back(e);
+    }
+    rec.resize((size_t)samples * TM_N, 0);
+    return 0;
+  }
+  void mark(int what, int edge, hipStream_t s) {
+    if (cur < 0) return;
+    if (hipEventRecord(ev[((size_t)cur * TM_N + what) * 2 + edge], s) == hipSuccess)
+      rec[(size_t)cur * TM_N + what] |= (unsigned char)(1 << edge);
+  }
+  bool recorded(int q, int what) const { return rec[(size_t)q * TM_N + what] == 3; }
+  ~Timer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+// ---------------------------------------------------------------------------- the time loop
+struct Run {
+  const Plan* P;
+  void* ws;
+  const WS* w;
+  int nmem;
+  const void* state;
+  const double* ctrl;  // NULL = unforced
+  hipStream_t s;
+  Timer* tm;
+};
+
+template <typename TT>
+static int pressure_solve(const Run& R, int cap) {
+  const Plan& P = *R.P;
+  const WS& w = *R.w;
+  void* ws = R.ws;
+  const int L = P.nlev_grid;
+  double* norms = at<double>(ws, w.norms);
+  typedef TT T;  // V-cycle type
+  auto level_args = [&](int l) {
+    MGArgs<T> a{};
+    a.g = P.lev[l];
+    a.gc = P.lev[l + 1];
+    a.tiling = P.mg_tl[l];
+    a.ntiles = P.mg_tiles[l];
+    a.nmem = R.nmem;
+    a.plane = P.lev[l].plane();
+    a.cplane_c = P.lev[l + 1].plane();
+    a.norms = norms;
+    a.norm_slots = P.norm_slots;
+    a.tol = P.tol;
+    a.dt = P.dt;
+    return a;
+  };
+  auto coarse_args = [&](int k) {
+    CoarseArgs c{};
+    c.g = P.lev[L];
+    c.nlev = P.ncoarse;
+    c.nmem = R.nmem;
+    c.plane = P.lev[L].plane();
+    c.ainv = at<double>(R.state, P.s_ainv);
+    c.aidx = at<int>(R.state, P.s_aidx);
+    c.nc = P.nc;
+    c.norms = norms;
+    c.norm_slots = P.norm_slots;
+    c.k = k;
+    c.tol = P.tol;
+    c.dt = P.dt;
+    c.nsweep_pre = 2;
+    c.nsweep_post = 2;
+    return c;
+  };
+  // one V-cycle from level 0 (right-hand side b0v, in/out phi0in -> phi0out)
+  Timer* tm = R.tm;
+  const int k_timed = P.mixed ? 1 : 0;
+  auto vcycle = [&](int k, const T* b0v, const T* phi0in, T* phi0out, double* add_to, int zero_guess, int write_norm) {
+    const bool timed = tm && k == k_timed;
+    if (timed) tm->mark(TM_CYCLE, 0, R.s);
+    if (L == 0) {
+      CoarseArgs c = coarse_args(k);
+      c.phi = (void*)phi0out;
+      c.b = b0v;
+      c.warm = !zero_guess;
+      c.write_norm = write_norm;
+      c.add_to = add_to;
+      launch_mg_coarse<T>(c, R.s);
+      return;
+    }
+    for (int l = 0; l < L; ++l) {
+      MGArgs<T> a = level_args(l);
+      a.k = k;
+      if (l == 0) {
+        a.phi_in = phi0in;
+        a.b = b0v;
+        a.zero_guess = zero_guess;
+        a.phi_out = (T*)(P.mixed ? at<float>(ws, w.e0) : nullptr);
+        if (!P.mixed) a.phi_out = (T*)at<double>(ws, w.phiB);
+      } else {
+        a.phi_in = nullptr;
+        a.b = at<T>(ws, w.lb[l]);
+        a.zero_guess = 1;
+        a.phi_out = at<T>(ws, w.lphiB[l]);
+      }
+      a.bc = at<T>(ws, w.lb[l + 1]);
+      if (timed && l == 0) tm->mark(TM_PRE, 0, R.s);
+      launch_mg_pre<T>(a, 2, R.s);
+      if (timed && l == 0) tm->mark(TM_PRE, 1, R.s);
+    }
+    CoarseArgs c = coarse_args(k);
+    c.phi = at<T>(ws, w.lphiA[L]);
+    c.b = at<T>(ws, w.lb[L]);
+    c.warm = 0;
+    c.write_norm = 0;
+    launch_mg_coarse<T>(c, R.s);
+    for (int l = L - 1; l >= 0; --l) {
+      MGArgs<T> a = level_args(l);
+      a.k = k;
+      a.phic = at<T>(ws, w.lphiA[l + 1]);
+      if (l == 0) {
+        a.phi_in = P.mixed ? (const T*)at<float>(ws, w.e0) : (const T*)at<double>(ws, w.phiB);
+        a.b = b0v;
+        a.phi_out = phi0out;
+        a.add_to = add_to;
+        a.write_norm = write_norm;
+      } else {
+        a.phi_in = at<T>(ws, w.lphiB[l]);
+        a.b = at<T>(ws, w.lb[l]);
+        a.phi_out = at<T>(ws, w.lphiA[l]);
+      }
+      if (timed && l == 0) tm->mark(TM_POST, 0, R.s);
+      launch_mg_post<T>(a, 2, R.s);
+      if (timed && l == 0) tm->mark(TM_POST, 1, R.s);
+    }
+    if (timed && !P.mixed) tm->mark(TM_CYCLE, 1, R.s);
+  };
+  if (!P.mixed) {
+    double* phi = at<double>(ws, w.phiA);
+    const double* b = at<double>(ws, w.b0);
+    for (int k = 0; k < cap; ++k) vcycle(k, (const T*)b, (const T*)phi, (T*)phi, nullptr, 0, 1);
+  } else {
+    ResidArgs r{};
+    r.g = P.lev[0];
+    r.tiling = P.st_tl;
+    r.ntiles = P.st_tiles;
+    r.nmem = R.nmem;
+    r.plane = P.lev[0].plane();
+    r.phi = at<double>(ws, w.phiA);
+    r.b = at<double>(ws, w.b0);
+    r.r = at<float>(ws, w.r0);
+    r.norms = norms;
+    r.norm_slots = P.norm_slots;
+    r.tol = P.tol;
+    r.dt = P.dt;
+    r.k = 0;
+    if (tm) tm->mark(TM_RESID, 0, R.s);
+    launch_resid64(r, R.s);
+    if (tm) tm->mark(TM_RESID, 1, R.s);
+    for (int k = 1; k <= cap; ++k) {
+      vcycle(k, (const T*)at<float>(ws, w.r0), nullptr, (T*)at<float>(ws, w.e0), at<double>(ws, w.phiA), 1, 0);
+      r.k = k;
+      launch_resid64(r, R.s);
+      if (tm && k == k_timed) tm->mark(TM_CYCLE, 1, R.s);
+    }
+  }
+  return ENVAR_OK;
+}
+
+template <typename TT>
+static int run_steps(const Run& R, int steps, int cold_first) {
+  const Plan& P = *R.P;
+  const WS& w = *R.w;
+  void* ws = R.ws;
+  const long pl = P.lev[0].plane();
+  TT* tA[2] = {at<TT>(ws, w.tuA), at<TT>(ws, w.tvA)};
+  TT* tB[2] = {at<TT>(ws, w.tuB), at<TT>(ws, w.tvB)};
+  int cap = P.cap_max;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+  double* host = g_pinned.get((size_t)R.nmem * STATS_STRIDE);
+  if (!host) return fail(ENVAR_EDEVICE, "hipHostMalloc failed");
+  const int check_every = 16;
+  HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  int rc = ENVAR_OK;
+  for (int s = 0; s < steps && rc == ENVAR_OK; ++s) {
+    if (R.tm && R.tm->begin_step(s, steps)) return fail(ENVAR_EDEVICE, "hipEventCreate failed");
+    TT** tp = (s % 2 == 0) ? tA : tB;
+    TT** tn = (s % 2 == 0) ? tB : tA;
+    PredArgs<TT> a{};
+    a.g = P.lev[0];
+    a.tiling = P.st_tl;
+    a.ntiles = P.st_tiles;
+    a.nmem = R.nmem;
+    a.plane = pl;
+    a.nu = P.nu;
+    a.dt = P.dt;
+    a.cold_flag = (s == 0 && cold_first) ? at<int>(R.state, P.s_meta) : nullptr;
+    a.u = at<double>(ws, w.u);
+    a.v = at<double>(ws, w.v);
+    a.us = at<double>(ws, w.us);
+    a.vs = at<double>(ws, w.vs);
+    a.tu_prev = tp[0];
+    a.tv_prev = tp[1];
+    a.tu = tn[0];
+    a.tv = tn[1];
+    a.b = at<double>(ws, w.b0);
+    a.ctrl = R.ctrl;
+    a.m = P.m;
+    a.nctrl = (int)(P.m / 2);
+    a.cmap = at<int>(R.state, P.s_cmap);
+    a.norms = at<double>(ws, w.norms);
+    a.norm_slots = P.norm_slots;
+    if (R.tm) R.tm->mark(TM_PRED, 0, R.s);
+    launch_predictor<TT>(a, R.s);
+    if (R.tm) R.tm->mark(TM_PRED, 1, R.s);
+    pressure_solve<TT>(R, cap);
+    ProjArgs pj{};
+    pj.g = P.lev[0];
+    pj.tiling = P.st_tl;
+    pj.ntiles = P.st_tiles;
+    pj.nmem = R.nmem;
+    pj.plane = pl;
+    pj.cplane = P.cplane;
+    pj.dt = P.dt;
+    pj.u = at<double>(ws, w.u);
+    pj.v = at<double>(ws, w.v);
+    pj.us = at<double>(ws, w.us);
+    pj.vs = at<double>(ws, w.vs);
+    pj.phi = at<double>(ws, w.phiA);
+    pj.shu = at<double>(R.state, P.s_shu);
+    pj.shv = at<double>(R.state, P.s_shv);
+    pj.s1u = at<double>(ws, w.s1u);
+    pj.s1v = at<double>(ws, w.s1v);
+    pj.s2part = at<double>(ws, w.s2part);
+    pj.divmax = at<double>(ws, w.divmax);
+    if (R.tm) R.tm->mark(TM_PROJ, 0, R.s);
+    launch_project_cost(pj, R.s);
+    if (R.tm) R.tm->mark(TM_PROJ, 1, R.s);
+    BookArgs bk{};
+    bk.nmem = R.nmem;
+    bk.norm_slots = P.norm_slots;
+    bk.cap = cap;
+    bk.slot_base = P.mixed ? 1 : 0;
+    bk.tol = P.tol;
+    bk.norms = at<double>(ws, w.norms);
+    bk.stats = at<double>(ws, w.stats);
+    launch_step_book(bk, R.s);
+    HIP_OK(hipGetLastError());
+    // adaptive cap: exact after the first step, then asynchronous checks
+    auto absorb = [&]() {
+      int mx = 0;
+      for (int i = 0; i < R.nmem; ++i) mx = std::max(mx, (int)host[(size_t)i * STATS_STRIDE + ST_MAXCYC]);
+      cap = std::min(P.cap_max, std::max(2, mx + 2));
+    };
+    if (s == 0) {
+      HIP_OK(hipMemcpyAsync(host, bk.stats, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
+      HIP_OK(hipStreamSynchronize(R.s));
+      absorb();
+    } else if (s % check_every == 0) {
+      if (pending && hipEventQuery(ev) == hipSuccess) {
+        absorb();
+        pending = false;
+      }
+      if (!pending) {
+        HIP_OK(hipMemcpyAsync(host, bk.stats, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
+        HIP_OK(hipEventRecord(ev, R.s));
+        pending = true;
+      }
+    }
+  }
+  if (pending) (void)hipEventSynchronize(ev);
+  (void)hipEventDestroy(ev);
+  return rc;
+}
+
+template <typename TT>
+static void init_members(const Plan& P, const WS& w, void* ws, const void* state, int nmem, hipStream_t s) {
+  InitArgs<TT> ia{};
+  ia.nmem = nmem;
+  ia.ntiles = P.st_tiles;
+  ia.plane = P.lev[0].plane();
+  ia.cplane = P.cplane;
+  ia.bu = at<double>(state, P.s_u);
+  ia.bv = at<double>(state, P.s_v);
+  ia.btu = at<double>(state, P.s_tu);
+  ia.btv = at<double>(state, P.s_tv);
+  ia.bphi = at<double>(state, P.s_phi);
+  ia.u = at<double>(ws, w.u);
+  ia.v = at<double>(ws, w.v);
+  ia.us = at<double>(ws, w.us);
+  ia.vs = at<double>(ws, w.vs);
+  ia.phi = at<double>(ws, w.phiA);
+  ia.tu = at<TT>(ws, w.tuA);
+  ia.tv = at<TT>(ws, w.tvA);
+  ia.s1u = at<double>(ws, w.s1u);
+  ia.s1v = at<double>(ws, w.s1v);
+  ia.s2part = at<double>(ws, w.s2part);
+  ia.stats = at<double>(ws, w.stats);
+  ia.divmax = at<double>(ws, w.divmax);
+  launch_init_members<TT>(ia, s);
+}
+
+static int collect_stats(const Plan& P, const WS& w, void* ws, int nmem, hipStream_t s, envar_stats* st,
+                         const double* J_dev) {
+  std::vector<double> h((size_t)nmem * STATS_STRIDE), dm(nmem), J(nmem);
+  HIP_OK(hipMemcpyAsync(h.data(), at<double>(ws, w.stats), h.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(dm.data(), at<double>(ws, w.divmax), dm.size() * 8, hipMemcpyDeviceToHost, s));
+  if (J_dev) HIP_OK(hipMemcpyAsync(J.data(), J_dev, J.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  std::memset(st, 0, sizeof *st);
+  double cyc = 0.0, steps = 0.0;
+  for (int i = 0; i < nmem; ++i) {
+    const double* r = &h[(size_t)i * STATS_STRIDE];
+    cyc += r[ST_CYCLES];
+    steps += r[ST_STEPS];
+    st->max_cycles_used = std::max(st->max_cycles_used, (int)r[ST_MAXCYC]);
+    st->unconverged += (int)r[ST_UNCONV];
+    st->max_resid = std::max(st->max_resid, r[ST_MAXRES]);
+    if (!(r[ST_MAXRES] == r[ST_MAXRES])) st->max_resid = NAN;
+    st->max_div = std::max(st->max_div, dm[i]);
+    if (!(dm[i] == dm[i])) st->max_div = NAN;
+    if (J_dev && !std::isfinite(J[i])) st->diverged += 1;
+  }
+  st->mean_cycles = steps > 0 ? cyc / steps : 0.0;
+  st->steps = nmem > 0 ? (int)(steps / nmem) : 0;
+  st->cell_steps = (double)P.ncells * steps;
+  return ENVAR_OK;
+}
+
+}  // namespace envar
+
+using namespace envar;
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char* envar_last_error(void) { return g_err.c_str(); }
+const char* envar_version(void) { return "envar-mi355x 0.1 (gfx950)"; }
+
+int envar_control_dim(const envar_problem* p, int64_t* m) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!m) return fail(ENVAR_EINVAL, "m is NULL");
+  *m = P.m;
+  return ENVAR_OK;
+}
+
+int envar_cell_count(const envar_problem* p, int64_t* ncells) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!ncells) return fail(ENVAR_EINVAL, "ncells is NULL");
+  *ncells = P.ncells;
+  return ENVAR_OK;
+}
+
+size_t envar_state_bytes(const envar_problem* p) {
+  Plan P;
+  if (make_plan(p, P)) return 0;
+  return P.s_total;
+}
+
+size_t envar_workspace_bytes(const envar_problem* p, int32_t n_rows) {
+  Plan P;
+  if (make_plan(p, P) || n_rows < 1) return 0;
+  return make_ws(P, n_rows).total;
+}
+
+int envar_state_init(const envar_problem* p, const double* u, const double* v, const double* tu_prev,
+                     const double* tv_prev, const double* phi, void* state_dev, void* stream) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!u || !v || !state_dev) return fail(ENVAR_EINVAL, "u, v and state_dev are required");
+  if ((tu_prev == nullptr) != (tv_prev == nullptr)) return fail(ENVAR_EINVAL, "tu_prev and tv_prev go together");
+  hipStream_t s = (hipStream_t)stream;
+  const Geo& g = P.lev[0];
+  const long pl = g.plane();
+  const int NX = g.nx, NY = g.ny;
+  std::vector<double> bu(pl, 0.0), bv(pl, 0.0), btu(pl, 0.0), btv(pl, 0.0), bphi(pl, 0.0);
+  const double y0 = p->geometry == ENVAR_CAVITY ? -1.0 : 0.0;
+  for (int j = 0; j < NY; ++j)
+    for (int i = 0; i <= NX; ++i) {
+      const bool w = g.fluid(i - 1, j), e = g.fluid(i, j);
+      double val = 0.0;
+      if (w && e) val = u[(size_t)j * (NX + 1) + i];
+      else if (i == NX && w) val = u[(size_t)j * (NX + 1) + i];
+      else if (i == 0 && e) {
+        const double y = y0 + (j + 0.5) * g.h;
+        val = 4.0 * y * (1.0 - y);
+      }
+      if (!std::isfinite(val)) return fail(ENVAR_EINVAL, "non-finite u at (%d, %d)", i, j);
+      bu[g.at(i, j)] = val;
+      if (tu_prev && w && e) btu[g.at(i, j)] = tu_prev[(size_t)j * (NX + 1) + i];
+    }
+  for (int j = 0; j <= NY; ++j)
+    for (int i = 0; i < NX; ++i) {
+      const bool sfl = g.fluid(i, j - 1), nfl = g.fluid(i, j);
+      double val = (sfl && nfl) ? v[(size_t)j * NX + i] : 0.0;
+      if (!std::isfinite(val)) return fail(ENVAR_EINVAL, "non-finite v at (%d, %d)", i, j);
+      bv[g.at(i, j)] = val;
+      if (tv_prev && sfl && nfl) btv[g.at(i, j)] = tv_prev[(size_t)j * NX + i];
+    }
+  if (phi)
+    for (int j = 0; j < NY; ++j)
+      for (int i = 0; i < NX; ++i)
+        if (g.fluid(i, j)) bphi[g.at(i, j)] = phi[(size_t)j * NX + i];
+  std::vector<int> cmap(pl, -1);
+  for (size_t k = 0; k < P.ctrl_cells.size(); ++k) {
+    const int c = P.ctrl_cells[k];
+    cmap[g.at(c % NX, c / NX)] = (int)k;
+  }
+  Geo gc = P.lev[P.nlev_grid];
+  for (int l = 1; l < P.ncoarse; ++l) gc = gc.coarser();
+  std::vector<double> ainv;
+  std::vector<int> aidx;
+  coarse_inverse(gc, ainv, aidx);
+  int meta[64] = {0};
+  meta[0] = tu_prev ? 0 : 1;  // cold start flag
+  char* S = (char*)state_dev;
+  HIP_OK(hipMemsetAsync(S, 0, P.s_total, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_meta, meta, sizeof meta, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_u, bu.data(), pl * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_v, bv.data(), pl * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_tu, btu.data(), pl * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_tv, btv.data(), pl * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_phi, bphi.data(), pl * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_cmap, cmap.data(), pl * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_ainv, ainv.data(), ainv.size() * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(S + P.s_aidx, aidx.data(), aidx.size() * 4, hipMemcpyHostToDevice, s));
+  launch_shift(g, at<double>(state_dev, P.s_u), at<double>(state_dev, P.s_v), at<double>(state_dev, P.s_shu),
+               at<double>(state_dev, P.s_shv), s);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(s));
+  return ENVAR_OK;
+}
+
+int envar_state_read(const envar_problem* p, const void* state_dev, double* u, double* v, double* tu_prev,
+                     double* tv_prev, double* phi) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!state_dev) return fail(ENVAR_EINVAL, "state_dev is NULL");
+  const Geo& g = P.lev[0];
+  const size_t pb = (size_t)g.pitch * 8;
+  const char* S = (const char*)state_dev;
+  if (u) HIP_OK(hipMemcpy2D(u, (g.nx + 1) * 8, S + P.s_u, pb, (g.nx + 1) * 8, g.ny, hipMemcpyDeviceToHost));
+  if (v) HIP_OK(hipMemcpy2D(v, g.nx * 8, S + P.s_v, pb, g.nx * 8, g.ny + 1, hipMemcpyDeviceToHost));
+  if (tu_prev)
+    HIP_OK(hipMemcpy2D(tu_prev, (g.nx + 1) * 8, S + P.s_tu, pb, (g.nx + 1) * 8, g.ny, hipMemcpyDeviceToHost));
+  if (tv_prev) HIP_OK(hipMemcpy2D(tv_prev, g.nx * 8, S + P.s_tv, pb, g.nx * 8, g.ny + 1, hipMemcpyDeviceToHost));
+  if (phi) HIP_OK(hipMemcpy2D(phi, g.nx * 8, S + P.s_phi, pb, g.nx * 8, g.ny, hipMemcpyDeviceToHost));
+  return ENVAR_OK;
+}
+
+static int forward_impl(const Plan& P, const void* state_dev, const double* controls_dev, int n_rows, int horizon,
+                        void* ws_dev, size_t ws_bytes, double* J_dev, double* fields_dev, envar_stats* stats,
+                        hipStream_t s, bool spinup_store) {
+  const WS w = make_ws(P, n_rows);
+  if (ws_bytes < w.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, w.total);
+  if (P.mixed)
+    init_members<float>(P, w, ws_dev, state_dev, n_rows, s);
+  else
+    init_members<double>(P, w, ws_dev, state_dev, n_rows, s);
+  Timer timer;
+  timer.on = stats != nullptr && (P.p.flags & ENVAR_FLAG_TIME_KERNELS);
+  timer.every = std::max(1, (horizon - 1 + timer.max_samples - 1) / timer.max_samples);
+  Run R{&P, ws_dev, &w, n_rows, state_dev, controls_dev, s, timer.on ? &timer : nullptr};
+  int rc = P.mixed ? run_steps<float>(R, horizon, 1) : run_steps<double>(R, horizon, 1);
+  if (rc) return rc;
+  if (J_dev) {
+    FinalArgs fa{};
+    fa.g = P.lev[0];
+    fa.nmem = n_rows;
+    fa.ntiles = P.st_tiles;
+    fa.cplane = P.cplane;
+    fa.K = horizon;
+    fa.dt = P.dt;
+    fa.penalty = P.penalty;
+    fa.s1u = at<double>(ws_dev, w.s1u);
+    fa.s1v = at<double>(ws_dev, w.s1v);
+    fa.s2part = at<double>(ws_dev, w.s2part);
+    fa.ctrl = controls_dev;
+    fa.m = P.m;
+    fa.J = J_dev;
+    fa.stats = at<double>(ws_dev, w.stats);
+    launch_finalize_J(fa, s);
+  }
+  if (fields_dev)
+    launch_fields_out(P.lev[0], P.lev[0].plane(), n_rows, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
+                      fields_dev, s);
+  if (spinup_store) {
+    // the last step wrote its tendency into buffer B when horizon is odd
+    const bool inB = (horizon % 2) == 1;
+    void* S = (void*)state_dev;
+    const long pl = P.lev[0].plane();
+    if (P.mixed)
+      launch_store_base<float>(pl, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
+                               at<float>(ws_dev, inB ? w.tuB : w.tuA), at<float>(ws_dev, inB ? w.tvB : w.tvA),
+                               at<double>(ws_dev, w.phiA), at<double>(S, P.s_u), at<double>(S, P.s_v),
+                               at<double>(S, P.s_tu), at<double>(S, P.s_tv), at<double>(S, P.s_phi), s);
+    else
+      launch_store_base<double>(pl, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
+                                at<double>(ws_dev, inB ? w.tuB : w.tuA), at<double>(ws_dev, inB ? w.tvB : w.tvA),
+                                at<double>(ws_dev, w.phiA), at<double>(S, P.s_u), at<double>(S, P.s_v),
+                                at<double>(S, P.s_tu), at<double>(S, P.s_tv), at<double>(S, P.s_phi), s);
+    launch_clear_flag(at<int>(S, P.s_meta), s);
+    launch_shift(P.lev[0], at<double>(S, P.s_u), at<double>(S, P.s_v), at<double>(S, P.s_shu),
+                 at<double>(S, P.s_shv), s);
+  }
+  HIP_OK(hipGetLastError());
+  if (stats) {
+    rc = collect_stats(P, w, ws_dev, n_rows, s, stats, J_dev);
+    if (rc) return rc;
+    if (timer.on && timer.samples > 0) {
+      double* outs[TM_N] = {&stats->predictor_us, &stats->pre_us, &stats->post_us,
+                            &stats->resid_us, &stats->project_us, &stats->vcycle_us};
+      for (int t = 0; t < TM_N; ++t) {
+        double sum = 0.0;
+        int cnt = 0;
+        for (int q = 0; q < timer.samples; ++q) {
+          if (!timer.recorded(q, t)) continue;
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, timer.ev[((size_t)q * TM_N + t) * 2], timer.ev[((size_t)q * TM_N + t) * 2 + 1]) ==
+              hipSuccess) {
+            sum += ms;
+            ++cnt;
+          }
+        }
+        *outs[t] = cnt ? 1e3 * sum / cnt : 0.0;
+      }
+      stats->timed_steps = timer.samples;
+      stats->timed_members = n_rows;
+      (void)hipGetLastError();  // the event queries leave no sticky error behind
+    }
+    if (stats->diverged > 0) return fail(ENVAR_EDIVERGED, "%d member(s) produced a non-finite cost", stats->diverged);
+  }
+  return ENVAR_OK;
+}
+
+int envar_spinup(const envar_problem* p, void* state_dev, int32_t steps, void* ws_dev, size_t ws_bytes,
+                 envar_stats* stats, void* stream) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!state_dev || !ws_dev) return fail(ENVAR_EINVAL, "state_dev and ws_dev are required");
+  if (steps < 1) return fail(ENVAR_EINVAL, "steps must be >= 1");
+  return forward_impl(P, state_dev, nullptr, 1, steps, ws_dev, ws_bytes, nullptr, nullptr, stats,
+                      (hipStream_t)stream, true);
+}
+
+int envar_forward(const envar_problem* p, const void* state_dev, const double* controls_dev, int32_t n_rows,
+                  int64_t m, int32_t horizon, void* ws_dev, size_t ws_bytes, double* J_dev, double* fields_dev,
+                  envar_stats* stats, void* stream) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!state_dev || !ws_dev || !J_dev || !controls_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  if (n_rows < 1) return fail(ENVAR_EINVAL, "n_rows must be >= 1");
+  if (m != P.m) return fail(ENVAR_EINVAL, "m = %lld but the control region has m = %ld", (long long)m, P.m);
+  if (horizon < 1) return fail(ENVAR_EINVAL, "horizon must be >= 1");
+  return forward_impl(P, state_dev, controls_dev, n_rows, horizon, ws_dev, ws_bytes, J_dev, fields_dev, stats,
+                      (hipStream_t)stream, false);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- gradient
+namespace envar {
+struct GradLayout {
+  size_t X, Xt, dJ, rhs, partial, G, c, info, total;
+  int nsplit, dim;
+  long kchunk;
+};
+
+static GradLayout grad_layout(int n, long m, int precision) {
+  GradLayout L{};
+  const size_t xs = precision == ENVAR_MIXED ? 4 : 8;
+  const bool tall = n <= m;
+  L.dim = tall ? n : (int)m;
+  const long klen = tall ? m : n;  // contraction length
+  // split the contraction so that >= ~512 workgroups run, chunks multiple of 32
+  const int nbt = (L.dim + 63) / 64;
+  long want = std::max(1L, 512L / (nbt * nbt));
+  long chunk = (klen + want - 1) / want;
+  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
+  L.kchunk = chunk;
+  L.nsplit = (int)((klen + chunk - 1) / chunk);
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t a = o;
+    o = align256(o + b);
+    return a;
+  };
+  L.X = take((size_t)n * m * xs);
+  L.Xt = tall ? 0 : take((size_t)n * m * xs);
+  L.dJ = take((size_t)n * 8);
+  L.rhs = take((size_t)L.dim * 8);
+  L.partial = take((size_t)L.nsplit * L.dim * L.dim * 8);
+  L.G = take((size_t)L.dim * L.dim * 8);
+  L.c = take((size_t)L.dim * 8);
+  L.info = take(256);
+  L.total = o;
+  return L;
+}
+
+}  // namespace envar
+
+extern "C" size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision) {
+  if (n < 1 || m < 1) return 0;
+  return grad_layout(n, m, precision).total;
+}
+
+namespace envar {
+template <typename TX>
+static int gradient_impl(const double* ctrl, const double* J, int n, long m, int precision, void* ws, double* g,
+                         hipStream_t s) {
+  const GradLayout L = grad_layout(n, m, precision);
+  TX* X = at<TX>(ws, L.X);
+  double* dJ = at<double>(ws, L.dJ);
+  double* G = at<double>(ws, L.G);
+  launch_anomaly<TX>(ctrl, J, n, m, X, dJ, s);
+  if (n <= m) {
+    launch_gram<TX>(X, n, m, m, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
+    launch_gram_reduce(at<double>(ws, L.partial), n, L.nsplit, G, s);
+    launch_chol_solve(G, dJ, n, at<double>(ws, L.c), at<double>(ws, L.info), s);
+    launch_gemv_t<TX>(X, n, m, m, at<double>(ws, L.c), g, s);
+  } else {
+    TX* Xt = at<TX>(ws, L.Xt);
+    launch_transpose<TX>(X, n, m, Xt, s);
+    launch_gram<TX>(Xt, (int)m, n, n, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
+    launch_gram_reduce(at<double>(ws, L.partial), (int)m, L.nsplit, G, s);
+    double* rhs = at<double>(ws, L.rhs);
+    launch_gemv_t<TX>(X, n, m, m, dJ, rhs, s);
+    launch_chol_solve(G, rhs, (int)m, g, at<double>(ws, L.info), s);
+  }
+  HIP_OK(hipGetLastError());
+  return ENVAR_OK;
+}
+
+}  // namespace envar
+
+extern "C" int envar_gradient(const double* controls_dev, const double* J_dev, int32_t n, int64_t m, int32_t precision,
+                   void* ws_dev, size_t ws_bytes, double* g_dev, void* stream) {
+  if (n < 1 || m < 1) return fail(ENVAR_EINVAL, "n and m must be >= 1");
+  if (!controls_dev || !J_dev || !ws_dev || !g_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  if (precision != ENVAR_FP64 && precision != ENVAR_MIXED) return fail(ENVAR_EINVAL, "unknown precision");
+  if (std::min<long>(n, m) > 1024) return fail(ENVAR_EINVAL, "min(n, m) = %ld exceeds 1024", std::min<long>(n, m));
+  const GradLayout L = grad_layout(n, m, precision);
+  if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+  if (precision == ENVAR_MIXED)
+    return gradient_impl<float>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
+  return gradient_impl<double>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------- iterate
+namespace envar {
+struct IterLayout {
+  size_t rows, J, g, fwd, grad, total;
+};
+static IterLayout iter_layout(const Plan& P, int n) {
+  IterLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t a = o;
+    o = align256(o + b);
+    return a;
+  };
+  L.rows = take((size_t)(n + 1) * P.m * 8);
+  L.J = take((size_t)(n + 1) * 8);
+  L.g = take((size_t)P.m * 8);
+  L.fwd = take(make_ws(P, n + 1).total);
+  L.grad = take(grad_layout(n, P.m, P.p.precision).total);
+  L.total = o;
+  return L;
+}
+
+__global__ void k_rows(const double* f, const double* pert, int n, long m, double* rows, double alpha,
+                       const double* g, double* ftrial);
+}  // namespace envar
+
+extern "C" size_t envar_iterate_bytes(const envar_problem* p, int32_t n, int64_t m) {
+  Plan P;
+  if (make_plan(p, P) || n < 1 || m != P.m) return 0;
+  return iter_layout(P, n).total;
+}
+
+namespace envar {
+__global__ void k_rows(const double* f, const double* pert, int n, long m, double* rows, double alpha,
+                       const double* g, double* ftrial) {
+  // rows[0] = f, rows[i] = f + pert[i-1]; ftrial = f - alpha g (when g != NULL)
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < m; k += (long)gridDim.x * blockDim.x) {
+    const double fk = f[k];
+    if (rows) {
+      rows[k] = fk;
+      for (int i = 0; i < n; ++i) rows[(long)(i + 1) * m + k] = fk + pert[(long)i * m + k];
+    }
+    if (g) ftrial[k] = fk - alpha * g[k];
+  }
+}
+
+}  // namespace envar
+
+extern "C" int envar_iterate(const envar_problem* p, const void* state_dev, double* f_dev, const double* perturb_dev, int32_t n,
+                  int64_t m, int32_t horizon, const envar_ls_params* ls, void* ws_dev, size_t ws_bytes,
+                  envar_iter_record* records, void* stream) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!ls || ls->iters < 1) return fail(ENVAR_EINVAL, "ls->iters must be >= 1");
+  if (m != P.m || n < 1) return fail(ENVAR_EINVAL, "bad n or m");
+  if (!state_dev || !f_dev || !perturb_dev || !ws_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  const IterLayout L = iter_layout(P, n);
+  if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  const int trials = ls->max_trials > 0 ? ls->max_trials : 8;
+  const double c1 = ls->c1 > 0 ? ls->c1 : 1e-4, shrink = ls->shrink > 0 ? ls->shrink : 0.5;
+  double* rows = at<double>(ws_dev, L.rows);
+  double* Jd = at<double>(ws_dev, L.J);
+  double* g = at<double>(ws_dev, L.g);
+  void* fws = at<char>(ws_dev, L.fwd);
+  void* gws = at<char>(ws_dev, L.grad);
+  const size_t fbytes = make_ws(P, n + 1).total;
+  const size_t gbytes = grad_layout(n, P.m, P.p.precision).total;
+  // max |perturb| for the default first step
+  std::vector<double> hp((size_t)n * m), hg(m);
+  HIP_OK(hipMemcpyAsync(hp.data(), perturb_dev, hp.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  double pmax = 0.0;
+  for (double x : hp) pmax = std::max(pmax, std::fabs(x));
+  double alpha_fixed = -1.0;
+  const int grid = (int)std::min<long>(4096, (m + 255) / 256);
+  for (int it = 0; it < ls->iters; ++it) {
+    hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, s, f_dev, perturb_dev, n, (long)m, rows, 0.0,
+                       (const double*)nullptr, (double*)nullptr);
+    rc = forward_impl(P, state_dev, rows, n + 1, horizon, fws, fbytes, Jd, nullptr, nullptr, s, false);
+    if (rc) return rc;
+    rc = envar_gradient(rows, Jd, n, m, P.p.precision, gws, gbytes, g, s);
+    if (rc) return rc;
+    double J0 = 0.0;
+    HIP_OK(hipMemcpyAsync(&J0, Jd, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(hg.data(), g, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double gg = 0.0, gmax = 0.0;
+    for (double x : hg) {
+      gg += x * x;
+      gmax = std::max(gmax, std::fabs(x));
+    }
+    envar_iter_record rec{J0, std::sqrt(gg), 0.0, NAN};
+    const bool search = alpha_fixed < 0.0 || (ls->search_every > 0 && it % ls->search_every == 0);
+    double alpha = alpha_fixed;
+    if (search) {
+      double a = ls->alpha0 > 0 ? ls->alpha0 : pmax / std::max(gmax, 1e-300);
+      bool ok = false;
+      for (int t = 0; t < trials; ++t) {
+        // trial row: f - a g, evaluated as a one-member forward into rows[0]
+        hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, s, f_dev, perturb_dev, 0, (long)m, (double*)nullptr, a,
+                           (const double*)g, rows);
+        rc = forward_impl(P, state_dev, rows, 1, horizon, fws, fbytes, Jd, nullptr, nullptr, s, false);
+        if (rc) return rc;
+        double Jt = 0.0;
+        HIP_OK(hipMemcpyAsync(&Jt, Jd, 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        if (Jt <= J0 - c1 * a * gg) {
+          ok = true;
+          rec.J_trial = Jt;
+          break;
+        }
+        a *= shrink;
+      }
+      if (!ok) {
+        if (records) records[it] = rec;
+        return ENVAR_OK;
+      }
+      alpha = a;
+      alpha_fixed = a;
+    }
+    rec.alpha = alpha;
+    // f <- f - alpha g
+    hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, s, f_dev, perturb_dev, 0, (long)m, (double*)nullptr, alpha,
+                       (const double*)g, f_dev);
+    HIP_OK(hipGetLastError());
+    if (records) records[it] = rec;
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  return ENVAR_OK;
+}

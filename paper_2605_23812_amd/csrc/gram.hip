@@ -1,0 +1,232 @@
+// Anomaly reduction {delta f_i, J_i} -> g on the matrix cores.
+//
+// The ensemble gradient of eq. (gradient_EnVar), in its scalar-cost form,
+// needs the minimum-norm least-squares solution of X g = dJ with
+// X_i = f_i - f_0 (n x m, tall-skinny as m^T) and dJ_i = J_i - J_0:
+//     G = X X^T (n x n),  G c = dJ,  g = X^T c.
+// G is the only dense contraction of the hot path: 2 n^2 m flops over n m
+// operands, so it runs on MFMA (v_mfma_f64_16x16x4f64, or
+// v_mfma_f32_16x16x4f32 for FP32 operands) with a split over m and FP64
+// partials reduced in a fixed order. The n x n solve is an FP64 Cholesky
+// in one workgroup; the projection g = X^T c is a bandwidth-bound GEMV with
+// FP64 accumulation.
+#include "common.h"
+#include "kernels.h"
+
+namespace envar {
+
+// ---------------------------------------------------------------------------- anomalies
+template <typename TX>
+__global__ void k_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, double* dJ) {
+  const int i = blockIdx.y;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < m; k += (long)gridDim.x * blockDim.x)
+    X[(long)i * m + k] = (TX)(ctrl[(long)(i + 1) * m + k] - ctrl[k]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) dJ[i] = J[i + 1] - J[0];
+}
+
+// ---------------------------------------------------------------------------- Gram on MFMA
+// One workgroup (4 waves) computes a 64 x 64 block G[I0:I0+64, J0:J0+64] of
+// one split's partial sum over columns [kbeg, kend). X rows are staged through
+// LDS in KC-column chunks (rows padded by one element against bank
+// conflicts); wave w owns rows I0 + 16w .. +16 and the four 16 x 16 tiles
+// across J. MFMA operand layout (16x16x4): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; the r-th result register of lane l holds D[row][l%16] with
+// row = l/16 + 4 r for the FP64 instruction and 4 (l/16) + r for the FP32 one
+// (measured on gfx950).
+template <typename TX>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  typedef double __attribute__((ext_vector_type(4))) V;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return lane / 16 + 4 * r; }
+};
+template <>
+struct MfmaAcc<float> {
+  typedef float __attribute__((ext_vector_type(4))) V;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
+constexpr int GRAM_KC = 32;
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, long m, long ldx,
+                                              double* __restrict__ partial, int nsplit, long kchunk, int nbt) {
+  typedef typename MfmaAcc<TX>::V V;
+  constexpr int KC = GRAM_KC, LDR = KC + 1;
+  __shared__ TX sa[64 * LDR];
+  __shared__ TX sb[64 * LDR];
+  const int split = blockIdx.x % nsplit;
+  const int pair = blockIdx.x / nsplit;
+  const int bi = pair / nbt, bj = pair % nbt;
+  const int I0 = bi * 64, J0 = bj * 64;
+  const long kbeg = (long)split * kchunk;
+  long kend = kbeg + kchunk;
+  if (kend > m) kend = m;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  V acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = V{0, 0, 0, 0};
+  for (long k0 = kbeg; k0 < kend; k0 += KC) {
+    // stage 64 rows x KC columns of both row blocks (zero outside X)
+    for (int q = threadIdx.x; q < 64 * KC; q += 256) {
+      const int r = q / KC, c = q % KC;
+      const long k = k0 + c;
+      const int ra = I0 + r, rb = J0 + r;
+      sa[r * LDR + c] = (ra < n && k < kend) ? X[(long)ra * ldx + k] : (TX)0;
+      sb[r * LDR + c] = (rb < n && k < kend) ? X[(long)rb * ldx + k] : (TX)0;
+    }
+    __syncthreads();
+    const int row = 16 * wave + lane % 16;
+    for (int kk = 0; kk < KC; kk += 4) {
+      const TX a = sa[row * LDR + kk + lane / 16];
+      for (int t = 0; t < 4; ++t) {
+        const TX b = sb[(16 * t + lane % 16) * LDR + kk + lane / 16];
+        acc[t] = MfmaAcc<TX>::mma(a, b, acc[t]);
+      }
+    }
+    __syncthreads();
+  }
+  double* P = partial + (long)split * n * n;
+  for (int t = 0; t < 4; ++t) {
+    const int j = J0 + 16 * t + lane % 16;
+    for (int r = 0; r < 4; ++r) {
+      const int i = I0 + 16 * wave + MfmaAcc<TX>::row(lane, r);
+      if (i < n && j < n) P[(long)i * n + j] = (double)acc[t][r];
+    }
+  }
+}
+
+__global__ void k_gram_reduce(const double* partial, int n, int nsplit, double* G) {
+  const long nn = (long)n * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int p = 0; p < nsplit; ++p) s += partial[(long)p * nn + e];
+    G[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------- FP64 Cholesky solve
+// Solves (G + ridge I) x = rhs in place (G lower triangle overwritten by L),
+// ridge = 1e-12 tr(G) / n; right-looking, one workgroup, fixed order.
+__global__ __launch_bounds__(1024) void k_chol_solve(double* G, const double* rhs, int n, double* x, int* info) {
+  __shared__ double ridge;
+  __shared__ double piv;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += G[(long)i * n + i];
+    ridge = 1e-12 * tr / (double)n;
+    *info = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    G[(long)i * n + i] += ridge;
+    x[i] = rhs[i];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = G[(long)k * n + k];
+      if (!(d > 0.0)) *info = k + 1;
+      piv = sqrt(d > 0.0 ? d : 1e-300);
+      G[(long)k * n + k] = piv;
+    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += nt) G[(long)i * n + k] /= piv;
+    __syncthreads();
+    const long rem = n - k - 1;
+    for (long e = tid; e < rem * rem; e += nt) {
+      const int i = k + 1 + (int)(e / rem), j = k + 1 + (int)(e % rem);
+      if (j <= i) G[(long)i * n + j] -= G[(long)i * n + k] * G[(long)j * n + k];
+    }
+    __syncthreads();
+  }
+  // L y = rhs
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) x[k] /= G[(long)k * n + k];
+    __syncthreads();
+    for (int i = k + 1 + tid; i < n; i += nt) x[i] -= G[(long)i * n + k] * x[k];
+    __syncthreads();
+  }
+  // L^T x = y
+  for (int k = n - 1; k >= 0; --k) {
+    if (tid == 0) x[k] /= G[(long)k * n + k];
+    __syncthreads();
+    for (int i = tid; i < k; i += nt) x[i] -= G[(long)k * n + i] * x[k];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------- GEMVs
+// g[k] = sum_i X[i][k] c[i]
+template <typename TX>
+__global__ void k_gemv_t(const TX* __restrict__ X, int n, long m, long ldx, const double* __restrict__ c,
+                         double* __restrict__ g) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < m; k += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += (double)X[(long)i * ldx + k] * c[i];
+    g[k] = s;
+  }
+}
+
+template <typename TX>
+__global__ void k_transpose(const TX* X, int n, long m, TX* Xt) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)n * m; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / m);
+    const long k = e % m;
+    Xt[k * n + i] = X[e];
+  }
+}
+
+// ---------------------------------------------------------------------------- launchers
+template <typename TX>
+void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, double* dJ, hipStream_t s) {
+  int bx = (int)((m + 255) / 256);
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_anomaly<TX>, dim3(bx, n), dim3(256), 0, s, ctrl, J, n, m, X, dJ);
+}
+template <typename TX>
+void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s) {
+  const int nbt = (n + 63) / 64;
+  hipLaunchKernelGGL(k_gram<TX>, dim3(nsplit * nbt * nbt), dim3(256), 0, s, X, n, m, ldx, partial, nsplit, kchunk,
+                     nbt);
+}
+void launch_gram_reduce(const double* partial, int n, int nsplit, double* G, hipStream_t s) {
+  const long nn = (long)n * n;
+  int bx = (int)((nn + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(bx), dim3(256), 0, s, partial, n, nsplit, G);
+}
+int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work);
+  return 0;
+}
+template <typename TX>
+void launch_gemv_t(const TX* X, int n, long m, long ldx, const double* c, double* g, hipStream_t s) {
+  int bx = (int)((m + 255) / 256);
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(k_gemv_t<TX>, dim3(bx), dim3(256), 0, s, X, n, m, ldx, c, g);
+}
+template <typename TX>
+void launch_transpose(const TX* X, int n, long m, TX* Xt, hipStream_t s) {
+  long e = (long)n * m;
+  int bx = (int)((e + 255) / 256);
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(k_transpose<TX>, dim3(bx), dim3(256), 0, s, X, n, m, Xt);
+}
+
+template void launch_anomaly<double>(const double*, const double*, int, long, double*, double*, hipStream_t);
+template void launch_anomaly<float>(const double*, const double*, int, long, float*, double*, hipStream_t);
+template void launch_gram<double>(const double*, int, long, long, double*, int, long, hipStream_t);
+template void launch_gram<float>(const float*, int, long, long, double*, int, long, hipStream_t);
+template void launch_gemv_t<double>(const double*, int, long, long, const double*, double*, hipStream_t);
+template void launch_gemv_t<float>(const float*, int, long, long, const double*, double*, hipStream_t);
+template void launch_transpose<double>(const double*, int, long, double*, hipStream_t);
+template void launch_transpose<float>(const float*, int, long, float*, hipStream_t);
+
+}  // namespace envar

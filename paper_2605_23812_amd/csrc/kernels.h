@@ -1,0 +1,190 @@
+// Kernel argument blocks and host launchers of the EnVar HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace envar {
+
+// per-member statistics slots (FP64)
+enum { ST_CYCLES = 0, ST_MAXCYC, ST_UNCONV, ST_MAXRES, ST_STEPS, ST_J, STATS_STRIDE = 8 };
+
+template <typename TT>
+struct PredArgs {
+  Geo g;
+  Tiling tiling;
+  int ntiles, nmem;
+  long plane;
+  double nu, dt;
+  const int* cold_flag;       // device flag: first step of a cold start (T^{-1} = T^0)
+  const double* u;            // u^n, v^n
+  const double* v;
+  double* us;                 // u*, v*
+  double* vs;
+  const TT* tu_prev;          // T^{n-1}
+  const TT* tv_prev;
+  TT* tu;                     // T^n
+  TT* tv;
+  double* b;                  // div_h u* / dt
+  const double* ctrl;         // [nmem][m] control rows, NULL = unforced
+  long m;
+  int nctrl;
+  const int* cmap;            // control index of every cell (plane layout), -1 outside
+  double* norms;              // [nmem][norm_slots], cleared here
+  int norm_slots;
+};
+
+struct ProjArgs {
+  Geo g;
+  Tiling tiling;
+  int ntiles, nmem;
+  long plane, cplane;
+  double dt;
+  double* u;
+  double* v;
+  const double* us;
+  const double* vs;
+  const double* phi;
+  const double* shu;  // cost shift (dense cells, shared by members)
+  const double* shv;
+  double* s1u;        // [nmem][cplane] running sums of (u_c - s_c); NULL = no cost
+  double* s1v;
+  double* s2part;     // [nmem][ntiles]
+  double* divmax;     // [nmem] max |div u^{n+1}| (atomicMax on the bit pattern)
+};
+
+struct BookArgs {
+  int nmem;
+  int norm_slots;
+  int cap;        // slots filled this step: cap + slot_base
+  int slot_base;  // 0 (FP64: slot k = after V-cycle k) or 1 (mixed: slot 0 = initial residual)
+  double tol;     // on dt * max|r|, in the units stored in norms
+  const double* norms;
+  double* stats;
+};
+
+struct FinalArgs {
+  Geo g;
+  int nmem, ntiles;
+  long cplane;
+  long K;
+  double dt, penalty;
+  const double* s1u;
+  const double* s1v;
+  const double* s2part;
+  const double* ctrl;
+  long m;
+  double* J;
+  double* stats;
+};
+
+template <typename TT>
+struct InitArgs {
+  int nmem, ntiles;
+  long plane, cplane;
+  const double *bu, *bv, *btu, *btv, *bphi;
+  double *u, *v, *us, *vs, *phi;
+  TT *tu, *tv;
+  double *s1u, *s1v, *s2part, *stats, *divmax;
+};
+
+// multigrid level arguments (T = arithmetic / storage type of the level)
+template <typename T>
+struct MGArgs {
+  Geo g, gc;          // this level and the next coarser one
+  Tiling tiling;
+  int ntiles, nmem;
+  long plane, cplane_c;  // plane of this level and of the coarse level
+  const T* phi_in;    // [nmem][plane] read (halo included); never written by this launch
+  T* phi_out;         // [nmem][plane] written (tile interiors) -- ping-pong avoids inter-tile races
+  const T* b;
+  T* phic;            // coarse correction
+  T* bc;              // coarse right-hand side
+  double* add_to;     // post, mixed: phi64 += phi instead of storing phi (NULL = store)
+  int zero_guess;     // pre: start from phi = 0
+  // convergence control: skip members whose previous cycle met tol
+  double* norms;      // [nmem][norm_slots]
+  int norm_slots;
+  int k;              // this cycle's slot (skip when k > 0 and norms[k-1] <= tol)
+  int write_norm;     // post at the finest level: write dt*max|r| into norms[k]
+  double tol;         // on dt*max|r|
+  double dt;          // residual scale for the stored norm
+};
+
+struct CoarseArgs {
+  Geo g;              // top level handled in LDS (inv_h <= 16)
+  int nlev;           // levels from the top down to inv_h = 4 (inclusive)
+  int nmem;
+  long plane;
+  void* phi;          // [nmem][plane] of type T
+  const void* b;
+  int warm;           // start from the stored phi (top = finest level)
+  double* add_to;     // mixed with no tiled level: phi64 += phi instead of storing phi
+  const double* ainv; // dense inverse of the coarsest operator [nc][nc]
+  const int* aidx;    // cell (i + j * nx) of each coarsest unknown
+  int nc;
+  double* norms;
+  int norm_slots;
+  int k;
+  int write_norm;
+  double tol, dt;
+  int nsweep_pre, nsweep_post;
+};
+
+struct ResidArgs {
+  Geo g;
+  Tiling tiling;
+  int ntiles, nmem;
+  long plane;
+  const double* phi;  // FP64 pressure
+  const double* b;    // FP64 right-hand side
+  float* r;           // FP32 residual (right-hand side of the next correction)
+  double* norms;
+  int norm_slots;
+  int k;
+  double tol, dt;
+};
+
+template <typename TT>
+void launch_predictor(const PredArgs<TT>& a, hipStream_t s);
+void launch_project_cost(const ProjArgs& a, hipStream_t s);
+void launch_step_book(const BookArgs& a, hipStream_t s);
+void launch_finalize_J(const FinalArgs& a, hipStream_t s);
+template <typename TT>
+void launch_init_members(const InitArgs<TT>& a, hipStream_t s);
+void launch_shift(const Geo& g, const double* u, const double* v, double* shu, double* shv, hipStream_t s);
+template <typename TT>
+void launch_store_base(long plane, const double* u, const double* v, const TT* tu, const TT* tv, const double* phi,
+                       double* bu, double* bv, double* btu, double* btv, double* bphi, hipStream_t s);
+void launch_fields_out(const Geo& g, long plane, int nmem, const double* u, const double* v, double* out,
+                       hipStream_t s);
+void launch_clear_flag(int* flag, hipStream_t s);
+
+template <typename T>
+void launch_mg_pre(const MGArgs<T>& a, int nsweep, hipStream_t s);
+template <typename T>
+void launch_mg_post(const MGArgs<T>& a, int nsweep, hipStream_t s);
+template <typename T>
+void launch_mg_coarse(const CoarseArgs& a, hipStream_t s);
+void launch_resid64(const ResidArgs& a, hipStream_t s);
+
+// anomaly reduction
+struct GramPlan {
+  int n;          // rows of X (Gram is n x n)
+  long m;         // contraction length
+  int nsplit;     // split-K partials
+  long kchunk;    // columns per split (multiple of 16)
+};
+template <typename TX>
+void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, double* dJ, hipStream_t s);
+template <typename TX>
+void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s);
+void launch_gram_reduce(const double* partial, int n, int nsplit, double* G, hipStream_t s);
+int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s);
+template <typename TX>
+void launch_gemv_t(const TX* X, int n, long m, long ldx, const double* c, double* g, hipStream_t s);
+template <typename TX>
+void launch_transpose(const TX* X, int n, long m, TX* Xt, hipStream_t s);
+
+}  // namespace envar

@@ -1,0 +1,429 @@
+// Time-step kernels: fused predictor (advection + diffusion + forcing + AB2 +
+// convective outflow + Poisson right-hand side), projection fused with the
+// on-the-fly cost accumulator, per-step convergence bookkeeping, and the
+// final cost reduction.
+//
+// Discretisation of eq. (forced_NS) / eq. (discrete_NS) on the MAC grid:
+//   T^n   = -div_h(u u) + nu lap_h u           (conservative central form, active faces)
+//   u*    = u^n + dt (3/2 T^n - 1/2 T^{n-1} + F),  F = P f (face mean of the cell forcing)
+//   u*_b  = u^n_b - dt U_c (u^n_b - u^n_{b-1}) / h   (outflow faces)
+//   b     = div_h u* / dt                      (Poisson right-hand side)
+//   u^{n+1} = u* - dt grad_h phi               (active and outflow faces; phi = 0 on the outflow face)
+// Neighbour rules: a wall face holds 0, a face with no fluid cell on either
+// side mirrors the own value (no-slip wall half a cell away), the v value
+// west of the inflow mirrors (v = 0 at the inlet) and east of the outflow
+// copies (zero normal gradient of v at the outlet).
+//
+// Cost (eq. Envarcost with the fluctuation energy of eq. kinenergy): per cell
+// S1_c += (u_c - s_c) and per tile S2 += sum |u_c - s_c|^2 with the shift s =
+// the base-state cell velocity; at the end J_obs = dt h^2 (S2 - sum_c |S1_c|^2 / K).
+#include "common.h"
+#include "kernels.h"
+
+namespace envar {
+
+// ---------------------------------------------------------------------------- predictor
+template <typename TT>
+__global__ __launch_bounds__(256) void k_predictor(PredArgs<TT> a) {
+  constexpr int TW = TILE_W, TH = STEP_TH;
+  constexpr int UW = TW + 3, UH = TH + 2;  // u halo: i in [x0-1, x0+TW+1], j in [y0-1, y0+TH]
+  constexpr int VW = TW + 2, VH = TH + 3;  // v halo: i in [x0-1, x0+TW],   j in [y0-1, y0+TH+1]
+  __shared__ double su[UH * UW];
+  __shared__ double sv[VH * VW];
+  __shared__ double sus[TH * (TW + 1)];
+  __shared__ double svs[(TH + 1) * TW];
+
+  const Geo& g = a.g;
+  const int total = a.ntiles * a.nmem;
+  const int item = xcd_remap(blockIdx.x, total);
+  const int mem = item / a.ntiles;
+  const int tile = item % a.ntiles;
+  int x0, y0;
+  a.tiling.origin(tile, x0, y0);
+  const long off = (long)mem * a.plane;
+  const double* __restrict__ u = a.u + off;
+  const double* __restrict__ v = a.v + off;
+  const TT* __restrict__ tup = a.tu_prev + off;
+  const TT* __restrict__ tvp = a.tv_prev + off;
+  const double* __restrict__ f = a.ctrl ? a.ctrl + (long)mem * a.m : nullptr;
+  const int tid = threadIdx.x;
+
+  if (tile == 0 && a.norms != nullptr)
+    for (int k = tid; k < a.norm_slots; k += 256) a.norms[(long)mem * a.norm_slots + k] = 0.0;
+
+  for (int k = tid; k < UH * UW; k += 256) {
+    const int i = x0 - 1 + k % UW, j = y0 - 1 + k / UW;
+    su[k] = (i >= 0 && i <= g.nx && j >= 0 && j < g.ny) ? u[g.at(i, j)] : 0.0;
+  }
+  for (int k = tid; k < VH * VW; k += 256) {
+    const int i = x0 - 1 + k % VW, j = y0 - 1 + k / VW;
+    sv[k] = (i >= 0 && i < g.nx && j >= 0 && j <= g.ny) ? v[g.at(i, j)] : 0.0;
+  }
+  __syncthreads();
+#define SU(i, j) su[((j) - y0 + 1) * UW + ((i) - x0 + 1)]
+#define SV(i, j) sv[((j) - y0 + 1) * VW + ((i) - x0 + 1)]
+
+  const TT h = (TT)g.h, inv4h = (TT)(0.25 / g.h), inv_h2 = (TT)(1.0 / (g.h * g.h)), nu = (TT)a.nu;
+  const double dt = a.dt;
+  const bool cold = a.cold_flag != nullptr && *a.cold_flag != 0;
+
+  // u faces i in [x0, x0+TW], j in [y0, y0+TH): the face i = x0+TW is the east
+  // face of the tile, computed here for the divergence and owned by the next tile.
+  for (int k = tid; k < TH * (TW + 1); k += 256) {
+    const int c = k % (TW + 1), r = k / (TW + 1);
+    const int i = x0 + c, j = y0 + r;
+    double us = 0.0;
+    if (i <= g.nx && j < g.ny) {
+      const bool w = g.fluid(i - 1, j), e = g.fluid(i, j);
+      const double uo = SU(i, j);
+      const bool owned = (c < TW) || (i == g.nx);
+      if (w && e) {
+        const TT uc = (TT)uo, uE = (TT)SU(i + 1, j), uW = (TT)SU(i - 1, j);
+        const TT uN = g.u_solid(i, j + 1) ? -uc : (TT)SU(i, j + 1);
+        const TT uS = g.u_solid(i, j - 1) ? -uc : (TT)SU(i, j - 1);
+        const TT vSW = (TT)SV(i - 1, j), vSE = (TT)SV(i, j), vNW = (TT)SV(i - 1, j + 1), vNE = (TT)SV(i, j + 1);
+        const TT adv = ((uc + uE) * (uc + uE) - (uW + uc) * (uW + uc)) * inv4h +
+                       ((uc + uN) * (vNW + vNE) - (uS + uc) * (vSW + vSE)) * inv4h;
+        const TT T = -adv + nu * (uE + uW + uN + uS - (TT)4 * uc) * inv_h2;
+        const long at = g.at(i, j);
+        const TT Tp = cold ? T : tup[at];
+        double F = 0.0;
+        if (f) {
+          const int cw = a.cmap[g.at(i - 1, j)], ce = a.cmap[g.at(i, j)];
+          F = 0.5 * ((cw >= 0 ? f[cw] : 0.0) + (ce >= 0 ? f[ce] : 0.0));
+        }
+        us = uo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + F);
+        if (owned) {
+          a.us[off + at] = us;
+          a.tu[off + at] = T;
+        }
+      } else if (w && i == g.nx) {
+        us = uo - dt * U_CONVECTIVE * (uo - SU(i - 1, j)) / g.h;
+        if (owned) a.us[off + g.at(i, j)] = us;
+      } else {
+        us = uo;  // wall (0) or inflow profile
+      }
+    }
+    sus[r * (TW + 1) + c] = us;
+  }
+  // v faces i in [x0, x0+TW), j in [y0, y0+TH]
+  for (int k = tid; k < (TH + 1) * TW; k += 256) {
+    const int c = k % TW, r = k / TW;
+    const int i = x0 + c, j = y0 + r;
+    double vs = 0.0;
+    if (i < g.nx && j <= g.ny) {
+      const bool s = g.fluid(i, j - 1), nn = g.fluid(i, j);
+      const double vo = SV(i, j);
+      const bool owned = (r < TH) || (j == g.ny);
+      if (s && nn) {
+        const TT vc = (TT)vo, vN = (TT)SV(i, j + 1), vS = (TT)SV(i, j - 1);
+        const TT vW = (i == 0 || g.v_solid(i - 1, j)) ? -vc : (TT)SV(i - 1, j);
+        const TT vE = (i == g.nx - 1) ? vc : (g.v_solid(i + 1, j) ? -vc : (TT)SV(i + 1, j));
+        const TT uSW = (TT)SU(i, j - 1), uSE = (TT)SU(i + 1, j - 1), uNW = (TT)SU(i, j), uNE = (TT)SU(i + 1, j);
+        const TT adv = ((uNE + uSE) * (vc + vE) - (uNW + uSW) * (vW + vc)) * inv4h +
+                       ((vc + vN) * (vc + vN) - (vS + vc) * (vS + vc)) * inv4h;
+        const TT T = -adv + nu * (vE + vW + vN + vS - (TT)4 * vc) * inv_h2;
+        const long at = g.at(i, j);
+        const TT Tp = cold ? T : tvp[at];
+        double F = 0.0;
+        if (f) {
+          const int cs = a.cmap[g.at(i, j - 1)], cn = a.cmap[g.at(i, j)];
+          F = 0.5 * ((cs >= 0 ? f[a.nctrl + cs] : 0.0) + (cn >= 0 ? f[a.nctrl + cn] : 0.0));
+        }
+        vs = vo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + F);
+        if (owned) {
+          a.vs[off + at] = vs;
+          a.tv[off + at] = T;
+        }
+      } else {
+        vs = vo;  // wall
+      }
+    }
+    svs[r * TW + c] = vs;
+  }
+  (void)h;
+  __syncthreads();
+  // Poisson right-hand side on the tile cells
+  const double inv_hdt = 1.0 / (g.h * dt);
+  for (int k = tid; k < TH * TW; k += 256) {
+    const int c = k % TW, r = k / TW;
+    const int i = x0 + c, j = y0 + r;
+    if (i < g.nx && j < g.ny) {
+      double bb = 0.0;
+      if (g.fluid(i, j))
+        bb = ((sus[r * (TW + 1) + c + 1] - sus[r * (TW + 1) + c]) + (svs[(r + 1) * TW + c] - svs[r * TW + c])) *
+             inv_hdt;
+      a.b[off + g.at(i, j)] = bb;
+    }
+  }
+#undef SU
+#undef SV
+}
+
+// ---------------------------------------------------------------------------- projection + cost
+__global__ __launch_bounds__(256) void k_project_cost(ProjArgs a) {
+  constexpr int TW = TILE_W, TH = STEP_TH;
+  __shared__ double red_s[4];
+  __shared__ double red_m[4];
+  const Geo& g = a.g;
+  const int total = a.ntiles * a.nmem;
+  const int item = xcd_remap(blockIdx.x, total);
+  const int mem = item / a.ntiles;
+  const int tile = item % a.ntiles;
+  int x0, y0;
+  a.tiling.origin(tile, x0, y0);
+  const long off = (long)mem * a.plane;
+  double* __restrict__ u = a.u + off;
+  double* __restrict__ v = a.v + off;
+  const double* __restrict__ us = a.us + off;
+  const double* __restrict__ vs = a.vs + off;
+  const double* __restrict__ phi = a.phi + off;
+  const long coff = (long)mem * a.cplane;
+  const double dt = a.dt, inv_h = 1.0 / g.h;
+  const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
+  double acc = 0.0, dmax = 0.0;
+  for (int r = ty; r < TH; r += 4) {
+    const int i = x0 + tx, j = y0 + r;
+    if (!g.fluid(i, j)) continue;
+    const long at = g.at(i, j);
+    const double pc = phi[at];
+    double uw, ue, vsv, vn;
+    if (g.fluid(i - 1, j)) {
+      uw = us[at] - dt * (pc - phi[g.at(i - 1, j)]) * inv_h;
+      u[at] = uw;
+    } else {
+      uw = u[at];
+    }
+    if (g.fluid(i + 1, j)) {
+      ue = us[g.at(i + 1, j)] - dt * (phi[g.at(i + 1, j)] - pc) * inv_h;
+    } else if (i + 1 == g.nx) {
+      ue = us[g.at(i + 1, j)] + 2.0 * dt * pc * inv_h;
+      u[g.at(i + 1, j)] = ue;
+    } else {
+      ue = u[g.at(i + 1, j)];
+    }
+    if (g.fluid(i, j - 1)) {
+      vsv = vs[at] - dt * (pc - phi[g.at(i, j - 1)]) * inv_h;
+      v[at] = vsv;
+    } else {
+      vsv = v[at];
+    }
+    if (g.fluid(i, j + 1)) {
+      vn = vs[g.at(i, j + 1)] - dt * (phi[g.at(i, j + 1)] - pc) * inv_h;
+    } else {
+      vn = v[g.at(i, j + 1)];
+    }
+    const double div = fabs((ue - uw + vn - vsv) * inv_h);
+    dmax = (div > dmax || div != div) ? div : dmax;
+    if (a.s1u) {
+      const long ac = (long)j * g.nx + i;  // dense cell index
+      const double du = 0.5 * (uw + ue) - a.shu[ac];
+      const double dv = 0.5 * (vsv + vn) - a.shv[ac];
+      a.s1u[coff + ac] += du;
+      a.s1v[coff + ac] += dv;
+      acc += du * du + dv * dv;
+    }
+  }
+  acc = wave_sum(acc);
+  dmax = wave_max(dmax);
+  if (tx == 0) {
+    red_s[ty] = acc;
+    red_m[ty] = dmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double s = ((red_s[0] + red_s[1]) + red_s[2]) + red_s[3];
+    double m = red_m[0];
+    for (int k = 1; k < 4; ++k) m = (red_m[k] > m || red_m[k] != red_m[k]) ? red_m[k] : m;
+    if (a.s2part) a.s2part[(long)mem * a.ntiles + tile] += s;
+    atomicMax((unsigned long long*)&a.divmax[mem], dbits(m));
+  }
+}
+
+// ---------------------------------------------------------------------------- per-step bookkeeping
+// norms[mem][k] holds dt*max|r| after cycle k; a skipped cycle carries the
+// previous value, so the first slot at or below tol ends the solve. Records
+// the cycles run, the final residual and whether the tolerance was met.
+__global__ void k_step_book(BookArgs a) {
+  const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mem >= a.nmem) return;
+  const double* nr = a.norms + (long)mem * a.norm_slots;
+  const int filled = a.cap + a.slot_base;
+  int used = filled;
+  for (int k = 0; k < filled; ++k)
+    if (nr[k] <= a.tol) {
+      used = k + 1;
+      break;
+    }
+  const double last = nr[used - 1];
+  const int cycles = used - a.slot_base;
+  double* st = a.stats + (long)mem * STATS_STRIDE;
+  st[ST_CYCLES] += (double)cycles;
+  st[ST_MAXCYC] = fmax(st[ST_MAXCYC], (double)cycles);
+  if (!(last <= a.tol)) st[ST_UNCONV] += 1.0;
+  st[ST_MAXRES] = (last > st[ST_MAXRES] || last != last) ? last : st[ST_MAXRES];
+  st[ST_STEPS] += 1.0;
+}
+
+// ---------------------------------------------------------------------------- J finalisation
+// J = dt h^2 (S2 - sum_c |S1_c|^2 / K) + lambda h^2 |f|^2, fixed-order reductions.
+__global__ __launch_bounds__(256) void k_finalize_J(FinalArgs a) {
+  __shared__ double red[3][4];
+  const int mem = blockIdx.x;
+  const Geo& g = a.g;
+  const long coff = (long)mem * a.cplane;
+  double q = 0.0, s2 = 0.0, ff = 0.0;
+  const long ncell = (long)g.nx * g.ny;
+  for (long c = threadIdx.x; c < ncell; c += 256) {
+    const double x = a.s1u[coff + c], y = a.s1v[coff + c];
+    q += x * x + y * y;
+  }
+  for (int t = threadIdx.x; t < a.ntiles; t += 256) s2 += a.s2part[(long)mem * a.ntiles + t];
+  if (a.ctrl)
+    for (long k = threadIdx.x; k < a.m; k += 256) {
+      const double x = a.ctrl[(long)mem * a.m + k];
+      ff += x * x;
+    }
+  q = wave_sum(q);
+  s2 = wave_sum(s2);
+  ff = wave_sum(ff);
+  const int w = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) {
+    red[0][w] = q;
+    red[1][w] = s2;
+    red[2][w] = ff;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double Q = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    const double S2 = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    const double FF = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
+    const double h2 = g.h * g.h;
+    const double J = a.dt * h2 * (S2 - Q / (double)a.K) + a.penalty * h2 * FF;
+    a.J[mem] = J;
+    if (a.stats) a.stats[(long)mem * STATS_STRIDE + ST_J] = J;
+  }
+}
+
+// ---------------------------------------------------------------------------- member initialisation
+// Copies the base state into every member, zeroes the cost accumulators.
+template <typename TT>
+__global__ __launch_bounds__(256) void k_init_members(InitArgs<TT> a) {
+  const int mem = blockIdx.y;
+  const long off = (long)mem * a.plane;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < a.plane; k += (long)gridDim.x * 256L) {
+    a.u[off + k] = a.bu[k];
+    a.v[off + k] = a.bv[k];
+    a.us[off + k] = a.bu[k];
+    a.vs[off + k] = a.bv[k];
+    a.tu[off + k] = (TT)a.btu[k];
+    a.tv[off + k] = (TT)a.btv[k];
+    a.phi[off + k] = a.bphi[k];
+  }
+  const long coff = (long)mem * a.cplane;
+  if (a.s1u)
+    for (long k = blockIdx.x * 256L + threadIdx.x; k < a.cplane; k += (long)gridDim.x * 256L) {
+      a.s1u[coff + k] = 0.0;
+      a.s1v[coff + k] = 0.0;
+    }
+  if (blockIdx.x == 0) {
+    for (int t = threadIdx.x; t < a.ntiles; t += 256)
+      if (a.s2part) a.s2part[(long)mem * a.ntiles + t] = 0.0;
+    for (int t = threadIdx.x; t < STATS_STRIDE; t += 256) a.stats[(long)mem * STATS_STRIDE + t] = 0.0;
+    if (threadIdx.x == 0) a.divmax[mem] = 0.0;
+  }
+}
+
+// Cell-centred base velocity (the cost shift s_c), dense (ny, nx).
+__global__ void k_shift(Geo g, const double* u, const double* v, double* shu, double* shv) {
+  const long c = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (c >= (long)g.nx * g.ny) return;
+  const int i = (int)(c % g.nx), j = (int)(c / g.nx);
+  if (g.fluid(i, j)) {
+    shu[c] = 0.5 * (u[g.at(i, j)] + u[g.at(i + 1, j)]);
+    shv[c] = 0.5 * (v[g.at(i, j)] + v[g.at(i, j + 1)]);
+  } else {
+    shu[c] = 0.0;
+    shv[c] = 0.0;
+  }
+}
+
+// Copy member 0's evolved fields back into a base state (spin-up).
+template <typename TT>
+__global__ void k_store_base(long plane, const double* u, const double* v, const TT* tu, const TT* tv,
+                             const double* phi, double* bu, double* bv, double* btu, double* btv, double* bphi) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < plane; k += (long)gridDim.x * blockDim.x) {
+    bu[k] = u[k];
+    bv[k] = v[k];
+    btu[k] = (double)tu[k];
+    btv[k] = (double)tv[k];
+    bphi[k] = phi[k];
+  }
+}
+
+// Member fields to the dense oracle layout [mem][u (ny, nx+1) | v (ny+1, nx)].
+__global__ void k_fields_out(Geo g, long plane, const double* u, const double* v, double* out) {
+  const int mem = blockIdx.y;
+  const long nu_ = (long)g.ny * (g.nx + 1), nv_ = (long)(g.ny + 1) * g.nx;
+  double* o = out + (long)mem * (nu_ + nv_);
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < nu_ + nv_; k += (long)gridDim.x * blockDim.x) {
+    if (k < nu_) {
+      const int i = (int)(k % (g.nx + 1)), j = (int)(k / (g.nx + 1));
+      o[k] = u[(long)mem * plane + g.at(i, j)];
+    } else {
+      const long q = k - nu_;
+      const int i = (int)(q % g.nx), j = (int)(q / g.nx);
+      o[k] = v[(long)mem * plane + g.at(i, j)];
+    }
+  }
+}
+
+__global__ void k_clear_flag(int* flag) { *flag = 0; }
+
+// ---------------------------------------------------------------------------- launchers
+template <typename TT>
+void launch_predictor(const PredArgs<TT>& a, hipStream_t s) {
+  const int total = a.ntiles * a.nmem;
+  hipLaunchKernelGGL(k_predictor<TT>, dim3(total), dim3(256), 0, s, a);
+}
+template void launch_predictor<double>(const PredArgs<double>&, hipStream_t);
+template void launch_predictor<float>(const PredArgs<float>&, hipStream_t);
+
+void launch_project_cost(const ProjArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_project_cost, dim3(a.ntiles * a.nmem), dim3(256), 0, s, a);
+}
+void launch_step_book(const BookArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_book, dim3((a.nmem + 63) / 64), dim3(64), 0, s, a);
+}
+void launch_finalize_J(const FinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_J, dim3(a.nmem), dim3(256), 0, s, a);
+}
+template <typename TT>
+void launch_init_members(const InitArgs<TT>& a, hipStream_t s) {
+  int bx = (int)((a.plane + 255) / 256);
+  if (bx > 128) bx = 128;
+  hipLaunchKernelGGL(k_init_members<TT>, dim3(bx, a.nmem), dim3(256), 0, s, a);
+}
+template void launch_init_members<double>(const InitArgs<double>&, hipStream_t);
+template void launch_init_members<float>(const InitArgs<float>&, hipStream_t);
+
+void launch_shift(const Geo& g, const double* u, const double* v, double* shu, double* shv, hipStream_t s) {
+  const long n = (long)g.nx * g.ny;
+  hipLaunchKernelGGL(k_shift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, u, v, shu, shv);
+}
+template <typename TT>
+void launch_store_base(long plane, const double* u, const double* v, const TT* tu, const TT* tv, const double* phi,
+                       double* bu, double* bv, double* btu, double* btv, double* bphi, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_base<TT>, dim3(256), dim3(256), 0, s, plane, u, v, tu, tv, phi, bu, bv, btu, btv, bphi);
+}
+template void launch_store_base<double>(long, const double*, const double*, const double*, const double*,
+                                        const double*, double*, double*, double*, double*, double*, hipStream_t);
+template void launch_store_base<float>(long, const double*, const double*, const float*, const float*,
+                                       const double*, double*, double*, double*, double*, double*, hipStream_t);
+void launch_fields_out(const Geo& g, long plane, int nmem, const double* u, const double* v, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_fields_out, dim3(64, nmem), dim3(256), 0, s, g, plane, u, v, out);
+}
+void launch_clear_flag(int* flag, hipStream_t s) { hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag); }
+
+}  // namespace envar

@@ -1,0 +1,299 @@
+"""Thin ctypes binding of libenvar.so (the C ABI declared in include/envar.h).
+
+Argument marshalling only: every computation runs in the HIP library. Device
+memory and streams come from PyTorch (tensors are passed by data pointer, the
+stream as torch's current HIP stream). Loading fails loudly when the library
+is missing; there is no fallback path.
+"""
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libenvar.so")
+
+OK, EINVAL, ENOMEM, EDIVERGED, EDEVICE, EBUSY, ECANCELLED, ETIMEOUT = range(8)
+CAVITY, CHANNEL = 0, 1
+REGION_COLUMN, REGION_CAVITY, REGION_BOX = 0, 1, 2
+FP64, MIXED = 0, 1
+FLAG_TIME_KERNELS = 1
+
+EXPORTS = (
+    "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",
+    "envar_state_init", "envar_state_read", "envar_spinup", "envar_forward",
+    "envar_gradient_bytes", "envar_gradient", "envar_iterate_bytes", "envar_iterate",
+    "envar_last_error", "envar_version",
+)
+
+
+class EnvarError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"envar error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("inv_h", ctypes.c_int32), ("geometry", ctypes.c_int32), ("region", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("Re", ctypes.c_double), ("dt", ctypes.c_double),
+        ("x_cav", ctypes.c_double), ("box", ctypes.c_double * 4), ("penalty", ctypes.c_double),
+        ("div_tol", ctypes.c_double), ("max_cycles", ctypes.c_int32), ("flags", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("max_resid", ctypes.c_double), ("max_div", ctypes.c_double), ("mean_cycles", ctypes.c_double),
+        ("max_cycles_used", ctypes.c_int32), ("unconverged", ctypes.c_int32), ("diverged", ctypes.c_int32),
+        ("steps", ctypes.c_int32), ("cell_steps", ctypes.c_double),
+        ("predictor_us", ctypes.c_double), ("pre_us", ctypes.c_double), ("post_us", ctypes.c_double),
+        ("resid_us", ctypes.c_double), ("project_us", ctypes.c_double), ("vcycle_us", ctypes.c_double),
+        ("timed_steps", ctypes.c_int32), ("timed_members", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LSParams(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("max_trials", ctypes.c_int32), ("c1", ctypes.c_double),
+        ("shrink", ctypes.c_double), ("alpha0", ctypes.c_double), ("search_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class IterRecord(ctypes.Structure):
+    _fields_ = [("J0", ctypes.c_double), ("gnorm", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("J_trial", ctypes.c_double)]
+
+
+@dataclass
+class Problem:
+    """Python mirror of envar_problem (fields <= 0 take the library defaults)."""
+    inv_h: int = 32
+    Re: float = 4000.0
+    dt: float = 0.0
+    x_cav: float = 1.25
+    geometry: int = CAVITY
+    region: int = REGION_COLUMN
+    box: tuple = (0.0, 0.0, 0.0, 0.0)
+    precision: int = FP64
+    penalty: float = 1e-3
+    div_tol: float = 0.0
+    max_cycles: int = 0
+    flags: int = 0
+
+    def c(self):
+        p = _Problem()
+        p.inv_h, p.geometry, p.region, p.precision = self.inv_h, self.geometry, self.region, self.precision
+        p.Re, p.dt, p.x_cav, p.penalty, p.div_tol = self.Re, self.dt, self.x_cav, self.penalty, self.div_tol
+        p.box = (ctypes.c_double * 4)(*self.box)
+        p.max_cycles, p.flags = self.max_cycles, self.flags
+        return p
+
+    @property
+    def step_dt(self):
+        return self.dt if self.dt > 0 else 0.064 / self.inv_h
+
+    def box_dims(self):
+        n = self.inv_h
+        return (4 * n, 2 * n) if self.geometry == CAVITY else (4 * n, n)
+
+
+_lib = None
+
+
+def lib():
+    """Load libenvar.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2605_23812_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(_Problem)
+    vp, dp, i32, i64, sz = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.envar_control_dim.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    L.envar_cell_count.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    L.envar_state_bytes.argtypes = [P]
+    L.envar_state_bytes.restype = sz
+    L.envar_workspace_bytes.argtypes = [P, i32]
+    L.envar_workspace_bytes.restype = sz
+    L.envar_state_init.argtypes = [P, dp, dp, dp, dp, dp, vp, vp]
+    L.envar_state_read.argtypes = [P, vp, dp, dp, dp, dp, dp]
+    L.envar_spinup.argtypes = [P, vp, i32, vp, sz, ctypes.POINTER(Stats), vp]
+    L.envar_forward.argtypes = [P, vp, dp, i32, i64, i32, vp, sz, dp, dp, ctypes.POINTER(Stats), vp]
+    L.envar_gradient_bytes.argtypes = [i32, i64, i32]
+    L.envar_gradient_bytes.restype = sz
+    L.envar_gradient.argtypes = [dp, dp, i32, i64, i32, vp, sz, dp, vp]
+    L.envar_iterate_bytes.argtypes = [P, i32, i64]
+    L.envar_iterate_bytes.restype = sz
+    L.envar_iterate.argtypes = [P, vp, dp, dp, i32, i64, i32, ctypes.POINTER(LSParams), vp, sz,
+                                ctypes.POINTER(IterRecord), vp]
+    L.envar_last_error.restype = ctypes.c_char_p
+    L.envar_version.restype = ctypes.c_char_p
+    for name in ("envar_control_dim", "envar_cell_count", "envar_state_init", "envar_state_read",
+                 "envar_spinup", "envar_forward", "envar_gradient", "envar_iterate"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        raise EnvarError(rc, lib().envar_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host(a):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _hptr(a):
+    return ctypes.c_void_p(0) if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------- sizes
+def control_dim(p):
+    m = ctypes.c_int64()
+    _check(lib().envar_control_dim(ctypes.byref(p.c()), ctypes.byref(m)))
+    return m.value
+
+
+def cell_count(p):
+    n = ctypes.c_int64()
+    _check(lib().envar_cell_count(ctypes.byref(p.c()), ctypes.byref(n)))
+    return n.value
+
+
+def state_bytes(p):
+    return lib().envar_state_bytes(ctypes.byref(p.c()))
+
+
+def workspace_bytes(p, n_rows):
+    return lib().envar_workspace_bytes(ctypes.byref(p.c()), n_rows)
+
+
+def gradient_bytes(n, m, precision=FP64):
+    return lib().envar_gradient_bytes(n, m, precision)
+
+
+def iterate_bytes(p, n, m):
+    return lib().envar_iterate_bytes(ctypes.byref(p.c()), n, m)
+
+
+# ---------------------------------------------------------------------------- calls
+def _bytes_tensor(nbytes, device="cuda"):
+    import torch
+
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def state_init(p, u, v, tu_prev=None, tv_prev=None, phi=None, state=None):
+    """Upload a base state (host arrays in oracle layout) into a (new) device buffer."""
+    if state is None:
+        state = _bytes_tensor(state_bytes(p))
+    arrs = [_host(a) for a in (u, v, tu_prev, tv_prev, phi)]
+    _check(lib().envar_state_init(ctypes.byref(p.c()), *[_hptr(a) for a in arrs], _ptr(state), _stream()))
+    return state
+
+
+def state_read(p, state):
+    NX, NY = p.box_dims()
+    u = np.empty((NY, NX + 1))
+    v = np.empty((NY + 1, NX))
+    tu = np.empty_like(u)
+    tv = np.empty_like(v)
+    phi = np.empty((NY, NX))
+    import torch
+
+    torch.cuda.current_stream().synchronize()
+    _check(lib().envar_state_read(ctypes.byref(p.c()), _ptr(state), *[_hptr(a) for a in (u, v, tu, tv, phi)]))
+    return u, v, tu, tv, phi
+
+
+def spinup(p, state, steps, ws=None):
+    if ws is None:
+        ws = _bytes_tensor(workspace_bytes(p, 1))
+    st = Stats()
+    _check(lib().envar_spinup(ctypes.byref(p.c()), _ptr(state), steps, _ptr(ws), ws.numel(), ctypes.byref(st),
+                              _stream()))
+    return st.as_dict()
+
+
+def forward(p, state, controls, horizon, ws=None, J=None, fields=False, stats=True):
+    """J [n_rows] (torch FP64 on the device) for control rows `controls` [n_rows, m] (torch FP64 device)."""
+    import torch
+
+    n_rows, m = controls.shape
+    assert controls.dtype == torch.float64 and controls.is_cuda and controls.is_contiguous()
+    if ws is None:
+        ws = _bytes_tensor(workspace_bytes(p, n_rows))
+    if J is None:
+        J = torch.empty(n_rows, dtype=torch.float64, device=controls.device)
+    F = None
+    if fields:
+        NX, NY = p.box_dims()
+        F = torch.empty((n_rows, NY * (NX + 1) + (NY + 1) * NX), dtype=torch.float64, device=controls.device)
+    st = Stats() if stats else None
+    rc = lib().envar_forward(ctypes.byref(p.c()), _ptr(state), _ptr(controls), n_rows, m, horizon, _ptr(ws),
+                             ws.numel(), _ptr(J), _ptr(F), ctypes.byref(st) if st is not None else None, _stream())
+    if rc == EDIVERGED:
+        return J, F, st.as_dict()
+    _check(rc)
+    return J, F, (st.as_dict() if st is not None else None)
+
+
+def split_fields(p, F):
+    """[n_rows, ...] flat fields -> (u [n, NY, NX+1], v [n, NY+1, NX]) numpy."""
+    NX, NY = p.box_dims()
+    F = F.cpu().numpy()
+    nu = NY * (NX + 1)
+    return F[:, :nu].reshape(-1, NY, NX + 1), F[:, nu:].reshape(-1, NY + 1, NX)
+
+
+def gradient(controls, J, precision=FP64, ws=None, g=None):
+    """g [m] = X^+ dJ for rows 1..n of controls [n+1, m] against row 0."""
+    import torch
+
+    n = controls.shape[0] - 1
+    m = controls.shape[1]
+    if ws is None:
+        ws = _bytes_tensor(gradient_bytes(n, m, precision))
+    if g is None:
+        g = torch.empty(m, dtype=torch.float64, device=controls.device)
+    _check(lib().envar_gradient(_ptr(controls), _ptr(J), n, m, precision, _ptr(ws), ws.numel(), _ptr(g), _stream()))
+    return g
+
+
+def iterate(p, state, f, perturb, horizon, iters=1, max_trials=8, c1=1e-4, shrink=0.5, alpha0=0.0,
+            search_every=0, ws=None):
+    """Fixed-ensemble descent; f (device FP64 [m]) is updated in place. Returns per-iteration records."""
+    n, m = perturb.shape
+    if ws is None:
+        ws = _bytes_tensor(iterate_bytes(p, n, m))
+    ls = LSParams(iters, max_trials, c1, shrink, alpha0, search_every, 0)
+    recs = (IterRecord * iters)()
+    _check(lib().envar_iterate(ctypes.byref(p.c()), _ptr(state), _ptr(f), _ptr(perturb), n, m, horizon,
+                               ctypes.byref(ls), _ptr(ws), ws.numel(), recs, _stream()))
+    return [dict(J0=r.J0, gnorm=r.gnorm, alpha=r.alpha, J_trial=r.J_trial) for r in recs]
+
+
+def version():
+    return lib().envar_version().decode()

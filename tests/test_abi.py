@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports what include/envar.h declares (CPU only, no compute calls)."""
+import os
+import re
+
+import pytest
+
+from paper_2605_23812_amd import envar as E
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "envar.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|size_t|const char\*)\s+(envar_[a-z_]+)\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = E.lib()
+    names = _declared()
+    assert "envar_forward" in names and "envar_gradient" in names and "envar_iterate" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(E.EXPORTS) == set(names)
+
+
+def test_sizes_and_control_dims():
+    p = E.Problem(inv_h=32)
+    assert E.control_dim(p) == 4096          # 2048 per component at h = 1/32
+    assert E.cell_count(p) == 5120           # 128 x 32 + 32 x 32
+    p2 = E.Problem(inv_h=128, Re=7500.0)
+    assert E.control_dim(p2) == 65536        # 32768 per component at h = 1/128
+    assert E.cell_count(p2) == 81920
+    assert E.control_dim(E.Problem(inv_h=32, region=E.REGION_CAVITY)) == 2048
+    assert E.control_dim(E.Problem(inv_h=16, region=E.REGION_BOX, box=(1.5, 1.6, -0.1, 0.0))) == 8
+    # workspace grows linearly with members
+    w1, w2 = E.workspace_bytes(p, 1), E.workspace_bytes(p, 2)
+    w9 = E.workspace_bytes(p, 9)
+    assert w1 > 0 and abs((w9 - w1) - 8 * (w2 - w1)) < 8 * 4096
+    assert E.workspace_bytes(E.Problem(inv_h=32, precision=E.MIXED), 9) < w9
+    assert E.gradient_bytes(8, 4096) > 8 * 4096 * 8
+    assert E.state_bytes(p) > 5 * 129 * 65 * 8
+
+
+@pytest.mark.parametrize("bad", [dict(inv_h=24), dict(inv_h=8), dict(Re=-1.0), dict(x_cav=1.1),
+                                 dict(geometry=7), dict(region=9), dict(precision=3)])
+def test_invalid_problems_are_rejected(bad):
+    with pytest.raises(E.EnvarError) as ei:
+        E.control_dim(E.Problem(**bad))
+    assert ei.value.code == E.EINVAL
+    assert E.workspace_bytes(E.Problem(**bad), 4) == 0
+
+
+def test_oracle_and_library_agree_on_the_control_region():
+    from oracle.envar import Problem as OP
+
+    for n, reg, oreg, box in [(32, E.REGION_COLUMN, "column", None), (32, E.REGION_CAVITY, "cavity", None),
+                              (16, E.REGION_BOX, "box", (1.2, 1.9, -0.5, 0.3))]:
+        kw = dict(box=box) if box else {}
+        assert E.control_dim(E.Problem(inv_h=n, region=reg, **kw)) == OP(inv_h=n, region=oreg, **kw).m

@@ -1,0 +1,162 @@
+"""GPU forward ensemble vs the FP64 oracle (needs an MI355X; calls the C ABI through the binding).
+
+Parity bar: FP64 path within 1e-10 relative of the oracle on J and on the
+velocity fields over short horizons; mixed precision within 1e-4 on J.
+Inputs are seeded: the parabolic channel flow plus N(0, 1e-6) noise, spun up
+by the oracle, and GRF control perturbations (squared-exponential covariance).
+"""
+import numpy as np
+import pytest
+
+from oracle import envar as OE
+from paper_2605_23812_amd import envar as E
+from paper_2605_23812_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _op(p):
+    geo = {E.CAVITY: "cavity", E.CHANNEL: "channel"}[p.geometry]
+    reg = {E.REGION_COLUMN: "column", E.REGION_CAVITY: "cavity", E.REGION_BOX: "box"}[p.region]
+    return OE.Problem(inv_h=p.inv_h, Re=p.Re, dt=p.dt, x_cav=p.x_cav, geometry=geo, region=reg,
+                      box=tuple(p.box), penalty=p.penalty)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+_BASES = {}
+
+
+def _base(n, Re, spin, seed=inputs.DEFAULT_SEED):
+    key = (n, Re, spin, seed)
+    if key not in _BASES:
+        p = E.Problem(inv_h=n, Re=Re)
+        op = _op(p)
+        u0, v0 = inputs.initial_field(n, amp=1e-3, seed=seed)
+        st = OE.spinup(op, OE.initial_state(op, u0, v0), spin)
+        _BASES[key] = (op, st)
+    return _BASES[key]
+
+
+def _rows(p, N, ell, sigma, seed=7):
+    m = E.control_dim(p)
+    pert = inputs.grf_perturbations(N, p.inv_h, ell, sigma, seed=seed)
+    assert pert.shape[1] == m
+    return np.vstack([np.zeros(m), pert])
+
+
+def _gpu_forward(p, st, rows, horizon, fields=True):
+    state = E.state_init(p, st.u, st.v, st.Tu_prev, st.Tv_prev)
+    ctrl = torch.tensor(rows, dtype=torch.float64, device="cuda")
+    J, F, stats = E.forward(p, state, ctrl, horizon, fields=fields)
+    torch.cuda.synchronize()
+    return J.cpu().numpy(), (E.split_fields(p, F) if fields else None), stats
+
+
+def test_spinup_from_cold_start_matches_oracle():
+    n, steps = 32, 30
+    p = E.Problem(inv_h=n, Re=4000.0)
+    op = _op(p)
+    u0, v0 = inputs.initial_field(n, amp=1e-3)
+    _say("spinup parity: h=1/32 cold start", steps, "steps")
+    ref = OE.spinup(op, OE.initial_state(op, u0, v0), steps)
+    state = E.state_init(p, u0, v0)
+    stats = E.spinup(p, state, steps)
+    u, v, tu, tv, phi = E.state_read(p, state)
+    _say("stats", stats)
+    scale = np.abs(ref.u).max()
+    assert np.abs(u - ref.u).max() < 1e-10 * scale
+    assert np.abs(v - ref.v).max() < 1e-10 * scale
+    assert np.abs(tu - ref.Tu_prev).max() < 1e-9 * np.abs(ref.Tu_prev).max()
+    assert stats["unconverged"] == 0 and stats["max_resid"] <= 1e-12
+
+
+@pytest.mark.parametrize("horizon", [1, 40])
+def test_forward_fp64_matches_oracle(horizon):
+    n, N = 32, 4
+    p = E.Problem(inv_h=n, Re=4000.0)
+    op, st = _base(n, 4000.0, 60)
+    rows = _rows(p, N, 0.1, 1e-2)
+    _say("forward parity: h=1/32 N+1 =", N + 1, "horizon", horizon)
+    J, (u, v), stats = _gpu_forward(p, st, rows, horizon)
+    _say("gpu J", J, "stats", stats)
+    for i in range(N + 1):
+        Jr, sr = OE.forward_member(op, st, rows[i], horizon, return_state=True)
+        _say(" member", i, "J", J[i], "oracle", Jr, "rel", abs(J[i] - Jr) / abs(Jr))
+        assert abs(J[i] - Jr) <= 1e-10 * abs(Jr)
+        scale = np.abs(sr.u).max()
+        assert np.abs(u[i] - sr.u).max() <= 1e-10 * scale
+        assert np.abs(v[i] - sr.v).max() <= 1e-10 * scale
+    assert stats["max_div"] <= 1e-9 and stats["unconverged"] == 0
+
+
+def test_batch_invariance_member_alone_equals_in_batch():
+    n = 32
+    p = E.Problem(inv_h=n, Re=4000.0)
+    op, st = _base(n, 4000.0, 60)
+    rows = _rows(p, 5, 0.1, 1e-2, seed=11)
+    Jb, (ub, vb), _ = _gpu_forward(p, st, rows, 12)
+    perm = [3, 0, 5, 1, 4, 2]
+    Jp, (up, vp), _ = _gpu_forward(p, st, rows[perm], 12)
+    J1, (u1, v1), _ = _gpu_forward(p, st, rows[2:3], 12)
+    _say("batch invariance", Jb[2], J1[0])
+    assert Jb[2] == J1[0] and np.array_equal(ub[2], u1[0]) and np.array_equal(vb[2], v1[0])
+    assert np.array_equal(Jp, Jb[perm])
+
+
+def test_forward_is_deterministic():
+    p = E.Problem(inv_h=32, Re=4000.0)
+    op, st = _base(32, 4000.0, 60)
+    rows = _rows(p, 3, 0.1, 1e-2)
+    a = _gpu_forward(p, st, rows, 10)[0]
+    b = _gpu_forward(p, st, rows, 10)[0]
+    assert np.array_equal(a, b)
+
+
+def test_mixed_precision_cost_within_1e_4():
+    n, N, horizon = 32, 4, 40
+    p = E.Problem(inv_h=n, Re=4000.0, precision=E.MIXED)
+    op, st = _base(n, 4000.0, 60)
+    rows = _rows(p, N, 0.1, 1e-2)
+    J, _, stats = _gpu_forward(p, st, rows, horizon, fields=False)
+    _say("mixed J", J, "stats", stats)
+    Jr = OE.forward(op, st, rows, horizon)
+    rel = np.abs(J - Jr) / np.abs(Jr)
+    _say("mixed rel err", rel)
+    assert rel.max() <= 1e-4
+    assert stats["max_div"] <= 1e-8 and stats["unconverged"] == 0
+
+
+def test_nan_member_is_isolated():
+    p = E.Problem(inv_h=32, Re=4000.0)
+    op, st = _base(32, 4000.0, 60)
+    rows = _rows(p, 3, 0.1, 1e-2)
+    bad = rows.copy()
+    bad[2, 100] = np.nan
+    J0, (u0, _), _ = _gpu_forward(p, st, rows, 5)
+    J1, (u1, _), stats = _gpu_forward(p, st, bad, 5)
+    _say("nan isolation", J1, stats)
+    assert np.isnan(J1[2]) and stats["diverged"] == 1
+    keep = [0, 1, 3]
+    assert np.array_equal(J0[keep], J1[keep]) and np.array_equal(u0[keep], u1[keep])
+
+
+def test_channel_geometry_keeps_discrete_poiseuille():
+    """A steady discrete Poiseuille profile a (y(1-y) + h^2/4) stays put on the GPU too."""
+    n = 16
+    p = E.Problem(inv_h=n, Re=10.0, geometry=E.CHANNEL, region=E.REGION_BOX, box=(1.0, 1.2, 0.2, 0.4))
+    op = _op(p)
+    st = OE.spinup(op, OE.initial_state(op, np.zeros((n, 4 * n + 1)), np.zeros((n + 1, 4 * n))), int(30 / op.step_dt))
+    state = E.state_init(p, st.u, st.v, st.Tu_prev, st.Tv_prev)
+    stats = E.spinup(p, state, 50)
+    u, v, *_ = E.state_read(p, state)
+    h = 1.0 / n
+    y = (np.arange(n) + 0.5) * h
+    a = 4 * (2 + h * h) / (2 + 4 * h * h)
+    disc = a * (y * (1 - y) + h * h / 4)
+    assert np.abs(u[:, 3 * n:] - disc[:, None]).max() < 1e-8
+    _say("poiseuille stats", stats)
