@@ -82,7 +82,10 @@ enum {
    * full cycle's finest-level multigrid launches and the projection of a
    * uniform sample of steps (at most ~256), filling the *_us fields of
    * envar_stats (requires stats != NULL). */
-  ENVAR_FLAG_TIME_KERNELS = 1
+  ENVAR_FLAG_TIME_KERNELS = 1,
+  /* Launch every step eagerly instead of replaying captured HIP graphs of
+   * the steady steps (for comparisons; results are identical). */
+  ENVAR_FLAG_NO_GRAPHS = 2
 };
 
 /* Per-call statistics (filled only when a non-NULL pointer is passed; then the

@@ -61,6 +61,7 @@ struct Plan {
   int norm_slots;
   // state layout
   size_t s_meta, s_u, s_v, s_tu, s_tv, s_phi, s_shu, s_shv, s_cmap, s_ainv, s_aidx, s_total;
+  size_t s_code[MAX_LEVELS];  // per-level Poisson diagonal codes (levels 0..nlev_grid)
 };
 
 static Geo make_geo(int n, int geometry, double x_cav) {
@@ -114,8 +115,9 @@ static int make_plan(const envar_problem* pin, Plan& P) {
   const int ntop = P.lev[nl].n;  // 16
   P.ncoarse = 0;
   for (int n = ntop; n >= 4; n /= 2) ++P.ncoarse;
+  if (ntop != 16 || P.ncoarse != 3) return fail(ENVAR_EINVAL, "internal: the LDS levels must be 16, 8, 4");
   for (int l = 0; l < nl; ++l) {
-    P.mg_tl[l] = Tiling::make(P.lev[l], MG_TH);
+    P.mg_tl[l] = Tiling::make(P.lev[l], MG_TH, MG_TW);
     P.mg_tiles[l] = P.mg_tl[l].count();
   }
   const Geo& g = P.lev[0];
@@ -150,7 +152,8 @@ static int make_plan(const envar_problem* pin, Plan& P) {
   P.nc = 0;
   for (int j = 0; j < gc.ny; ++j)
     for (int i = 0; i < gc.nx; ++i) P.nc += gc.fluid(i, j);
-  if (P.nc > MAX_COARSE_UNKNOWNS) return fail(ENVAR_EINVAL, "coarsest level too large (%d unknowns)", P.nc);
+  if (P.nc > MAX_COARSE_UNKNOWNS || P.nc * P.nc > COARSE_INV_MAX)
+    return fail(ENVAR_EINVAL, "coarsest level too large (%d unknowns)", P.nc);
   // state layout
   const long pl = g.plane();
   size_t o = 0;
@@ -170,13 +173,14 @@ static int make_plan(const envar_problem* pin, Plan& P) {
   P.s_cmap = take(pl * 4);
   P.s_ainv = take((size_t)P.nc * P.nc * 8);
   P.s_aidx = take((size_t)P.nc * 4);
+  for (int l = 0; l <= nl; ++l) P.s_code[l] = take((size_t)P.lev[l].plane());
   P.s_total = o;
   return ENVAR_OK;
 }
 
 // workspace layout of a forward over nmem members
 struct WS {
-  size_t u, v, us, vs, tuA, tvA, tuB, tvB, phiA, phiB, b0, e0, r0;
+  size_t u, v, us, vs, tuA, tvA, tuB, tvB, phiA, phiB, phiC, b0, e0, r0;
   size_t lphiA[MAX_LEVELS], lphiB[MAX_LEVELS], lb[MAX_LEVELS];
   size_t s1u, s1v, s2part, norms, stats, divmax;
   size_t total;
@@ -203,6 +207,7 @@ static WS make_ws(const Plan& P, int nmem) {
   w.tvB = take(nmem * pl * tsz);
   w.phiA = take(nmem * pl * 8);
   w.phiB = P.mixed ? 0 : take(nmem * pl * 8);
+  w.phiC = take(nmem * pl * 8);  // previous pressure / next warm start
   w.b0 = take(nmem * pl * 8);
   w.e0 = P.mixed ? take(nmem * pl * 4) : 0;
   w.r0 = P.mixed ? take(nmem * pl * 4) : 0;
@@ -346,7 +351,7 @@ struct Run {
 };
 
 template <typename TT>
-static int pressure_solve(const Run& R, int cap) {
+static int pressure_solve(const Run& R, int cap, double* phi_cur) {
   const Plan& P = *R.P;
   const WS& w = *R.w;
   void* ws = R.ws;
@@ -366,6 +371,8 @@ static int pressure_solve(const Run& R, int cap) {
     a.norm_slots = P.norm_slots;
     a.tol = P.tol;
     a.dt = P.dt;
+    a.code = at<unsigned char>(R.state, P.s_code[l]);
+    a.codec = at<unsigned char>(R.state, P.s_code[l + 1]);
     return a;
   };
   auto coarse_args = [&](int k) {
@@ -450,7 +457,7 @@ static int pressure_solve(const Run& R, int cap) {
     if (timed && !P.mixed) tm->mark(TM_CYCLE, 1, R.s);
   };
   if (!P.mixed) {
-    double* phi = at<double>(ws, w.phiA);
+    double* phi = phi_cur;
     const double* b = at<double>(ws, w.b0);
     for (int k = 0; k < cap; ++k) vcycle(k, (const T*)b, (const T*)phi, (T*)phi, nullptr, 0, 1);
   } else {
@@ -460,7 +467,7 @@ static int pressure_solve(const Run& R, int cap) {
     r.ntiles = P.st_tiles;
     r.nmem = R.nmem;
     r.plane = P.lev[0].plane();
-    r.phi = at<double>(ws, w.phiA);
+    r.phi = phi_cur;
     r.b = at<double>(ws, w.b0);
     r.r = at<float>(ws, w.r0);
     r.norms = norms;
@@ -472,7 +479,7 @@ static int pressure_solve(const Run& R, int cap) {
     launch_resid64(r, R.s);
     if (tm) tm->mark(TM_RESID, 1, R.s);
     for (int k = 1; k <= cap; ++k) {
-      vcycle(k, (const T*)at<float>(ws, w.r0), nullptr, (T*)at<float>(ws, w.e0), at<double>(ws, w.phiA), 1, 0);
+      vcycle(k, (const T*)at<float>(ws, w.r0), nullptr, (T*)at<float>(ws, w.e0), phi_cur, 1, 0);
       r.k = k;
       launch_resid64(r, R.s);
       if (tm && k == k_timed) tm->mark(TM_CYCLE, 1, R.s);
@@ -481,94 +488,165 @@ static int pressure_solve(const Run& R, int cap) {
   return ENVAR_OK;
 }
 
+// One time step: predictor, pressure solve with at most `cap` cycles per
+// member, projection + cost, bookkeeping. The launch sequence depends only on
+// the step parity (AB2 history and pressure buffers alternate), the cap and
+// whether this is the first step of a cold start, so steady steps are
+// captured once into a HIP graph per parity and replayed.
 template <typename TT>
-static int run_steps(const Run& R, int steps, int cold_first) {
+static int launch_step(const Run& R, hipStream_t st, int s, int cap, bool cold) {
   const Plan& P = *R.P;
   const WS& w = *R.w;
   void* ws = R.ws;
   const long pl = P.lev[0].plane();
   TT* tA[2] = {at<TT>(ws, w.tuA), at<TT>(ws, w.tvA)};
   TT* tB[2] = {at<TT>(ws, w.tuB), at<TT>(ws, w.tvB)};
+  double* phis[2] = {at<double>(ws, w.phiA), at<double>(ws, w.phiC)};
+  const int cur = s & 1;
+  TT** tp = (s % 2 == 0) ? tA : tB;
+  TT** tn = (s % 2 == 0) ? tB : tA;
+  Run Rs = R;
+  Rs.s = st;
+  PredArgs<TT> a{};
+  a.g = P.lev[0];
+  a.tiling = P.st_tl;
+  a.ntiles = P.st_tiles;
+  a.nmem = R.nmem;
+  a.plane = pl;
+  a.nu = P.nu;
+  a.dt = P.dt;
+  a.cold_flag = cold ? at<int>(R.state, P.s_meta) : nullptr;
+  a.u = at<double>(ws, w.u);
+  a.v = at<double>(ws, w.v);
+  a.us = at<double>(ws, w.us);
+  a.vs = at<double>(ws, w.vs);
+  a.tu_prev = tp[0];
+  a.tv_prev = tp[1];
+  a.tu = tn[0];
+  a.tv = tn[1];
+  a.b = at<double>(ws, w.b0);
+  a.ctrl = R.ctrl;
+  a.m = P.m;
+  a.nctrl = (int)(P.m / 2);
+  a.cmap = at<int>(R.state, P.s_cmap);
+  a.norms = at<double>(ws, w.norms);
+  a.norm_slots = P.norm_slots;
+  if (Rs.tm) Rs.tm->mark(TM_PRED, 0, st);
+  launch_predictor<TT>(a, st);
+  if (Rs.tm) Rs.tm->mark(TM_PRED, 1, st);
+  pressure_solve<TT>(Rs, cap, phis[cur]);
+  ProjArgs pj{};
+  pj.g = P.lev[0];
+  pj.tiling = P.st_tl;
+  pj.ntiles = P.st_tiles;
+  pj.nmem = R.nmem;
+  pj.plane = pl;
+  pj.cplane = P.cplane;
+  pj.dt = P.dt;
+  pj.u = at<double>(ws, w.u);
+  pj.v = at<double>(ws, w.v);
+  pj.us = at<double>(ws, w.us);
+  pj.vs = at<double>(ws, w.vs);
+  pj.phi = phis[cur];
+  pj.phi_next = phis[cur ^ 1];
+  pj.shu = at<double>(R.state, P.s_shu);
+  pj.shv = at<double>(R.state, P.s_shv);
+  pj.s1u = at<double>(ws, w.s1u);
+  pj.s1v = at<double>(ws, w.s1v);
+  pj.s2part = at<double>(ws, w.s2part);
+  pj.divmax = at<double>(ws, w.divmax);
+  if (Rs.tm) Rs.tm->mark(TM_PROJ, 0, st);
+  launch_project_cost(pj, st);
+  if (Rs.tm) Rs.tm->mark(TM_PROJ, 1, st);
+  BookArgs bk{};
+  bk.nmem = R.nmem;
+  bk.norm_slots = P.norm_slots;
+  bk.cap = cap;
+  bk.slot_base = P.mixed ? 1 : 0;
+  bk.tol = P.tol;
+  bk.norms = at<double>(ws, w.norms);
+  bk.stats = at<double>(ws, w.stats);
+  launch_step_book(bk, st);
+  HIP_OK(hipGetLastError());
+  return ENVAR_OK;
+}
+
+// captured step graphs (one per parity) for the current cap
+struct StepGraphs {
+  hipStream_t cs = nullptr;
+  hipGraph_t g[2] = {nullptr, nullptr};
+  hipGraphExec_t x[2] = {nullptr, nullptr};
+  int cap[2] = {-1, -1};
+  void drop(int p) {
+    if (x[p]) (void)hipGraphExecDestroy(x[p]);
+    if (g[p]) (void)hipGraphDestroy(g[p]);
+    x[p] = nullptr;
+    g[p] = nullptr;
+    cap[p] = -1;
+  }
+  ~StepGraphs() {
+    drop(0);
+    drop(1);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+// Returns (through phi_final) the buffer holding the last solved pressure.
+template <typename TT>
+static int run_steps(const Run& R, int steps, int cold_first, double** phi_final) {
+  const Plan& P = *R.P;
+  const WS& w = *R.w;
+  void* ws = R.ws;
   int cap = P.cap_max;
   hipEvent_t ev = nullptr;
   bool pending = false;
   double* host = g_pinned.get((size_t)R.nmem * STATS_STRIDE);
   if (!host) return fail(ENVAR_EDEVICE, "hipHostMalloc failed");
   const int check_every = 16;
+  double* phis[2] = {at<double>(ws, w.phiA), at<double>(ws, w.phiC)};
+  double* stats_dev = at<double>(ws, w.stats);
+  StepGraphs G;
+  const bool use_graphs = !(P.p.flags & ENVAR_FLAG_NO_GRAPHS);
   HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  auto absorb = [&]() {
+    int mx = 0;
+    for (int i = 0; i < R.nmem; ++i) mx = std::max(mx, (int)host[(size_t)i * STATS_STRIDE + ST_MAXCYC]);
+    cap = std::min(P.cap_max, std::max(2, mx + 1));
+  };
   int rc = ENVAR_OK;
   for (int s = 0; s < steps && rc == ENVAR_OK; ++s) {
     if (R.tm && R.tm->begin_step(s, steps)) return fail(ENVAR_EDEVICE, "hipEventCreate failed");
-    TT** tp = (s % 2 == 0) ? tA : tB;
-    TT** tn = (s % 2 == 0) ? tB : tA;
-    PredArgs<TT> a{};
-    a.g = P.lev[0];
-    a.tiling = P.st_tl;
-    a.ntiles = P.st_tiles;
-    a.nmem = R.nmem;
-    a.plane = pl;
-    a.nu = P.nu;
-    a.dt = P.dt;
-    a.cold_flag = (s == 0 && cold_first) ? at<int>(R.state, P.s_meta) : nullptr;
-    a.u = at<double>(ws, w.u);
-    a.v = at<double>(ws, w.v);
-    a.us = at<double>(ws, w.us);
-    a.vs = at<double>(ws, w.vs);
-    a.tu_prev = tp[0];
-    a.tv_prev = tp[1];
-    a.tu = tn[0];
-    a.tv = tn[1];
-    a.b = at<double>(ws, w.b0);
-    a.ctrl = R.ctrl;
-    a.m = P.m;
-    a.nctrl = (int)(P.m / 2);
-    a.cmap = at<int>(R.state, P.s_cmap);
-    a.norms = at<double>(ws, w.norms);
-    a.norm_slots = P.norm_slots;
-    if (R.tm) R.tm->mark(TM_PRED, 0, R.s);
-    launch_predictor<TT>(a, R.s);
-    if (R.tm) R.tm->mark(TM_PRED, 1, R.s);
-    pressure_solve<TT>(R, cap);
-    ProjArgs pj{};
-    pj.g = P.lev[0];
-    pj.tiling = P.st_tl;
-    pj.ntiles = P.st_tiles;
-    pj.nmem = R.nmem;
-    pj.plane = pl;
-    pj.cplane = P.cplane;
-    pj.dt = P.dt;
-    pj.u = at<double>(ws, w.u);
-    pj.v = at<double>(ws, w.v);
-    pj.us = at<double>(ws, w.us);
-    pj.vs = at<double>(ws, w.vs);
-    pj.phi = at<double>(ws, w.phiA);
-    pj.shu = at<double>(R.state, P.s_shu);
-    pj.shv = at<double>(R.state, P.s_shv);
-    pj.s1u = at<double>(ws, w.s1u);
-    pj.s1v = at<double>(ws, w.s1v);
-    pj.s2part = at<double>(ws, w.s2part);
-    pj.divmax = at<double>(ws, w.divmax);
-    if (R.tm) R.tm->mark(TM_PROJ, 0, R.s);
-    launch_project_cost(pj, R.s);
-    if (R.tm) R.tm->mark(TM_PROJ, 1, R.s);
-    BookArgs bk{};
-    bk.nmem = R.nmem;
-    bk.norm_slots = P.norm_slots;
-    bk.cap = cap;
-    bk.slot_base = P.mixed ? 1 : 0;
-    bk.tol = P.tol;
-    bk.norms = at<double>(ws, w.norms);
-    bk.stats = at<double>(ws, w.stats);
-    launch_step_book(bk, R.s);
-    HIP_OK(hipGetLastError());
+    const bool cold = s == 0 && cold_first;
+    const bool sampled = R.tm && R.tm->cur >= 0;
+    const int par = s & 1;
+    if (s > 0 && !sampled && use_graphs && steps - s >= 16) {
+      if (G.cap[par] != cap) {
+        G.drop(par);
+        if (!G.cs) HIP_OK(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+        HIP_OK(hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal));
+        Run Rn = R;
+        Rn.tm = nullptr;
+        rc = launch_step<TT>(Rn, G.cs, s, cap, false);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(G.cs, &g);
+        if (rc) {
+          if (g) (void)hipGraphDestroy(g);
+          return rc;
+        }
+        if (ec != hipSuccess) return fail(ENVAR_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        G.g[par] = g;
+        HIP_OK(hipGraphInstantiate(&G.x[par], g, nullptr, nullptr, 0));
+        G.cap[par] = cap;
+      }
+      HIP_OK(hipGraphLaunch(G.x[par], R.s));
+    } else {
+      rc = launch_step<TT>(R, R.s, s, cap, cold);
+      if (rc) return rc;
+    }
+    if (phi_final) *phi_final = phis[par];
     // adaptive cap: exact after the first step, then asynchronous checks
-    auto absorb = [&]() {
-      int mx = 0;
-      for (int i = 0; i < R.nmem; ++i) mx = std::max(mx, (int)host[(size_t)i * STATS_STRIDE + ST_MAXCYC]);
-      cap = std::min(P.cap_max, std::max(2, mx + 2));
-    };
     if (s == 0) {
-      HIP_OK(hipMemcpyAsync(host, bk.stats, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
+      HIP_OK(hipMemcpyAsync(host, stats_dev, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
       HIP_OK(hipStreamSynchronize(R.s));
       absorb();
     } else if (s % check_every == 0) {
@@ -577,7 +655,7 @@ static int run_steps(const Run& R, int steps, int cold_first) {
         pending = false;
       }
       if (!pending) {
-        HIP_OK(hipMemcpyAsync(host, bk.stats, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
+        HIP_OK(hipMemcpyAsync(host, stats_dev, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
         HIP_OK(hipEventRecord(ev, R.s));
         pending = true;
       }
@@ -605,6 +683,7 @@ static void init_members(const Plan& P, const WS& w, void* ws, const void* state
   ia.us = at<double>(ws, w.us);
   ia.vs = at<double>(ws, w.vs);
   ia.phi = at<double>(ws, w.phiA);
+  ia.phi2 = at<double>(ws, w.phiC);
   ia.tu = at<TT>(ws, w.tuA);
   ia.tv = at<TT>(ws, w.tvA);
   ia.s1u = at<double>(ws, w.s1u);
@@ -731,6 +810,22 @@ int envar_state_init(const envar_problem* p, const double* u, const double* v, c
   std::vector<double> ainv;
   std::vector<int> aidx;
   coarse_inverse(gc, ainv, aidx);
+  {
+    const size_t nc = aidx.size();
+    std::vector<double> t(ainv.size());
+    for (size_t q = 0; q < nc; ++q)
+      for (size_t r = 0; r < nc; ++r) t[r * nc + q] = ainv[q * nc + r];
+    ainv.swap(t);  // the coarse kernel reads the transpose
+  }
+  // Poisson diagonal codes of the tiled levels and the first LDS level
+  std::vector<std::vector<unsigned char>> codes(P.nlev_grid + 1);
+  for (int l = 0; l <= P.nlev_grid; ++l) {
+    const Geo& gl = P.lev[l];
+    codes[l].assign(gl.plane(), 0);
+    for (int j = 0; j < gl.ny; ++j)
+      for (int i = 0; i < gl.nx; ++i)
+        if (gl.fluid(i, j)) codes[l][gl.at(i, j)] = (unsigned char)gl.diag_count(i, j);
+  }
   int meta[64] = {0};
   meta[0] = tu_prev ? 0 : 1;  // cold start flag
   char* S = (char*)state_dev;
@@ -744,6 +839,8 @@ int envar_state_init(const envar_problem* p, const double* u, const double* v, c
   HIP_OK(hipMemcpyAsync(S + P.s_cmap, cmap.data(), pl * 4, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(S + P.s_ainv, ainv.data(), ainv.size() * 8, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(S + P.s_aidx, aidx.data(), aidx.size() * 4, hipMemcpyHostToDevice, s));
+  for (int l = 0; l <= P.nlev_grid; ++l)
+    HIP_OK(hipMemcpyAsync(S + P.s_code[l], codes[l].data(), codes[l].size(), hipMemcpyHostToDevice, s));
   launch_shift(g, at<double>(state_dev, P.s_u), at<double>(state_dev, P.s_v), at<double>(state_dev, P.s_shu),
                at<double>(state_dev, P.s_shv), s);
   HIP_OK(hipGetLastError());
@@ -782,7 +879,8 @@ static int forward_impl(const Plan& P, const void* state_dev, const double* cont
   timer.on = stats != nullptr && (P.p.flags & ENVAR_FLAG_TIME_KERNELS);
   timer.every = std::max(1, (horizon - 1 + timer.max_samples - 1) / timer.max_samples);
   Run R{&P, ws_dev, &w, n_rows, state_dev, controls_dev, s, timer.on ? &timer : nullptr};
-  int rc = P.mixed ? run_steps<float>(R, horizon, 1) : run_steps<double>(R, horizon, 1);
+  double* phi_last = at<double>(ws_dev, w.phiA);
+  int rc = P.mixed ? run_steps<float>(R, horizon, 1, &phi_last) : run_steps<double>(R, horizon, 1, &phi_last);
   if (rc) return rc;
   if (J_dev) {
     FinalArgs fa{};
@@ -813,12 +911,12 @@ static int forward_impl(const Plan& P, const void* state_dev, const double* cont
     if (P.mixed)
       launch_store_base<float>(pl, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
                                at<float>(ws_dev, inB ? w.tuB : w.tuA), at<float>(ws_dev, inB ? w.tvB : w.tvA),
-                               at<double>(ws_dev, w.phiA), at<double>(S, P.s_u), at<double>(S, P.s_v),
+                               phi_last, at<double>(S, P.s_u), at<double>(S, P.s_v),
                                at<double>(S, P.s_tu), at<double>(S, P.s_tv), at<double>(S, P.s_phi), s);
     else
       launch_store_base<double>(pl, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
                                 at<double>(ws_dev, inB ? w.tuB : w.tuA), at<double>(ws_dev, inB ? w.tvB : w.tvA),
-                                at<double>(ws_dev, w.phiA), at<double>(S, P.s_u), at<double>(S, P.s_v),
+                                phi_last, at<double>(S, P.s_u), at<double>(S, P.s_v),
                                 at<double>(S, P.s_tu), at<double>(S, P.s_tv), at<double>(S, P.s_phi), s);
     launch_clear_flag(at<int>(S, P.s_meta), s);
     launch_shift(P.lev[0], at<double>(S, P.s_u), at<double>(S, P.s_v), at<double>(S, P.s_shu),

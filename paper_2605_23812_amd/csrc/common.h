@@ -21,9 +21,13 @@ namespace envar {
 constexpr int TILE_W = 64;
 constexpr int STEP_TH = 8;   // predictor / projection tile height
 constexpr int MG_TH = 16;    // multigrid tile height
+constexpr int MG_NS = 2;     // red-black sweeps before and after the coarse correction
+constexpr int MG_H = 2 * MG_NS + 1;           // window halo of the multigrid kernels
+constexpr int MG_TW = 64 - 2 * MG_H;          // multigrid tile width: the window is one wave wide
 constexpr int COARSE_N = 16; // levels with inv_h <= 16 run inside one workgroup per member
 constexpr int MAX_LEVELS = 12;
 constexpr int MAX_COARSE_UNKNOWNS = 128;
+constexpr int COARSE_INV_MAX = 8192;  // LDS budget for the coarsest inverse (nc^2 doubles)
 constexpr double U_CONVECTIVE = 2.0 / 3.0;  // bulk speed of the 4y(1-y) inflow
 
 struct Geo {
@@ -72,13 +76,14 @@ struct Geo {
 // Tiling of the fluid part of the box into TW x TH tiles: first the cavity tile
 // rows (only the tile columns that meet the cavity), then full channel rows.
 struct Tiling {
-  int cav_c0, cav_cols, cav_rows, ch_cols, ch_rows, th, jc_tiles;
-  __host__ __device__ static Tiling make(const Geo& g, int th) {
+  int cav_c0, cav_cols, cav_rows, ch_cols, ch_rows, th, jc_tiles, tw;
+  __host__ __device__ static Tiling make(const Geo& g, int th, int tw = TILE_W) {
     Tiling t;
     t.th = th;
+    t.tw = tw;
     if (g.jc % th == 0 && g.ic1 > g.ic0) {
-      t.cav_c0 = g.ic0 / TILE_W;
-      t.cav_cols = (g.ic1 - 1) / TILE_W - t.cav_c0 + 1;
+      t.cav_c0 = g.ic0 / tw;
+      t.cav_cols = (g.ic1 - 1) / tw - t.cav_c0 + 1;
       t.cav_rows = g.jc / th;
       t.jc_tiles = g.jc;
     } else {
@@ -87,7 +92,7 @@ struct Tiling {
       t.cav_rows = 0;
       t.jc_tiles = 0;
     }
-    t.ch_cols = (g.nx + TILE_W - 1) / TILE_W;
+    t.ch_cols = (g.nx + tw - 1) / tw;
     t.ch_rows = (g.ny - t.jc_tiles + th - 1) / th;
     return t;
   }
@@ -96,11 +101,11 @@ struct Tiling {
     int ncav = cav_cols * cav_rows;
     if (t < ncav) {
       y0 = (t / cav_cols) * th;
-      x0 = (cav_c0 + t % cav_cols) * TILE_W;
+      x0 = (cav_c0 + t % cav_cols) * tw;
     } else {
       t -= ncav;
       y0 = jc_tiles + (t / ch_cols) * th;
-      x0 = (t % ch_cols) * TILE_W;
+      x0 = (t % ch_cols) * tw;
     }
   }
 };

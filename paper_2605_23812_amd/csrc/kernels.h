@@ -46,6 +46,7 @@ struct ProjArgs {
   const double* us;
   const double* vs;
   const double* phi;
+  double* phi_next;   // optional: receives the warm start 2 phi^{n+1} - phi^n of the next solve (holds phi^n on entry)
   const double* shu;  // cost shift (dense cells, shared by members)
   const double* shv;
   double* s1u;        // [nmem][cplane] running sums of (u_c - s_c); NULL = no cost
@@ -84,7 +85,7 @@ struct InitArgs {
   int nmem, ntiles;
   long plane, cplane;
   const double *bu, *bv, *btu, *btv, *bphi;
-  double *u, *v, *us, *vs, *phi;
+  double *u, *v, *us, *vs, *phi, *phi2;
   TT *tu, *tv;
   double *s1u, *s1v, *s2part, *stats, *divmax;
 };
@@ -93,6 +94,8 @@ struct InitArgs {
 template <typename T>
 struct MGArgs {
   Geo g, gc;          // this level and the next coarser one
+  const unsigned char* code;   // this level: Poisson diagonal count of every cell (0 = not fluid), plane layout
+  const unsigned char* codec;  // the coarser level
   Tiling tiling;
   int ntiles, nmem;
   long plane, cplane_c;  // plane of this level and of the coarse level
@@ -121,7 +124,7 @@ struct CoarseArgs {
   const void* b;
   int warm;           // start from the stored phi (top = finest level)
   double* add_to;     // mixed with no tiled level: phi64 += phi instead of storing phi
-  const double* ainv; // dense inverse of the coarsest operator [nc][nc]
+  const double* ainv; // dense inverse of the coarsest operator, transposed: ainv[r * nc + q] = A^{-1}[q][r]
   const int* aidx;    // cell (i + j * nx) of each coarsest unknown
   int nc;
   double* norms;

@@ -30,32 +30,6 @@ __device__ __forceinline__ T inv_diag(int d) {
   return d == 4 ? (T)0.25 : d == 3 ? (T)(1.0 / 3.0) : d == 2 ? (T)0.5 : d == 5 ? (T)0.2 : d == 6 ? (T)(1.0 / 6.0) : (T)1;
 }
 
-// One red-black sweep on an LDS window (LW x LH) whose origin is (ox, oy) in
-// level coordinates; the outermost ring is never updated. Non-fluid entries
-// hold 0 and stay 0.
-template <typename T, int LW, int LH>
-__device__ __forceinline__ void rb_sweep(T* sp, const T* sb, const Geo& g, int ox, int oy, T h2) {
-  for (int color = 0; color < 2; ++color) {
-    for (int q = threadIdx.x; q < LH * (LW / 2); q += blockDim.x) {
-      const int r = q / (LW / 2);
-      const int c = 2 * (q % (LW / 2)) + ((color ^ r ^ ox ^ oy) & 1);
-      if (r == 0 || r == LH - 1 || c == 0 || c == LW - 1) continue;
-      const int i = ox + c, j = oy + r;
-      if (!g.fluid(i, j)) continue;
-      const int k = r * LW + c;
-      const T s = (sp[k - 1] + sp[k + 1]) + (sp[k - LW] + sp[k + LW]);
-      sp[k] = (s - h2 * sb[k]) * inv_diag<T>(g.diag_count(i, j));
-    }
-    __syncthreads();
-  }
-}
-
-template <typename T, int LW>
-__device__ __forceinline__ T resid_at(const T* sp, const T* sb, const Geo& g, int i, int j, int k, T inv_h2) {
-  const T s = (sp[k - 1] + sp[k + 1]) + (sp[k - LW] + sp[k + LW]);
-  return sb[k] - (s - (T)g.diag_count(i, j) * sp[k]) * inv_h2;
-}
-
 template <typename T>
 __device__ __forceinline__ bool mg_skip(const MGArgs<T>& a, int mem, int tile) {
   if (a.k <= 0 || a.norms == nullptr) return false;
@@ -67,59 +41,212 @@ __device__ __forceinline__ bool mg_skip(const MGArgs<T>& a, int mem, int tile) {
   return false;
 }
 
+// The multigrid tile kernels hold a 64 x (MG_TH + 2H) window of one level in
+// LDS around a (64 - 2H) x MG_TH tile: a window row is one wave, lane = column,
+// so no index needs a division. The two red-black colours live in separate
+// padded planes; a cell's four neighbours are all of the other colour and sit
+// at consecutive addresses for consecutive lanes. Each thread owns one column
+// position q of each colour in every eighth window row; its 1/diag, diag and
+// h^2 b stay in registers. Ring cells of the window and cells outside the
+// fluid are frozen (1/diag = 0). The Poisson diagonal of every cell is read
+// from a per-level byte plane shared by all members.
+// (ox + oy) is even, so a cell's colour is (r + col) & 1 in window coordinates.
+template <typename T>
+struct Win {
+  static constexpr int H = MG_H, LW = 64, TWI = MG_TW, TH = MG_TH, LH = TH + 2 * H;
+  static constexpr int QS = 34;                 // padded row stride of a colour plane (32 cells)
+  static constexpr int CS = (LH + 2) * QS;      // padded colour plane
+  static constexpr int NR = (LH + 3) / 4;       // window rows per wave
+  static constexpr int NIT = (LH + 7) / 8;      // cells per thread and colour
+  static __device__ __forceinline__ int idx(int r, int col) {
+    return ((r + col) & 1) * CS + (r + 1) * QS + (col >> 1) + 1;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ T inv_of(int d) {
+  return d == 4 ? (T)0.25 : d == 3 ? (T)(1.0 / 3.0) : d == 2 ? (T)0.5 : d == 5 ? (T)0.2 : d == 6 ? (T)(1.0 / 6.0)
+                                                                                          : (T)1;
+}
+
+template <typename T>
+struct Items {
+  typedef Win<T> W;
+  int own0[2];        // LDS offset of the first item of each colour
+  int left0[2];       // offset of its left neighbour (other colour)
+  int r0, q;
+  T hb[2][W::NIT];    // h^2 b
+  T invd[2][W::NIT];  // 1/diag, 0 = frozen
+  T d[2][W::NIT];     // diag
+
+  __device__ __forceinline__ void init(const T* sb, const unsigned char* scode, T h2) {
+    r0 = threadIdx.x >> 5;
+    q = threadIdx.x & 31;
+    for (int c = 0; c < 2; ++c) {
+      const int p = (c ^ r0) & 1;  // column parity of this colour in rows r0 + 8n
+      own0[c] = c * W::CS + (r0 + 1) * W::QS + q + 1;
+      left0[c] = (1 - c) * W::CS + (r0 + 1) * W::QS + q + p;
+#pragma unroll
+      for (int n = 0; n < W::NIT; ++n) {
+        const int r = r0 + 8 * n, col = 2 * q + p;
+        const int o = own0[c] + 8 * n * W::QS;
+        invd[c][n] = (T)0;
+        d[c][n] = (T)1;
+        hb[c][n] = (T)0;
+        if (r < W::LH) {
+          const int code = scode[o];
+          const bool ring = r == 0 || r == W::LH - 1 || col == 0 || col == W::LW - 1;
+          if (code && !ring) {
+            invd[c][n] = inv_of<T>(code);
+            d[c][n] = (T)code;
+            hb[c][n] = h2 * sb[o];
+          }
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ T nbsum(const T* sp, int c, int n) const {
+    const int l = left0[c] + 8 * n * W::QS;
+    const int m = l + 1 - ((c ^ r0) & 1);  // other colour, same column
+    return (sp[l] + sp[l + 1]) + (sp[m - W::QS] + sp[m + W::QS]);
+  }
+  __device__ __forceinline__ void sweep(T* sp) const {
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+      for (int n = 0; n < W::NIT; ++n)
+        if (invd[c][n] != (T)0) sp[own0[c] + 8 * n * W::QS] = (nbsum(sp, c, n) - hb[c][n]) * invd[c][n];
+      __syncthreads();
+    }
+  }
+  // h^2 r = h^2 b - (sum nb - d phi)
+  __device__ __forceinline__ T resid_h2(const T* sp, int c, int n) const {
+    return hb[c][n] - (nbsum(sp, c, n) - d[c][n] * sp[own0[c] + 8 * n * W::QS]);
+  }
+  // window row and column of item (c, n)
+  __device__ __forceinline__ int row(int n) const { return r0 + 8 * n; }
+  __device__ __forceinline__ int col(int c) const { return 2 * q + ((c ^ r0) & 1); }
+};
+
+// window load shared by pre and post: phi (+ correction), b and the diagonal codes
+template <typename T>
+struct WinLoad {
+  typedef Win<T> W;
+  T vp[W::NR], vb[W::NR];
+  unsigned char vc[W::NR];
+  __device__ __forceinline__ void fetch(const Geo& g, const unsigned char* code, const T* phi, const T* b, long off,
+                                        int ox, int oy) {
+    const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = ox + col;
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m, j = oy + r;
+      vp[m] = (T)0;
+      vb[m] = (T)0;
+      vc[m] = 0;
+      if (r < W::LH && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+        const long at = g.at(i, j);
+        // independent loads (no wait on the code); non-fluid values are masked below
+        vc[m] = code[at];
+        vb[m] = b[off + at];
+        if (phi) vp[m] = phi[off + at];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m)
+      if (!vc[m]) {
+        vp[m] = (T)0;
+        vb[m] = (T)0;
+      }
+  }
+};
+
 // ---------------------------------------------------------------------------- pre-smoothing + restriction
 template <typename T, int NS>
 __global__ __launch_bounds__(256) void k_mg_pre(MGArgs<T> a) {
-  constexpr int TW = TILE_W, TH = MG_TH, H = 2 * NS + 1;
-  constexpr int LW = TW + 2 * H, LH = TH + 2 * H;
-  __shared__ T sp[LH * LW];
-  __shared__ T sb[LH * LW];
+  typedef Win<T> W;
+  static_assert(2 * NS + 1 <= W::H, "window halo too small for the sweep count");
+  static_assert(W::TH * 64 <= 2 * W::CS, "residual staging does not fit");
+  __shared__ T sp[2 * W::CS];
+  __shared__ T sb[2 * W::CS];
+  __shared__ unsigned char scode[2 * W::CS];
   const Geo& g = a.g;
   const int item = xcd_remap(blockIdx.x, a.ntiles * a.nmem);
   const int mem = item / a.ntiles, tile = item % a.ntiles;
   if (mg_skip(a, mem, tile)) return;
   int x0, y0;
   a.tiling.origin(tile, x0, y0);
-  const int ox = x0 - H, oy = y0 - H;
+  const int ox = x0 - W::H, oy = y0 - W::H;
   const long off = (long)mem * a.plane;
-  for (int k = threadIdx.x; k < LH * LW; k += 256) {
-    const int i = ox + k % LW, j = oy + k / LW;
-    const bool fl = g.fluid(i, j);
-    sp[k] = (fl && !a.zero_guess) ? a.phi_in[off + g.at(i, j)] : (T)0;
-    sb[k] = fl ? a.b[off + g.at(i, j)] : (T)0;
-  }
-  __syncthreads();
-  const T h2 = (T)(g.h * g.h), inv_h2 = (T)(1.0 / (g.h * g.h));
-  for (int s = 0; s < NS; ++s) rb_sweep<T, LW, LH>(sp, sb, g, ox, oy, h2);
-  // restriction: one coarse cell per thread (32 x 8 per tile)
+  const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
   {
-    const Geo& gc = a.gc;
-    const int ci = threadIdx.x % (TW / 2), cj = threadIdx.x / (TW / 2);
-    const int I = x0 / 2 + ci, J = y0 / 2 + cj;
-    if (gc.fluid(I, J)) {
-      T rs = 0;
-      for (int dj = 0; dj < 2; ++dj)
-        for (int di = 0; di < 2; ++di) {
-          const int c = H + 2 * ci + di, r = H + 2 * cj + dj;
-          rs += resid_at<T, LW>(sp, sb, g, ox + c, oy + r, r * LW + c, inv_h2);
-        }
-      a.bc[(long)mem * a.cplane_c + gc.at(I, J)] = (T)0.25 * rs;
+    WinLoad<T> L;
+    L.fetch(g, a.code, a.zero_guess ? nullptr : a.phi_in, a.b, off, ox, oy);
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m;
+      if (r < W::LH) {
+        const int x = W::idx(r, col);
+        sp[x] = L.vp[m];
+        sb[x] = L.vb[m];
+        scode[x] = L.vc[m];
+      }
     }
   }
-  for (int k = threadIdx.x; k < TW * TH; k += 256) {
-    const int c = H + k % TW, r = H + k / TW;
-    const int i = ox + c, j = oy + r;
-    if (g.fluid(i, j)) a.phi_out[off + g.at(i, j)] = sp[r * LW + c];
+  __syncthreads();
+  const T h2 = (T)(g.h * g.h);
+  Items<T> it;
+  it.init(sb, scode, h2);
+  for (int s = 0; s < NS; ++s) it.sweep(sp);
+  // interior residuals staged in sb (dead by now) as a MG_TH x 64 array
+  T res[2][W::NIT];
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int n = 0; n < W::NIT; ++n) res[c][n] = it.invd[c][n] != (T)0 ? it.resid_h2(sp, c, n) : (T)0;
+  __syncthreads();
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int n = 0; n < W::NIT; ++n) {
+      const int r = it.row(n) - W::H;
+      if (r >= 0 && r < W::TH) sb[r * 64 + it.col(c)] = res[c][n];
+    }
+  __syncthreads();
+  {
+    const Geo& gc = a.gc;
+    const int ci = threadIdx.x & 31;
+    for (int cj = 2 * w + (threadIdx.x >> 5 & 1); cj < W::TH / 2; cj += 8) {
+      const int I = x0 / 2 + ci, J = y0 / 2 + cj;
+      if (ci < W::TWI / 2 && gc.fluid(I, J)) {
+        const T* rr = sb + (2 * cj) * 64 + W::H + 2 * ci;
+        const T rs = (rr[0] + rr[1]) + (rr[64] + rr[65]);
+        a.bc[(long)mem * a.cplane_c + gc.at(I, J)] = rs * (T)(0.25 / (g.h * g.h));
+      }
+    }
+  }
+  const int i = ox + col;
+  if (col >= W::H && col < W::H + W::TWI && i < g.nx) {
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m;
+      const int j = oy + r;
+      if (r >= W::H && r < W::H + W::TH && j < g.ny) {
+        const int x = W::idx(r, col);
+        if (scode[x]) a.phi_out[off + g.at(i, j)] = sp[x];
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------- prolongation + post-smoothing
 template <typename T, int NS, int NORM>
 __global__ __launch_bounds__(256) void k_mg_post(MGArgs<T> a) {
-  constexpr int TW = TILE_W, TH = MG_TH, H = 2 * NS + NORM;
-  constexpr int LW = TW + 2 * H, LH = TH + 2 * H;
-  __shared__ T sp[LH * LW];
-  __shared__ T sb[LH * LW];
+  typedef Win<T> W;
+  static_assert(2 * NS + NORM <= W::H, "window halo too small for the sweep count");
+  constexpr int CW = 36, CH = W::LH / 2 + 3;
+  __shared__ T sp[2 * W::CS];
+  __shared__ T sb[2 * W::CS];
+  __shared__ unsigned char scode[2 * W::CS];
+  __shared__ T scw[CH * CW];
+  __shared__ unsigned char sccode[CH * CW];
   __shared__ double red[4];
   const Geo& g = a.g;
   const Geo& gc = a.gc;
@@ -128,76 +255,131 @@ __global__ __launch_bounds__(256) void k_mg_post(MGArgs<T> a) {
   if (mg_skip(a, mem, tile)) return;
   int x0, y0;
   a.tiling.origin(tile, x0, y0);
-  const int ox = x0 - H, oy = y0 - H;
+  const int ox = x0 - W::H, oy = y0 - W::H;
   const long off = (long)mem * a.plane;
   const T* __restrict__ pc = a.phic + (long)mem * a.cplane_c;
-  for (int k = threadIdx.x; k < LH * LW; k += 256) {
-    const int i = ox + k % LW, j = oy + k / LW;
-    T p = 0, bb = 0;
-    if (g.fluid(i, j)) {
-      const long at = g.at(i, j);
-      bb = a.b[off + at];
-      // bilinear prolongation of the coarse correction
-      const int I = i >> 1, J = j >> 1;
-      const int IX = I + ((i & 1) ? 1 : -1), JY = J + ((j & 1) ? 1 : -1);
-      const T P = pc[gc.at(I, J)];
-      const T X = gc.fluid(IX, J) ? pc[gc.at(IX, J)] : (IX == gc.nx ? -P : P);
-      const T Y = gc.fluid(I, JY) ? pc[gc.at(I, JY)] : P;
-      const T D = gc.fluid(IX, JY) ? pc[gc.at(IX, JY)] : X + Y - P;
-      p = a.phi_in[off + at] + ((T)9 * P + (T)3 * (X + Y) + D) * (T)0.0625;
-    }
-    sp[k] = p;
-    sb[k] = bb;
-  }
-  __syncthreads();
-  const T h2 = (T)(g.h * g.h), inv_h2 = (T)(1.0 / (g.h * g.h));
-  for (int s = 0; s < NS; ++s) rb_sweep<T, LW, LH>(sp, sb, g, ox, oy, h2);
-  if (NORM && a.write_norm) {
-    double m = 0.0;
-    for (int k = threadIdx.x; k < TW * TH; k += 256) {
-      const int c = H + k % TW, r = H + k / TW;
-      const int i = ox + c, j = oy + r;
-      if (g.fluid(i, j)) {
-        const double rr = fabs((double)resid_at<T, LW>(sp, sb, g, i, j, r * LW + c, inv_h2)) * a.dt;
-        m = (rr > m || rr != rr) ? rr : m;
+  const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cox = (ox >> 1) - 1, coy = (oy >> 1) - 1;
+  WinLoad<T> L;
+  L.fetch(g, a.code, a.phi_in, a.b, off, ox, oy);
+  // coarse correction window [cox, cox + 36) x [coy, coy + CH)
+  {
+    constexpr int NCR = (CH + 3) / 4;
+    T vc[NCR];
+    unsigned char cc[NCR];
+    const int I = cox + col;
+#pragma unroll
+    for (int m = 0; m < NCR; ++m) {
+      const int r = w + 4 * m, J = coy + r;
+      vc[m] = (T)0;
+      cc[m] = 0;
+      if (col < CW && r < CH && I >= 0 && I < gc.nx && J >= 0 && J < gc.ny) {
+        const long at = gc.at(I, J);
+        cc[m] = a.codec[at];
+        vc[m] = pc[at];
       }
     }
+#pragma unroll
+    for (int m = 0; m < NCR; ++m)
+      if (!cc[m]) vc[m] = (T)0;
+#pragma unroll
+    for (int m = 0; m < NCR; ++m) {
+      const int r = w + 4 * m;
+      if (col < CW && r < CH) {
+        scw[r * CW + col] = vc[m];
+        sccode[r * CW + col] = cc[m];
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int i = ox + col;
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m;
+      if (r >= W::LH) continue;
+      const int j = oy + r;
+      T p = (T)0;
+      if (L.vc[m]) {
+        // bilinear prolongation: Neumann mirror at walls, sign flip across the outflow face
+        const int I = i >> 1, J = j >> 1;
+        const int IX = I + ((i & 1) ? 1 : -1), JY = J + ((j & 1) ? 1 : -1);
+        const int cI = I - cox, cJ = J - coy, cX = IX - cox, cY = JY - coy;
+        const T P = scw[cJ * CW + cI];
+        const T X = sccode[cJ * CW + cX] ? scw[cJ * CW + cX] : (IX == gc.nx ? -P : P);
+        const T Y = sccode[cY * CW + cI] ? scw[cY * CW + cI] : P;
+        const T D = sccode[cY * CW + cX] ? scw[cY * CW + cX] : X + Y - P;
+        p = L.vp[m] + ((T)9 * P + (T)3 * (X + Y) + D) * (T)0.0625;
+      }
+      const int x = W::idx(r, col);
+      sp[x] = p;
+      sb[x] = L.vb[m];
+      scode[x] = L.vc[m];
+    }
+  }
+  __syncthreads();
+  const T h2 = (T)(g.h * g.h);
+  Items<T> it;
+  it.init(sb, scode, h2);
+  for (int s = 0; s < NS; ++s) it.sweep(sp);
+  if (NORM && a.write_norm) {
+    double m = 0.0;
+    const double sc = a.dt / (g.h * g.h);
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int n = 0; n < W::NIT; ++n) {
+        const int r = it.row(n), cl = it.col(c);
+        if (it.invd[c][n] != (T)0 && r >= W::H && r < W::H + W::TH && cl >= W::H && cl < W::H + W::TWI) {
+          const double rr = fabs((double)it.resid_h2(sp, c, n)) * sc;
+          m = (rr > m || rr != rr) ? rr : m;
+        }
+      }
     m = wave_max(m);
-    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = m;
+    if ((threadIdx.x & 63) == 0) red[w] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
       double mm = red[0];
-      for (int w = 1; w < 4; ++w) mm = (red[w] > mm || red[w] != red[w]) ? red[w] : mm;
+      for (int q = 1; q < 4; ++q) mm = (red[q] > mm || red[q] != red[q]) ? red[q] : mm;
       atomicMax((unsigned long long*)&a.norms[(long)mem * a.norm_slots + a.k], dbits(mm));
     }
   }
-  for (int k = threadIdx.x; k < TW * TH; k += 256) {
-    const int c = H + k % TW, r = H + k / TW;
-    const int i = ox + c, j = oy + r;
-    if (g.fluid(i, j)) {
-      if (a.add_to)
-        a.add_to[off + g.at(i, j)] += (double)sp[r * LW + c];
-      else
-        a.phi_out[off + g.at(i, j)] = sp[r * LW + c];
+  const int i = ox + col;
+  if (col >= W::H && col < W::H + W::TWI && i < g.nx) {
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m;
+      const int j = oy + r;
+      if (r >= W::H && r < W::H + W::TH && j < g.ny) {
+        const int x = W::idx(r, col);
+        if (scode[x]) {
+          if (a.add_to)
+            a.add_to[off + g.at(i, j)] += (double)sp[x];
+          else
+            a.phi_out[off + g.at(i, j)] = sp[x];
+        }
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------- coarse levels in LDS
 constexpr int COARSE_LDS = 2 * (64 * 32 + 32 * 16 + 16 * 8);
+constexpr int COARSE_THREADS = 512;
 
 __device__ __forceinline__ void lds_sweep(double* p, const double* b, const Geo& g, double h2) {
-  const int nx = g.nx, ncell = g.nx * g.ny;
+  const int nx = g.nx, hx = g.nx / 2, half = hx * g.ny;
   for (int color = 0; color < 2; ++color) {
-    for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
-      const int i = q % nx, j = q / nx;
-      if (((i + j) & 1) != color || !g.fluid(i, j)) continue;
+    for (int q = threadIdx.x; q < half; q += blockDim.x) {
+      const int j = q / hx;
+      const int i = 2 * (q % hx) + ((color ^ j) & 1);
+      if (!g.fluid(i, j)) continue;
+      const int x = j * nx + i;
       double s = 0.0;
-      if (g.fluid(i - 1, j)) s += p[q - 1];
-      if (g.fluid(i + 1, j)) s += p[q + 1];
-      if (g.fluid(i, j - 1)) s += p[q - nx];
-      if (g.fluid(i, j + 1)) s += p[q + nx];
-      p[q] = (s - h2 * b[q]) / (double)g.diag_count(i, j);
+      if (g.fluid(i - 1, j)) s += p[x - 1];
+      if (g.fluid(i + 1, j)) s += p[x + 1];
+      if (g.fluid(i, j - 1)) s += p[x - nx];
+      if (g.fluid(i, j + 1)) s += p[x + nx];
+      p[x] = (s - h2 * b[x]) * inv_diag<double>(g.diag_count(i, j));
     }
     __syncthreads();
   }
@@ -213,10 +395,48 @@ __device__ __forceinline__ double lds_resid(const double* p, const double* b, co
   return b[q] - (s - (double)g.diag_count(i, j) * p[q]) * inv_h2;
 }
 
+// restriction of the residual of level g (p, b) into the right-hand side of level c, zero guess on c
+__device__ __forceinline__ void lds_restrict(const double* p, const double* b, const Geo& g, double* pc, double* bc,
+                                             const Geo& c) {
+  const double inv_h2 = 1.0 / (g.h * g.h);
+  for (int q = threadIdx.x; q < c.nx * c.ny; q += blockDim.x) {
+    const int I = q % c.nx, J = q / c.nx;
+    double rs = 0.0;
+    if (c.fluid(I, J))
+      for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) rs += lds_resid(p, b, g, 2 * I + di, 2 * J + dj, inv_h2);
+    bc[q] = 0.25 * rs;
+    pc[q] = 0.0;
+  }
+  __syncthreads();
+}
+
+// bilinear prolongation of the correction on level c into level g
+__device__ __forceinline__ void lds_prolong(double* p, const Geo& g, const double* pc, const Geo& c) {
+  for (int q = threadIdx.x; q < g.nx * g.ny; q += blockDim.x) {
+    const int i = q % g.nx, j = q / g.nx;
+    if (!g.fluid(i, j)) continue;
+    const int I = i >> 1, J = j >> 1;
+    const int IX = I + ((i & 1) ? 1 : -1), JY = J + ((j & 1) ? 1 : -1);
+    const double Pv = pc[J * c.nx + I];
+    const double X = c.fluid(IX, J) ? pc[J * c.nx + IX] : (IX == c.nx ? -Pv : Pv);
+    const double Y = c.fluid(I, JY) ? pc[JY * c.nx + I] : Pv;
+    const double D = c.fluid(IX, JY) ? pc[JY * c.nx + IX] : X + Y - Pv;
+    p[q] += (9.0 * Pv + 3.0 * (X + Y) + D) * 0.0625;
+  }
+  __syncthreads();
+}
+
+// The levels inv_h = 16, 8, 4 of one member in one workgroup, all resident in
+// LDS: V-cycle with NS red-black sweeps per level and a dense solve of the
+// h = 1/4 operator through its inverse. The three levels are unrolled at
+// compile time so that every geometry predicate stays in registers.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mg_coarse(CoarseArgs a) {
+__global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(CoarseArgs a) {
   __shared__ double lds[COARSE_LDS];
-  __shared__ double red[4];
+  __shared__ double sinv[COARSE_INV_MAX];
+  __shared__ double sbc[MAX_COARSE_UNKNOWNS];
+  __shared__ double red[COARSE_THREADS / 64];
   const int mem = blockIdx.x;
   if (a.k > 0 && a.norms != nullptr) {
     const double prev = a.norms[(long)mem * a.norm_slots + a.k - 1];
@@ -225,86 +445,72 @@ __global__ __launch_bounds__(256) void k_mg_coarse(CoarseArgs a) {
       return;
     }
   }
-  Geo gl[6];
-  double* P[6];
-  double* B[6];
-  gl[0] = a.g;
-  int offs = 0;
-  for (int l = 0; l < a.nlev; ++l) {
-    if (l > 0) gl[l] = gl[l - 1].coarser();
-    const int nc = gl[l].nx * gl[l].ny;
-    P[l] = lds + offs;
-    B[l] = lds + offs + nc;
-    offs += 2 * nc;
-  }
+  const Geo g0 = a.g;
+  const Geo g1 = g0.coarser();
+  const Geo g2 = g1.coarser();
+  const int n0 = g0.nx * g0.ny, n1 = g1.nx * g1.ny, n2 = g2.nx * g2.ny;
+  double* P0 = lds;
+  double* B0 = P0 + n0;
+  double* P1 = B0 + n0;
+  double* B1 = P1 + n1;
+  double* P2 = B1 + n1;
+  double* B2 = P2 + n2;
   const long off = (long)mem * a.plane;
   const T* gphi = (const T*)a.phi + off;
   const T* gb = (const T*)a.b + off;
   {
-    const Geo& g = gl[0];
-    for (int q = threadIdx.x; q < g.nx * g.ny; q += 256) {
-      const int i = q % g.nx, j = q / g.nx;
-      const bool fl = g.fluid(i, j);
-      P[0][q] = (fl && a.warm) ? (double)gphi[g.at(i, j)] : 0.0;
-      B[0][q] = fl ? (double)gb[g.at(i, j)] : 0.0;
+    constexpr int NL = (64 * 32 + COARSE_THREADS - 1) / COARSE_THREADS;
+    double vp[NL], vb[NL];
+#pragma unroll
+    for (int n = 0; n < NL; ++n) {
+      const int q = threadIdx.x + COARSE_THREADS * n;
+      vp[n] = 0.0;
+      vb[n] = 0.0;
+      if (q < n0) {
+        const int i = q % g0.nx, j = q / g0.nx;
+        if (g0.fluid(i, j)) {
+          vb[n] = (double)gb[g0.at(i, j)];
+          if (a.warm) vp[n] = (double)gphi[g0.at(i, j)];
+        }
+      }
+    }
+    // the transposed inverse of the coarsest operator, read once per workgroup
+    const int ninv = a.nc * a.nc;
+    for (int q = threadIdx.x; q < ninv; q += COARSE_THREADS) sinv[q] = a.ainv[q];
+#pragma unroll
+    for (int n = 0; n < NL; ++n) {
+      const int q = threadIdx.x + COARSE_THREADS * n;
+      if (q < n0) {
+        P0[q] = vp[n];
+        B0[q] = vb[n];
+      }
     }
   }
   __syncthreads();
-  const int L = a.nlev - 1;
-  for (int l = 0; l < L; ++l) {
-    const Geo& g = gl[l];
-    const double h2 = g.h * g.h, inv_h2 = 1.0 / h2;
-    for (int s = 0; s < a.nsweep_pre; ++s) lds_sweep(P[l], B[l], g, h2);
-    const Geo& c = gl[l + 1];
-    for (int q = threadIdx.x; q < c.nx * c.ny; q += 256) {
-      const int I = q % c.nx, J = q / c.nx;
-      double rs = 0.0;
-      if (c.fluid(I, J))
-        for (int dj = 0; dj < 2; ++dj)
-          for (int di = 0; di < 2; ++di) rs += lds_resid(P[l], B[l], g, 2 * I + di, 2 * J + dj, inv_h2);
-      B[l + 1][q] = 0.25 * rs;
-      P[l + 1][q] = 0.0;
-    }
-    __syncthreads();
+  for (int s = 0; s < a.nsweep_pre; ++s) lds_sweep(P0, B0, g0, g0.h * g0.h);
+  lds_restrict(P0, B0, g0, P1, B1, g1);
+  for (int s = 0; s < a.nsweep_pre; ++s) lds_sweep(P1, B1, g1, g1.h * g1.h);
+  lds_restrict(P1, B1, g1, P2, B2, g2);
+  // dense solve on the coarsest level: sinv holds the inverse transposed, thread q reads column q
+  for (int q = threadIdx.x; q < a.nc; q += COARSE_THREADS) sbc[q] = B2[a.aidx[q]];
+  __syncthreads();
+  for (int q = threadIdx.x; q < a.nc; q += COARSE_THREADS) {
+    double s = 0.0;
+    for (int r = 0; r < a.nc; ++r) s += sinv[r * a.nc + q] * sbc[r];
+    P2[a.aidx[q]] = s;
   }
-  // dense solve on the coarsest level
-  {
-    const Geo& g = gl[L];
-    for (int q = threadIdx.x; q < a.nc; q += 256) {
-      double s = 0.0;
-      for (int r = 0; r < a.nc; ++r) s += a.ainv[(long)q * a.nc + r] * B[L][a.aidx[r]];
-      P[L][a.aidx[q]] = s;
-    }
-    (void)g;
-    __syncthreads();
-  }
-  for (int l = L - 1; l >= 0; --l) {
-    const Geo& g = gl[l];
-    const Geo& c = gl[l + 1];
-    for (int q = threadIdx.x; q < g.nx * g.ny; q += 256) {
-      const int i = q % g.nx, j = q / g.nx;
-      if (!g.fluid(i, j)) continue;
-      const int I = i >> 1, J = j >> 1;
-      const int IX = I + ((i & 1) ? 1 : -1), JY = J + ((j & 1) ? 1 : -1);
-      const double* pc = P[l + 1];
-      const double Pv = pc[J * c.nx + I];
-      const double X = c.fluid(IX, J) ? pc[J * c.nx + IX] : (IX == c.nx ? -Pv : Pv);
-      const double Y = c.fluid(I, JY) ? pc[JY * c.nx + I] : Pv;
-      const double D = c.fluid(IX, JY) ? pc[JY * c.nx + IX] : X + Y - Pv;
-      P[l][q] += (9.0 * Pv + 3.0 * (X + Y) + D) * 0.0625;
-    }
-    __syncthreads();
-    const double h2 = g.h * g.h;
-    for (int s = 0; s < a.nsweep_post; ++s) lds_sweep(P[l], B[l], g, h2);
-  }
-  const Geo& g = gl[0];
+  __syncthreads();
+  lds_prolong(P1, g1, P2, g2);
+  for (int s = 0; s < a.nsweep_post; ++s) lds_sweep(P1, B1, g1, g1.h * g1.h);
+  lds_prolong(P0, g0, P1, g1);
+  for (int s = 0; s < a.nsweep_post; ++s) lds_sweep(P0, B0, g0, g0.h * g0.h);
   if (a.write_norm) {
-    const double inv_h2 = 1.0 / (g.h * g.h);
+    const double inv_h2 = 1.0 / (g0.h * g0.h);
     double m = 0.0;
-    for (int q = threadIdx.x; q < g.nx * g.ny; q += 256) {
-      const int i = q % g.nx, j = q / g.nx;
-      if (g.fluid(i, j)) {
-        const double rr = fabs(lds_resid(P[0], B[0], g, i, j, inv_h2)) * a.dt;
+    for (int q = threadIdx.x; q < n0; q += COARSE_THREADS) {
+      const int i = q % g0.nx, j = q / g0.nx;
+      if (g0.fluid(i, j)) {
+        const double rr = fabs(lds_resid(P0, B0, g0, i, j, inv_h2)) * a.dt;
         m = (rr > m || rr != rr) ? rr : m;
       }
     }
@@ -313,18 +519,18 @@ __global__ __launch_bounds__(256) void k_mg_coarse(CoarseArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) {
       double mm = red[0];
-      for (int w = 1; w < 4; ++w) mm = (red[w] > mm || red[w] != red[w]) ? red[w] : mm;
+      for (int w = 1; w < COARSE_THREADS / 64; ++w) mm = (red[w] > mm || red[w] != red[w]) ? red[w] : mm;
       a.norms[(long)mem * a.norm_slots + a.k] = mm;
     }
   }
   T* wphi = (T*)a.phi + off;
-  for (int q = threadIdx.x; q < g.nx * g.ny; q += 256) {
-    const int i = q % g.nx, j = q / g.nx;
-    if (!g.fluid(i, j)) continue;
+  for (int q = threadIdx.x; q < n0; q += COARSE_THREADS) {
+    const int i = q % g0.nx, j = q / g0.nx;
+    if (!g0.fluid(i, j)) continue;
     if (a.add_to)
-      a.add_to[off + g.at(i, j)] += P[0][q];
+      a.add_to[off + g0.at(i, j)] += P0[q];
     else
-      wphi[g.at(i, j)] = (T)P[0][q];
+      wphi[g0.at(i, j)] = (T)P0[q];
   }
 }
 
@@ -377,33 +583,21 @@ __global__ __launch_bounds__(256) void k_resid64(ResidArgs a) {
 // ---------------------------------------------------------------------------- launchers
 template <typename T>
 void launch_mg_pre(const MGArgs<T>& a, int nsweep, hipStream_t s) {
-  const dim3 grid(a.ntiles * a.nmem), block(256);
-  switch (nsweep) {
-    case 1: hipLaunchKernelGGL((k_mg_pre<T, 1>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_mg_pre<T, 3>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_mg_pre<T, 2>), grid, block, 0, s, a); break;
-  }
+  (void)nsweep;  // the window halo is sized for MG_NS sweeps
+  hipLaunchKernelGGL((k_mg_pre<T, MG_NS>), dim3(a.ntiles * a.nmem), dim3(256), 0, s, a);
 }
 template <typename T>
 void launch_mg_post(const MGArgs<T>& a, int nsweep, hipStream_t s) {
+  (void)nsweep;
   const dim3 grid(a.ntiles * a.nmem), block(256);
-  if (a.write_norm) {
-    switch (nsweep) {
-      case 1: hipLaunchKernelGGL((k_mg_post<T, 1, 1>), grid, block, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_mg_post<T, 3, 1>), grid, block, 0, s, a); break;
-      default: hipLaunchKernelGGL((k_mg_post<T, 2, 1>), grid, block, 0, s, a); break;
-    }
-  } else {
-    switch (nsweep) {
-      case 1: hipLaunchKernelGGL((k_mg_post<T, 1, 0>), grid, block, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_mg_post<T, 3, 0>), grid, block, 0, s, a); break;
-      default: hipLaunchKernelGGL((k_mg_post<T, 2, 0>), grid, block, 0, s, a); break;
-    }
-  }
+  if (a.write_norm)
+    hipLaunchKernelGGL((k_mg_post<T, MG_NS, 1>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_mg_post<T, MG_NS, 0>), grid, block, 0, s, a);
 }
 template <typename T>
 void launch_mg_coarse(const CoarseArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_mg_coarse<T>, dim3(a.nmem), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mg_coarse<T>, dim3(a.nmem), dim3(COARSE_THREADS), 0, s, a);
 }
 void launch_resid64(const ResidArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_resid64, dim3(a.ntiles * a.nmem), dim3(256), 0, s, a);

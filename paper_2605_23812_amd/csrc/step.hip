@@ -51,13 +51,28 @@ __global__ __launch_bounds__(256) void k_predictor(PredArgs<TT> a) {
   if (tile == 0 && a.norms != nullptr)
     for (int k = tid; k < a.norm_slots; k += 256) a.norms[(long)mem * a.norm_slots + k] = 0.0;
 
-  for (int k = tid; k < UH * UW; k += 256) {
-    const int i = x0 - 1 + k % UW, j = y0 - 1 + k / UW;
-    su[k] = (i >= 0 && i <= g.nx && j >= 0 && j < g.ny) ? u[g.at(i, j)] : 0.0;
-  }
-  for (int k = tid; k < VH * VW; k += 256) {
-    const int i = x0 - 1 + k % VW, j = y0 - 1 + k / VW;
-    sv[k] = (i >= 0 && i < g.nx && j >= 0 && j <= g.ny) ? v[g.at(i, j)] : 0.0;
+  {
+    // all global loads of the halo first, then the LDS stores
+    constexpr int NU = (UH * UW + 255) / 256, NV = (VH * VW + 255) / 256;
+    double lu[NU], lv[NV];
+#pragma unroll
+    for (int n = 0; n < NU; ++n) {
+      const int k = tid + 256 * n;
+      const int i = x0 - 1 + k % UW, j = y0 - 1 + k / UW;
+      lu[n] = (k < UH * UW && i >= 0 && i <= g.nx && j >= 0 && j < g.ny) ? u[g.at(i, j)] : 0.0;
+    }
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+      const int k = tid + 256 * n;
+      const int i = x0 - 1 + k % VW, j = y0 - 1 + k / VW;
+      lv[n] = (k < VH * VW && i >= 0 && i < g.nx && j >= 0 && j <= g.ny) ? v[g.at(i, j)] : 0.0;
+    }
+#pragma unroll
+    for (int n = 0; n < NU; ++n)
+      if (tid + 256 * n < UH * UW) su[tid + 256 * n] = lu[n];
+#pragma unroll
+    for (int n = 0; n < NV; ++n)
+      if (tid + 256 * n < VH * VW) sv[tid + 256 * n] = lv[n];
   }
   __syncthreads();
 #define SU(i, j) su[((j) - y0 + 1) * UW + ((i) - x0 + 1)]
@@ -69,7 +84,10 @@ __global__ __launch_bounds__(256) void k_predictor(PredArgs<TT> a) {
 
   // u faces i in [x0, x0+TW], j in [y0, y0+TH): the face i = x0+TW is the east
   // face of the tile, computed here for the divergence and owned by the next tile.
-  for (int k = tid; k < TH * (TW + 1); k += 256) {
+#pragma unroll
+  for (int kk = 0; kk < (TH * (TW + 1) + 255) / 256; ++kk) {
+    const int k = tid + 256 * kk;
+    if (k >= TH * (TW + 1)) break;
     const int c = k % (TW + 1), r = k / (TW + 1);
     const int i = x0 + c, j = y0 + r;
     double us = 0.0;
@@ -107,7 +125,10 @@ __global__ __launch_bounds__(256) void k_predictor(PredArgs<TT> a) {
     sus[r * (TW + 1) + c] = us;
   }
   // v faces i in [x0, x0+TW), j in [y0, y0+TH]
-  for (int k = tid; k < (TH + 1) * TW; k += 256) {
+#pragma unroll
+  for (int kk = 0; kk < ((TH + 1) * TW + 255) / 256; ++kk) {
+    const int k = tid + 256 * kk;
+    if (k >= (TH + 1) * TW) break;
     const int c = k % TW, r = k / TW;
     const int i = x0 + c, j = y0 + r;
     double vs = 0.0;
@@ -182,7 +203,9 @@ __global__ __launch_bounds__(256) void k_project_cost(ProjArgs a) {
   const double dt = a.dt, inv_h = 1.0 / g.h;
   const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
   double acc = 0.0, dmax = 0.0;
-  for (int r = ty; r < TH; r += 4) {
+#pragma unroll
+  for (int rr = 0; rr < TH / 4; ++rr) {
+    const int r = ty + 4 * rr;
     const int i = x0 + tx, j = y0 + r;
     if (!g.fluid(i, j)) continue;
     const long at = g.at(i, j);
@@ -213,6 +236,7 @@ __global__ __launch_bounds__(256) void k_project_cost(ProjArgs a) {
     } else {
       vn = v[g.at(i, j + 1)];
     }
+    if (a.phi_next) a.phi_next[off + at] = 2.0 * pc - a.phi_next[off + at];
     const double div = fabs((ue - uw + vn - vsv) * inv_h);
     dmax = (div > dmax || div != div) ? div : dmax;
     if (a.s1u) {
@@ -319,6 +343,7 @@ __global__ __launch_bounds__(256) void k_init_members(InitArgs<TT> a) {
     a.tu[off + k] = (TT)a.btu[k];
     a.tv[off + k] = (TT)a.btv[k];
     a.phi[off + k] = a.bphi[k];
+    a.phi2[off + k] = a.bphi[k];
   }
   const long coff = (long)mem * a.cplane;
   if (a.s1u)

@@ -19,6 +19,7 @@ CAVITY, CHANNEL = 0, 1
 REGION_COLUMN, REGION_CAVITY, REGION_BOX = 0, 1, 2
 FP64, MIXED = 0, 1
 FLAG_TIME_KERNELS = 1
+FLAG_NO_GRAPHS = 2
 
 EXPORTS = (
     "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",

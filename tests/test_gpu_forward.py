@@ -160,3 +160,21 @@ def test_channel_geometry_keeps_discrete_poiseuille():
     disc = a * (y * (1 - y) + h * h / 4)
     assert np.abs(u[:, 3 * n:] - disc[:, None]).max() < 1e-8
     _say("poiseuille stats", stats)
+
+
+@pytest.mark.parametrize("precision", [E.FP64, E.MIXED])
+def test_graph_replay_matches_eager_launches(precision):
+    """Steady steps replay captured HIP graphs; every replay must equal the eager launch sequence.
+
+    The forward is long enough for many replays of both parity graphs, and the
+    eager run (no graphs) is interleaved with them on the same stream.
+    """
+    p = E.Problem(inv_h=32, Re=4000.0, precision=precision)
+    pe = E.Problem(inv_h=32, Re=4000.0, precision=precision, flags=E.FLAG_NO_GRAPHS)
+    op, st = _base(32, 4000.0, 60)
+    rows = _rows(p, 3, 0.1, 1e-2, seed=5)
+    for horizon in (20, 57):
+        Jg, (ug, vg), sg = _gpu_forward(p, st, rows, horizon)
+        Je, (ue, ve), se = _gpu_forward(pe, st, rows, horizon)
+        _say("graph vs eager", horizon, Jg, Je, sg["mean_cycles"], se["mean_cycles"])
+        assert np.array_equal(Jg, Je) and np.array_equal(ug, ue) and np.array_equal(vg, ve)
