@@ -158,6 +158,30 @@ int envar_forward(const envar_problem* p, const void* state_dev, const double* c
                   int32_t n_rows, int64_t m, int32_t horizon, void* ws_dev, size_t ws_bytes,
                   double* J_dev, double* fields_dev, envar_stats* stats, void* stream);
 
+/* One ensemble of a batched forward (envar_forward_batch). */
+typedef struct {
+  envar_problem problem;     /* its own grid, Re, region, dt; precision must match across the batch */
+  const void* state_dev;     /* its base state (envar_state_init) */
+  const double* controls_dev;/* [n_rows][m] */
+  int32_t n_rows;
+  int32_t horizon;           /* its own number of steps */
+  int64_t m;
+  void* ws_dev;              /* envar_workspace_bytes(&problem, n_rows) bytes */
+  size_t ws_bytes;
+  double* J_dev;             /* [n_rows] */
+  envar_stats* stats;        /* optional (the call then synchronises) */
+} envar_job;
+
+/* Uneven batching: up to 8 ensembles that differ in grid size, Reynolds
+ * number, member count and horizon advance together, every kernel launch
+ * carrying one segment per ensemble (the N+1 forward evaluations of several
+ * EnVar iterations at once, Sec. 5.3). An ensemble leaves the batch when its
+ * horizon is reached. Results equal those of separate envar_forward calls
+ * (per-member convergence). Errors: EINVAL (njobs outside [1, 8], mixed
+ * precisions, bad shapes), ENOMEM, EDIVERGED (stats requested and a cost is
+ * non-finite). */
+int envar_forward_batch(envar_job* jobs, int32_t njobs, void* stream);
+
 /* Device bytes of the workspace of envar_gradient. */
 size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
 

@@ -284,25 +284,6 @@ static const T* at(const void* base, size_t off) {
   return (const T*)((const char*)base + off);
 }
 
-// pinned host staging for the asynchronous cycle-cap monitor
-struct Pinned {
-  double* p = nullptr;
-  size_t n = 0;
-  ~Pinned() {
-    if (p) (void)hipHostFree(p);
-  }
-  double* get(size_t need) {
-    if (need > n) {
-      if (p) (void)hipHostFree(p);
-      p = nullptr;
-      n = 0;
-      if (hipHostMalloc((void**)&p, need * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
-      n = need;
-    }
-    return p;
-  }
-};
-static thread_local Pinned g_pinned;
 
 // HIP-event sampling of the main kernels on the call's stream
 enum { TM_PRED = 0, TM_PRE = 1, TM_POST = 2, TM_RESID = 3, TM_PROJ = 4, TM_CYCLE = 5, TM_N = 6 };
@@ -338,251 +319,383 @@ struct Timer {
   }
 };
 
-// ---------------------------------------------------------------------------- the time loop
-struct Run {
-  const Plan* P;
-  void* ws;
-  const WS* w;
-  int nmem;
-  const void* state;
-  const double* ctrl;  // NULL = unforced
-  hipStream_t s;
-  Timer* tm;
+// ---------------------------------------------------------------------------- jobs and merged launches
+// A job is one ensemble: a problem, its base state, its workspace and its
+// control rows. A batch advances several jobs by one time step each with one
+// launch per phase (predictor, every multigrid level, coarse solve,
+// refinement residual, projection, bookkeeping): each launch carries one
+// segment per job, and jobs may differ in grid, Reynolds number, member count,
+// horizon and multigrid depth. A single forward is a batch of one job.
+struct Job {
+  Plan P;
+  WS w;
+  void* ws = nullptr;
+  const void* state = nullptr;
+  const double* ctrl = nullptr;
+  int nmem = 0;
+  int horizon = 0;
+  int step = 0;            // steps launched so far
+  bool cold_first = true;  // the state's cold-start flag applies to step 0
+  int last_cur = 0;        // pressure buffer of the last solved step
+  template <typename T>
+  T* w_(size_t off) const {
+    return at<T>(ws, off);
+  }
+  double* phi(int k) const { return w_<double>(k ? w.phiC : w.phiA); }
 };
 
+template <typename A>
+static void seg_add(Multi<A>& m, const A& a, int wgs) {
+  m.seg[m.nseg] = a;
+  m.start[m.nseg + 1] = m.start[m.nseg] + wgs;
+  ++m.nseg;
+}
+template <typename A>
+static Multi<A> seg_begin() {
+  Multi<A> m;
+  std::memset((void*)&m, 0, sizeof m);
+  return m;
+}
+
 template <typename TT>
-static int pressure_solve(const Run& R, int cap, double* phi_cur) {
-  const Plan& P = *R.P;
-  const WS& w = *R.w;
-  void* ws = R.ws;
-  const int L = P.nlev_grid;
-  double* norms = at<double>(ws, w.norms);
+static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
   typedef TT T;  // V-cycle type
-  auto level_args = [&](int l) {
+  const bool mixed = J[0]->P.mixed;
+  int Lmax = 0;
+  for (Job* j : J) Lmax = std::max(Lmax, j->P.nlev_grid);
+  auto level_args = [&](const Job& j, int l, int k) {
+    const Plan& P = j.P;
     MGArgs<T> a{};
     a.g = P.lev[l];
     a.gc = P.lev[l + 1];
     a.tiling = P.mg_tl[l];
     a.ntiles = P.mg_tiles[l];
-    a.nmem = R.nmem;
+    a.nmem = j.nmem;
     a.plane = P.lev[l].plane();
     a.cplane_c = P.lev[l + 1].plane();
-    a.norms = norms;
+    a.norms = j.w_<double>(j.w.norms);
     a.norm_slots = P.norm_slots;
     a.tol = P.tol;
     a.dt = P.dt;
-    a.code = at<unsigned char>(R.state, P.s_code[l]);
-    a.codec = at<unsigned char>(R.state, P.s_code[l + 1]);
+    a.code = at<unsigned char>(j.state, P.s_code[l]);
+    a.codec = at<unsigned char>(j.state, P.s_code[l + 1]);
+    a.k = k;
     return a;
   };
-  auto coarse_args = [&](int k) {
-    CoarseArgs c{};
-    c.g = P.lev[L];
-    c.nlev = P.ncoarse;
-    c.nmem = R.nmem;
-    c.plane = P.lev[L].plane();
-    c.ainv = at<double>(R.state, P.s_ainv);
-    c.aidx = at<int>(R.state, P.s_aidx);
-    c.nc = P.nc;
-    c.norms = norms;
-    c.norm_slots = P.norm_slots;
-    c.k = k;
-    c.tol = P.tol;
-    c.dt = P.dt;
-    c.nsweep_pre = 2;
-    c.nsweep_post = 2;
-    return c;
-  };
-  // one V-cycle from level 0 (right-hand side b0v, in/out phi0in -> phi0out)
-  Timer* tm = R.tm;
-  const int k_timed = P.mixed ? 1 : 0;
-  auto vcycle = [&](int k, const T* b0v, const T* phi0in, T* phi0out, double* add_to, int zero_guess, int write_norm) {
+  const int k_timed = mixed ? 1 : 0;
+  auto vcycle = [&](int k) {
     const bool timed = tm && k == k_timed;
-    if (timed) tm->mark(TM_CYCLE, 0, R.s);
-    if (L == 0) {
-      CoarseArgs c = coarse_args(k);
-      c.phi = (void*)phi0out;
-      c.b = b0v;
-      c.warm = !zero_guess;
-      c.write_norm = write_norm;
-      c.add_to = add_to;
-      launch_mg_coarse<T>(c, R.s);
-      return;
-    }
-    for (int l = 0; l < L; ++l) {
-      MGArgs<T> a = level_args(l);
-      a.k = k;
-      if (l == 0) {
-        a.phi_in = phi0in;
-        a.b = b0v;
-        a.zero_guess = zero_guess;
-        a.phi_out = (T*)(P.mixed ? at<float>(ws, w.e0) : nullptr);
-        if (!P.mixed) a.phi_out = (T*)at<double>(ws, w.phiB);
-      } else {
-        a.phi_in = nullptr;
-        a.b = at<T>(ws, w.lb[l]);
-        a.zero_guess = 1;
-        a.phi_out = at<T>(ws, w.lphiB[l]);
+    if (timed) tm->mark(TM_CYCLE, 0, st);
+    for (int l = 0; l < Lmax; ++l) {
+      auto m = seg_begin<MGArgs<T>>();
+      for (Job* j : J) {
+        if (l >= j->P.nlev_grid) continue;
+        const WS& w = j->w;
+        MGArgs<T> a = level_args(*j, l, k);
+        if (l == 0) {
+          const int cur = j->step & 1;
+          a.phi_in = mixed ? nullptr : (const T*)j->phi(cur);
+          a.b = mixed ? (const T*)j->w_<float>(w.r0) : (const T*)j->w_<double>(w.b0);
+          a.zero_guess = mixed ? 1 : 0;
+          a.phi_out = mixed ? (T*)j->w_<float>(w.e0) : (T*)j->w_<double>(w.phiB);
+        } else {
+          a.phi_in = nullptr;
+          a.b = j->w_<T>(w.lb[l]);
+          a.zero_guess = 1;
+          a.phi_out = j->w_<T>(w.lphiB[l]);
+        }
+        a.bc = j->w_<T>(w.lb[l + 1]);
+        seg_add(m, a, a.ntiles * a.nmem);
       }
-      a.bc = at<T>(ws, w.lb[l + 1]);
-      if (timed && l == 0) tm->mark(TM_PRE, 0, R.s);
-      launch_mg_pre<T>(a, 2, R.s);
-      if (timed && l == 0) tm->mark(TM_PRE, 1, R.s);
+      if (timed && l == 0) tm->mark(TM_PRE, 0, st);
+      launch_mg_pre<T>(m, st);
+      if (timed && l == 0) tm->mark(TM_PRE, 1, st);
     }
-    CoarseArgs c = coarse_args(k);
-    c.phi = at<T>(ws, w.lphiA[L]);
-    c.b = at<T>(ws, w.lb[L]);
-    c.warm = 0;
-    c.write_norm = 0;
-    launch_mg_coarse<T>(c, R.s);
-    for (int l = L - 1; l >= 0; --l) {
-      MGArgs<T> a = level_args(l);
-      a.k = k;
-      a.phic = at<T>(ws, w.lphiA[l + 1]);
-      if (l == 0) {
-        a.phi_in = P.mixed ? (const T*)at<float>(ws, w.e0) : (const T*)at<double>(ws, w.phiB);
-        a.b = b0v;
-        a.phi_out = phi0out;
-        a.add_to = add_to;
-        a.write_norm = write_norm;
-      } else {
-        a.phi_in = at<T>(ws, w.lphiB[l]);
-        a.b = at<T>(ws, w.lb[l]);
-        a.phi_out = at<T>(ws, w.lphiA[l]);
+    {
+      auto m = seg_begin<CoarseArgs>();
+      for (Job* j : J) {
+        const Plan& P = j->P;
+        const WS& w = j->w;
+        const int L = P.nlev_grid;
+        CoarseArgs c{};
+        c.g = P.lev[L];
+        c.nlev = P.ncoarse;
+        c.nmem = j->nmem;
+        c.plane = P.lev[L].plane();
+        c.ainv = at<double>(j->state, P.s_ainv);
+        c.aidx = at<int>(j->state, P.s_aidx);
+        c.nc = P.nc;
+        c.norms = j->w_<double>(w.norms);
+        c.norm_slots = P.norm_slots;
+        c.k = k;
+        c.tol = P.tol;
+        c.dt = P.dt;
+        c.nsweep_pre = MG_NS;
+        c.nsweep_post = MG_NS;
+        if (L == 0) {  // the whole V-cycle runs in LDS
+          const int cur = j->step & 1;
+          if (mixed) {
+            c.phi = j->w_<float>(w.e0);
+            c.b = j->w_<float>(w.r0);
+            c.add_to = j->phi(cur);
+          } else {
+            c.phi = j->phi(cur);
+            c.b = j->w_<double>(w.b0);
+            c.warm = 1;
+            c.write_norm = 1;
+          }
+        } else {
+          c.phi = j->w_<T>(w.lphiA[L]);
+          c.b = j->w_<T>(w.lb[L]);
+        }
+        seg_add(m, c, j->nmem);
       }
-      if (timed && l == 0) tm->mark(TM_POST, 0, R.s);
-      launch_mg_post<T>(a, 2, R.s);
-      if (timed && l == 0) tm->mark(TM_POST, 1, R.s);
+      launch_mg_coarse<T>(m, st);
     }
-    if (timed && !P.mixed) tm->mark(TM_CYCLE, 1, R.s);
+    for (int l = Lmax - 1; l >= 0; --l) {
+      auto m = seg_begin<MGArgs<T>>();
+      for (Job* j : J) {
+        if (l >= j->P.nlev_grid) continue;
+        const WS& w = j->w;
+        MGArgs<T> a = level_args(*j, l, k);
+        a.phic = j->w_<T>(w.lphiA[l + 1]);
+        if (l == 0) {
+          const int cur = j->step & 1;
+          a.phi_in = mixed ? (const T*)j->w_<float>(w.e0) : (const T*)j->w_<double>(w.phiB);
+          a.b = mixed ? (const T*)j->w_<float>(w.r0) : (const T*)j->w_<double>(w.b0);
+          a.phi_out = mixed ? (T*)j->w_<float>(w.e0) : (T*)j->phi(cur);
+          a.add_to = mixed ? j->phi(cur) : nullptr;
+          a.write_norm = mixed ? 0 : 1;
+        } else {
+          a.phi_in = j->w_<T>(w.lphiB[l]);
+          a.b = j->w_<T>(w.lb[l]);
+          a.phi_out = j->w_<T>(w.lphiA[l]);
+        }
+        seg_add(m, a, a.ntiles * a.nmem);
+      }
+      if (timed && l == 0) tm->mark(TM_POST, 0, st);
+      launch_mg_post<T>(m, l == 0 && !mixed, st);
+      if (timed && l == 0) tm->mark(TM_POST, 1, st);
+    }
+    if (timed && !mixed) tm->mark(TM_CYCLE, 1, st);
   };
-  if (!P.mixed) {
-    double* phi = phi_cur;
-    const double* b = at<double>(ws, w.b0);
-    for (int k = 0; k < cap; ++k) vcycle(k, (const T*)b, (const T*)phi, (T*)phi, nullptr, 0, 1);
-  } else {
-    ResidArgs r{};
-    r.g = P.lev[0];
-    r.tiling = P.st_tl;
-    r.ntiles = P.st_tiles;
-    r.nmem = R.nmem;
-    r.plane = P.lev[0].plane();
-    r.phi = phi_cur;
-    r.b = at<double>(ws, w.b0);
-    r.r = at<float>(ws, w.r0);
-    r.norms = norms;
-    r.norm_slots = P.norm_slots;
-    r.tol = P.tol;
-    r.dt = P.dt;
-    r.k = 0;
-    if (tm) tm->mark(TM_RESID, 0, R.s);
-    launch_resid64(r, R.s);
-    if (tm) tm->mark(TM_RESID, 1, R.s);
-    for (int k = 1; k <= cap; ++k) {
-      vcycle(k, (const T*)at<float>(ws, w.r0), nullptr, (T*)at<float>(ws, w.e0), phi_cur, 1, 0);
+  auto resid = [&](int k) {
+    auto m = seg_begin<ResidArgs>();
+    for (Job* j : J) {
+      const Plan& P = j->P;
+      ResidArgs r{};
+      r.g = P.lev[0];
+      r.tiling = P.st_tl;
+      r.ntiles = P.st_tiles;
+      r.nmem = j->nmem;
+      r.plane = P.lev[0].plane();
+      r.phi = j->phi(j->step & 1);
+      r.b = j->w_<double>(j->w.b0);
+      r.r = j->w_<float>(j->w.r0);
+      r.norms = j->w_<double>(j->w.norms);
+      r.norm_slots = P.norm_slots;
+      r.tol = P.tol;
+      r.dt = P.dt;
       r.k = k;
-      launch_resid64(r, R.s);
-      if (tm && k == k_timed) tm->mark(TM_CYCLE, 1, R.s);
+      seg_add(m, r, r.ntiles * r.nmem);
+    }
+    launch_resid64(m, st);
+  };
+  if (!mixed) {
+    for (int k = 0; k < cap; ++k) vcycle(k);
+  } else {
+    if (tm) tm->mark(TM_RESID, 0, st);
+    resid(0);
+    if (tm) tm->mark(TM_RESID, 1, st);
+    for (int k = 1; k <= cap; ++k) {
+      vcycle(k);
+      resid(k);
+      if (tm && k == k_timed) tm->mark(TM_CYCLE, 1, st);
     }
   }
-  return ENVAR_OK;
 }
 
-// One time step: predictor, pressure solve with at most `cap` cycles per
-// member, projection + cost, bookkeeping. The launch sequence depends only on
-// the step parity (AB2 history and pressure buffers alternate), the cap and
-// whether this is the first step of a cold start, so steady steps are
-// captured once into a HIP graph per parity and replayed.
+// One time step of every job of the batch (each at its own step index).
 template <typename TT>
-static int launch_step(const Run& R, hipStream_t st, int s, int cap, bool cold) {
-  const Plan& P = *R.P;
-  const WS& w = *R.w;
-  void* ws = R.ws;
-  const long pl = P.lev[0].plane();
-  TT* tA[2] = {at<TT>(ws, w.tuA), at<TT>(ws, w.tvA)};
-  TT* tB[2] = {at<TT>(ws, w.tuB), at<TT>(ws, w.tvB)};
-  double* phis[2] = {at<double>(ws, w.phiA), at<double>(ws, w.phiC)};
-  const int cur = s & 1;
-  TT** tp = (s % 2 == 0) ? tA : tB;
-  TT** tn = (s % 2 == 0) ? tB : tA;
-  Run Rs = R;
-  Rs.s = st;
-  PredArgs<TT> a{};
-  a.g = P.lev[0];
-  a.tiling = P.st_tl;
-  a.ntiles = P.st_tiles;
-  a.nmem = R.nmem;
-  a.plane = pl;
-  a.nu = P.nu;
-  a.dt = P.dt;
-  a.cold_flag = cold ? at<int>(R.state, P.s_meta) : nullptr;
-  a.u = at<double>(ws, w.u);
-  a.v = at<double>(ws, w.v);
-  a.us = at<double>(ws, w.us);
-  a.vs = at<double>(ws, w.vs);
-  a.tu_prev = tp[0];
-  a.tv_prev = tp[1];
-  a.tu = tn[0];
-  a.tv = tn[1];
-  a.b = at<double>(ws, w.b0);
-  a.ctrl = R.ctrl;
-  a.m = P.m;
-  a.nctrl = (int)(P.m / 2);
-  a.cmap = at<int>(R.state, P.s_cmap);
-  a.norms = at<double>(ws, w.norms);
-  a.norm_slots = P.norm_slots;
-  if (Rs.tm) Rs.tm->mark(TM_PRED, 0, st);
-  launch_predictor<TT>(a, st);
-  if (Rs.tm) Rs.tm->mark(TM_PRED, 1, st);
-  pressure_solve<TT>(Rs, cap, phis[cur]);
-  ProjArgs pj{};
-  pj.g = P.lev[0];
-  pj.tiling = P.st_tl;
-  pj.ntiles = P.st_tiles;
-  pj.nmem = R.nmem;
-  pj.plane = pl;
-  pj.cplane = P.cplane;
-  pj.dt = P.dt;
-  pj.u = at<double>(ws, w.u);
-  pj.v = at<double>(ws, w.v);
-  pj.us = at<double>(ws, w.us);
-  pj.vs = at<double>(ws, w.vs);
-  pj.phi = phis[cur];
-  pj.phi_next = phis[cur ^ 1];
-  pj.shu = at<double>(R.state, P.s_shu);
-  pj.shv = at<double>(R.state, P.s_shv);
-  pj.s1u = at<double>(ws, w.s1u);
-  pj.s1v = at<double>(ws, w.s1v);
-  pj.s2part = at<double>(ws, w.s2part);
-  pj.divmax = at<double>(ws, w.divmax);
-  if (Rs.tm) Rs.tm->mark(TM_PROJ, 0, st);
-  launch_project_cost(pj, st);
-  if (Rs.tm) Rs.tm->mark(TM_PROJ, 1, st);
-  BookArgs bk{};
-  bk.nmem = R.nmem;
-  bk.norm_slots = P.norm_slots;
-  bk.cap = cap;
-  bk.slot_base = P.mixed ? 1 : 0;
-  bk.tol = P.tol;
-  bk.norms = at<double>(ws, w.norms);
-  bk.stats = at<double>(ws, w.stats);
-  launch_step_book(bk, st);
+static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
+  {
+    auto m = seg_begin<PredArgs<TT>>();
+    for (Job* j : J) {
+      const Plan& P = j->P;
+      const WS& w = j->w;
+      const bool even = (j->step & 1) == 0;
+      PredArgs<TT> a{};
+      a.g = P.lev[0];
+      a.tiling = P.st_tl;
+      a.ntiles = P.st_tiles;
+      a.nmem = j->nmem;
+      a.plane = P.lev[0].plane();
+      a.nu = P.nu;
+      a.dt = P.dt;
+      a.cold_flag = (j->step == 0 && j->cold_first) ? at<int>(j->state, P.s_meta) : nullptr;
+      a.u = j->w_<double>(w.u);
+      a.v = j->w_<double>(w.v);
+      a.us = j->w_<double>(w.us);
+      a.vs = j->w_<double>(w.vs);
+      a.tu_prev = j->w_<TT>(even ? w.tuA : w.tuB);
+      a.tv_prev = j->w_<TT>(even ? w.tvA : w.tvB);
+      a.tu = j->w_<TT>(even ? w.tuB : w.tuA);
+      a.tv = j->w_<TT>(even ? w.tvB : w.tvA);
+      a.b = j->w_<double>(w.b0);
+      a.ctrl = j->ctrl;
+      a.m = P.m;
+      a.nctrl = (int)(P.m / 2);
+      a.cmap = at<int>(j->state, P.s_cmap);
+      a.norms = j->w_<double>(w.norms);
+      a.norm_slots = P.norm_slots;
+      seg_add(m, a, a.ntiles * a.nmem);
+    }
+    if (tm) tm->mark(TM_PRED, 0, st);
+    launch_predictor<TT>(m, st);
+    if (tm) tm->mark(TM_PRED, 1, st);
+  }
+  batch_pressure<TT>(J, st, cap, tm);
+  {
+    auto m = seg_begin<ProjArgs>();
+    for (Job* j : J) {
+      const Plan& P = j->P;
+      const WS& w = j->w;
+      const int cur = j->step & 1;
+      ProjArgs pj{};
+      pj.g = P.lev[0];
+      pj.tiling = P.st_tl;
+      pj.ntiles = P.st_tiles;
+      pj.nmem = j->nmem;
+      pj.plane = P.lev[0].plane();
+      pj.cplane = P.cplane;
+      pj.dt = P.dt;
+      pj.u = j->w_<double>(w.u);
+      pj.v = j->w_<double>(w.v);
+      pj.us = j->w_<double>(w.us);
+      pj.vs = j->w_<double>(w.vs);
+      pj.phi = j->phi(cur);
+      pj.phi_next = j->phi(cur ^ 1);
+      pj.shu = at<double>(j->state, P.s_shu);
+      pj.shv = at<double>(j->state, P.s_shv);
+      pj.s1u = j->w_<double>(w.s1u);
+      pj.s1v = j->w_<double>(w.s1v);
+      pj.s2part = j->w_<double>(w.s2part);
+      pj.divmax = j->w_<double>(w.divmax);
+      seg_add(m, pj, pj.ntiles * pj.nmem);
+    }
+    if (tm) tm->mark(TM_PROJ, 0, st);
+    launch_project_cost(m, st);
+    if (tm) tm->mark(TM_PROJ, 1, st);
+  }
+  {
+    auto m = seg_begin<BookArgs>();
+    for (Job* j : J) {
+      BookArgs bk{};
+      bk.nmem = j->nmem;
+      bk.norm_slots = j->P.norm_slots;
+      bk.cap = cap;
+      bk.slot_base = j->P.mixed ? 1 : 0;
+      bk.tol = j->P.tol;
+      bk.norms = j->w_<double>(j->w.norms);
+      bk.stats = j->w_<double>(j->w.stats);
+      seg_add(m, bk, (j->nmem + 63) / 64);
+    }
+    launch_step_book(m, st);
+  }
   HIP_OK(hipGetLastError());
   return ENVAR_OK;
 }
 
-// captured step graphs (one per parity) for the current cap
+template <typename TT>
+static void init_members(const Job& j, hipStream_t s) {
+  const Plan& P = j.P;
+  const WS& w = j.w;
+  InitArgs<TT> ia{};
+  ia.nmem = j.nmem;
+  ia.ntiles = P.st_tiles;
+  ia.plane = P.lev[0].plane();
+  ia.cplane = P.cplane;
+  ia.bu = at<double>(j.state, P.s_u);
+  ia.bv = at<double>(j.state, P.s_v);
+  ia.btu = at<double>(j.state, P.s_tu);
+  ia.btv = at<double>(j.state, P.s_tv);
+  ia.bphi = at<double>(j.state, P.s_phi);
+  ia.u = j.w_<double>(w.u);
+  ia.v = j.w_<double>(w.v);
+  ia.us = j.w_<double>(w.us);
+  ia.vs = j.w_<double>(w.vs);
+  ia.phi = j.w_<double>(w.phiA);
+  ia.phi2 = j.w_<double>(w.phiC);
+  ia.tu = j.w_<TT>(w.tuA);
+  ia.tv = j.w_<TT>(w.tvA);
+  ia.s1u = j.w_<double>(w.s1u);
+  ia.s1v = j.w_<double>(w.s1v);
+  ia.s2part = j.w_<double>(w.s2part);
+  ia.stats = j.w_<double>(w.stats);
+  ia.divmax = j.w_<double>(w.divmax);
+  launch_init_members<TT>(ia, s);
+}
+
+// J of a finished job (and optionally its fields / the spin-up store)
+static void finish_job(const Job& j, double* J_dev, double* fields_dev, bool spinup_store, hipStream_t s) {
+  const Plan& P = j.P;
+  const WS& w = j.w;
+  if (J_dev) {
+    FinalArgs fa{};
+    fa.g = P.lev[0];
+    fa.nmem = j.nmem;
+    fa.ntiles = P.st_tiles;
+    fa.cplane = P.cplane;
+    fa.K = j.horizon;
+    fa.dt = P.dt;
+    fa.penalty = P.penalty;
+    fa.s1u = j.w_<double>(w.s1u);
+    fa.s1v = j.w_<double>(w.s1v);
+    fa.s2part = j.w_<double>(w.s2part);
+    fa.ctrl = j.ctrl;
+    fa.m = P.m;
+    fa.J = J_dev;
+    fa.stats = j.w_<double>(w.stats);
+    launch_finalize_J(fa, s);
+  }
+  if (fields_dev)
+    launch_fields_out(P.lev[0], P.lev[0].plane(), j.nmem, j.w_<double>(w.u), j.w_<double>(w.v), fields_dev, s);
+  if (spinup_store) {
+    // the last step wrote its tendency into buffer B when the horizon is odd
+    const bool inB = (j.horizon % 2) == 1;
+    void* S = (void*)j.state;
+    const long pl = P.lev[0].plane();
+    double* phi_last = j.phi(j.last_cur);
+    if (P.mixed)
+      launch_store_base<float>(pl, j.w_<double>(w.u), j.w_<double>(w.v), j.w_<float>(inB ? w.tuB : w.tuA),
+                               j.w_<float>(inB ? w.tvB : w.tvA), phi_last, at<double>(S, P.s_u),
+                               at<double>(S, P.s_v), at<double>(S, P.s_tu), at<double>(S, P.s_tv),
+                               at<double>(S, P.s_phi), s);
+    else
+      launch_store_base<double>(pl, j.w_<double>(w.u), j.w_<double>(w.v), j.w_<double>(inB ? w.tuB : w.tuA),
+                                j.w_<double>(inB ? w.tvB : w.tvA), phi_last, at<double>(S, P.s_u),
+                                at<double>(S, P.s_v), at<double>(S, P.s_tu), at<double>(S, P.s_tv),
+                                at<double>(S, P.s_phi), s);
+    launch_clear_flag(at<int>(S, P.s_meta), s);
+    launch_shift(P.lev[0], at<double>(S, P.s_u), at<double>(S, P.s_v), at<double>(S, P.s_shu), at<double>(S, P.s_shv),
+                 s);
+  }
+}
+
+// Captured batch steps. All jobs advance together, so a step's launch
+// sequence depends on the job set, the step parities and the cycle cap: two
+// graphs (one per parity) are kept per (job set, cap) and replayed.
 struct StepGraphs {
   hipStream_t cs = nullptr;
   hipGraph_t g[2] = {nullptr, nullptr};
   hipGraphExec_t x[2] = {nullptr, nullptr};
-  int cap[2] = {-1, -1};
+  long key[2] = {-1, -1};
   void drop(int p) {
     if (x[p]) (void)hipGraphExecDestroy(x[p]);
     if (g[p]) (void)hipGraphDestroy(g[p]);
     x[p] = nullptr;
     g[p] = nullptr;
-    cap[p] = -1;
+    key[p] = -1;
   }
   ~StepGraphs() {
     drop(0);
@@ -591,42 +704,98 @@ struct StepGraphs {
   }
 };
 
-// Returns (through phi_final) the buffer holding the last solved pressure.
-template <typename TT>
-static int run_steps(const Run& R, int steps, int cold_first, double** phi_final) {
-  const Plan& P = *R.P;
-  const WS& w = *R.w;
-  void* ws = R.ws;
-  int cap = P.cap_max;
+// Batch driver shared by envar_forward, envar_forward_batch and the server.
+struct Driver {
+  int cap = 0;
+  int cap_max = 0;
+  long epoch = 0;  // bumps whenever the job set changes
+  StepGraphs G;
   hipEvent_t ev = nullptr;
   bool pending = false;
-  double* host = g_pinned.get((size_t)R.nmem * STATS_STRIDE);
-  if (!host) return fail(ENVAR_EDEVICE, "hipHostMalloc failed");
-  const int check_every = 16;
-  double* phis[2] = {at<double>(ws, w.phiA), at<double>(ws, w.phiC)};
-  double* stats_dev = at<double>(ws, w.stats);
-  StepGraphs G;
-  const bool use_graphs = !(P.p.flags & ENVAR_FLAG_NO_GRAPHS);
-  HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  auto absorb = [&]() {
+  std::vector<double> host;  // per-job stats snapshots for the cap monitor
+  std::vector<Job*> watched;
+  double* pinned = nullptr;
+  size_t pinned_n = 0;
+  ~Driver() {
+    if (ev) (void)hipEventDestroy(ev);
+    if (pinned) (void)hipHostFree(pinned);
+  }
+  int ensure_pinned(size_t n) {
+    if (n <= pinned_n) return ENVAR_OK;
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_n = 0;
+    HIP_OK(hipHostMalloc((void**)&pinned, n * sizeof(double), hipHostMallocDefault));
+    pinned_n = n;
+    return ENVAR_OK;
+  }
+  int absorb_now(const std::vector<Job*>& J, hipStream_t s) {
+    size_t n = 0;
+    for (Job* j : J) n += (size_t)j->nmem * STATS_STRIDE;
+    int rc = ensure_pinned(n);
+    if (rc) return rc;
+    size_t o = 0;
+    for (Job* j : J) {
+      HIP_OK(hipMemcpyAsync(pinned + o, j->w_<double>(j->w.stats), (size_t)j->nmem * STATS_STRIDE * 8,
+                            hipMemcpyDeviceToHost, s));
+      o += (size_t)j->nmem * STATS_STRIDE;
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    absorb(n);
+    return ENVAR_OK;
+  }
+  void absorb(size_t n) {
     int mx = 0;
-    for (int i = 0; i < R.nmem; ++i) mx = std::max(mx, (int)host[(size_t)i * STATS_STRIDE + ST_MAXCYC]);
-    cap = std::min(P.cap_max, std::max(2, mx + 1));
-  };
-  int rc = ENVAR_OK;
-  for (int s = 0; s < steps && rc == ENVAR_OK; ++s) {
-    if (R.tm && R.tm->begin_step(s, steps)) return fail(ENVAR_EDEVICE, "hipEventCreate failed");
-    const bool cold = s == 0 && cold_first;
-    const bool sampled = R.tm && R.tm->cur >= 0;
-    const int par = s & 1;
-    if (s > 0 && !sampled && use_graphs && steps - s >= 16) {
-      if (G.cap[par] != cap) {
+    for (size_t q = 0; q < n; q += STATS_STRIDE) mx = std::max(mx, (int)pinned[q + ST_MAXCYC]);
+    // ST_MAXCYC is a running maximum, so the cap never drops below what any member needed
+    cap = std::min(cap_max, std::max(2, mx + 1));
+  }
+  int start_async(const std::vector<Job*>& J, hipStream_t s) {
+    size_t n = 0;
+    for (Job* j : J) n += (size_t)j->nmem * STATS_STRIDE;
+    if (n > pinned_n) return ENVAR_OK;  // sized by the last synchronous absorb
+    if (!ev) HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    size_t o = 0;
+    for (Job* j : J) {
+      HIP_OK(hipMemcpyAsync(pinned + o, j->w_<double>(j->w.stats), (size_t)j->nmem * STATS_STRIDE * 8,
+                            hipMemcpyDeviceToHost, s));
+      o += (size_t)j->nmem * STATS_STRIDE;
+    }
+    HIP_OK(hipEventRecord(ev, s));
+    pending = true;
+    watched_n = n;
+    return ENVAR_OK;
+  }
+  size_t watched_n = 0;
+  void poll() {
+    if (pending && hipEventQuery(ev) == hipSuccess) {
+      absorb(watched_n);
+      pending = false;
+    }
+  }
+  void drain() {
+    if (pending) {
+      (void)hipEventSynchronize(ev);
+      pending = false;
+    }
+  }
+
+  // Advance every job by one step. `fresh` = some job is at its first step
+  // (eager launch followed by an exact cap calibration).
+  template <typename TT>
+  int step(std::vector<Job*>& J, hipStream_t s, Timer* tm, int steps_left_min, bool use_graphs) {
+    bool fresh = false;
+    for (Job* j : J) fresh = fresh || j->step == 0;
+    const bool sampled = tm && tm->cur >= 0;
+    const int par = J[0]->step & 1;
+    int rc;
+    if (!fresh && !sampled && use_graphs && steps_left_min >= 16) {
+      const long key = epoch * 1024 + cap;
+      if (G.key[par] != key) {
         G.drop(par);
         if (!G.cs) HIP_OK(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
         HIP_OK(hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal));
-        Run Rn = R;
-        Rn.tm = nullptr;
-        rc = launch_step<TT>(Rn, G.cs, s, cap, false);
+        rc = batch_step<TT>(J, G.cs, cap, nullptr);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(G.cs, &g);
         if (rc) {
@@ -636,63 +805,26 @@ static int run_steps(const Run& R, int steps, int cold_first, double** phi_final
         if (ec != hipSuccess) return fail(ENVAR_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
         G.g[par] = g;
         HIP_OK(hipGraphInstantiate(&G.x[par], g, nullptr, nullptr, 0));
-        G.cap[par] = cap;
+        G.key[par] = key;
       }
-      HIP_OK(hipGraphLaunch(G.x[par], R.s));
+      HIP_OK(hipGraphLaunch(G.x[par], s));
     } else {
-      rc = launch_step<TT>(R, R.s, s, cap, cold);
+      rc = batch_step<TT>(J, s, cap, sampled ? tm : nullptr);
       if (rc) return rc;
     }
-    if (phi_final) *phi_final = phis[par];
-    // adaptive cap: exact after the first step, then asynchronous checks
-    if (s == 0) {
-      HIP_OK(hipMemcpyAsync(host, stats_dev, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
-      HIP_OK(hipStreamSynchronize(R.s));
-      absorb();
-    } else if (s % check_every == 0) {
-      if (pending && hipEventQuery(ev) == hipSuccess) {
-        absorb();
-        pending = false;
-      }
-      if (!pending) {
-        HIP_OK(hipMemcpyAsync(host, stats_dev, (size_t)R.nmem * STATS_STRIDE * 8, hipMemcpyDeviceToHost, R.s));
-        HIP_OK(hipEventRecord(ev, R.s));
-        pending = true;
-      }
+    for (Job* j : J) {
+      j->last_cur = j->step & 1;
+      ++j->step;
     }
+    if (fresh) return absorb_now(J, s);
+    const int s0 = J[0]->step;
+    if (s0 % 16 == 0) {
+      poll();
+      if (!pending) return start_async(J, s);
+    }
+    return ENVAR_OK;
   }
-  if (pending) (void)hipEventSynchronize(ev);
-  (void)hipEventDestroy(ev);
-  return rc;
-}
-
-template <typename TT>
-static void init_members(const Plan& P, const WS& w, void* ws, const void* state, int nmem, hipStream_t s) {
-  InitArgs<TT> ia{};
-  ia.nmem = nmem;
-  ia.ntiles = P.st_tiles;
-  ia.plane = P.lev[0].plane();
-  ia.cplane = P.cplane;
-  ia.bu = at<double>(state, P.s_u);
-  ia.bv = at<double>(state, P.s_v);
-  ia.btu = at<double>(state, P.s_tu);
-  ia.btv = at<double>(state, P.s_tv);
-  ia.bphi = at<double>(state, P.s_phi);
-  ia.u = at<double>(ws, w.u);
-  ia.v = at<double>(ws, w.v);
-  ia.us = at<double>(ws, w.us);
-  ia.vs = at<double>(ws, w.vs);
-  ia.phi = at<double>(ws, w.phiA);
-  ia.phi2 = at<double>(ws, w.phiC);
-  ia.tu = at<TT>(ws, w.tuA);
-  ia.tv = at<TT>(ws, w.tvA);
-  ia.s1u = at<double>(ws, w.s1u);
-  ia.s1v = at<double>(ws, w.s1v);
-  ia.s2part = at<double>(ws, w.s2part);
-  ia.stats = at<double>(ws, w.stats);
-  ia.divmax = at<double>(ws, w.divmax);
-  launch_init_members<TT>(ia, s);
-}
+};
 
 static int collect_stats(const Plan& P, const WS& w, void* ws, int nmem, hipStream_t s, envar_stats* st,
                          const double* J_dev) {
@@ -866,89 +998,160 @@ int envar_state_read(const envar_problem* p, const void* state_dev, double* u, d
   return ENVAR_OK;
 }
 
+}  // extern "C"
+
+namespace envar {
+
+struct JobOut {
+  double* J = nullptr;
+  double* fields = nullptr;
+  bool spinup_store = false;
+};
+
+// Integrate every job to its own horizon; jobs leave the batch as they finish.
+template <typename TT>
+static int run_batch(std::vector<Job>& jobs, const std::vector<JobOut>& outs, hipStream_t s, Timer* tm, bool graphs) {
+  int cap_max = 0;
+  for (Job& j : jobs) {
+    init_members<TT>(j, s);
+    cap_max = std::max(cap_max, j.P.cap_max);
+  }
+  Driver D;
+  D.cap = D.cap_max = cap_max;
+  std::vector<Job*> active;
+  std::vector<int> which;
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    active.push_back(&jobs[k]);
+    which.push_back((int)k);
+  }
+  while (!active.empty()) {
+    int left = 1 << 30, longest = 0;
+    for (Job* j : active) {
+      left = std::min(left, j->horizon - j->step);
+      longest = std::max(longest, j->horizon);
+    }
+    if (tm && tm->begin_step(active[0]->step, longest)) return fail(ENVAR_EDEVICE, "hipEventCreate failed");
+    int rc = D.step<TT>(active, s, tm, left, graphs);
+    if (rc) return rc;
+    bool changed = false;
+    for (size_t k = 0; k < active.size();) {
+      if (active[k]->step >= active[k]->horizon) {
+        const JobOut& o = outs[which[k]];
+        finish_job(*active[k], o.J, o.fields, o.spinup_store, s);
+        active.erase(active.begin() + k);
+        which.erase(which.begin() + k);
+        changed = true;
+      } else {
+        ++k;
+      }
+    }
+    if (changed) ++D.epoch;
+  }
+  D.drain();
+  HIP_OK(hipGetLastError());
+  return ENVAR_OK;
+}
+
+static void fill_timer_stats(Timer& timer, envar_stats* stats, int n_rows) {
+  if (!timer.on || timer.samples == 0) return;
+  double* outs[TM_N] = {&stats->predictor_us, &stats->pre_us, &stats->post_us,
+                        &stats->resid_us, &stats->project_us, &stats->vcycle_us};
+  for (int t = 0; t < TM_N; ++t) {
+    double sum = 0.0;
+    int cnt = 0;
+    for (int q = 0; q < timer.samples; ++q) {
+      if (!timer.recorded(q, t)) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, timer.ev[((size_t)q * TM_N + t) * 2], timer.ev[((size_t)q * TM_N + t) * 2 + 1]) ==
+          hipSuccess) {
+        sum += ms;
+        ++cnt;
+      }
+    }
+    *outs[t] = cnt ? 1e3 * sum / cnt : 0.0;
+  }
+  stats->timed_steps = timer.samples;
+  stats->timed_members = n_rows;
+  (void)hipGetLastError();  // the event queries leave no sticky error behind
+}
+
+static int make_job(const Plan& P, const void* state_dev, const double* controls_dev, int n_rows, int horizon,
+                    void* ws_dev, size_t ws_bytes, Job& j) {
+  j.P = P;
+  j.w = make_ws(P, n_rows);
+  if (ws_bytes < j.w.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, j.w.total);
+  j.ws = ws_dev;
+  j.state = state_dev;
+  j.ctrl = controls_dev;
+  j.nmem = n_rows;
+  j.horizon = horizon;
+  j.step = 0;
+  return ENVAR_OK;
+}
+
 static int forward_impl(const Plan& P, const void* state_dev, const double* controls_dev, int n_rows, int horizon,
                         void* ws_dev, size_t ws_bytes, double* J_dev, double* fields_dev, envar_stats* stats,
                         hipStream_t s, bool spinup_store) {
-  const WS w = make_ws(P, n_rows);
-  if (ws_bytes < w.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, w.total);
-  if (P.mixed)
-    init_members<float>(P, w, ws_dev, state_dev, n_rows, s);
-  else
-    init_members<double>(P, w, ws_dev, state_dev, n_rows, s);
+  std::vector<Job> jobs(1);
+  int rc = make_job(P, state_dev, controls_dev, n_rows, horizon, ws_dev, ws_bytes, jobs[0]);
+  if (rc) return rc;
+  std::vector<JobOut> outs(1);
+  outs[0].J = J_dev;
+  outs[0].fields = fields_dev;
+  outs[0].spinup_store = spinup_store;
   Timer timer;
   timer.on = stats != nullptr && (P.p.flags & ENVAR_FLAG_TIME_KERNELS);
   timer.every = std::max(1, (horizon - 1 + timer.max_samples - 1) / timer.max_samples);
-  Run R{&P, ws_dev, &w, n_rows, state_dev, controls_dev, s, timer.on ? &timer : nullptr};
-  double* phi_last = at<double>(ws_dev, w.phiA);
-  int rc = P.mixed ? run_steps<float>(R, horizon, 1, &phi_last) : run_steps<double>(R, horizon, 1, &phi_last);
+  const bool graphs = !(P.p.flags & ENVAR_FLAG_NO_GRAPHS);
+  rc = P.mixed ? run_batch<float>(jobs, outs, s, timer.on ? &timer : nullptr, graphs)
+               : run_batch<double>(jobs, outs, s, timer.on ? &timer : nullptr, graphs);
   if (rc) return rc;
-  if (J_dev) {
-    FinalArgs fa{};
-    fa.g = P.lev[0];
-    fa.nmem = n_rows;
-    fa.ntiles = P.st_tiles;
-    fa.cplane = P.cplane;
-    fa.K = horizon;
-    fa.dt = P.dt;
-    fa.penalty = P.penalty;
-    fa.s1u = at<double>(ws_dev, w.s1u);
-    fa.s1v = at<double>(ws_dev, w.s1v);
-    fa.s2part = at<double>(ws_dev, w.s2part);
-    fa.ctrl = controls_dev;
-    fa.m = P.m;
-    fa.J = J_dev;
-    fa.stats = at<double>(ws_dev, w.stats);
-    launch_finalize_J(fa, s);
-  }
-  if (fields_dev)
-    launch_fields_out(P.lev[0], P.lev[0].plane(), n_rows, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
-                      fields_dev, s);
-  if (spinup_store) {
-    // the last step wrote its tendency into buffer B when horizon is odd
-    const bool inB = (horizon % 2) == 1;
-    void* S = (void*)state_dev;
-    const long pl = P.lev[0].plane();
-    if (P.mixed)
-      launch_store_base<float>(pl, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
-                               at<float>(ws_dev, inB ? w.tuB : w.tuA), at<float>(ws_dev, inB ? w.tvB : w.tvA),
-                               phi_last, at<double>(S, P.s_u), at<double>(S, P.s_v),
-                               at<double>(S, P.s_tu), at<double>(S, P.s_tv), at<double>(S, P.s_phi), s);
-    else
-      launch_store_base<double>(pl, at<double>(ws_dev, w.u), at<double>(ws_dev, w.v),
-                                at<double>(ws_dev, inB ? w.tuB : w.tuA), at<double>(ws_dev, inB ? w.tvB : w.tvA),
-                                phi_last, at<double>(S, P.s_u), at<double>(S, P.s_v),
-                                at<double>(S, P.s_tu), at<double>(S, P.s_tv), at<double>(S, P.s_phi), s);
-    launch_clear_flag(at<int>(S, P.s_meta), s);
-    launch_shift(P.lev[0], at<double>(S, P.s_u), at<double>(S, P.s_v), at<double>(S, P.s_shu),
-                 at<double>(S, P.s_shv), s);
-  }
-  HIP_OK(hipGetLastError());
   if (stats) {
-    rc = collect_stats(P, w, ws_dev, n_rows, s, stats, J_dev);
+    rc = collect_stats(P, jobs[0].w, ws_dev, n_rows, s, stats, J_dev);
     if (rc) return rc;
-    if (timer.on && timer.samples > 0) {
-      double* outs[TM_N] = {&stats->predictor_us, &stats->pre_us, &stats->post_us,
-                            &stats->resid_us, &stats->project_us, &stats->vcycle_us};
-      for (int t = 0; t < TM_N; ++t) {
-        double sum = 0.0;
-        int cnt = 0;
-        for (int q = 0; q < timer.samples; ++q) {
-          if (!timer.recorded(q, t)) continue;
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, timer.ev[((size_t)q * TM_N + t) * 2], timer.ev[((size_t)q * TM_N + t) * 2 + 1]) ==
-              hipSuccess) {
-            sum += ms;
-            ++cnt;
-          }
-        }
-        *outs[t] = cnt ? 1e3 * sum / cnt : 0.0;
-      }
-      stats->timed_steps = timer.samples;
-      stats->timed_members = n_rows;
-      (void)hipGetLastError();  // the event queries leave no sticky error behind
-    }
+    fill_timer_stats(timer, stats, n_rows);
     if (stats->diverged > 0) return fail(ENVAR_EDIVERGED, "%d member(s) produced a non-finite cost", stats->diverged);
   }
+  return ENVAR_OK;
+}
+
+}  // namespace envar
+
+extern "C" {
+
+int envar_forward_batch(envar_job* jobs_in, int32_t njobs, void* stream) {
+  if (!jobs_in || njobs < 1 || njobs > MAX_SEG) return fail(ENVAR_EINVAL, "njobs must be in [1, %d]", MAX_SEG);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<Job> jobs(njobs);
+  std::vector<JobOut> outs(njobs);
+  int prec = -1;
+  bool graphs = true;
+  for (int k = 0; k < njobs; ++k) {
+    envar_job& q = jobs_in[k];
+    Plan P;
+    int rc = make_plan(&q.problem, P);
+    if (rc) return rc;
+    if (prec < 0) prec = P.mixed;
+    if (P.mixed != prec) return fail(ENVAR_EINVAL, "all jobs of a batch must share one precision");
+    if (!q.state_dev || !q.ws_dev || !q.J_dev || !q.controls_dev) return fail(ENVAR_EINVAL, "job %d: NULL pointer", k);
+    if (q.n_rows < 1 || q.horizon < 1) return fail(ENVAR_EINVAL, "job %d: n_rows and horizon must be >= 1", k);
+    if (q.m != P.m) return fail(ENVAR_EINVAL, "job %d: m = %lld but the control region has m = %ld", k,
+                                (long long)q.m, P.m);
+    rc = make_job(P, q.state_dev, q.controls_dev, q.n_rows, q.horizon, q.ws_dev, q.ws_bytes, jobs[k]);
+    if (rc) return rc;
+    outs[k].J = q.J_dev;
+    graphs = graphs && !(P.p.flags & ENVAR_FLAG_NO_GRAPHS);
+  }
+  int rc = prec ? run_batch<float>(jobs, outs, s, nullptr, graphs) : run_batch<double>(jobs, outs, s, nullptr, graphs);
+  if (rc) return rc;
+  int diverged = 0;
+  for (int k = 0; k < njobs; ++k)
+    if (jobs_in[k].stats) {
+      rc = collect_stats(jobs[k].P, jobs[k].w, jobs[k].ws, jobs[k].nmem, s, jobs_in[k].stats, jobs_in[k].J_dev);
+      if (rc) return rc;
+      diverged += jobs_in[k].stats->diverged;
+    }
+  if (diverged > 0) return fail(ENVAR_EDIVERGED, "%d member(s) produced a non-finite cost", diverged);
   return ENVAR_OK;
 }
 

@@ -7,6 +7,31 @@
 
 namespace envar {
 
+// A launch carries up to MAX_SEG ensembles ("segments"): segment s owns the
+// workgroups [start[s], start[s+1]) of the grid. Workgroup ids are first
+// remapped for XCD locality, then looked up here.
+constexpr int MAX_SEG = 8;
+template <typename A>
+struct Multi {
+  int nseg;
+  int start[MAX_SEG + 1];
+  A seg[MAX_SEG];
+  // ONE: the launch carries a single segment (known at compile time)
+  template <bool ONE>
+  __device__ __forceinline__ const A& pick(int wg, int& local) const {
+    if (ONE) {
+      local = wg;
+      return seg[0];
+    }
+    int s = 0;
+#pragma unroll
+    for (int q = 1; q < MAX_SEG; ++q) s += (q < nseg && wg >= start[q]) ? 1 : 0;
+    local = wg - start[s];
+    return seg[s];
+  }
+  int total() const { return start[nseg]; }
+};
+
 // per-member statistics slots (FP64)
 enum { ST_CYCLES = 0, ST_MAXCYC, ST_UNCONV, ST_MAXRES, ST_STEPS, ST_J, STATS_STRIDE = 8 };
 
@@ -150,9 +175,9 @@ struct ResidArgs {
 };
 
 template <typename TT>
-void launch_predictor(const PredArgs<TT>& a, hipStream_t s);
-void launch_project_cost(const ProjArgs& a, hipStream_t s);
-void launch_step_book(const BookArgs& a, hipStream_t s);
+void launch_predictor(const Multi<PredArgs<TT>>& m, hipStream_t s);
+void launch_project_cost(const Multi<ProjArgs>& m, hipStream_t s);
+void launch_step_book(const Multi<BookArgs>& m, hipStream_t s);
 void launch_finalize_J(const FinalArgs& a, hipStream_t s);
 template <typename TT>
 void launch_init_members(const InitArgs<TT>& a, hipStream_t s);
@@ -165,12 +190,12 @@ void launch_fields_out(const Geo& g, long plane, int nmem, const double* u, cons
 void launch_clear_flag(int* flag, hipStream_t s);
 
 template <typename T>
-void launch_mg_pre(const MGArgs<T>& a, int nsweep, hipStream_t s);
+void launch_mg_pre(const Multi<MGArgs<T>>& m, hipStream_t s);
 template <typename T>
-void launch_mg_post(const MGArgs<T>& a, int nsweep, hipStream_t s);
+void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s);
 template <typename T>
-void launch_mg_coarse(const CoarseArgs& a, hipStream_t s);
-void launch_resid64(const ResidArgs& a, hipStream_t s);
+void launch_mg_coarse(const Multi<CoarseArgs>& m, hipStream_t s);
+void launch_resid64(const Multi<ResidArgs>& m, hipStream_t s);
 
 // anomaly reduction
 struct GramPlan {

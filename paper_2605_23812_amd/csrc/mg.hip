@@ -161,16 +161,17 @@ struct WinLoad {
 };
 
 // ---------------------------------------------------------------------------- pre-smoothing + restriction
-template <typename T, int NS>
-__global__ __launch_bounds__(256) void k_mg_pre(MGArgs<T> a) {
+template <typename T, int NS, bool ONE>
+__global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
   typedef Win<T> W;
   static_assert(2 * NS + 1 <= W::H, "window halo too small for the sweep count");
   static_assert(W::TH * 64 <= 2 * W::CS, "residual staging does not fit");
   __shared__ T sp[2 * W::CS];
   __shared__ T sb[2 * W::CS];
   __shared__ unsigned char scode[2 * W::CS];
+  int item;
+  const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
-  const int item = xcd_remap(blockIdx.x, a.ntiles * a.nmem);
   const int mem = item / a.ntiles, tile = item % a.ntiles;
   if (mg_skip(a, mem, tile)) return;
   int x0, y0;
@@ -237,8 +238,8 @@ __global__ __launch_bounds__(256) void k_mg_pre(MGArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------- prolongation + post-smoothing
-template <typename T, int NS, int NORM>
-__global__ __launch_bounds__(256) void k_mg_post(MGArgs<T> a) {
+template <typename T, int NS, int NORM, bool ONE>
+__global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
   typedef Win<T> W;
   static_assert(2 * NS + NORM <= W::H, "window halo too small for the sweep count");
   constexpr int CW = 36, CH = W::LH / 2 + 3;
@@ -248,9 +249,10 @@ __global__ __launch_bounds__(256) void k_mg_post(MGArgs<T> a) {
   __shared__ T scw[CH * CW];
   __shared__ unsigned char sccode[CH * CW];
   __shared__ double red[4];
+  int item;
+  const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
   const Geo& gc = a.gc;
-  const int item = xcd_remap(blockIdx.x, a.ntiles * a.nmem);
   const int mem = item / a.ntiles, tile = item % a.ntiles;
   if (mg_skip(a, mem, tile)) return;
   int x0, y0;
@@ -431,13 +433,14 @@ __device__ __forceinline__ void lds_prolong(double* p, const Geo& g, const doubl
 // LDS: V-cycle with NS red-black sweeps per level and a dense solve of the
 // h = 1/4 operator through its inverse. The three levels are unrolled at
 // compile time so that every geometry predicate stays in registers.
-template <typename T>
-__global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(CoarseArgs a) {
+template <typename T, bool ONE>
+__global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> ms) {
   __shared__ double lds[COARSE_LDS];
   __shared__ double sinv[COARSE_INV_MAX];
   __shared__ double sbc[MAX_COARSE_UNKNOWNS];
   __shared__ double red[COARSE_THREADS / 64];
-  const int mem = blockIdx.x;
+  int mem;
+  const CoarseArgs& a = ms.template pick<ONE>(blockIdx.x, mem);
   if (a.k > 0 && a.norms != nullptr) {
     const double prev = a.norms[(long)mem * a.norm_slots + a.k - 1];
     if (prev <= a.tol) {
@@ -535,11 +538,13 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(CoarseArgs a) {
 }
 
 // ---------------------------------------------------------------------------- FP64 residual (refinement)
-__global__ __launch_bounds__(256) void k_resid64(ResidArgs a) {
+template <bool ONE>
+__global__ __launch_bounds__(256) void k_resid64(Multi<ResidArgs> ms) {
   constexpr int TW = TILE_W, TH = STEP_TH;
   __shared__ double red[4];
+  int item;
+  const ResidArgs& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
-  const int item = xcd_remap(blockIdx.x, a.ntiles * a.nmem);
   const int mem = item / a.ntiles, tile = item % a.ntiles;
   if (a.k > 0) {
     const double prev = a.norms[(long)mem * a.norm_slots + a.k - 1];
@@ -582,32 +587,46 @@ __global__ __launch_bounds__(256) void k_resid64(ResidArgs a) {
 
 // ---------------------------------------------------------------------------- launchers
 template <typename T>
-void launch_mg_pre(const MGArgs<T>& a, int nsweep, hipStream_t s) {
-  (void)nsweep;  // the window halo is sized for MG_NS sweeps
-  hipLaunchKernelGGL((k_mg_pre<T, MG_NS>), dim3(a.ntiles * a.nmem), dim3(256), 0, s, a);
-}
-template <typename T>
-void launch_mg_post(const MGArgs<T>& a, int nsweep, hipStream_t s) {
-  (void)nsweep;
-  const dim3 grid(a.ntiles * a.nmem), block(256);
-  if (a.write_norm)
-    hipLaunchKernelGGL((k_mg_post<T, MG_NS, 1>), grid, block, 0, s, a);
+void launch_mg_pre(const Multi<MGArgs<T>>& m, hipStream_t s) {
+  if (m.nseg == 1)
+    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, true>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_mg_post<T, MG_NS, 0>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, false>), dim3(m.total()), dim3(256), 0, s, m);
 }
 template <typename T>
-void launch_mg_coarse(const CoarseArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_mg_coarse<T>, dim3(a.nmem), dim3(COARSE_THREADS), 0, s, a);
+void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s) {
+  const dim3 g(m.total()), b(256);
+  if (m.nseg == 1) {
+    if (write_norm)
+      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 1, true>), g, b, 0, s, m);
+    else
+      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 0, true>), g, b, 0, s, m);
+  } else {
+    if (write_norm)
+      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 1, false>), g, b, 0, s, m);
+    else
+      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 0, false>), g, b, 0, s, m);
+  }
 }
-void launch_resid64(const ResidArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_resid64, dim3(a.ntiles * a.nmem), dim3(256), 0, s, a);
+template <typename T>
+void launch_mg_coarse(const Multi<CoarseArgs>& m, hipStream_t s) {
+  if (m.nseg == 1)
+    hipLaunchKernelGGL((k_mg_coarse<T, true>), dim3(m.total()), dim3(COARSE_THREADS), 0, s, m);
+  else
+    hipLaunchKernelGGL((k_mg_coarse<T, false>), dim3(m.total()), dim3(COARSE_THREADS), 0, s, m);
+}
+void launch_resid64(const Multi<ResidArgs>& m, hipStream_t s) {
+  if (m.nseg == 1)
+    hipLaunchKernelGGL(k_resid64<true>, dim3(m.total()), dim3(256), 0, s, m);
+  else
+    hipLaunchKernelGGL(k_resid64<false>, dim3(m.total()), dim3(256), 0, s, m);
 }
 
-template void launch_mg_pre<double>(const MGArgs<double>&, int, hipStream_t);
-template void launch_mg_pre<float>(const MGArgs<float>&, int, hipStream_t);
-template void launch_mg_post<double>(const MGArgs<double>&, int, hipStream_t);
-template void launch_mg_post<float>(const MGArgs<float>&, int, hipStream_t);
-template void launch_mg_coarse<double>(const CoarseArgs&, hipStream_t);
-template void launch_mg_coarse<float>(const CoarseArgs&, hipStream_t);
+template void launch_mg_pre<double>(const Multi<MGArgs<double>>&, hipStream_t);
+template void launch_mg_pre<float>(const Multi<MGArgs<float>>&, hipStream_t);
+template void launch_mg_post<double>(const Multi<MGArgs<double>>&, bool, hipStream_t);
+template void launch_mg_post<float>(const Multi<MGArgs<float>>&, bool, hipStream_t);
+template void launch_mg_coarse<double>(const Multi<CoarseArgs>&, hipStream_t);
+template void launch_mg_coarse<float>(const Multi<CoarseArgs>&, hipStream_t);
 
 }  // namespace envar

@@ -23,8 +23,8 @@
 namespace envar {
 
 // ---------------------------------------------------------------------------- predictor
-template <typename TT>
-__global__ __launch_bounds__(256) void k_predictor(PredArgs<TT> a) {
+template <typename TT, bool ONE>
+__global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
   constexpr int TW = TILE_W, TH = STEP_TH;
   constexpr int UW = TW + 3, UH = TH + 2;  // u halo: i in [x0-1, x0+TW+1], j in [y0-1, y0+TH]
   constexpr int VW = TW + 2, VH = TH + 3;  // v halo: i in [x0-1, x0+TW],   j in [y0-1, y0+TH+1]
@@ -33,9 +33,9 @@ __global__ __launch_bounds__(256) void k_predictor(PredArgs<TT> a) {
   __shared__ double sus[TH * (TW + 1)];
   __shared__ double svs[(TH + 1) * TW];
 
+  int item;
+  const PredArgs<TT>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
-  const int total = a.ntiles * a.nmem;
-  const int item = xcd_remap(blockIdx.x, total);
   const int mem = item / a.ntiles;
   const int tile = item % a.ntiles;
   int x0, y0;
@@ -182,13 +182,14 @@ __global__ __launch_bounds__(256) void k_predictor(PredArgs<TT> a) {
 }
 
 // ---------------------------------------------------------------------------- projection + cost
-__global__ __launch_bounds__(256) void k_project_cost(ProjArgs a) {
+template <bool ONE>
+__global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
   constexpr int TW = TILE_W, TH = STEP_TH;
   __shared__ double red_s[4];
   __shared__ double red_m[4];
+  int item;
+  const ProjArgs& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
-  const int total = a.ntiles * a.nmem;
-  const int item = xcd_remap(blockIdx.x, total);
   const int mem = item / a.ntiles;
   const int tile = item % a.ntiles;
   int x0, y0;
@@ -268,8 +269,10 @@ __global__ __launch_bounds__(256) void k_project_cost(ProjArgs a) {
 // norms[mem][k] holds dt*max|r| after cycle k; a skipped cycle carries the
 // previous value, so the first slot at or below tol ends the solve. Records
 // the cycles run, the final residual and whether the tolerance was met.
-__global__ void k_step_book(BookArgs a) {
-  const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_step_book(Multi<BookArgs> ms) {
+  int blk;
+  const BookArgs& a = ms.template pick<false>(blockIdx.x, blk);
+  const int mem = blk * blockDim.x + threadIdx.x;
   if (mem >= a.nmem) return;
   const double* nr = a.norms + (long)mem * a.norm_slots;
   const int filled = a.cap + a.slot_base;
@@ -407,18 +410,23 @@ __global__ void k_clear_flag(int* flag) { *flag = 0; }
 
 // ---------------------------------------------------------------------------- launchers
 template <typename TT>
-void launch_predictor(const PredArgs<TT>& a, hipStream_t s) {
-  const int total = a.ntiles * a.nmem;
-  hipLaunchKernelGGL(k_predictor<TT>, dim3(total), dim3(256), 0, s, a);
+void launch_predictor(const Multi<PredArgs<TT>>& m, hipStream_t s) {
+  if (m.nseg == 1)
+    hipLaunchKernelGGL((k_predictor<TT, true>), dim3(m.total()), dim3(256), 0, s, m);
+  else
+    hipLaunchKernelGGL((k_predictor<TT, false>), dim3(m.total()), dim3(256), 0, s, m);
 }
-template void launch_predictor<double>(const PredArgs<double>&, hipStream_t);
-template void launch_predictor<float>(const PredArgs<float>&, hipStream_t);
+template void launch_predictor<double>(const Multi<PredArgs<double>>&, hipStream_t);
+template void launch_predictor<float>(const Multi<PredArgs<float>>&, hipStream_t);
 
-void launch_project_cost(const ProjArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_project_cost, dim3(a.ntiles * a.nmem), dim3(256), 0, s, a);
+void launch_project_cost(const Multi<ProjArgs>& m, hipStream_t s) {
+  if (m.nseg == 1)
+    hipLaunchKernelGGL(k_project_cost<true>, dim3(m.total()), dim3(256), 0, s, m);
+  else
+    hipLaunchKernelGGL(k_project_cost<false>, dim3(m.total()), dim3(256), 0, s, m);
 }
-void launch_step_book(const BookArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_book, dim3((a.nmem + 63) / 64), dim3(64), 0, s, a);
+void launch_step_book(const Multi<BookArgs>& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_book, dim3(m.total()), dim3(64), 0, s, m);
 }
 void launch_finalize_J(const FinalArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize_J, dim3(a.nmem), dim3(256), 0, s, a);

@@ -23,7 +23,7 @@ FLAG_NO_GRAPHS = 2
 
 EXPORTS = (
     "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",
-    "envar_state_init", "envar_state_read", "envar_spinup", "envar_forward",
+    "envar_state_init", "envar_state_read", "envar_spinup", "envar_forward", "envar_forward_batch",
     "envar_gradient_bytes", "envar_gradient", "envar_iterate_bytes", "envar_iterate",
     "envar_last_error", "envar_version",
 )
@@ -56,6 +56,15 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [
+        ("problem", _Problem), ("state_dev", ctypes.c_void_p), ("controls_dev", ctypes.c_void_p),
+        ("n_rows", ctypes.c_int32), ("horizon", ctypes.c_int32), ("m", ctypes.c_int64),
+        ("ws_dev", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("J_dev", ctypes.c_void_p),
+        ("stats", ctypes.POINTER(Stats)),
+    ]
 
 
 class LSParams(ctypes.Structure):
@@ -127,6 +136,7 @@ def lib():
     L.envar_state_read.argtypes = [P, vp, dp, dp, dp, dp, dp]
     L.envar_spinup.argtypes = [P, vp, i32, vp, sz, ctypes.POINTER(Stats), vp]
     L.envar_forward.argtypes = [P, vp, dp, i32, i64, i32, vp, sz, dp, dp, ctypes.POINTER(Stats), vp]
+    L.envar_forward_batch.argtypes = [ctypes.POINTER(_Job), i32, vp]
     L.envar_gradient_bytes.argtypes = [i32, i64, i32]
     L.envar_gradient_bytes.restype = sz
     L.envar_gradient.argtypes = [dp, dp, i32, i64, i32, vp, sz, dp, vp]
@@ -137,7 +147,7 @@ def lib():
     L.envar_last_error.restype = ctypes.c_char_p
     L.envar_version.restype = ctypes.c_char_p
     for name in ("envar_control_dim", "envar_cell_count", "envar_state_init", "envar_state_read",
-                 "envar_spinup", "envar_forward", "envar_gradient", "envar_iterate"):
+                 "envar_spinup", "envar_forward", "envar_forward_batch", "envar_gradient", "envar_iterate"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -259,6 +269,34 @@ def forward(p, state, controls, horizon, ws=None, J=None, fields=False, stats=Tr
         return J, F, st.as_dict()
     _check(rc)
     return J, F, (st.as_dict() if st is not None else None)
+
+
+def forward_batch(jobs):
+    """Uneven batch: jobs = [(problem, state, controls [n, m] device FP64, horizon)], up to 8.
+
+    Returns a list of (J tensor, stats dict) in job order.
+    """
+    import torch
+
+    arr = (_Job * len(jobs))()
+    keep = []
+    for k, (p, state, ctrl, horizon) in enumerate(jobs):
+        n, m = ctrl.shape
+        ws = _bytes_tensor(workspace_bytes(p, n))
+        J = torch.empty(n, dtype=torch.float64, device=ctrl.device)
+        st = Stats()
+        keep.append((ws, J, st))
+        arr[k].problem = p.c()
+        arr[k].state_dev = state.data_ptr()
+        arr[k].controls_dev = ctrl.data_ptr()
+        arr[k].n_rows, arr[k].horizon, arr[k].m = n, horizon, m
+        arr[k].ws_dev, arr[k].ws_bytes = ws.data_ptr(), ws.numel()
+        arr[k].J_dev = J.data_ptr()
+        arr[k].stats = ctypes.pointer(st)
+    rc = lib().envar_forward_batch(arr, len(jobs), _stream())
+    if rc != EDIVERGED:
+        _check(rc)
+    return [(J, st.as_dict()) for (_, J, st) in keep]
 
 
 def split_fields(p, F):

@@ -1,0 +1,54 @@
+"""Uneven batching: several ensembles of different grids, Reynolds numbers, sizes and
+horizons advance together in merged launches (needs an MI355X).
+
+Each ensemble's costs must equal those of its own envar_forward call bitwise
+(per-member convergence, fixed-order reductions), in FP64 and in mixed precision.
+"""
+import numpy as np
+import pytest
+
+from paper_2605_23812_amd import envar as E
+from paper_2605_23812_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _job(n, Re, N, horizon, precision, seed):
+    p = E.Problem(inv_h=n, Re=Re, precision=precision)
+    p64 = E.Problem(inv_h=n, Re=Re)
+    u0, v0 = inputs.initial_field(n, amp=1e-3, seed=seed)
+    state = E.state_init(p64, u0, v0)
+    E.spinup(p64, state, 30)
+    m = E.control_dim(p)
+    rows = np.vstack([np.zeros(m), inputs.grf_perturbations(N - 1, n, 0.05, 5e-3, seed=seed)])
+    return p, state, torch.tensor(rows, dtype=torch.float64, device="cuda"), horizon
+
+
+@pytest.mark.parametrize("precision", [E.FP64, E.MIXED])
+def test_uneven_batch_equals_separate_forwards(precision):
+    jobs = [
+        _job(64, 4000.0, 5, 37, precision, 1),
+        _job(32, 7500.0, 9, 60, precision, 2),
+        _job(16, 12000.0, 3, 23, precision, 3),
+        _job(128, 7500.0, 2, 20, precision, 4),
+    ]
+    out = E.forward_batch(jobs)
+    torch.cuda.synchronize()
+    for (p, state, ctrl, horizon), (Jb, st) in zip(jobs, out):
+        Js, _, sts = E.forward(p, state, ctrl, horizon)
+        torch.cuda.synchronize()
+        a, b = Jb.cpu().numpy(), Js.cpu().numpy()
+        print("batch", p.inv_h, horizon, a, b, st["mean_cycles"], sts["mean_cycles"], flush=True)
+        assert np.array_equal(a, b)
+        assert st["unconverged"] == 0 and st["steps"] == horizon
+
+
+def test_batch_rejects_mixed_precisions_and_too_many_jobs():
+    a = _job(32, 4000.0, 2, 5, E.FP64, 1)
+    b = _job(32, 4000.0, 2, 5, E.MIXED, 2)
+    with pytest.raises(E.EnvarError) as ei:
+        E.forward_batch([a, b])
+    assert ei.value.code == E.EINVAL
+    with pytest.raises(E.EnvarError):
+        E.forward_batch([a] * 9)
