@@ -226,6 +226,63 @@ int envar_iterate(const envar_problem* p, const void* state_dev, double* f_dev,
                   const envar_ls_params* ls, void* ws_dev, size_t ws_bytes,
                   envar_iter_record* records, void* stream);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of forward-solve requests from concurrent EnVar
+ * optimisations (each request is one set of N+1 forward evaluations,
+ * Sec. 3.3.1). A worker thread owns a HIP stream; admitted requests join the
+ * running batch at the next step boundary and leave it at their own horizon,
+ * so requests that arrive while others are on the GPU overlap with them in
+ * the same merged launches. Device memory comes from one caller-provided
+ * pool: a request is admitted (FIFO) when its footprint
+ * (envar_request_bytes) fits next to the resident ones. */
+typedef struct envar_server envar_server;
+
+typedef struct {
+  int32_t max_jobs;    /* ensembles per merged launch, 1..8 */
+  int32_t precision;   /* ENVAR_FP64 | ENVAR_MIXED for every request */
+  int32_t max_queue;   /* pending (not yet admitted) requests; <= 0: 1024 */
+  int32_t flags;       /* ENVAR_FLAG_NO_GRAPHS to disable graph replay */
+} envar_server_config;
+
+typedef struct {
+  envar_problem problem;   /* its grid, Re, region (precision is the server's) */
+  const void* state_dev;   /* resident base state; must stay valid until the request completes */
+  const double* controls;  /* HOST [n_rows][m]; copied at submission */
+  int32_t n_rows;
+  int32_t horizon;
+  int64_t m;
+} envar_request;
+
+typedef struct {
+  double submit_s;    /* host clock, seconds since envar_server_create */
+  double start_s;     /* admitted into the batch */
+  double done_s;      /* costs available on the host */
+  double latency_s;   /* done_s - submit_s */
+  double queue_s;     /* start_s - submit_s */
+  double cell_steps;  /* fluid cells x horizon x n_rows */
+  int32_t status;     /* ENVAR_OK, ENVAR_EDIVERGED (some J non-finite) or ENVAR_ECANCELLED */
+  int32_t peak_jobs;  /* largest batch this request shared launches with */
+} envar_request_stats;
+
+/* Pool bytes one request occupies while resident. */
+size_t envar_request_bytes(const envar_problem* p, int32_t n_rows);
+
+/* Start a server over the caller's device pool (pool_dev, pool_bytes). */
+int envar_server_create(const envar_server_config* cfg, void* pool_dev, size_t pool_bytes, envar_server** out);
+
+/* Queue a request; returns at once with a ticket. Errors: EINVAL (shape),
+ * ENOMEM (footprint larger than the whole pool), EBUSY (queue full). */
+int envar_submit(envar_server* srv, const envar_request* req, uint64_t* ticket);
+
+/* Wait up to timeout_s (< 0: forever) for a ticket; copies its n_rows costs
+ * into J_host (may be NULL) and fills stats (may be NULL). Each ticket can be
+ * waited on once. Errors: EINVAL (unknown ticket), ETIMEOUT. */
+int envar_wait(envar_server* srv, uint64_t ticket, double timeout_s, double* J_host, envar_request_stats* stats);
+
+/* Stop the worker (pending requests complete as ENVAR_ECANCELLED) and free
+ * the server. The pool is not touched after return. */
+int envar_server_destroy(envar_server* srv);
+
 /* Thread-local message of the last failing call. */
 const char* envar_last_error(void);
 

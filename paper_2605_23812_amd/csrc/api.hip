@@ -5,7 +5,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1402,3 +1408,342 @@ extern "C" int envar_iterate(const envar_problem* p, const void* state_dev, doub
   HIP_OK(hipStreamSynchronize(s));
   return ENVAR_OK;
 }
+
+
+// ============================================================================ serving
+namespace envar {
+
+// first-fit allocator over the caller's device pool (offsets only)
+struct PoolAlloc {
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  void init(size_t n) {
+    size = n & ~size_t(255);
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t n, size_t& off) {
+    n = align256(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n) {
+        off = it->first;
+        const size_t rem = it->second - n;
+        free_.erase(it);
+        if (rem) free_[off + n] = rem;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align256(n);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct ReqLayout {
+  size_t ws, ctrl, J, total;
+};
+static ReqLayout req_layout(const Plan& P, int n) {
+  ReqLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t a = o;
+    o = align256(o + b);
+    return a;
+  };
+  L.ws = take(make_ws(P, n).total);
+  L.ctrl = take((size_t)n * P.m * 8);
+  L.J = take((size_t)n * 8);
+  L.total = o;
+  return L;
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int n = 0, horizon = 0;
+  std::vector<double> controls;
+  Plan P;
+  ReqLayout L{};
+  size_t off = 0;
+  Job job;
+  double* J_pinned = nullptr;
+  hipEvent_t done_ev = nullptr;
+  std::vector<double> J;
+  envar_request_stats st{};
+  int phase = 0;  // 0 queued, 1 running, 2 finishing, 3 done
+};
+
+struct Server {
+  envar_server_config cfg{};
+  char* pool = nullptr;
+  PoolAlloc alloc;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> queue;
+  std::map<uint64_t, Request*> table;
+  std::vector<Request*> running, finishing;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  hipStream_t s = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  Driver D;
+  std::string err;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  template <typename TT>
+  void loop() {
+    (void)hipSetDevice(device);
+    D.cap_max = 0;
+    for (;;) {
+      std::vector<Request*> admitted;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        if (stop) break;
+        while (!queue.empty() && (int)running.size() < cfg.max_jobs) {
+          Request* r = queue.front();
+          size_t off;
+          if (!alloc.alloc(r->L.total, off)) break;  // FIFO: wait for memory
+          queue.pop_front();
+          r->off = off;
+          r->phase = 1;
+          r->st.start_s = now();
+          running.push_back(r);
+          admitted.push_back(r);
+        }
+        if (running.empty() && finishing.empty()) {
+          cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+          continue;
+        }
+      }
+      for (Request* r : admitted) {
+        char* base = pool + r->off;
+        (void)hipMemcpyAsync(base + r->L.ctrl, r->controls.data(), r->controls.size() * 8, hipMemcpyHostToDevice, s);
+        r->job.ws = base + r->L.ws;
+        r->job.ctrl = (const double*)(base + r->L.ctrl);
+        init_members<TT>(r->job, s);
+        D.cap_max = std::max(D.cap_max, r->P.cap_max);
+        if (D.cap == 0) D.cap = D.cap_max;
+        ++D.epoch;
+      }
+      if (!running.empty()) {
+        std::vector<Job*> jobs;
+        int left = 1 << 30;
+        for (Request* r : running) {
+          jobs.push_back(&r->job);
+          left = std::min(left, r->job.horizon - r->job.step);
+          r->st.peak_jobs = std::max(r->st.peak_jobs, (int)running.size());
+        }
+        const int rc = D.step<TT>(jobs, s, nullptr, left, !(cfg.flags & ENVAR_FLAG_NO_GRAPHS));
+        if (rc) {
+          std::lock_guard<std::mutex> lk(mu);
+          err = g_err;
+          stop = true;
+          cv_done.notify_all();
+          break;
+        }
+        bool changed = false;
+        for (size_t k = 0; k < running.size();) {
+          Request* r = running[k];
+          if (r->job.step >= r->job.horizon) {
+            double* Jd = (double*)(pool + r->off + r->L.J);
+            finish_job(r->job, Jd, nullptr, false, s);
+            (void)hipMemcpyAsync(r->J_pinned, Jd, (size_t)r->n * 8, hipMemcpyDeviceToHost, s);
+            (void)hipEventRecord(r->done_ev, s);
+            r->phase = 2;
+            finishing.push_back(r);
+            running.erase(running.begin() + k);
+            changed = true;
+          } else {
+            ++k;
+          }
+        }
+        if (changed) ++D.epoch;
+      }
+      // completions
+      for (size_t k = 0; k < finishing.size();) {
+        Request* r = finishing[k];
+        hipError_t q = hipEventQuery(r->done_ev);
+        if (q == hipErrorNotReady && running.empty()) q = hipEventSynchronize(r->done_ev);
+        if (q == hipSuccess) {
+          r->J.assign(r->J_pinned, r->J_pinned + r->n);
+          bool finite = true;
+          for (double x : r->J) finite = finite && std::isfinite(x);
+          std::lock_guard<std::mutex> lk(mu);
+          r->st.done_s = now();
+          r->st.latency_s = r->st.done_s - r->st.submit_s;
+          r->st.queue_s = r->st.start_s - r->st.submit_s;
+          r->st.status = finite ? ENVAR_OK : ENVAR_EDIVERGED;
+          alloc.release(r->off, r->L.total);
+          r->phase = 3;
+          finishing.erase(finishing.begin() + k);
+          cv_done.notify_all();
+        } else {
+          ++k;
+        }
+      }
+    }
+    D.drain();
+    (void)hipStreamSynchronize(s);
+  }
+};
+
+}  // namespace envar
+
+struct envar_server {
+  envar::Server impl;
+};
+
+extern "C" {
+
+size_t envar_request_bytes(const envar_problem* p, int32_t n_rows) {
+  Plan P;
+  if (make_plan(p, P) || n_rows < 1) return 0;
+  return req_layout(P, n_rows).total;
+}
+
+int envar_server_create(const envar_server_config* cfg, void* pool_dev, size_t pool_bytes, envar_server** out) {
+  if (!cfg || !pool_dev || !out) return fail(ENVAR_EINVAL, "cfg, pool_dev and out are required");
+  if (cfg->max_jobs < 1 || cfg->max_jobs > MAX_SEG) return fail(ENVAR_EINVAL, "max_jobs must be in [1, %d]", MAX_SEG);
+  if (cfg->precision != ENVAR_FP64 && cfg->precision != ENVAR_MIXED) return fail(ENVAR_EINVAL, "unknown precision");
+  auto* srv = new envar_server;
+  Server& S = srv->impl;
+  S.cfg = *cfg;
+  if (S.cfg.max_queue <= 0) S.cfg.max_queue = 1024;
+  S.pool = (char*)pool_dev;
+  S.alloc.init(pool_bytes);
+  S.t0 = std::chrono::steady_clock::now();
+  if (hipGetDevice(&S.device) != hipSuccess || hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess) {
+    delete srv;
+    return fail(ENVAR_EDEVICE, "cannot create the server stream");
+  }
+  if (S.cfg.precision == ENVAR_MIXED)
+    S.worker = std::thread([&S] { S.loop<float>(); });
+  else
+    S.worker = std::thread([&S] { S.loop<double>(); });
+  *out = srv;
+  return ENVAR_OK;
+}
+
+int envar_submit(envar_server* srv, const envar_request* req, uint64_t* ticket) {
+  if (!srv || !req || !ticket) return fail(ENVAR_EINVAL, "NULL argument");
+  Server& S = srv->impl;
+  envar_problem pb = req->problem;
+  pb.precision = S.cfg.precision;
+  pb.flags |= S.cfg.flags & ENVAR_FLAG_NO_GRAPHS;
+  auto* r = new Request;
+  int rc = make_plan(&pb, r->P);
+  if (rc) {
+    delete r;
+    return rc;
+  }
+  if (!req->state_dev || !req->controls || req->n_rows < 1 || req->horizon < 1 || req->m != r->P.m) {
+    delete r;
+    return fail(ENVAR_EINVAL, "bad request (NULL pointer, n_rows/horizon < 1 or m mismatch)");
+  }
+  r->n = req->n_rows;
+  r->horizon = req->horizon;
+  r->L = req_layout(r->P, r->n);
+  if (r->L.total > S.alloc.size) {
+    delete r;
+    return fail(ENVAR_ENOMEM, "request needs %zu bytes, the pool holds %zu", r->L.total, S.alloc.size);
+  }
+  r->controls.assign(req->controls, req->controls + (size_t)r->n * r->P.m);
+  r->job.P = r->P;
+  r->job.w = make_ws(r->P, r->n);
+  r->job.state = req->state_dev;
+  r->job.nmem = r->n;
+  r->job.horizon = r->horizon;
+  r->st.cell_steps = (double)r->P.ncells * r->horizon * r->n;
+  if (hipHostMalloc((void**)&r->J_pinned, (size_t)r->n * 8, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
+    if (r->J_pinned) (void)hipHostFree(r->J_pinned);
+    delete r;
+    return fail(ENVAR_EDEVICE, "cannot allocate the request's host staging");
+  }
+  std::lock_guard<std::mutex> lk(S.mu);
+  if (S.stop) {
+    (void)hipHostFree(r->J_pinned);
+    (void)hipEventDestroy(r->done_ev);
+    delete r;
+    return fail(ENVAR_ECANCELLED, "server stopped: %s", S.err.c_str());
+  }
+  if ((int)S.queue.size() >= S.cfg.max_queue) {
+    (void)hipHostFree(r->J_pinned);
+    (void)hipEventDestroy(r->done_ev);
+    delete r;
+    return fail(ENVAR_EBUSY, "queue full (%d requests)", S.cfg.max_queue);
+  }
+  r->ticket = S.next_ticket++;
+  r->st.submit_s = S.now();
+  S.table[r->ticket] = r;
+  S.queue.push_back(r);
+  *ticket = r->ticket;
+  S.cv_work.notify_one();
+  return ENVAR_OK;
+}
+
+int envar_wait(envar_server* srv, uint64_t ticket, double timeout_s, double* J_host, envar_request_stats* stats) {
+  if (!srv) return fail(ENVAR_EINVAL, "NULL server");
+  Server& S = srv->impl;
+  std::unique_lock<std::mutex> lk(S.mu);
+  auto it = S.table.find(ticket);
+  if (it == S.table.end()) return fail(ENVAR_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  auto ready = [&] { return r->phase == 3 || S.stop; };
+  if (timeout_s < 0)
+    S.cv_done.wait(lk, ready);
+  else if (!S.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready))
+    return fail(ENVAR_ETIMEOUT, "ticket %llu not done after %.3f s", (unsigned long long)ticket, timeout_s);
+  if (r->phase != 3) return fail(ENVAR_ECANCELLED, "server stopped: %s", S.err.c_str());
+  if (J_host) std::copy(r->J.begin(), r->J.end(), J_host);
+  if (stats) *stats = r->st;
+  const int status = r->st.status;
+  S.table.erase(it);
+  (void)hipHostFree(r->J_pinned);
+  (void)hipEventDestroy(r->done_ev);
+  delete r;
+  return status == ENVAR_EDIVERGED ? fail(ENVAR_EDIVERGED, "a cost of ticket %llu is non-finite",
+                                         (unsigned long long)ticket)
+                                   : ENVAR_OK;
+}
+
+int envar_server_destroy(envar_server* srv) {
+  if (!srv) return ENVAR_OK;
+  Server& S = srv->impl;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stop = true;
+    S.cv_work.notify_all();
+    S.cv_done.notify_all();
+  }
+  if (S.worker.joinable()) S.worker.join();
+  for (auto& kv : S.table) {
+    Request* r = kv.second;
+    if (r->J_pinned) (void)hipHostFree(r->J_pinned);
+    if (r->done_ev) (void)hipEventDestroy(r->done_ev);
+    delete r;
+  }
+  S.table.clear();
+  (void)hipStreamDestroy(S.s);
+  delete srv;
+  return ENVAR_OK;
+}
+
+}  // extern "C"

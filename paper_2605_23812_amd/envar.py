@@ -26,6 +26,7 @@ EXPORTS = (
     "envar_state_init", "envar_state_read", "envar_spinup", "envar_forward", "envar_forward_batch",
     "envar_gradient_bytes", "envar_gradient", "envar_iterate_bytes", "envar_iterate",
     "envar_last_error", "envar_version",
+    "envar_request_bytes", "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
 )
 
 
@@ -65,6 +66,25 @@ class _Job(ctypes.Structure):
         ("ws_dev", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("J_dev", ctypes.c_void_p),
         ("stats", ctypes.POINTER(Stats)),
     ]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("max_jobs", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("problem", _Problem), ("state_dev", ctypes.c_void_p), ("controls", ctypes.c_void_p),
+                ("n_rows", ctypes.c_int32), ("horizon", ctypes.c_int32), ("m", ctypes.c_int64)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double), ("cell_steps", ctypes.c_double),
+                ("status", ctypes.c_int32), ("peak_jobs", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class LSParams(ctypes.Structure):
@@ -144,10 +164,17 @@ def lib():
     L.envar_iterate_bytes.restype = sz
     L.envar_iterate.argtypes = [P, vp, dp, dp, i32, i64, i32, ctypes.POINTER(LSParams), vp, sz,
                                 ctypes.POINTER(IterRecord), vp]
+    L.envar_request_bytes.argtypes = [P, i32]
+    L.envar_request_bytes.restype = sz
+    L.envar_server_create.argtypes = [ctypes.POINTER(_ServerConfig), vp, sz, ctypes.POINTER(ctypes.c_void_p)]
+    L.envar_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.envar_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, dp, ctypes.POINTER(RequestStats)]
+    L.envar_server_destroy.argtypes = [vp]
     L.envar_last_error.restype = ctypes.c_char_p
     L.envar_version.restype = ctypes.c_char_p
     for name in ("envar_control_dim", "envar_cell_count", "envar_state_init", "envar_state_read",
-                 "envar_spinup", "envar_forward", "envar_forward_batch", "envar_gradient", "envar_iterate"):
+                 "envar_spinup", "envar_forward", "envar_forward_batch", "envar_gradient", "envar_iterate",
+                 "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -332,6 +359,58 @@ def iterate(p, state, f, perturb, horizon, iters=1, max_trials=8, c1=1e-4, shrin
     _check(lib().envar_iterate(ctypes.byref(p.c()), _ptr(state), _ptr(f), _ptr(perturb), n, m, horizon,
                                ctypes.byref(ls), _ptr(ws), ws.numel(), recs, _stream()))
     return [dict(J0=r.J0, gnorm=r.gnorm, alpha=r.alpha, J_trial=r.J_trial) for r in recs]
+
+
+def request_bytes(p, n_rows):
+    return lib().envar_request_bytes(ctypes.byref(p.c()), n_rows)
+
+
+class Server:
+    """Continuous-batching forward server over a device pool (worker thread in the library)."""
+
+    def __init__(self, pool_bytes, max_jobs=8, precision=MIXED, max_queue=0, flags=0):
+        import torch
+
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        cfg = _ServerConfig(max_jobs, precision, max_queue, flags)
+        h = ctypes.c_void_p()
+        _check(lib().envar_server_create(ctypes.byref(cfg), _ptr(self.pool), self.pool.numel(), ctypes.byref(h)))
+        self.h = h
+        self.precision = precision
+        self._keep = {}
+
+    def submit(self, p, state, controls, horizon):
+        """controls: host numpy [n, m] FP64 (copied by the library); state: device base state tensor."""
+        c = np.ascontiguousarray(controls, dtype=np.float64)
+        req = _Request(p.c(), state.data_ptr(), c.ctypes.data, c.shape[0], horizon, c.shape[1])
+        t = ctypes.c_uint64()
+        _check(lib().envar_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (state, c.shape[0])
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        state, n = self._keep[ticket]
+        J = np.empty(n)
+        st = RequestStats()
+        rc = lib().envar_wait(self.h, ticket, timeout, J.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
+        if rc == ETIMEOUT:
+            raise TimeoutError(lib().envar_last_error().decode())
+        if rc not in (OK, EDIVERGED):
+            _check(rc)
+        del self._keep[ticket]
+        return J, st.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().envar_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version():

@@ -1,0 +1,91 @@
+"""Serving with continuous batching (needs an MI355X).
+
+Requests of different grids, Reynolds numbers, member counts and horizons are
+submitted at staggered times; they join and leave the running batch at step
+boundaries. Each request's costs must equal its own envar_forward bitwise (the
+batch never changes a member's arithmetic), admission must respect the pool
+(FIFO queueing when memory is short, rejection when a request can never fit).
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2605_23812_amd import envar as E
+from paper_2605_23812_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+_STATES = {}
+
+
+def _state(n, Re, seed):
+    key = (n, Re, seed)
+    if key not in _STATES:
+        p = E.Problem(inv_h=n, Re=Re)
+        u0, v0 = inputs.initial_field(n, amp=1e-3, seed=seed)
+        st = E.state_init(p, u0, v0)
+        E.spinup(p, st, 20)
+        torch.cuda.synchronize()
+        _STATES[key] = st
+    return _STATES[key]
+
+
+def _requests(precision):
+    reqs = []
+    specs = [(32, 4000.0, 4, 30), (64, 7500.0, 3, 45), (16, 12000.0, 6, 25), (32, 7500.0, 2, 60),
+             (64, 4000.0, 5, 20), (16, 4000.0, 3, 33)]
+    for k, (n, Re, N, horizon) in enumerate(specs):
+        p = E.Problem(inv_h=n, Re=Re, precision=precision)
+        m = E.control_dim(p)
+        rows = np.vstack([np.zeros(m), inputs.grf_perturbations(N - 1, n, 0.05, 5e-3, seed=100 + k)])
+        reqs.append((p, _state(n, Re, k % 2), rows, horizon))
+    return reqs
+
+
+@pytest.mark.parametrize("precision", [E.FP64, E.MIXED])
+def test_each_request_alone_equals_in_the_mix(precision):
+    reqs = _requests(precision)
+    srv = E.Server(2 << 30, max_jobs=4, precision=precision)
+    try:
+        tickets = []
+        for k, (p, st, rows, horizon) in enumerate(reqs):
+            tickets.append(srv.submit(p, st, rows, horizon))
+            if k % 2 == 1:
+                time.sleep(0.02)  # later requests arrive while earlier ones run
+        results = [srv.wait(t, timeout=120.0) for t in tickets]
+    finally:
+        srv.close()
+    peak = max(r[1]["peak_jobs"] for r in results)
+    print("peak batch", peak, [round(r[1]["latency_s"], 4) for r in results], flush=True)
+    assert peak >= 2  # requests really shared launches
+    for (p, st, rows, horizon), (J, info) in zip(reqs, results):
+        Js, _, _ = E.forward(p, st, torch.tensor(rows, device="cuda"), horizon)
+        torch.cuda.synchronize()
+        assert info["status"] == E.OK
+        assert np.array_equal(J, Js.cpu().numpy()), (p.inv_h, horizon)
+
+
+def test_admission_by_footprint():
+    reqs = _requests(E.MIXED)
+    sizes = [E.request_bytes(p, rows.shape[0]) for p, _, rows, _ in reqs]
+    pool = int(max(sizes) * 1.5)  # room for one large request at a time: the rest queue (FIFO)
+    srv = E.Server(pool, max_jobs=8, precision=E.MIXED)
+    try:
+        tickets = [srv.submit(p, st, rows, h) for p, st, rows, h in reqs]
+        results = [srv.wait(t, timeout=120.0) for t in tickets]
+        # a request larger than the whole pool is rejected at submission
+        p = E.Problem(inv_h=128, Re=7500.0, precision=E.MIXED)
+        big = np.zeros((64, E.control_dim(p)))
+        with pytest.raises(E.EnvarError) as ei:
+            srv.submit(p, _state(32, 4000.0, 0), big, 10)
+        assert ei.value.code in (E.ENOMEM, E.EINVAL)
+    finally:
+        srv.close()
+    for (p, st, rows, horizon), (J, info) in zip(reqs, results):
+        Js, _, _ = E.forward(p, st, torch.tensor(rows, device="cuda"), horizon)
+        torch.cuda.synchronize()
+        assert np.array_equal(J, Js.cpu().numpy())
+    starts = [r[1]["start_s"] for r in results]
+    assert starts == sorted(starts)  # FIFO admission
