@@ -92,6 +92,97 @@ def roofline(st, prec, ncells, members):
     }
 
 
+def serving(torch, E, inputs, nreq, horizon_scale, seed=2605238125):
+    """Poisson arrivals of forward-solve requests (4 optimisations, mixed grids / Re / N / horizons).
+
+    Every request draws h in {1/64, 1/128, 1/256}, Re in {4000, 7500, 12000},
+    N in {16, 32, 64, 128} and a horizon in {2k, 5k, 10k} steps (scaled by
+    horizon_scale) from a seeded generator. Arrivals are Poisson at 0.8 x the
+    capacity measured on the same mix. Reported: throughput and p50/p99
+    latency of the continuous-batching server (mixed precision), beside a
+    queue-then-plain-FP64 server (one request at a time, FIFO) simulated from
+    measured FP64 service times of the same requests at the same arrival times.
+    """
+    rng = np.random.default_rng(seed)
+    grids, res, sizes = [64, 128, 256], [4000.0, 7500.0, 12000.0], [16, 32, 64, 128]
+    horizons = [max(1, int(round(hz * horizon_scale))) for hz in (2000, 5000, 10000)]
+    states, pools = {}, {}
+    for n in grids:
+        pools[n] = inputs.grf_perturbations(8, n, ELL, SIGMA, seed=seed + n)
+        for Re in res:
+            p64 = E.Problem(inv_h=n, Re=Re)
+            u0, v0 = inputs.initial_field(n, amp=1e-3)
+            st = E.state_init(p64, u0, v0)
+            E.spinup(p64, st, 200)
+            states[(n, Re)] = st
+    torch.cuda.synchronize()
+    reqs = []
+    for k in range(nreq):
+        n, Re = int(rng.choice(grids)), float(rng.choice(res))
+        N, hz = int(rng.choice(sizes)), int(rng.choice(horizons))
+        pick = rng.integers(0, 8, size=N)
+        scale = rng.uniform(0.5, 1.5, size=(N, 1))
+        rows = np.vstack([np.zeros(pools[n].shape[1]), pools[n][pick][1:] * scale[1:]])
+        reqs.append(dict(opt=k % 4, n=n, Re=Re, rows=rows, horizon=hz, cells=5 * n * n))
+    work = sum(r["cells"] * r["rows"].shape[0] * r["horizon"] for r in reqs)
+    # FP64 one-at-a-time service times (also the capacity reference of the baseline)
+    svc64 = []
+    for r in reqs:
+        p = E.Problem(inv_h=r["n"], Re=r["Re"], precision=E.FP64)
+        c = torch.tensor(r["rows"], device="cuda")
+        torch.cuda.synchronize()
+        t = time.time()
+        E.forward(p, states[(r["n"], r["Re"])], c, r["horizon"], stats=False)
+        torch.cuda.synchronize()
+        svc64.append(time.time() - t)
+    # capacity of the batched mixed-precision server: all requests at once
+    def run(arrivals):
+        srv = E.Server(96 << 30, max_jobs=8, precision=E.MIXED)
+        try:
+            t0 = time.time()
+            tickets = []
+            for r, ta in zip(reqs, arrivals):
+                dtw = ta - (time.time() - t0)
+                if dtw > 0:
+                    time.sleep(dtw)
+                p = E.Problem(inv_h=r["n"], Re=r["Re"], precision=E.MIXED)
+                tickets.append(srv.submit(p, states[(r["n"], r["Re"])], r["rows"], r["horizon"]))
+            res_ = [srv.wait(t, timeout=600.0) for t in tickets]
+            makespan = time.time() - t0
+        finally:
+            srv.close()
+        return res_, makespan
+    burst, burst_span = run([0.0] * nreq)
+    capacity = nreq / burst_span  # requests per second with the queue always full
+    lam = 0.8 * capacity
+    gaps = rng.exponential(1.0 / lam, size=nreq)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    res_, makespan = run(list(arrivals))
+    lat = np.array([r[1]["latency_s"] for r in res_])
+    # queue-then-FP64 baseline: FIFO single server with the measured service times
+    done, lat64 = 0.0, []
+    for ta, sv in zip(arrivals, svc64):
+        start = max(ta, done)
+        done = start + sv
+        lat64.append(done - ta)
+    lat64 = np.array(lat64)
+    finite = all(np.all(np.isfinite(r[0])) for r in res_)
+    return {
+        "requests": nreq, "horizon_scale": horizon_scale, "horizons": horizons,
+        "arrival_rate_per_s": round(lam, 3), "capacity_req_per_s": round(capacity, 3),
+        "cell_steps": work, "throughput_cell_steps_per_s": round(work / makespan, 1),
+        "burst_throughput_cell_steps_per_s": round(work / burst_span, 1),
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 4), "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+        "peak_concurrent_requests": int(max(r[1]["peak_jobs"] for r in res_)),
+        "baseline_queue_fp64": {
+            "throughput_cell_steps_per_s": round(work / max(done, 1e-9), 1),
+            "p50_latency_s": round(float(np.percentile(lat64, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat64, 99)), 4),
+        },
+        "all_J_finite": bool(finite),
+    }
+
+
 def cpu_baseline(state_host, rows, steps, procs):
     """The oracle (plain FP64 numpy/scipy) on a bounded sample: every member for `steps` steps."""
     from oracle import envar as OE
@@ -119,6 +210,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-horizon-scale", type=float, default=0.05)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the ensemble members of one MI355X "
@@ -203,6 +297,11 @@ def main():
         }
         log("baselines", extra)
 
+    serve = None
+    if not args.no_serve:
+        serve = serving(torch, E, inputs, args.serve_requests, args.serve_horizon_scale)
+        log("serving", serve)
+
     cpu = None
     if not args.no_cpu:
         u, v, tu, tv, _ = E.state_read(E.Problem(inv_h=INV_H, Re=RE), state)
@@ -239,7 +338,11 @@ def main():
         "J_finite": bool(np.all(np.isfinite(J_mixed_long))),
         "roofline": roofline(st, "mixed", ncells, nrows),
         "cpu_baseline": cpu,
+        "serving": serve,
     }
+    if serve is not None:
+        out["p50_latency_s"] = serve["p50_latency_s"]
+        out["p99_latency_s"] = serve["p99_latency_s"]
     out.update(extra)
     print(json.dumps(out), flush=True)
 

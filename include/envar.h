@@ -219,7 +219,9 @@ typedef struct {
  * the N+1 forwards of f and f + perturb_i, forms g, and moves f <- f - alpha g.
  * f_dev [m] (device, in/out), perturb_dev [n][m] (device, held fixed).
  * ws_dev must hold envar_iterate_bytes. records (host, `iters` entries) may be
- * NULL. Synchronous (the step decisions read costs on the host). */
+ * NULL. When a line search finds no sufficient decrease the loop stops: that
+ * record has alpha = 0 and f is left unchanged. Synchronous (the step
+ * decisions read costs on the host). */
 size_t envar_iterate_bytes(const envar_problem* p, int32_t n, int64_t m);
 int envar_iterate(const envar_problem* p, const void* state_dev, double* f_dev,
                   const double* perturb_dev, int32_t n, int64_t m, int32_t horizon,

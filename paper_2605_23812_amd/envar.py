@@ -358,7 +358,12 @@ def iterate(p, state, f, perturb, horizon, iters=1, max_trials=8, c1=1e-4, shrin
     recs = (IterRecord * iters)()
     _check(lib().envar_iterate(ctypes.byref(p.c()), _ptr(state), _ptr(f), _ptr(perturb), n, m, horizon,
                                ctypes.byref(ls), _ptr(ws), ws.numel(), recs, _stream()))
-    return [dict(J0=r.J0, gnorm=r.gnorm, alpha=r.alpha, J_trial=r.J_trial) for r in recs]
+    out = []
+    for r in recs:
+        out.append(dict(J0=r.J0, gnorm=r.gnorm, alpha=r.alpha, J_trial=r.J_trial))
+        if r.alpha == 0.0:  # the line search failed: the loop stopped here
+            break
+    return out
 
 
 def request_bytes(p, n_rows):
