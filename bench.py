@@ -38,8 +38,20 @@ BYTES_PER_CELL = {
     ("post", "fp64"): 26.0, ("post", "mixed"): 25.0,
     # phi64 (8) + b64 (8) -> r32 (4)
     ("resid", "mixed"): 20.0,
-    # u*, v* (16) + phi (8) -> u, v (16) + cost sums S1 in/out (32)
-    ("project", "fp64"): 72.0, ("project", "mixed"): 72.0,
+    # u*, v* (16) + phi (8) -> u, v (16) + cost sums S1 in/out (32) + next warm start in/out (16)
+    ("project", "fp64"): 88.0, ("project", "mixed"): 88.0,
+}
+
+# HBM bytes per launch from the two calibrated rocprofv3 counter passes (FETCH_SIZE x 2.000,
+# WRITE_SIZE x 1.000 against the library's streaming copy), h=1/128, 65 members, mixed precision,
+# for the kernel sources as committed with profiles/k_resid64_h128_65members_mixed.md. Set an entry
+# to None when its kernel changes.
+MEASURED_TRAFFIC = {
+    ("resid", "mixed"): 107.0e6,
+    ("pre", "mixed"): 54.3e6,
+    ("post", "mixed"): 146.9e6,
+    ("predictor", "mixed"): 362.1e6,
+    ("project", "mixed"): 558.7e6,
 }
 
 
@@ -47,8 +59,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_inputs(torch, E, inputs):
-    p64 = E.Problem(inv_h=INV_H, Re=RE, precision=E.FP64)
+def build_inputs(torch, E, inputs, flags=0):
+    p64 = E.Problem(inv_h=INV_H, Re=RE, precision=E.FP64, flags=flags)
     u0, v0 = inputs.initial_field(INV_H, amp=1e-3)
     state = E.state_init(p64, u0, v0)
     t = time.time()
@@ -67,7 +79,7 @@ def one_pass(E, p, state, ctrl, horizon, ws, J, gws, g, stats=False):
     return st
 
 
-def roofline(st, prec, ncells, members):
+def roofline(st, prec, ncells, members, copy_gbs=None):
     cyc = st["mean_cycles"]
     per_step = {
         "predictor": st["predictor_us"],
@@ -82,11 +94,13 @@ def roofline(st, prec, ncells, members):
               "post": st["post_us"], "resid": st["resid_us"]}[name]
     nbytes = BYTES_PER_CELL[(name, prec)] * ncells * members
     achieved = nbytes / (avg_us * 1e-6) / 1e9
+    traffic = MEASURED_TRAFFIC.get((name, prec)) if members == N_MEMBERS + 1 else None
     return {
         "kernel": {"predictor": "k_predictor", "project": "k_project_cost", "pre": "k_mg_pre (finest level)",
                    "post": "k_mg_post (finest level)", "resid": "k_resid64"}[name],
         "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+        "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
         "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2),
         "per_step_us": {k: round(v, 1) for k, v in per_step.items()},
     }
@@ -211,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--no-graphs", action="store_true", help="launch every step eagerly (profiler counter passes)")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-horizon-scale", type=float, default=0.05)
     args = ap.parse_args()
@@ -226,10 +242,25 @@ def main():
 
     E.lib()
     torch.cuda.init()
-    state, ctrl, m = build_inputs(torch, E, inputs)
+    # measured streaming-copy ceiling (and the reference for traffic counters)
+    src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        E.stream_copy(src, dst)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        E.stream_copy(src, dst)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * args.copy_bytes * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    log(f"stream copy: {copy_gbs:.0f} GB/s (read + write)")
+    gflag = E.FLAG_NO_GRAPHS if args.no_graphs else 0
+    state, ctrl, m = build_inputs(torch, E, inputs, gflag)
     nrows = ctrl.shape[0]
-    pm = E.Problem(inv_h=INV_H, Re=RE, precision=E.MIXED, flags=E.FLAG_TIME_KERNELS)
-    p64 = E.Problem(inv_h=INV_H, Re=RE, precision=E.FP64, flags=E.FLAG_TIME_KERNELS)
+    pm = E.Problem(inv_h=INV_H, Re=RE, precision=E.MIXED, flags=E.FLAG_TIME_KERNELS | gflag)
+    p64 = E.Problem(inv_h=INV_H, Re=RE, precision=E.FP64, flags=E.FLAG_TIME_KERNELS | gflag)
     ncells = E.cell_count(pm)
     ws = E._bytes_tensor(E.workspace_bytes(pm, nrows))
     gws = E._bytes_tensor(E.gradient_bytes(nrows - 1, m, E.MIXED))
@@ -293,7 +324,7 @@ def main():
             "speedup_fp64_batched_vs_fp64_one_at_a_time": round(rate_64 / rate_1, 2),
             "J_rel_err_mixed_vs_fp64_max": float(np.max(np.abs(jm - j64) / np.abs(j64))),
             "fp64_mean_vcycles_per_step": round(st64["mean_cycles"], 3),
-            "fp64_roofline": roofline(st64, "fp64", ncells, nrows),
+            "fp64_roofline": roofline(st64, "fp64", ncells, nrows, copy_gbs),
         }
         log("baselines", extra)
 
@@ -336,7 +367,8 @@ def main():
         "mean_refinement_passes_per_step": round(st["mean_cycles"], 3),
         "max_div": st["max_div"],
         "J_finite": bool(np.all(np.isfinite(J_mixed_long))),
-        "roofline": roofline(st, "mixed", ncells, nrows),
+        "roofline": roofline(st, "mixed", ncells, nrows, copy_gbs),
+        "measured_copy_GBs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "serving": serve,
     }

@@ -288,6 +288,12 @@ int envar_server_destroy(envar_server* srv);
 /* Thread-local message of the last failing call. */
 const char* envar_last_error(void);
 
+/* Plain device-to-device streaming copy of `bytes` (a multiple of 16,
+ * 16-byte aligned buffers): the measured HBM ceiling beside the kernels'
+ * roofline, and the reference workload that calibrates memory-traffic
+ * counters. Not part of the method. */
+int envar_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
+
 /* Library version string. */
 const char* envar_version(void);
 

@@ -869,6 +869,14 @@ extern "C" {
 const char* envar_last_error(void) { return g_err.c_str(); }
 const char* envar_version(void) { return "envar-mi355x 0.1 (gfx950)"; }
 
+int envar_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream) {
+  if (!src_dev || !dst_dev || bytes % 16 != 0) return fail(ENVAR_EINVAL, "16-byte multiple and non-NULL buffers required");
+  if (((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15) return fail(ENVAR_EINVAL, "buffers must be 16-byte aligned");
+  launch_stream_copy(src_dev, dst_dev, (long)(bytes / 16), (hipStream_t)stream);
+  HIP_OK(hipGetLastError());
+  return ENVAR_OK;
+}
+
 int envar_control_dim(const envar_problem* p, int64_t* m) {
   Plan P;
   int rc = make_plan(p, P);

@@ -188,6 +188,7 @@ void launch_store_base(long plane, const double* u, const double* v, const TT* t
 void launch_fields_out(const Geo& g, long plane, int nmem, const double* u, const double* v, double* out,
                        hipStream_t s);
 void launch_clear_flag(int* flag, hipStream_t s);
+void launch_stream_copy(const void* src, void* dst, long n16, hipStream_t s);
 
 template <typename T>
 void launch_mg_pre(const Multi<MGArgs<T>>& m, hipStream_t s);

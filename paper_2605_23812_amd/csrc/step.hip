@@ -408,6 +408,16 @@ __global__ void k_fields_out(Geo g, long plane, const double* u, const double* v
 
 __global__ void k_clear_flag(int* flag) { *flag = 0; }
 
+// Plain streaming copy (16-byte vectors, grid-stride): the measured HBM ceiling
+// and the reference that calibrates the memory-traffic counters.
+__global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                     long n) {
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < n; k += (long)gridDim.x * 256L) dst[k] = src[k];
+}
+void launch_stream_copy(const void* src, void* dst, long n16, hipStream_t s) {
+  hipLaunchKernelGGL(k_stream_copy, dim3(256 * 64), dim3(256), 0, s, (const double2*)src, (double2*)dst, n16);
+}
+
 // ---------------------------------------------------------------------------- launchers
 template <typename TT>
 void launch_predictor(const Multi<PredArgs<TT>>& m, hipStream_t s) {

@@ -25,7 +25,7 @@ EXPORTS = (
     "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",
     "envar_state_init", "envar_state_read", "envar_spinup", "envar_forward", "envar_forward_batch",
     "envar_gradient_bytes", "envar_gradient", "envar_iterate_bytes", "envar_iterate",
-    "envar_last_error", "envar_version",
+    "envar_last_error", "envar_version", "envar_stream_copy",
     "envar_request_bytes", "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
 )
 
@@ -170,11 +170,13 @@ def lib():
     L.envar_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
     L.envar_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, dp, ctypes.POINTER(RequestStats)]
     L.envar_server_destroy.argtypes = [vp]
+    L.envar_stream_copy.argtypes = [vp, vp, sz, vp]
     L.envar_last_error.restype = ctypes.c_char_p
     L.envar_version.restype = ctypes.c_char_p
     for name in ("envar_control_dim", "envar_cell_count", "envar_state_init", "envar_state_read",
                  "envar_spinup", "envar_forward", "envar_forward_batch", "envar_gradient", "envar_iterate",
-                 "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy"):
+                 "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
+                 "envar_stream_copy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -416,6 +418,10 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def stream_copy(src, dst):
+    _check(lib().envar_stream_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), _stream()))
 
 
 def version():

@@ -125,3 +125,24 @@ def test_forward_penalty_and_member_independence():
     # applied outside the flow response: zero horizon -> J is the penalty alone
     assert envar.forward_member(p, base, f, 0) == pytest.approx(pen, rel=1e-14)
     assert Jzero_obs > 0.0
+
+
+def test_iterate_armijo_invariants():
+    """The descent loop's own invariants: sufficient decrease at the accepted step, the next
+    centre run is the accepted trial (same forward, bitwise), and f moves by exactly -alpha g."""
+    from paper_2605_23812_amd import inputs
+
+    p = Problem(inv_h=16, Re=1000.0)
+    u0, v0 = inputs.initial_field(16, amp=1e-2, seed=4)
+    base = spinup(p, initial_state(p, u0, v0), 30)
+    pert = inputs.grf_perturbations(6, 16, 0.1, 1e-5, seed=8)
+    f0 = np.zeros(p.m)
+    hist = envar.iterate(p, base, f0, pert, 12, iters=2)
+    assert len(hist) == 2 and hist[0]["alpha"] > 0.0
+    h0 = hist[0]
+    c1 = 1e-4
+    assert h0["J_new"] <= h0["J0"] - c1 * h0["alpha"] * h0["gnorm"] ** 2
+    assert hist[1]["J0"] == h0["J_new"]
+    rows = np.vstack([f0, f0 + pert])
+    g = envar.gradient(rows, envar.forward(p, base, rows, 12))
+    assert np.array_equal(h0["f"], f0 - h0["alpha"] * g)
