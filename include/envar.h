@@ -55,9 +55,11 @@ enum { ENVAR_CAVITY = 0, ENVAR_CHANNEL = 1 };
  *  CAVITY: the cavity cells only, 1 / h^2 cells
  *  BOX:    fluid cells with centre in [box[0], box[1]] x [box[2], box[3]] (Sec. 4.1 actuation window) */
 enum { ENVAR_REGION_COLUMN = 0, ENVAR_REGION_CAVITY = 1, ENVAR_REGION_BOX = 2 };
-/* FP64: every kernel in FP64. MIXED: stencil tendencies and the multigrid
- * V-cycle in FP32, wrapped in FP64 iterative refinement of the pressure; the
- * state, the coarse solve, the cost sums and the least squares stay FP64. */
+/* FP64: every kernel in FP64. MIXED: the multigrid V-cycle (every smoothing,
+ * restriction and prolongation) in FP32, wrapped in FP64 iterative refinement
+ * of the pressure; the state, the AB2 tendencies, the coarse solve, the cost
+ * sums and the least squares stay FP64 (tendencies rounded to FP32 would put
+ * rounding noise into every step's divergence and cost a refinement pass). */
 enum { ENVAR_FP64 = 0, ENVAR_MIXED = 1 };
 
 /* One forward problem, passed by value-pointer; fields <= 0 take defaults. */

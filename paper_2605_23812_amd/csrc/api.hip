@@ -186,7 +186,7 @@ static int make_plan(const envar_problem* pin, Plan& P) {
 
 // workspace layout of a forward over nmem members
 struct WS {
-  size_t u, v, us, vs, tuA, tvA, tuB, tvB, phiA, phiB, phiC, b0, e0, r0;
+  size_t u, v, us, vs, tuA, tvA, tuB, tvB, phiA, phiB, phiC, phiQ, b0, e0, r0;
   size_t lphiA[MAX_LEVELS], lphiB[MAX_LEVELS], lb[MAX_LEVELS];
   size_t s1u, s1v, s2part, norms, stats, divmax;
   size_t total;
@@ -201,7 +201,7 @@ static WS make_ws(const Plan& P, int nmem) {
     return at;
   };
   const long pl = P.lev[0].plane();
-  const size_t tsz = P.mixed ? 4 : 8;  // tendency storage
+  const size_t tsz = 8;  // tendency storage (FP64 in both precisions)
   const size_t vsz = P.mixed ? 4 : 8;  // V-cycle storage
   w.u = take(nmem * pl * 8);
   w.v = take(nmem * pl * 8);
@@ -214,6 +214,7 @@ static WS make_ws(const Plan& P, int nmem) {
   w.phiA = take(nmem * pl * 8);
   w.phiB = P.mixed ? 0 : take(nmem * pl * 8);
   w.phiC = take(nmem * pl * 8);  // previous pressure / next warm start
+  w.phiQ = take(nmem * pl * 8);  // pressure two steps back (quadratic warm start)
   w.b0 = take(nmem * pl * 8);
   w.e0 = P.mixed ? take(nmem * pl * 4) : 0;
   w.r0 = P.mixed ? take(nmem * pl * 4) : 0;
@@ -401,9 +402,15 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
         if (l == 0) {
           const int cur = j->step & 1;
           a.phi_in = mixed ? nullptr : (const T*)j->phi(cur);
-          a.b = mixed ? (const T*)j->w_<float>(w.r0) : (const T*)j->w_<double>(w.b0);
+          a.b = mixed ? nullptr : (const T*)j->w_<double>(w.b0);
           a.zero_guess = mixed ? 1 : 0;
           a.phi_out = mixed ? (T*)j->w_<float>(w.e0) : (T*)j->w_<double>(w.phiB);
+          if (mixed) {  // the residual of the FP64 pressure after pass k - 1 is formed in this launch
+            a.phi64 = j->phi(cur);
+            a.b64 = j->w_<double>(w.b0);
+            a.r_out = (T*)j->w_<float>(w.r0);
+            a.rslot = k - 1;
+          }
         } else {
           a.phi_in = nullptr;
           a.b = j->w_<T>(w.lb[l]);
@@ -485,10 +492,14 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
     }
     if (timed && !mixed) tm->mark(TM_CYCLE, 1, st);
   };
-  auto resid = [&](int k) {
+  // standalone FP64 residual into slot k: for every job when `all`, else only for
+  // jobs whose finest level runs in the one-workgroup coarse kernel (the tiled
+  // finest pre kernel forms it otherwise)
+  auto resid = [&](int k, bool all) {
     auto m = seg_begin<ResidArgs>();
     for (Job* j : J) {
       const Plan& P = j->P;
+      if (!all && P.nlev_grid > 0) continue;
       ResidArgs r{};
       r.g = P.lev[0];
       r.tiling = P.st_tl;
@@ -505,19 +516,21 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
       r.k = k;
       seg_add(m, r, r.ntiles * r.nmem);
     }
-    launch_resid64(m, st);
+    if (m.nseg > 0) launch_resid64(m, st);
   };
   if (!mixed) {
     for (int k = 0; k < cap; ++k) vcycle(k);
   } else {
-    if (tm) tm->mark(TM_RESID, 0, st);
-    resid(0);
-    if (tm) tm->mark(TM_RESID, 1, st);
+    // slot k - 1 is written by pass k (its finest pre kernel), slot cap by the last residual
+    resid(0, false);
     for (int k = 1; k <= cap; ++k) {
       vcycle(k);
-      resid(k);
+      if (k < cap) resid(k, false);
       if (tm && k == k_timed) tm->mark(TM_CYCLE, 1, st);
     }
+    if (tm) tm->mark(TM_RESID, 0, st);
+    resid(cap, true);
+    if (tm) tm->mark(TM_RESID, 1, st);
   }
 }
 
@@ -525,12 +538,12 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
 template <typename TT>
 static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
   {
-    auto m = seg_begin<PredArgs<TT>>();
+    auto m = seg_begin<PredArgs<double>>();
     for (Job* j : J) {
       const Plan& P = j->P;
       const WS& w = j->w;
       const bool even = (j->step & 1) == 0;
-      PredArgs<TT> a{};
+      PredArgs<double> a{};
       a.g = P.lev[0];
       a.tiling = P.st_tl;
       a.ntiles = P.st_tiles;
@@ -543,10 +556,10 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer
       a.v = j->w_<double>(w.v);
       a.us = j->w_<double>(w.us);
       a.vs = j->w_<double>(w.vs);
-      a.tu_prev = j->w_<TT>(even ? w.tuA : w.tuB);
-      a.tv_prev = j->w_<TT>(even ? w.tvA : w.tvB);
-      a.tu = j->w_<TT>(even ? w.tuB : w.tuA);
-      a.tv = j->w_<TT>(even ? w.tvB : w.tvA);
+      a.tu_prev = j->w_<double>(even ? w.tuA : w.tuB);
+      a.tv_prev = j->w_<double>(even ? w.tvA : w.tvB);
+      a.tu = j->w_<double>(even ? w.tuB : w.tuA);
+      a.tv = j->w_<double>(even ? w.tvB : w.tvA);
       a.b = j->w_<double>(w.b0);
       a.ctrl = j->ctrl;
       a.m = P.m;
@@ -557,7 +570,7 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer
       seg_add(m, a, a.ntiles * a.nmem);
     }
     if (tm) tm->mark(TM_PRED, 0, st);
-    launch_predictor<TT>(m, st);
+    launch_predictor<double>(m, st);
     if (tm) tm->mark(TM_PRED, 1, st);
   }
   batch_pressure<TT>(J, st, cap, tm);
@@ -581,6 +594,8 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer
       pj.vs = j->w_<double>(w.vs);
       pj.phi = j->phi(cur);
       pj.phi_next = j->phi(cur ^ 1);
+      pj.phi_old = j->w_<double>(w.phiQ);
+      pj.stats = j->w_<double>(w.stats);
       pj.shu = at<double>(j->state, P.s_shu);
       pj.shv = at<double>(j->state, P.s_shv);
       pj.s1u = j->w_<double>(w.s1u);
@@ -616,7 +631,7 @@ template <typename TT>
 static void init_members(const Job& j, hipStream_t s) {
   const Plan& P = j.P;
   const WS& w = j.w;
-  InitArgs<TT> ia{};
+  InitArgs<double> ia{};
   ia.nmem = j.nmem;
   ia.ntiles = P.st_tiles;
   ia.plane = P.lev[0].plane();
@@ -632,14 +647,14 @@ static void init_members(const Job& j, hipStream_t s) {
   ia.vs = j.w_<double>(w.vs);
   ia.phi = j.w_<double>(w.phiA);
   ia.phi2 = j.w_<double>(w.phiC);
-  ia.tu = j.w_<TT>(w.tuA);
-  ia.tv = j.w_<TT>(w.tvA);
+  ia.tu = j.w_<double>(w.tuA);
+  ia.tv = j.w_<double>(w.tvA);
   ia.s1u = j.w_<double>(w.s1u);
   ia.s1v = j.w_<double>(w.s1v);
   ia.s2part = j.w_<double>(w.s2part);
   ia.stats = j.w_<double>(w.stats);
   ia.divmax = j.w_<double>(w.divmax);
-  launch_init_members<TT>(ia, s);
+  launch_init_members<double>(ia, s);
 }
 
 // J of a finished job (and optionally its fields / the spin-up store)
@@ -672,16 +687,9 @@ static void finish_job(const Job& j, double* J_dev, double* fields_dev, bool spi
     void* S = (void*)j.state;
     const long pl = P.lev[0].plane();
     double* phi_last = j.phi(j.last_cur);
-    if (P.mixed)
-      launch_store_base<float>(pl, j.w_<double>(w.u), j.w_<double>(w.v), j.w_<float>(inB ? w.tuB : w.tuA),
-                               j.w_<float>(inB ? w.tvB : w.tvA), phi_last, at<double>(S, P.s_u),
-                               at<double>(S, P.s_v), at<double>(S, P.s_tu), at<double>(S, P.s_tv),
-                               at<double>(S, P.s_phi), s);
-    else
-      launch_store_base<double>(pl, j.w_<double>(w.u), j.w_<double>(w.v), j.w_<double>(inB ? w.tuB : w.tuA),
-                                j.w_<double>(inB ? w.tvB : w.tvA), phi_last, at<double>(S, P.s_u),
-                                at<double>(S, P.s_v), at<double>(S, P.s_tu), at<double>(S, P.s_tv),
-                                at<double>(S, P.s_phi), s);
+    launch_store_base<double>(pl, j.w_<double>(w.u), j.w_<double>(w.v), j.w_<double>(inB ? w.tuB : w.tuA),
+                              j.w_<double>(inB ? w.tvB : w.tvA), phi_last, at<double>(S, P.s_u), at<double>(S, P.s_v),
+                              at<double>(S, P.s_tu), at<double>(S, P.s_tv), at<double>(S, P.s_phi), s);
     launch_clear_flag(at<int>(S, P.s_meta), s);
     launch_shift(P.lev[0], at<double>(S, P.s_u), at<double>(S, P.s_v), at<double>(S, P.s_shu), at<double>(S, P.s_shv),
                  s);
@@ -752,8 +760,10 @@ struct Driver {
   }
   void absorb(size_t n) {
     int mx = 0;
-    for (size_t q = 0; q < n; q += STATS_STRIDE) mx = std::max(mx, (int)pinned[q + ST_MAXCYC]);
-    // ST_MAXCYC is a running maximum, so the cap never drops below what any member needed
+    for (size_t q = 0; q < n; q += STATS_STRIDE) mx = std::max(mx, (int)std::ceil(pinned[q + ST_RECENT]));
+    // ST_RECENT decays by one cycle per 16 steps: the cap follows what the members needed
+    // lately (start-up transients fade), one cycle of headroom above it; a member that hits
+    // the cap reports cap cycles, so the next poll raises it
     cap = std::min(cap_max, std::max(2, mx + 1));
   }
   int start_async(const std::vector<Job*>& J, hipStream_t s) {

@@ -33,7 +33,8 @@ struct Multi {
 };
 
 // per-member statistics slots (FP64)
-enum { ST_CYCLES = 0, ST_MAXCYC, ST_UNCONV, ST_MAXRES, ST_STEPS, ST_J, STATS_STRIDE = 8 };
+// ST_RECENT: a maximum of the cycles used that decays by 1/16 per step (drives the cycle cap)
+enum { ST_CYCLES = 0, ST_MAXCYC, ST_UNCONV, ST_MAXRES, ST_STEPS, ST_J, ST_RECENT, STATS_STRIDE = 8 };
 
 template <typename TT>
 struct PredArgs {
@@ -71,7 +72,12 @@ struct ProjArgs {
   const double* us;
   const double* vs;
   const double* phi;
-  double* phi_next;   // optional: receives the warm start 2 phi^{n+1} - phi^n of the next solve (holds phi^n on entry)
+  // optional warm start of the next solve, extrapolated from the pressures of the last steps:
+  // phi_next holds phi^{n-1} on entry and receives the guess for phi^{n+1};
+  // phi_old holds phi^{n-2} on entry and receives phi^{n-1}
+  double* phi_next;
+  double* phi_old;
+  const double* stats;  // [nmem][STATS_STRIDE]: steps done so far select the extrapolation order
   const double* shu;  // cost shift (dense cells, shared by members)
   const double* shv;
   double* s1u;        // [nmem][cplane] running sums of (u_c - s_c); NULL = no cost
@@ -131,6 +137,14 @@ struct MGArgs {
   T* bc;              // coarse right-hand side
   double* add_to;     // post, mixed: phi64 += phi instead of storing phi (NULL = store)
   int zero_guess;     // pre: start from phi = 0
+  // pre, mixed finest level (iterative refinement): the right-hand side is the
+  // FP64 residual b64 - L phi64, computed on the window; dt*max|r| of the tile
+  // goes to norms[rslot] (members with norms[rslot-1] <= tol exit at once)
+  // (also stored, as T, in r_out on the tile's cells for the post kernel)
+  const double* phi64;
+  const double* b64;
+  T* r_out;
+  int rslot;
   // convergence control: skip members whose previous cycle met tol
   double* norms;      // [nmem][norm_slots]
   int norm_slots;

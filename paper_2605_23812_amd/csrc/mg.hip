@@ -14,6 +14,11 @@
 //         across the outflow face), NS sweeps, optionally the per-member
 //         max-norm of dt r (wave reductions + atomicMax); writes phi (or adds
 //         it to the FP64 pressure in iterative refinement).
+// In iterative refinement (FP32 V-cycles inside an FP64 solve) the finest
+// pre kernel starts from the FP64 pressure instead of an FP32 right-hand side:
+// it stages phi64 of its window in LDS, forms r = b64 - L phi64 there (the
+// FP32 right-hand side of the correction), and records dt max|r| over its tile.
+// phi64 is only read in that launch, so neighbouring tiles see one version.
 // Levels with inv_h <= 16 (at most 2048 box cells) run inside one workgroup
 // per member with every level resident in LDS, ending in a dense FP64 solve
 // of the h = 1/4 operator through its precomputed inverse.
@@ -160,26 +165,114 @@ struct WinLoad {
   }
 };
 
+// refinement pre: the previous pass's norm decides; a skipped member carries it forward
+template <typename T>
+__device__ __forceinline__ bool ref_skip(const MGArgs<T>& a, int mem, int tile) {
+  if (a.rslot <= 0) return false;
+  const double prev = a.norms[(long)mem * a.norm_slots + a.rslot - 1];
+  if (prev <= a.tol) {
+    if (tile == 0 && threadIdx.x == 0) a.norms[(long)mem * a.norm_slots + a.rslot] = prev;
+    return true;
+  }
+  return false;
+}
+
 // ---------------------------------------------------------------------------- pre-smoothing + restriction
-template <typename T, int NS, bool ONE>
+template <typename T, int NS, bool REF, bool ONE>
 __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
   typedef Win<T> W;
   static_assert(2 * NS + 1 <= W::H, "window halo too small for the sweep count");
   static_assert(W::TH * 64 <= 2 * W::CS, "residual staging does not fit");
-  __shared__ T sp[2 * W::CS];
-  __shared__ T sb[2 * W::CS];
+  static_assert(!REF || sizeof(double) * 64 * W::LH <= sizeof(T) * 4 * W::CS, "FP64 window does not fit");
+  __shared__ T spb[4 * W::CS];  // sp | sb; in refinement first the FP64 pressure window
   __shared__ unsigned char scode[2 * W::CS];
+  __shared__ double red[4];
+  T* const sp = spb;
+  T* const sb = spb + 2 * W::CS;
   int item;
   const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
   const int mem = item / a.ntiles, tile = item % a.ntiles;
-  if (mg_skip(a, mem, tile)) return;
+  if (REF ? ref_skip(a, mem, tile) : mg_skip(a, mem, tile)) return;
   int x0, y0;
   a.tiling.origin(tile, x0, y0);
   const int ox = x0 - W::H, oy = y0 - W::H;
   const long off = (long)mem * a.plane;
   const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
-  {
+  if (REF) {
+    // r = b64 - L phi64 on the window (ring excluded), same arithmetic order as k_resid64
+    double* const P64 = (double*)spb;
+    double vp[W::NR], vb[W::NR];
+    unsigned char vc[W::NR];
+    const int i = ox + col;
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m, j = oy + r;
+      vp[m] = 0.0;
+      vb[m] = 0.0;
+      vc[m] = 0;
+      if (r < W::LH && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+        const long at = g.at(i, j);
+        vc[m] = a.code[at];
+        vb[m] = a.b64[off + at];
+        vp[m] = a.phi64[off + at];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m;
+      if (!vc[m]) {
+        vp[m] = 0.0;
+        vb[m] = 0.0;
+      }
+      if (r < W::LH) {
+        P64[r * 64 + col] = vp[m];
+        scode[W::idx(r, col)] = vc[m];
+      }
+    }
+    __syncthreads();
+    const double inv_h2 = 1.0 / (g.h * g.h);
+    const bool tcol = col >= W::H && col < W::H + W::TWI;
+    double mx = 0.0;
+    T rf[W::NR];
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m;
+      rf[m] = (T)0;
+      if (vc[m] && r >= 1 && r < W::LH - 1 && col >= 1 && col < 63) {
+        const double* q = P64 + r * 64 + col;
+        double s = 0.0;
+        s += q[-1];
+        s += q[1];
+        s += q[-64];
+        s += q[64];
+        const double rr = vb[m] - (s - (double)vc[m] * q[0]) * inv_h2;
+        rf[m] = (T)rr;
+        if (tcol && r >= W::H && r < W::H + W::TH) {
+          a.r_out[off + g.at(i, oy + r)] = rf[m];
+          const double ar = fabs(rr) * a.dt;
+          mx = (ar > mx || ar != ar) ? ar : mx;
+        }
+      }
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) red[w] = mx;
+    __syncthreads();  // every FP64 read is done before sp / sb overwrite the window
+    if (threadIdx.x == 0) {
+      double mm = red[0];
+      for (int q = 1; q < 4; ++q) mm = (red[q] > mm || red[q] != red[q]) ? red[q] : mm;
+      atomicMax((unsigned long long*)&a.norms[(long)mem * a.norm_slots + a.rslot], dbits(mm));
+    }
+#pragma unroll
+    for (int m = 0; m < W::NR; ++m) {
+      const int r = w + 4 * m;
+      if (r < W::LH) {
+        const int x = W::idx(r, col);
+        sp[x] = (T)0;
+        sb[x] = rf[m];
+      }
+    }
+  } else {
     WinLoad<T> L;
     L.fetch(g, a.code, a.zero_guess ? nullptr : a.phi_in, a.b, off, ox, oy);
 #pragma unroll
@@ -586,12 +679,24 @@ __global__ __launch_bounds__(256) void k_resid64(Multi<ResidArgs> ms) {
 }
 
 // ---------------------------------------------------------------------------- launchers
-template <typename T>
-void launch_mg_pre(const Multi<MGArgs<T>>& m, hipStream_t s) {
+template <typename T, bool REF>
+static void launch_mg_pre_(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, true>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, true>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, false>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, false>), dim3(m.total()), dim3(256), 0, s, m);
+}
+template <>
+void launch_mg_pre<double>(const Multi<MGArgs<double>>& m, hipStream_t s) {
+  launch_mg_pre_<double, false>(m, s);
+}
+template <>
+void launch_mg_pre<float>(const Multi<MGArgs<float>>& m, hipStream_t s) {
+  // every segment of a finest-level launch in mixed precision refines (one precision per batch)
+  if (m.seg[0].phi64)
+    launch_mg_pre_<float, true>(m, s);
+  else
+    launch_mg_pre_<float, false>(m, s);
 }
 template <typename T>
 void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s) {
@@ -622,8 +727,6 @@ void launch_resid64(const Multi<ResidArgs>& m, hipStream_t s) {
     hipLaunchKernelGGL(k_resid64<false>, dim3(m.total()), dim3(256), 0, s, m);
 }
 
-template void launch_mg_pre<double>(const Multi<MGArgs<double>>&, hipStream_t);
-template void launch_mg_pre<float>(const Multi<MGArgs<float>>&, hipStream_t);
 template void launch_mg_post<double>(const Multi<MGArgs<double>>&, bool, hipStream_t);
 template void launch_mg_post<float>(const Multi<MGArgs<float>>&, bool, hipStream_t);
 template void launch_mg_coarse<double>(const Multi<CoarseArgs>&, hipStream_t);

@@ -203,6 +203,10 @@ __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
   const long coff = (long)mem * a.cplane;
   const double dt = a.dt, inv_h = 1.0 / g.h;
   const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
+  // extrapolation order of the warm start: constant after the first step (where the forcing
+  // switches on) and linear after the second, quadratic from then on
+  const double done = a.stats ? a.stats[(long)mem * STATS_STRIDE + ST_STEPS] : 1.0;
+  const int order = done < 0.5 ? 0 : done < 1.5 ? 1 : 2;
   double acc = 0.0, dmax = 0.0;
 #pragma unroll
   for (int rr = 0; rr < TH / 4; ++rr) {
@@ -237,7 +241,15 @@ __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
     } else {
       vn = v[g.at(i, j + 1)];
     }
-    if (a.phi_next) a.phi_next[off + at] = 2.0 * pc - a.phi_next[off + at];
+    if (a.phi_next) {
+      const double p1 = a.phi_next[off + at];
+      double wn = order == 0 ? pc : 2.0 * pc - p1;
+      if (a.phi_old) {
+        if (order == 2) wn = 3.0 * (pc - p1) + a.phi_old[off + at];
+        a.phi_old[off + at] = p1;
+      }
+      a.phi_next[off + at] = wn;
+    }
     const double div = fabs((ue - uw + vn - vsv) * inv_h);
     dmax = (div > dmax || div != div) ? div : dmax;
     if (a.s1u) {
@@ -290,6 +302,7 @@ __global__ void k_step_book(Multi<BookArgs> ms) {
   if (!(last <= a.tol)) st[ST_UNCONV] += 1.0;
   st[ST_MAXRES] = (last > st[ST_MAXRES] || last != last) ? last : st[ST_MAXRES];
   st[ST_STEPS] += 1.0;
+  st[ST_RECENT] = fmax((double)cycles, st[ST_RECENT] - 1.0 / 16.0);
 }
 
 // ---------------------------------------------------------------------------- J finalisation
@@ -427,7 +440,6 @@ void launch_predictor(const Multi<PredArgs<TT>>& m, hipStream_t s) {
     hipLaunchKernelGGL((k_predictor<TT, false>), dim3(m.total()), dim3(256), 0, s, m);
 }
 template void launch_predictor<double>(const Multi<PredArgs<double>>&, hipStream_t);
-template void launch_predictor<float>(const Multi<PredArgs<float>>&, hipStream_t);
 
 void launch_project_cost(const Multi<ProjArgs>& m, hipStream_t s) {
   if (m.nseg == 1)
@@ -448,7 +460,6 @@ void launch_init_members(const InitArgs<TT>& a, hipStream_t s) {
   hipLaunchKernelGGL(k_init_members<TT>, dim3(bx, a.nmem), dim3(256), 0, s, a);
 }
 template void launch_init_members<double>(const InitArgs<double>&, hipStream_t);
-template void launch_init_members<float>(const InitArgs<float>&, hipStream_t);
 
 void launch_shift(const Geo& g, const double* u, const double* v, double* shu, double* shv, hipStream_t s) {
   const long n = (long)g.nx * g.ny;
@@ -461,8 +472,6 @@ void launch_store_base(long plane, const double* u, const double* v, const TT* t
 }
 template void launch_store_base<double>(long, const double*, const double*, const double*, const double*,
                                         const double*, double*, double*, double*, double*, double*, hipStream_t);
-template void launch_store_base<float>(long, const double*, const double*, const float*, const float*,
-                                       const double*, double*, double*, double*, double*, double*, hipStream_t);
 void launch_fields_out(const Geo& g, long plane, int nmem, const double* u, const double* v, double* out,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_fields_out, dim3(64, nmem), dim3(256), 0, s, g, plane, u, v, out);
