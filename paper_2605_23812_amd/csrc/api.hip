@@ -121,7 +121,8 @@ static int make_plan(const envar_problem* pin, Plan& P) {
   const int ntop = P.lev[nl].n;  // 16
   P.ncoarse = 0;
   for (int n = ntop; n >= 4; n /= 2) ++P.ncoarse;
-  if (ntop != 16 || P.ncoarse != 3) return fail(ENVAR_EINVAL, "internal: the LDS levels must be 16, 8, 4");
+  if (ntop != 16 || P.ncoarse != 3 || P.lev[nl].nx != 64 || P.lev[nl].ny > 32)
+    return fail(ENVAR_EINVAL, "internal: the LDS levels must be 16, 8, 4 on a 64 x (<= 32) top box");
   for (int l = 0; l < nl; ++l) {
     P.mg_tl[l] = Tiling::make(P.lev[l], MG_TH, MG_TW);
     P.mg_tiles[l] = P.mg_tl[l].count();

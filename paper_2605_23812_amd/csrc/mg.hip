@@ -458,77 +458,120 @@ __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
 }
 
 // ---------------------------------------------------------------------------- coarse levels in LDS
-constexpr int COARSE_LDS = 2 * (64 * 32 + 32 * 16 + 16 * 8);
-constexpr int COARSE_THREADS = 512;
+// The levels inv_h = 16, 8, 4 of one member run in one workgroup, every level
+// resident in LDS as a padded array: NX x ny cells plus a ring of ghost cells,
+// row pitch NX + 2. Cells outside the fluid (and the ring) hold phi = 0 and a
+// zero diagonal code, so a neighbour sum needs no geometry test; the code of a
+// fluid cell is its Poisson diagonal count. NX is 64, 32, 16 (the channel is
+// four units long); ny is the runtime height (cavity or plain channel).
+constexpr int COARSE_THREADS = 1024;
+constexpr int CNX0 = 64, CNX1 = 32, CNX2 = 16;
+constexpr int CP0 = CNX0 + 2, CP1 = CNX1 + 2, CP2 = CNX2 + 2;
+constexpr int CMAXNY0 = 32;
+constexpr int CS0 = (CMAXNY0 + 2) * CP0, CS1 = (CMAXNY0 / 2 + 2) * CP1, CS2 = (CMAXNY0 / 4 + 2) * CP2;
 
-__device__ __forceinline__ void lds_sweep(double* p, const double* b, const Geo& g, double h2) {
-  const int nx = g.nx, hx = g.nx / 2, half = hx * g.ny;
-  for (int color = 0; color < 2; ++color) {
-    for (int q = threadIdx.x; q < half; q += blockDim.x) {
-      const int j = q / hx;
-      const int i = 2 * (q % hx) + ((color ^ j) & 1);
-      if (!g.fluid(i, j)) continue;
-      const int x = j * nx + i;
-      double s = 0.0;
-      if (g.fluid(i - 1, j)) s += p[x - 1];
-      if (g.fluid(i + 1, j)) s += p[x + 1];
-      if (g.fluid(i, j - 1)) s += p[x - nx];
-      if (g.fluid(i, j + 1)) s += p[x + nx];
-      p[x] = (s - h2 * b[x]) * inv_diag<double>(g.diag_count(i, j));
+template <int NX>
+__device__ __forceinline__ int cx(int i, int j) {
+  return (j + 1) * (NX + 2) + i + 1;
+}
+
+// diagonal codes of one level (ghost ring included)
+template <int NX>
+__device__ __forceinline__ void lvl_codes(unsigned char* C, const Geo& g) {
+  const int n = (g.ny + 2) * (NX + 2);
+  for (int q = threadIdx.x; q < n; q += COARSE_THREADS) {
+    const int jj = q / (NX + 2), i = q - jj * (NX + 2) - 1, j = jj - 1;
+    C[q] = g.fluid(i, j) ? (unsigned char)g.diag_count(i, j) : (unsigned char)0;
+  }
+}
+
+// one red-black Gauss-Seidel sweep (same operand order as the tiled kernels)
+template <int NX>
+__device__ __forceinline__ void lvl_sweep(double* p, const double* b, const unsigned char* C, int ny, double h2) {
+  constexpr int HX = NX / 2, P = NX + 2;
+  constexpr int K = (HX * (CMAXNY0 * NX / CNX0) + COARSE_THREADS - 1) / COARSE_THREADS;
+  const int n = HX * ny;
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = threadIdx.x + k * COARSE_THREADS;
+      if (q >= n) break;
+      const int j = q / HX, i = 2 * (q % HX) + ((c ^ j) & 1);
+      const int x = cx<NX>(i, j);
+      const int d = C[x];
+      if (d) {
+        double s = 0.0;
+        s += p[x - 1];
+        s += p[x + 1];
+        s += p[x - P];
+        s += p[x + P];
+        p[x] = (s - h2 * b[x]) * inv_diag<double>(d);
+      }
     }
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ double lds_resid(const double* p, const double* b, const Geo& g, int i, int j, double inv_h2) {
-  const int nx = g.nx, q = j * nx + i;
+template <int NX>
+__device__ __forceinline__ double lvl_resid(const double* p, const double* b, const unsigned char* C, int x,
+                                            double inv_h2) {
+  constexpr int P = NX + 2;
   double s = 0.0;
-  if (g.fluid(i - 1, j)) s += p[q - 1];
-  if (g.fluid(i + 1, j)) s += p[q + 1];
-  if (g.fluid(i, j - 1)) s += p[q - nx];
-  if (g.fluid(i, j + 1)) s += p[q + nx];
-  return b[q] - (s - (double)g.diag_count(i, j) * p[q]) * inv_h2;
+  s += p[x - 1];
+  s += p[x + 1];
+  s += p[x - P];
+  s += p[x + P];
+  return b[x] - (s - (double)C[x] * p[x]) * inv_h2;
 }
 
-// restriction of the residual of level g (p, b) into the right-hand side of level c, zero guess on c
-__device__ __forceinline__ void lds_restrict(const double* p, const double* b, const Geo& g, double* pc, double* bc,
-                                             const Geo& c) {
-  const double inv_h2 = 1.0 / (g.h * g.h);
-  for (int q = threadIdx.x; q < c.nx * c.ny; q += blockDim.x) {
-    const int I = q % c.nx, J = q / c.nx;
+// residual of the fine level restricted (mean of the four children) into the
+// coarse right-hand side; zero coarse guess
+template <int NX>
+__device__ __forceinline__ void lvl_restrict(const double* p, const double* b, const unsigned char* C, double h,
+                                             double* pc, double* bc, const unsigned char* Cc, int nyc) {
+  constexpr int NXC = NX / 2;
+  const double inv_h2 = 1.0 / (h * h);
+  for (int q = threadIdx.x; q < NXC * nyc; q += COARSE_THREADS) {
+    const int J = q / NXC, I = q % NXC;
+    const int xc = cx<NXC>(I, J);
     double rs = 0.0;
-    if (c.fluid(I, J))
+    if (Cc[xc])
       for (int dj = 0; dj < 2; ++dj)
-        for (int di = 0; di < 2; ++di) rs += lds_resid(p, b, g, 2 * I + di, 2 * J + dj, inv_h2);
-    bc[q] = 0.25 * rs;
-    pc[q] = 0.0;
+        for (int di = 0; di < 2; ++di) rs += lvl_resid<NX>(p, b, C, cx<NX>(2 * I + di, 2 * J + dj), inv_h2);
+    bc[xc] = 0.25 * rs;
+    pc[xc] = 0.0;
   }
   __syncthreads();
 }
 
-// bilinear prolongation of the correction on level c into level g
-__device__ __forceinline__ void lds_prolong(double* p, const Geo& g, const double* pc, const Geo& c) {
-  for (int q = threadIdx.x; q < g.nx * g.ny; q += blockDim.x) {
-    const int i = q % g.nx, j = q / g.nx;
-    if (!g.fluid(i, j)) continue;
+// bilinear prolongation of the coarse correction (Neumann mirror at walls,
+// sign flip across the outflow face) added to the fine level
+template <int NX>
+__device__ __forceinline__ void lvl_prolong(double* p, const unsigned char* C, int ny, const double* pc,
+                                            const unsigned char* Cc) {
+  constexpr int NXC = NX / 2;
+  for (int q = threadIdx.x; q < NX * ny; q += COARSE_THREADS) {
+    const int j = q / NX, i = q % NX;
+    const int x = cx<NX>(i, j);
+    if (!C[x]) continue;
     const int I = i >> 1, J = j >> 1;
     const int IX = I + ((i & 1) ? 1 : -1), JY = J + ((j & 1) ? 1 : -1);
-    const double Pv = pc[J * c.nx + I];
-    const double X = c.fluid(IX, J) ? pc[J * c.nx + IX] : (IX == c.nx ? -Pv : Pv);
-    const double Y = c.fluid(I, JY) ? pc[JY * c.nx + I] : Pv;
-    const double D = c.fluid(IX, JY) ? pc[JY * c.nx + IX] : X + Y - Pv;
-    p[q] += (9.0 * Pv + 3.0 * (X + Y) + D) * 0.0625;
+    const int xP = cx<NXC>(I, J), xX = cx<NXC>(IX, J), xY = cx<NXC>(I, JY), xD = cx<NXC>(IX, JY);
+    const double Pv = pc[xP];
+    const double X = Cc[xX] ? pc[xX] : (IX == NXC ? -Pv : Pv);
+    const double Y = Cc[xY] ? pc[xY] : Pv;
+    const double D = Cc[xD] ? pc[xD] : X + Y - Pv;
+    p[x] += (9.0 * Pv + 3.0 * (X + Y) + D) * 0.0625;
   }
   __syncthreads();
 }
 
-// The levels inv_h = 16, 8, 4 of one member in one workgroup, all resident in
-// LDS: V-cycle with NS red-black sweeps per level and a dense solve of the
-// h = 1/4 operator through its inverse. The three levels are unrolled at
-// compile time so that every geometry predicate stays in registers.
+// V-cycle over the three LDS levels with NS red-black sweeps per level and a
+// dense solve of the h = 1/4 operator through its inverse.
 template <typename T, bool ONE>
 __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> ms) {
-  __shared__ double lds[COARSE_LDS];
+  __shared__ double P0[CS0], B0[CS0], P1[CS1], B1[CS1], P2[CS2], B2[CS2];
+  __shared__ unsigned char C0[CS0], C1[CS1], C2[CS2];
   __shared__ double sinv[COARSE_INV_MAX];
   __shared__ double sbc[MAX_COARSE_UNKNOWNS];
   __shared__ double red[COARSE_THREADS / 64];
@@ -544,70 +587,98 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
   const Geo g0 = a.g;
   const Geo g1 = g0.coarser();
   const Geo g2 = g1.coarser();
-  const int n0 = g0.nx * g0.ny, n1 = g1.nx * g1.ny, n2 = g2.nx * g2.ny;
-  double* P0 = lds;
-  double* B0 = P0 + n0;
-  double* P1 = B0 + n0;
-  double* B1 = P1 + n1;
-  double* P2 = B1 + n1;
-  double* B2 = P2 + n2;
+  const int ny0 = g0.ny, ny1 = g1.ny, ny2 = g2.ny;
   const long off = (long)mem * a.plane;
   const T* gphi = (const T*)a.phi + off;
   const T* gb = (const T*)a.b + off;
+  // thread t owns the top-level cells (t & 63, (t >> 6) + 16 k)
+  constexpr int RS = COARSE_THREADS / 64;
+  constexpr int NL = CMAXNY0 / RS;
+  const int ti = threadIdx.x & 63, tj = threadIdx.x >> 6;
   {
-    constexpr int NL = (64 * 32 + COARSE_THREADS - 1) / COARSE_THREADS;
     double vp[NL], vb[NL];
 #pragma unroll
-    for (int n = 0; n < NL; ++n) {
-      const int q = threadIdx.x + COARSE_THREADS * n;
-      vp[n] = 0.0;
-      vb[n] = 0.0;
-      if (q < n0) {
-        const int i = q % g0.nx, j = q / g0.nx;
-        if (g0.fluid(i, j)) {
-          vb[n] = (double)gb[g0.at(i, j)];
-          if (a.warm) vp[n] = (double)gphi[g0.at(i, j)];
-        }
+    for (int k = 0; k < NL; ++k) {
+      const int j = tj + RS * k;
+      vp[k] = 0.0;
+      vb[k] = 0.0;
+      if (j < ny0 && g0.fluid(ti, j)) {
+        vb[k] = (double)gb[g0.at(ti, j)];
+        if (a.warm) vp[k] = (double)gphi[g0.at(ti, j)];
       }
     }
     // the transposed inverse of the coarsest operator, read once per workgroup
     const int ninv = a.nc * a.nc;
     for (int q = threadIdx.x; q < ninv; q += COARSE_THREADS) sinv[q] = a.ainv[q];
+    for (int q = threadIdx.x; q < CS0; q += COARSE_THREADS) {
+      P0[q] = 0.0;
+      B0[q] = 0.0;
+    }
+    for (int q = threadIdx.x; q < CS1; q += COARSE_THREADS) {
+      P1[q] = 0.0;
+      B1[q] = 0.0;
+    }
+    for (int q = threadIdx.x; q < CS2; q += COARSE_THREADS) {
+      P2[q] = 0.0;
+      B2[q] = 0.0;
+    }
+    lvl_codes<CNX0>(C0, g0);
+    lvl_codes<CNX1>(C1, g1);
+    lvl_codes<CNX2>(C2, g2);
+    __syncthreads();
 #pragma unroll
-    for (int n = 0; n < NL; ++n) {
-      const int q = threadIdx.x + COARSE_THREADS * n;
-      if (q < n0) {
-        P0[q] = vp[n];
-        B0[q] = vb[n];
+    for (int k = 0; k < NL; ++k) {
+      const int j = tj + RS * k;
+      if (j < ny0) {
+        P0[cx<CNX0>(ti, j)] = vp[k];
+        B0[cx<CNX0>(ti, j)] = vb[k];
       }
     }
   }
   __syncthreads();
-  for (int s = 0; s < a.nsweep_pre; ++s) lds_sweep(P0, B0, g0, g0.h * g0.h);
-  lds_restrict(P0, B0, g0, P1, B1, g1);
-  for (int s = 0; s < a.nsweep_pre; ++s) lds_sweep(P1, B1, g1, g1.h * g1.h);
-  lds_restrict(P1, B1, g1, P2, B2, g2);
+  const double h20 = g0.h * g0.h, h21 = g1.h * g1.h;
+  for (int s = 0; s < a.nsweep_pre; ++s) lvl_sweep<CNX0>(P0, B0, C0, ny0, h20);
+  lvl_restrict<CNX0>(P0, B0, C0, g0.h, P1, B1, C1, ny1);
+  for (int s = 0; s < a.nsweep_pre; ++s) lvl_sweep<CNX1>(P1, B1, C1, ny1, h21);
+  lvl_restrict<CNX1>(P1, B1, C1, g1.h, P2, B2, C2, ny2);
   // dense solve on the coarsest level: sinv holds the inverse transposed, thread q reads column q
-  for (int q = threadIdx.x; q < a.nc; q += COARSE_THREADS) sbc[q] = B2[a.aidx[q]];
-  __syncthreads();
   for (int q = threadIdx.x; q < a.nc; q += COARSE_THREADS) {
-    double s = 0.0;
-    for (int r = 0; r < a.nc; ++r) s += sinv[r * a.nc + q] * sbc[r];
-    P2[a.aidx[q]] = s;
+    const int c = a.aidx[q];
+    sbc[q] = B2[cx<CNX2>(c % g2.nx, c / g2.nx)];
   }
   __syncthreads();
-  lds_prolong(P1, g1, P2, g2);
-  for (int s = 0; s < a.nsweep_post; ++s) lds_sweep(P1, B1, g1, g1.h * g1.h);
-  lds_prolong(P0, g0, P1, g1);
-  for (int s = 0; s < a.nsweep_post; ++s) lds_sweep(P0, B0, g0, g0.h * g0.h);
+  {
+    // eight threads (consecutive lanes) per unknown, each summing every eighth term
+    static_assert(MAX_COARSE_UNKNOWNS * 8 <= COARSE_THREADS, "dense solve needs 8 threads per unknown");
+    const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
+    double s = 0.0;
+    if (q < a.nc)
+      for (int r = part; r < a.nc; r += 8) s += sinv[r * a.nc + q] * sbc[r];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    if (q < a.nc && part == 0) {
+      const int c = a.aidx[q];
+      P2[cx<CNX2>(c % g2.nx, c / g2.nx)] = s;
+    }
+  }
+  __syncthreads();
+  lvl_prolong<CNX1>(P1, C1, ny1, P2, C2);
+  for (int s = 0; s < a.nsweep_post; ++s) lvl_sweep<CNX1>(P1, B1, C1, ny1, h21);
+  lvl_prolong<CNX0>(P0, C0, ny0, P1, C1);
+  for (int s = 0; s < a.nsweep_post; ++s) lvl_sweep<CNX0>(P0, B0, C0, ny0, h20);
   if (a.write_norm) {
-    const double inv_h2 = 1.0 / (g0.h * g0.h);
+    const double inv_h2 = 1.0 / h20;
     double m = 0.0;
-    for (int q = threadIdx.x; q < n0; q += COARSE_THREADS) {
-      const int i = q % g0.nx, j = q / g0.nx;
-      if (g0.fluid(i, j)) {
-        const double rr = fabs(lds_resid(P0, B0, g0, i, j, inv_h2)) * a.dt;
-        m = (rr > m || rr != rr) ? rr : m;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int j = tj + RS * k;
+      if (j < ny0) {
+        const int x = cx<CNX0>(ti, j);
+        if (C0[x]) {
+          const double rr = fabs(lvl_resid<CNX0>(P0, B0, C0, x, inv_h2)) * a.dt;
+          m = (rr > m || rr != rr) ? rr : m;
+        }
       }
     }
     m = wave_max(m);
@@ -620,13 +691,16 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
     }
   }
   T* wphi = (T*)a.phi + off;
-  for (int q = threadIdx.x; q < n0; q += COARSE_THREADS) {
-    const int i = q % g0.nx, j = q / g0.nx;
-    if (!g0.fluid(i, j)) continue;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int j = tj + RS * k;
+    if (j >= ny0) continue;
+    const int x = cx<CNX0>(ti, j);
+    if (!C0[x]) continue;
     if (a.add_to)
-      a.add_to[off + g0.at(i, j)] += P0[q];
+      a.add_to[off + g0.at(ti, j)] += P0[x];
     else
-      wphi[g0.at(i, j)] = (T)P0[q];
+      wphi[g0.at(ti, j)] = (T)P0[x];
   }
 }
 
