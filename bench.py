@@ -366,6 +366,8 @@ def main():
             "div_tol": 1e-10,
         },
         "mean_refinement_passes_per_step": round(st["mean_cycles"], 3),
+        "tile_rows": {"predictor": st["rows_pred"], "projection": st["rows_proj"],
+                      "multigrid_levels": [r for r in st["rows_mg"] if r]},
         "max_div": st["max_div"],
         "J_finite": bool(np.all(np.isfinite(J_mixed_long))),
         "roofline": roofline(st, "mixed", ncells, nrows, copy_gbs),

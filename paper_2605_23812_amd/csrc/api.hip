@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
@@ -55,9 +56,12 @@ struct Plan {
   int nlev_grid;        // levels run by the tiled kernels (inv_h > 16)
   int ncoarse;          // levels run by the LDS kernel (top inv_h <= 16 .. 4)
   Geo lev[MAX_LEVELS];  // lev[nlev_grid] is the top of the LDS part
-  Tiling mg_tl[MAX_LEVELS];
-  int mg_tiles[MAX_LEVELS];
-  Tiling st_tl;
+  Tiling mg_tl[2][MAX_LEVELS];  // [8 | 16 rows][level]
+  int mg_tiles[2][MAX_LEVELS];
+  Tiling sk_tl[2];              // predictor / projection tiles, 8 | 16 rows
+  int sk_tiles[2];
+  bool rows16;                  // 16-row step tiles align with the cavity and channel rows
+  Tiling st_tl;                 // 64 x 8 cost blocks (also the refinement residual tiles)
   int st_tiles;
   long cplane;  // nx * ny
   int ncells;
@@ -123,13 +127,19 @@ static int make_plan(const envar_problem* pin, Plan& P) {
   for (int n = ntop; n >= 4; n /= 2) ++P.ncoarse;
   if (ntop != 16 || P.ncoarse != 3 || P.lev[nl].nx != 64 || P.lev[nl].ny > 32)
     return fail(ENVAR_EINVAL, "internal: the LDS levels must be 16, 8, 4 on a 64 x (<= 32) top box");
-  for (int l = 0; l < nl; ++l) {
-    P.mg_tl[l] = Tiling::make(P.lev[l], MG_TH, MG_TW);
-    P.mg_tiles[l] = P.mg_tl[l].count();
-  }
+  for (int l = 0; l < nl; ++l)
+    for (int v = 0; v < 2; ++v) {
+      P.mg_tl[v][l] = Tiling::make(P.lev[l], v ? 16 : 8, MG_TW);
+      P.mg_tiles[v][l] = P.mg_tl[v][l].count();
+    }
   const Geo& g = P.lev[0];
-  P.st_tl = Tiling::make(g, STEP_TH);
+  P.st_tl = Tiling::make(g, COST_TH);
   P.st_tiles = P.st_tl.count();
+  for (int v = 0; v < 2; ++v) {
+    P.sk_tl[v] = Tiling::make(g, v ? 16 : 8);
+    P.sk_tiles[v] = P.sk_tl[v].count();
+  }
+  P.rows16 = g.jc % 16 == 0 && (g.ny - g.jc) % 16 == 0;
   P.cplane = (long)g.nx * g.ny;
   P.ncells = 0;
   for (int j = 0; j < g.ny; ++j)
@@ -345,6 +355,9 @@ struct Job {
   int step = 0;            // steps launched so far
   bool cold_first = true;  // the state's cold-start flag applies to step 0
   int last_cur = 0;        // pressure buffer of the last solved step
+  // tile heights (8 | 16) of the predictor, the projection and each tiled multigrid level
+  int rows_pred = 8, rows_proj = 8;
+  int rows_mg[MAX_LEVELS] = {16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16};
   template <typename T>
   T* w_(size_t off) const {
     return at<T>(ws, off);
@@ -365,130 +378,248 @@ static Multi<A> seg_begin() {
   return m;
 }
 
+// ---------------------------------------------------------------------------- launch arguments
+// Builders shared by the time step and the tile tuner. `rows` is the tile
+// height (8 or 16) of the launch; k is the V-cycle pass.
+static int vidx(int rows) { return rows == 16 ? 1 : 0; }
+
+static PredArgs<double> pred_args(const Job& j, int rows) {
+  const Plan& P = j.P;
+  const WS& w = j.w;
+  const bool even = (j.step & 1) == 0;
+  PredArgs<double> a{};
+  a.g = P.lev[0];
+  a.tiling = P.sk_tl[vidx(rows)];
+  a.trows = rows;
+  a.ntiles = P.sk_tiles[vidx(rows)];
+  a.nmem = j.nmem;
+  a.plane = P.lev[0].plane();
+  a.nu = P.nu;
+  a.dt = P.dt;
+  a.cold_flag = (j.step == 0 && j.cold_first) ? at<int>(j.state, P.s_meta) : nullptr;
+  a.u = j.w_<double>(w.u);
+  a.v = j.w_<double>(w.v);
+  a.us = j.w_<double>(w.us);
+  a.vs = j.w_<double>(w.vs);
+  a.tu_prev = j.w_<double>(even ? w.tuA : w.tuB);
+  a.tv_prev = j.w_<double>(even ? w.tvA : w.tvB);
+  a.tu = j.w_<double>(even ? w.tuB : w.tuA);
+  a.tv = j.w_<double>(even ? w.tvB : w.tvA);
+  a.b = j.w_<double>(w.b0);
+  a.ctrl = j.ctrl;
+  a.m = P.m;
+  a.nctrl = (int)(P.m / 2);
+  a.cmap = at<int>(j.state, P.s_cmap);
+  a.norms = j.w_<double>(w.norms);
+  a.norm_slots = P.norm_slots;
+  return a;
+}
+
+static ProjArgs proj_args(const Job& j, int rows) {
+  const Plan& P = j.P;
+  const WS& w = j.w;
+  const int cur = j.step & 1;
+  ProjArgs pj{};
+  pj.g = P.lev[0];
+  pj.tiling = P.sk_tl[vidx(rows)];
+  pj.trows = rows;
+  pj.ntiles = P.sk_tiles[vidx(rows)];
+  pj.cost_tiling = P.st_tl;
+  pj.cost_ntiles = P.st_tiles;
+  pj.nmem = j.nmem;
+  pj.plane = P.lev[0].plane();
+  pj.cplane = P.cplane;
+  pj.dt = P.dt;
+  pj.u = j.w_<double>(w.u);
+  pj.v = j.w_<double>(w.v);
+  pj.us = j.w_<double>(w.us);
+  pj.vs = j.w_<double>(w.vs);
+  pj.phi = j.phi(cur);
+  pj.phi_next = j.phi(cur ^ 1);
+  pj.phi_old = j.w_<double>(w.phiQ);
+  pj.stats = j.w_<double>(w.stats);
+  pj.shu = at<double>(j.state, P.s_shu);
+  pj.shv = at<double>(j.state, P.s_shv);
+  pj.s1u = j.w_<double>(w.s1u);
+  pj.s1v = j.w_<double>(w.s1v);
+  pj.s2part = j.w_<double>(w.s2part);
+  pj.divmax = j.w_<double>(w.divmax);
+  return pj;
+}
+
+template <typename T>
+static MGArgs<T> level_args(const Job& j, int l, int k, int rows) {
+  const Plan& P = j.P;
+  MGArgs<T> a{};
+  a.g = P.lev[l];
+  a.gc = P.lev[l + 1];
+  a.tiling = P.mg_tl[vidx(rows)][l];
+  a.trows = rows;
+  a.ntiles = P.mg_tiles[vidx(rows)][l];
+  a.nmem = j.nmem;
+  a.plane = P.lev[l].plane();
+  a.cplane_c = P.lev[l + 1].plane();
+  a.norms = j.w_<double>(j.w.norms);
+  a.norm_slots = P.norm_slots;
+  a.tol = P.tol;
+  a.dt = P.dt;
+  a.code = at<unsigned char>(j.state, P.s_code[l]);
+  a.codec = at<unsigned char>(j.state, P.s_code[l + 1]);
+  a.k = k;
+  return a;
+}
+
+template <typename T>
+static MGArgs<T> pre_args(const Job& j, int l, int k, int rows) {
+  const WS& w = j.w;
+  const bool mixed = j.P.mixed;
+  MGArgs<T> a = level_args<T>(j, l, k, rows);
+  if (l == 0) {
+    const int cur = j.step & 1;
+    a.phi_in = mixed ? nullptr : (const T*)j.phi(cur);
+    a.b = mixed ? nullptr : (const T*)j.w_<double>(w.b0);
+    a.zero_guess = mixed ? 1 : 0;
+    a.phi_out = mixed ? (T*)j.w_<float>(w.e0) : (T*)j.w_<double>(w.phiB);
+    if (mixed) {  // the residual of the FP64 pressure after pass k - 1 is formed in this launch
+      a.phi64 = j.phi(cur);
+      a.b64 = j.w_<double>(w.b0);
+      a.r_out = (T*)j.w_<float>(w.r0);
+      a.rslot = k - 1;
+    }
+  } else {
+    a.phi_in = nullptr;
+    a.b = j.w_<T>(w.lb[l]);
+    a.zero_guess = 1;
+    a.phi_out = j.w_<T>(w.lphiB[l]);
+  }
+  a.bc = j.w_<T>(w.lb[l + 1]);
+  return a;
+}
+
+template <typename T>
+static MGArgs<T> post_args(const Job& j, int l, int k, int rows) {
+  const WS& w = j.w;
+  const bool mixed = j.P.mixed;
+  MGArgs<T> a = level_args<T>(j, l, k, rows);
+  a.phic = j.w_<T>(w.lphiA[l + 1]);
+  if (l == 0) {
+    const int cur = j.step & 1;
+    a.phi_in = mixed ? (const T*)j.w_<float>(w.e0) : (const T*)j.w_<double>(w.phiB);
+    a.b = mixed ? (const T*)j.w_<float>(w.r0) : (const T*)j.w_<double>(w.b0);
+    a.phi_out = mixed ? (T*)j.w_<float>(w.e0) : (T*)j.phi(cur);
+    a.add_to = mixed ? j.phi(cur) : nullptr;
+    a.write_norm = mixed ? 0 : 1;
+  } else {
+    a.phi_in = j.w_<T>(w.lphiB[l]);
+    a.b = j.w_<T>(w.lb[l]);
+    a.phi_out = j.w_<T>(w.lphiA[l]);
+  }
+  return a;
+}
+
+template <typename T>
+static CoarseArgs coarse_args(const Job& j, int k) {
+  const Plan& P = j.P;
+  const WS& w = j.w;
+  const int L = P.nlev_grid;
+  CoarseArgs c{};
+  c.g = P.lev[L];
+  c.nlev = P.ncoarse;
+  c.nmem = j.nmem;
+  c.plane = P.lev[L].plane();
+  c.ainv = at<double>(j.state, P.s_ainv);
+  c.aidx = at<int>(j.state, P.s_aidx);
+  c.nc = P.nc;
+  c.norms = j.w_<double>(w.norms);
+  c.norm_slots = P.norm_slots;
+  c.k = k;
+  c.tol = P.tol;
+  c.dt = P.dt;
+  c.nsweep_pre = MG_NS;
+  c.nsweep_post = MG_NS;
+  if (L == 0) {  // the whole V-cycle runs in LDS
+    const int cur = j.step & 1;
+    if (P.mixed) {
+      c.phi = j.w_<float>(w.e0);
+      c.b = j.w_<float>(w.r0);
+      c.add_to = j.phi(cur);
+    } else {
+      c.phi = j.phi(cur);
+      c.b = j.w_<double>(w.b0);
+      c.warm = 1;
+      c.write_norm = 1;
+    }
+  } else {
+    c.phi = j.w_<T>(w.lphiA[L]);
+    c.b = j.w_<T>(w.lb[L]);
+  }
+  return c;
+}
+
+static ResidArgs resid_args(const Job& j, int k) {
+  const Plan& P = j.P;
+  ResidArgs r{};
+  r.g = P.lev[0];
+  r.tiling = P.st_tl;
+  r.ntiles = P.st_tiles;
+  r.nmem = j.nmem;
+  r.plane = P.lev[0].plane();
+  r.phi = j.phi(j.step & 1);
+  r.b = j.w_<double>(j.w.b0);
+  r.r = j.w_<float>(j.w.r0);
+  r.norms = j.w_<double>(j.w.norms);
+  r.norm_slots = P.norm_slots;
+  r.tol = P.tol;
+  r.dt = P.dt;
+  r.k = k;
+  return r;
+}
+
+// One launch per tile height present among the jobs (the kernels take the
+// height as a compile-time parameter); `rows_of` gives a job's height for the
+// phase, or 0 when the job has no work in it.
+template <typename A, typename RowsOf, typename Make, typename Launch>
+static void grouped(const std::vector<Job*>& J, RowsOf rows_of, Make make, Launch launch) {
+  for (int rows : {8, 16}) {
+    auto m = seg_begin<A>();
+    for (Job* j : J)
+      if (rows_of(*j) == rows) {
+        const A a = make(*j, rows);
+        seg_add(m, a, a.ntiles * a.nmem);
+      }
+    if (m.nseg) launch(m);
+  }
+}
+
 template <typename TT>
 static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
   typedef TT T;  // V-cycle type
   const bool mixed = J[0]->P.mixed;
   int Lmax = 0;
   for (Job* j : J) Lmax = std::max(Lmax, j->P.nlev_grid);
-  auto level_args = [&](const Job& j, int l, int k) {
-    const Plan& P = j.P;
-    MGArgs<T> a{};
-    a.g = P.lev[l];
-    a.gc = P.lev[l + 1];
-    a.tiling = P.mg_tl[l];
-    a.ntiles = P.mg_tiles[l];
-    a.nmem = j.nmem;
-    a.plane = P.lev[l].plane();
-    a.cplane_c = P.lev[l + 1].plane();
-    a.norms = j.w_<double>(j.w.norms);
-    a.norm_slots = P.norm_slots;
-    a.tol = P.tol;
-    a.dt = P.dt;
-    a.code = at<unsigned char>(j.state, P.s_code[l]);
-    a.codec = at<unsigned char>(j.state, P.s_code[l + 1]);
-    a.k = k;
-    return a;
-  };
   const int k_timed = mixed ? 1 : 0;
   auto vcycle = [&](int k) {
     const bool timed = tm && k == k_timed;
     if (timed) tm->mark(TM_CYCLE, 0, st);
     for (int l = 0; l < Lmax; ++l) {
-      auto m = seg_begin<MGArgs<T>>();
-      for (Job* j : J) {
-        if (l >= j->P.nlev_grid) continue;
-        const WS& w = j->w;
-        MGArgs<T> a = level_args(*j, l, k);
-        if (l == 0) {
-          const int cur = j->step & 1;
-          a.phi_in = mixed ? nullptr : (const T*)j->phi(cur);
-          a.b = mixed ? nullptr : (const T*)j->w_<double>(w.b0);
-          a.zero_guess = mixed ? 1 : 0;
-          a.phi_out = mixed ? (T*)j->w_<float>(w.e0) : (T*)j->w_<double>(w.phiB);
-          if (mixed) {  // the residual of the FP64 pressure after pass k - 1 is formed in this launch
-            a.phi64 = j->phi(cur);
-            a.b64 = j->w_<double>(w.b0);
-            a.r_out = (T*)j->w_<float>(w.r0);
-            a.rslot = k - 1;
-          }
-        } else {
-          a.phi_in = nullptr;
-          a.b = j->w_<T>(w.lb[l]);
-          a.zero_guess = 1;
-          a.phi_out = j->w_<T>(w.lphiB[l]);
-        }
-        a.bc = j->w_<T>(w.lb[l + 1]);
-        seg_add(m, a, a.ntiles * a.nmem);
-      }
       if (timed && l == 0) tm->mark(TM_PRE, 0, st);
-      launch_mg_pre<T>(m, st);
+      grouped<MGArgs<T>>(
+          J, [&](const Job& j) { return l < j.P.nlev_grid ? j.rows_mg[l] : 0; },
+          [&](const Job& j, int rows) { return pre_args<T>(j, l, k, rows); },
+          [&](const Multi<MGArgs<T>>& m) { launch_mg_pre<T>(m, st); });
       if (timed && l == 0) tm->mark(TM_PRE, 1, st);
     }
     {
       auto m = seg_begin<CoarseArgs>();
-      for (Job* j : J) {
-        const Plan& P = j->P;
-        const WS& w = j->w;
-        const int L = P.nlev_grid;
-        CoarseArgs c{};
-        c.g = P.lev[L];
-        c.nlev = P.ncoarse;
-        c.nmem = j->nmem;
-        c.plane = P.lev[L].plane();
-        c.ainv = at<double>(j->state, P.s_ainv);
-        c.aidx = at<int>(j->state, P.s_aidx);
-        c.nc = P.nc;
-        c.norms = j->w_<double>(w.norms);
-        c.norm_slots = P.norm_slots;
-        c.k = k;
-        c.tol = P.tol;
-        c.dt = P.dt;
-        c.nsweep_pre = MG_NS;
-        c.nsweep_post = MG_NS;
-        if (L == 0) {  // the whole V-cycle runs in LDS
-          const int cur = j->step & 1;
-          if (mixed) {
-            c.phi = j->w_<float>(w.e0);
-            c.b = j->w_<float>(w.r0);
-            c.add_to = j->phi(cur);
-          } else {
-            c.phi = j->phi(cur);
-            c.b = j->w_<double>(w.b0);
-            c.warm = 1;
-            c.write_norm = 1;
-          }
-        } else {
-          c.phi = j->w_<T>(w.lphiA[L]);
-          c.b = j->w_<T>(w.lb[L]);
-        }
-        seg_add(m, c, j->nmem);
-      }
+      for (Job* j : J) seg_add(m, coarse_args<T>(*j, k), j->nmem);
       launch_mg_coarse<T>(m, st);
     }
     for (int l = Lmax - 1; l >= 0; --l) {
-      auto m = seg_begin<MGArgs<T>>();
-      for (Job* j : J) {
-        if (l >= j->P.nlev_grid) continue;
-        const WS& w = j->w;
-        MGArgs<T> a = level_args(*j, l, k);
-        a.phic = j->w_<T>(w.lphiA[l + 1]);
-        if (l == 0) {
-          const int cur = j->step & 1;
-          a.phi_in = mixed ? (const T*)j->w_<float>(w.e0) : (const T*)j->w_<double>(w.phiB);
-          a.b = mixed ? (const T*)j->w_<float>(w.r0) : (const T*)j->w_<double>(w.b0);
-          a.phi_out = mixed ? (T*)j->w_<float>(w.e0) : (T*)j->phi(cur);
-          a.add_to = mixed ? j->phi(cur) : nullptr;
-          a.write_norm = mixed ? 0 : 1;
-        } else {
-          a.phi_in = j->w_<T>(w.lphiB[l]);
-          a.b = j->w_<T>(w.lb[l]);
-          a.phi_out = j->w_<T>(w.lphiA[l]);
-        }
-        seg_add(m, a, a.ntiles * a.nmem);
-      }
       if (timed && l == 0) tm->mark(TM_POST, 0, st);
-      launch_mg_post<T>(m, l == 0 && !mixed, st);
+      grouped<MGArgs<T>>(
+          J, [&](const Job& j) { return l < j.P.nlev_grid ? j.rows_mg[l] : 0; },
+          [&](const Job& j, int rows) { return post_args<T>(j, l, k, rows); },
+          [&](const Multi<MGArgs<T>>& m) { launch_mg_post<T>(m, l == 0 && !mixed, st); });
       if (timed && l == 0) tm->mark(TM_POST, 1, st);
     }
     if (timed && !mixed) tm->mark(TM_CYCLE, 1, st);
@@ -499,22 +630,8 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
   auto resid = [&](int k, bool all) {
     auto m = seg_begin<ResidArgs>();
     for (Job* j : J) {
-      const Plan& P = j->P;
-      if (!all && P.nlev_grid > 0) continue;
-      ResidArgs r{};
-      r.g = P.lev[0];
-      r.tiling = P.st_tl;
-      r.ntiles = P.st_tiles;
-      r.nmem = j->nmem;
-      r.plane = P.lev[0].plane();
-      r.phi = j->phi(j->step & 1);
-      r.b = j->w_<double>(j->w.b0);
-      r.r = j->w_<float>(j->w.r0);
-      r.norms = j->w_<double>(j->w.norms);
-      r.norm_slots = P.norm_slots;
-      r.tol = P.tol;
-      r.dt = P.dt;
-      r.k = k;
+      if (!all && j->P.nlev_grid > 0) continue;
+      const ResidArgs r = resid_args(*j, k);
       seg_add(m, r, r.ntiles * r.nmem);
     }
     if (m.nseg > 0) launch_resid64(m, st);
@@ -538,77 +655,17 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
 // One time step of every job of the batch (each at its own step index).
 template <typename TT>
 static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
-  {
-    auto m = seg_begin<PredArgs<double>>();
-    for (Job* j : J) {
-      const Plan& P = j->P;
-      const WS& w = j->w;
-      const bool even = (j->step & 1) == 0;
-      PredArgs<double> a{};
-      a.g = P.lev[0];
-      a.tiling = P.st_tl;
-      a.ntiles = P.st_tiles;
-      a.nmem = j->nmem;
-      a.plane = P.lev[0].plane();
-      a.nu = P.nu;
-      a.dt = P.dt;
-      a.cold_flag = (j->step == 0 && j->cold_first) ? at<int>(j->state, P.s_meta) : nullptr;
-      a.u = j->w_<double>(w.u);
-      a.v = j->w_<double>(w.v);
-      a.us = j->w_<double>(w.us);
-      a.vs = j->w_<double>(w.vs);
-      a.tu_prev = j->w_<double>(even ? w.tuA : w.tuB);
-      a.tv_prev = j->w_<double>(even ? w.tvA : w.tvB);
-      a.tu = j->w_<double>(even ? w.tuB : w.tuA);
-      a.tv = j->w_<double>(even ? w.tvB : w.tvA);
-      a.b = j->w_<double>(w.b0);
-      a.ctrl = j->ctrl;
-      a.m = P.m;
-      a.nctrl = (int)(P.m / 2);
-      a.cmap = at<int>(j->state, P.s_cmap);
-      a.norms = j->w_<double>(w.norms);
-      a.norm_slots = P.norm_slots;
-      seg_add(m, a, a.ntiles * a.nmem);
-    }
-    if (tm) tm->mark(TM_PRED, 0, st);
-    launch_predictor<double>(m, st);
-    if (tm) tm->mark(TM_PRED, 1, st);
-  }
+  if (tm) tm->mark(TM_PRED, 0, st);
+  grouped<PredArgs<double>>(
+      J, [](const Job& j) { return j.rows_pred; }, [](const Job& j, int rows) { return pred_args(j, rows); },
+      [&](const Multi<PredArgs<double>>& m) { launch_predictor<double>(m, st); });
+  if (tm) tm->mark(TM_PRED, 1, st);
   batch_pressure<TT>(J, st, cap, tm);
-  {
-    auto m = seg_begin<ProjArgs>();
-    for (Job* j : J) {
-      const Plan& P = j->P;
-      const WS& w = j->w;
-      const int cur = j->step & 1;
-      ProjArgs pj{};
-      pj.g = P.lev[0];
-      pj.tiling = P.st_tl;
-      pj.ntiles = P.st_tiles;
-      pj.nmem = j->nmem;
-      pj.plane = P.lev[0].plane();
-      pj.cplane = P.cplane;
-      pj.dt = P.dt;
-      pj.u = j->w_<double>(w.u);
-      pj.v = j->w_<double>(w.v);
-      pj.us = j->w_<double>(w.us);
-      pj.vs = j->w_<double>(w.vs);
-      pj.phi = j->phi(cur);
-      pj.phi_next = j->phi(cur ^ 1);
-      pj.phi_old = j->w_<double>(w.phiQ);
-      pj.stats = j->w_<double>(w.stats);
-      pj.shu = at<double>(j->state, P.s_shu);
-      pj.shv = at<double>(j->state, P.s_shv);
-      pj.s1u = j->w_<double>(w.s1u);
-      pj.s1v = j->w_<double>(w.s1v);
-      pj.s2part = j->w_<double>(w.s2part);
-      pj.divmax = j->w_<double>(w.divmax);
-      seg_add(m, pj, pj.ntiles * pj.nmem);
-    }
-    if (tm) tm->mark(TM_PROJ, 0, st);
-    launch_project_cost(m, st);
-    if (tm) tm->mark(TM_PROJ, 1, st);
-  }
+  if (tm) tm->mark(TM_PROJ, 0, st);
+  grouped<ProjArgs>(
+      J, [](const Job& j) { return j.rows_proj; }, [](const Job& j, int rows) { return proj_args(j, rows); },
+      [&](const Multi<ProjArgs>& m) { launch_project_cost(m, st); });
+  if (tm) tm->mark(TM_PROJ, 1, st);
   {
     auto m = seg_begin<BookArgs>();
     for (Job* j : J) {
@@ -1033,11 +1090,126 @@ struct JobOut {
   bool spinup_store = false;
 };
 
+// ---------------------------------------------------------------------------- tile tuner
+// Chooses the tile height (8 or 16 rows) of the predictor, the projection and
+// each tiled multigrid level by timing both candidates with HIP events on the
+// job's own workspace, before its members are initialised (the trial launches
+// only write workspace buffers that the initialisation or the first step
+// rewrites). No launch in the trial depends on the convergence slots: the
+// multigrid trials run as the first pass of a cycle. Every candidate gives
+// bitwise the same results, so the choice only affects speed. Choices are kept
+// per (grid, geometry, precision, member count rounded up to a power of two).
+struct TileChoice {
+  int pred = 8, proj = 8;
+  int mg[MAX_LEVELS] = {16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16};
+};
+static std::mutex g_tune_mu;
+static std::map<std::array<int, 4>, TileChoice> g_tune;
+
+static void apply_choice(Job& j, const TileChoice& c) {
+  j.rows_pred = c.pred;
+  j.rows_proj = c.proj;
+  for (int l = 0; l < MAX_LEVELS; ++l) j.rows_mg[l] = c.mg[l];
+}
+
+template <typename TT>
+static int tune_job(Job& j, hipStream_t s) {
+  typedef TT T;
+  const Plan& P = j.P;
+  const int fl = P.p.flags;
+  TileChoice c;
+  if (fl & (ENVAR_FLAG_TILES_8 | ENVAR_FLAG_TILES_16)) {
+    const int r = (fl & ENVAR_FLAG_TILES_16) ? 16 : 8;
+    c.pred = c.proj = (r == 16 && P.rows16) ? 16 : 8;
+    for (int l = 0; l < MAX_LEVELS; ++l) c.mg[l] = r;
+    apply_choice(j, c);
+    return ENVAR_OK;
+  }
+  if (fl & ENVAR_FLAG_NO_TUNE) {
+    apply_choice(j, c);
+    return ENVAR_OK;
+  }
+  int bucket = 1;
+  while (bucket < j.nmem) bucket *= 2;
+  const std::array<int, 4> key = {P.n, P.p.geometry, P.mixed, bucket};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      apply_choice(j, it->second);
+      return ENVAR_OK;
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ENVAR_EDEVICE, "hipEventCreate failed");
+  }
+  constexpr int REPS = 3;
+  int rc = ENVAR_OK;
+  // mean device time of one call of `launch` (after one untimed call)
+  auto timed = [&](auto launch) -> float {
+    launch();
+    float ms = 0.f;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = ENVAR_EDEVICE;
+    for (int r = 0; r < REPS; ++r) launch();
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = ENVAR_EDEVICE;
+    return ms / REPS;
+  };
+  auto one = [](auto a) {
+    auto m = seg_begin<decltype(a)>();
+    seg_add(m, a, a.ntiles * a.nmem);
+    return m;
+  };
+  if (P.rows16) {
+    float t[2];
+    for (int v = 0; v < 2; ++v)
+      t[v] = timed([&] { launch_predictor<double>(one(pred_args(j, v ? 16 : 8)), s); });
+    c.pred = t[1] < t[0] ? 16 : 8;
+    for (int v = 0; v < 2; ++v) t[v] = timed([&] { launch_project_cost(one(proj_args(j, v ? 16 : 8)), s); });
+    c.proj = t[1] < t[0] ? 16 : 8;
+  }
+  for (int l = 0; l < P.nlev_grid; ++l) {
+    const int k = (P.mixed && l == 0) ? 1 : 0;  // a first pass: no launch reads a convergence slot
+    float t[2];
+    for (int v = 0; v < 2; ++v) {
+      const int rows = v ? 16 : 8;
+      t[v] = timed([&] {
+        launch_mg_pre<T>(one(pre_args<T>(j, l, k, rows)), s);
+        launch_mg_post<T>(one(post_args<T>(j, l, 0, rows)), l == 0 && !P.mixed, s);
+      });
+    }
+    c.mg[l] = t[0] < t[1] ? 8 : 16;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != ENVAR_OK) return fail(rc, "tile tuner: event timing failed");
+  HIP_OK(hipGetLastError());
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = c;
+  }
+  apply_choice(j, c);
+  return ENVAR_OK;
+}
+
+static void put_rows(const Job& j, envar_stats* st) {
+  if (!st) return;
+  st->rows_pred = j.rows_pred;
+  st->rows_proj = j.rows_proj;
+  for (int l = 0; l < 4; ++l) st->rows_mg[l] = l < j.P.nlev_grid ? j.rows_mg[l] : 0;
+}
+
 // Integrate every job to its own horizon; jobs leave the batch as they finish.
 template <typename TT>
 static int run_batch(std::vector<Job>& jobs, const std::vector<JobOut>& outs, hipStream_t s, Timer* tm, bool graphs) {
   int cap_max = 0;
   for (Job& j : jobs) {
+    const int rc = tune_job<TT>(j, s);
+    if (rc) return rc;
     init_members<TT>(j, s);
     cap_max = std::max(cap_max, j.P.cap_max);
   }
@@ -1133,6 +1305,7 @@ static int forward_impl(const Plan& P, const void* state_dev, const double* cont
   if (rc) return rc;
   if (stats) {
     rc = collect_stats(P, jobs[0].w, ws_dev, n_rows, s, stats, J_dev);
+    put_rows(jobs[0], stats);
     if (rc) return rc;
     fill_timer_stats(timer, stats, n_rows);
     if (stats->diverged > 0) return fail(ENVAR_EDIVERGED, "%d member(s) produced a non-finite cost", stats->diverged);
@@ -1173,6 +1346,7 @@ int envar_forward_batch(envar_job* jobs_in, int32_t njobs, void* stream) {
   for (int k = 0; k < njobs; ++k)
     if (jobs_in[k].stats) {
       rc = collect_stats(jobs[k].P, jobs[k].w, jobs[k].ws, jobs[k].nmem, s, jobs_in[k].stats, jobs_in[k].J_dev);
+      put_rows(jobs[k], jobs_in[k].stats);
       if (rc) return rc;
       diverged += jobs_in[k].stats->diverged;
     }
@@ -1556,6 +1730,7 @@ struct Server {
         (void)hipMemcpyAsync(base + r->L.ctrl, r->controls.data(), r->controls.size() * 8, hipMemcpyHostToDevice, s);
         r->job.ws = base + r->L.ws;
         r->job.ctrl = (const double*)(base + r->L.ctrl);
+        if (tune_job<TT>(r->job, s) != ENVAR_OK) apply_choice(r->job, TileChoice());
         init_members<TT>(r->job, s);
         D.cap_max = std::max(D.cap_max, r->P.cap_max);
         if (D.cap == 0) D.cap = D.cap_max;

@@ -19,8 +19,7 @@ namespace envar {
 
 // Tiles of the stencil kernels: 64 cells (one wave) wide.
 constexpr int TILE_W = 64;
-constexpr int STEP_TH = 8;   // predictor / projection tile height
-constexpr int MG_TH = 16;    // multigrid tile height
+constexpr int COST_TH = 8;   // rows of a cost block: the S2 partial sums live on a fixed 64 x 8 grid
 constexpr int MG_NS = 2;     // red-black sweeps before and after the coarse correction
 constexpr int MG_H = 2 * MG_NS + 1;           // window halo of the multigrid kernels
 constexpr int MG_TW = 64 - 2 * MG_H;          // multigrid tile width: the window is one wave wide
@@ -97,6 +96,11 @@ struct Tiling {
     return t;
   }
   __host__ __device__ int count() const { return cav_cols * cav_rows + ch_cols * ch_rows; }
+  // index of the tile whose origin is (x0, y0) (the inverse of origin())
+  __device__ __forceinline__ int index(int x0, int y0) const {
+    if (y0 < jc_tiles) return (y0 / th) * cav_cols + (x0 / tw - cav_c0);
+    return cav_cols * cav_rows + ((y0 - jc_tiles) / th) * ch_cols + x0 / tw;
+  }
   __device__ __forceinline__ void origin(int t, int& x0, int& y0) const {
     int ncav = cav_cols * cav_rows;
     if (t < ncav) {

@@ -40,6 +40,7 @@ template <typename TT>
 struct PredArgs {
   Geo g;
   Tiling tiling;
+  int trows;                  // tile height of `tiling` (8 or 16)
   int ntiles, nmem;
   long plane;
   double nu, dt;
@@ -64,7 +65,10 @@ struct PredArgs {
 struct ProjArgs {
   Geo g;
   Tiling tiling;
+  int trows;          // tile height of `tiling` (8 or 16)
   int ntiles, nmem;
+  Tiling cost_tiling; // 64 x 8 cost blocks: s2part[mem][cost_ntiles]
+  int cost_ntiles;
   long plane, cplane;
   double dt;
   double* u;
@@ -82,7 +86,7 @@ struct ProjArgs {
   const double* shv;
   double* s1u;        // [nmem][cplane] running sums of (u_c - s_c); NULL = no cost
   double* s1v;
-  double* s2part;     // [nmem][ntiles]
+  double* s2part;     // [nmem][cost_ntiles]
   double* divmax;     // [nmem] max |div u^{n+1}| (atomicMax on the bit pattern)
 };
 
@@ -128,6 +132,7 @@ struct MGArgs {
   const unsigned char* code;   // this level: Poisson diagonal count of every cell (0 = not fluid), plane layout
   const unsigned char* codec;  // the coarser level
   Tiling tiling;
+  int trows;          // tile height of `tiling` (8 or 16): selects the kernel instance
   int ntiles, nmem;
   long plane, cplane_c;  // plane of this level and of the coarse level
   const T* phi_in;    // [nmem][plane] read (halo included); never written by this launch

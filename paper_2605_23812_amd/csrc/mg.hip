@@ -46,8 +46,9 @@ __device__ __forceinline__ bool mg_skip(const MGArgs<T>& a, int mem, int tile) {
   return false;
 }
 
-// The multigrid tile kernels hold a 64 x (MG_TH + 2H) window of one level in
-// LDS around a (64 - 2H) x MG_TH tile: a window row is one wave, lane = column,
+// The multigrid tile kernels hold a 64 x (TR + 2H) window of one level in
+// LDS around a (64 - 2H) x TR tile (TR = 8 or 16 rows, chosen per level by
+// the tile tuner): a window row is one wave, lane = column,
 // so no index needs a division. The two red-black colours live in separate
 // padded planes; a cell's four neighbours are all of the other colour and sit
 // at consecutive addresses for consecutive lanes. Each thread owns one column
@@ -56,9 +57,9 @@ __device__ __forceinline__ bool mg_skip(const MGArgs<T>& a, int mem, int tile) {
 // fluid are frozen (1/diag = 0). The Poisson diagonal of every cell is read
 // from a per-level byte plane shared by all members.
 // (ox + oy) is even, so a cell's colour is (r + col) & 1 in window coordinates.
-template <typename T>
+template <typename T, int TR>
 struct Win {
-  static constexpr int H = MG_H, LW = 64, TWI = MG_TW, TH = MG_TH, LH = TH + 2 * H;
+  static constexpr int H = MG_H, LW = 64, TWI = MG_TW, TH = TR, LH = TH + 2 * H;
   static constexpr int QS = 34;                 // padded row stride of a colour plane (32 cells)
   static constexpr int CS = (LH + 2) * QS;      // padded colour plane
   static constexpr int NR = (LH + 3) / 4;       // window rows per wave
@@ -74,9 +75,9 @@ __device__ __forceinline__ T inv_of(int d) {
                                                                                           : (T)1;
 }
 
-template <typename T>
+template <typename T, int TR>
 struct Items {
-  typedef Win<T> W;
+  typedef Win<T, TR> W;
   int own0[2];        // LDS offset of the first item of each colour
   int left0[2];       // offset of its left neighbour (other colour)
   int r0, q;
@@ -133,9 +134,9 @@ struct Items {
 };
 
 // window load shared by pre and post: phi (+ correction), b and the diagonal codes
-template <typename T>
+template <typename T, int TR>
 struct WinLoad {
-  typedef Win<T> W;
+  typedef Win<T, TR> W;
   T vp[W::NR], vb[W::NR];
   unsigned char vc[W::NR];
   __device__ __forceinline__ void fetch(const Geo& g, const unsigned char* code, const T* phi, const T* b, long off,
@@ -178,9 +179,9 @@ __device__ __forceinline__ bool ref_skip(const MGArgs<T>& a, int mem, int tile) 
 }
 
 // ---------------------------------------------------------------------------- pre-smoothing + restriction
-template <typename T, int NS, bool REF, bool ONE>
+template <typename T, int NS, bool REF, bool ONE, int TR>
 __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
-  typedef Win<T> W;
+  typedef Win<T, TR> W;
   static_assert(2 * NS + 1 <= W::H, "window halo too small for the sweep count");
   static_assert(W::TH * 64 <= 2 * W::CS, "residual staging does not fit");
   static_assert(!REF || sizeof(double) * 64 * W::LH <= sizeof(T) * 4 * W::CS, "FP64 window does not fit");
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
       }
     }
   } else {
-    WinLoad<T> L;
+    WinLoad<T, TR> L;
     L.fetch(g, a.code, a.zero_guess ? nullptr : a.phi_in, a.b, off, ox, oy);
 #pragma unroll
     for (int m = 0; m < W::NR; ++m) {
@@ -288,10 +289,10 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
   }
   __syncthreads();
   const T h2 = (T)(g.h * g.h);
-  Items<T> it;
+  Items<T, TR> it;
   it.init(sb, scode, h2);
   for (int s = 0; s < NS; ++s) it.sweep(sp);
-  // interior residuals staged in sb (dead by now) as a MG_TH x 64 array
+  // interior residuals staged in sb (dead by now) as a TR x 64 array
   T res[2][W::NIT];
   for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -331,9 +332,9 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
 }
 
 // ---------------------------------------------------------------------------- prolongation + post-smoothing
-template <typename T, int NS, int NORM, bool ONE>
+template <typename T, int NS, int NORM, bool ONE, int TR>
 __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
-  typedef Win<T> W;
+  typedef Win<T, TR> W;
   static_assert(2 * NS + NORM <= W::H, "window halo too small for the sweep count");
   constexpr int CW = 36, CH = W::LH / 2 + 3;
   __shared__ T sp[2 * W::CS];
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
   const T* __restrict__ pc = a.phic + (long)mem * a.cplane_c;
   const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int cox = (ox >> 1) - 1, coy = (oy >> 1) - 1;
-  WinLoad<T> L;
+  WinLoad<T, TR> L;
   L.fetch(g, a.code, a.phi_in, a.b, off, ox, oy);
   // coarse correction window [cox, cox + 36) x [coy, coy + CH)
   {
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
   }
   __syncthreads();
   const T h2 = (T)(g.h * g.h);
-  Items<T> it;
+  Items<T, TR> it;
   it.init(sb, scode, h2);
   for (int s = 0; s < NS; ++s) it.sweep(sp);
   if (NORM && a.write_norm) {
@@ -707,7 +708,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
 // ---------------------------------------------------------------------------- FP64 residual (refinement)
 template <bool ONE>
 __global__ __launch_bounds__(256) void k_resid64(Multi<ResidArgs> ms) {
-  constexpr int TW = TILE_W, TH = STEP_TH;
+  constexpr int TW = TILE_W, TH = COST_TH;
   __shared__ double red[4];
   int item;
   const ResidArgs& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
@@ -753,38 +754,53 @@ __global__ __launch_bounds__(256) void k_resid64(Multi<ResidArgs> ms) {
 }
 
 // ---------------------------------------------------------------------------- launchers
-template <typename T, bool REF>
+template <typename T, bool REF, int TR>
 static void launch_mg_pre_(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, true>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, false>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
+}
+// every segment of one launch shares the tile height (the host groups segments by it)
+template <typename T, bool REF>
+static void launch_mg_pre_rows(const Multi<MGArgs<T>>& m, hipStream_t s) {
+  if (m.seg[0].trows == 8)
+    launch_mg_pre_<T, REF, 8>(m, s);
+  else
+    launch_mg_pre_<T, REF, 16>(m, s);
 }
 template <>
 void launch_mg_pre<double>(const Multi<MGArgs<double>>& m, hipStream_t s) {
-  launch_mg_pre_<double, false>(m, s);
+  launch_mg_pre_rows<double, false>(m, s);
 }
 template <>
 void launch_mg_pre<float>(const Multi<MGArgs<float>>& m, hipStream_t s) {
   // every segment of a finest-level launch in mixed precision refines (one precision per batch)
   if (m.seg[0].phi64)
-    launch_mg_pre_<float, true>(m, s);
+    launch_mg_pre_rows<float, true>(m, s);
   else
-    launch_mg_pre_<float, false>(m, s);
+    launch_mg_pre_rows<float, false>(m, s);
+}
+template <typename T, int NORM, int TR>
+static void launch_mg_post_(const Multi<MGArgs<T>>& m, hipStream_t s) {
+  if (m.nseg == 1)
+    hipLaunchKernelGGL((k_mg_post<T, MG_NS, NORM, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
+  else
+    hipLaunchKernelGGL((k_mg_post<T, MG_NS, NORM, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
 }
 template <typename T>
 void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s) {
-  const dim3 g(m.total()), b(256);
-  if (m.nseg == 1) {
-    if (write_norm)
-      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 1, true>), g, b, 0, s, m);
+  const bool r8 = m.seg[0].trows == 8;
+  if (write_norm) {
+    if (r8)
+      launch_mg_post_<T, 1, 8>(m, s);
     else
-      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 0, true>), g, b, 0, s, m);
+      launch_mg_post_<T, 1, 16>(m, s);
   } else {
-    if (write_norm)
-      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 1, false>), g, b, 0, s, m);
+    if (r8)
+      launch_mg_post_<T, 0, 8>(m, s);
     else
-      hipLaunchKernelGGL((k_mg_post<T, MG_NS, 0, false>), g, b, 0, s, m);
+      launch_mg_post_<T, 0, 16>(m, s);
   }
 }
 template <typename T>

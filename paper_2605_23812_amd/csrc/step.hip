@@ -23,9 +23,9 @@
 namespace envar {
 
 // ---------------------------------------------------------------------------- predictor
-template <typename TT, bool ONE>
+template <typename TT, bool ONE, int TH>
 __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
-  constexpr int TW = TILE_W, TH = STEP_TH;
+  constexpr int TW = TILE_W;
   constexpr int UW = TW + 3, UH = TH + 2;  // u halo: i in [x0-1, x0+TW+1], j in [y0-1, y0+TH]
   constexpr int VW = TW + 2, VH = TH + 3;  // v halo: i in [x0-1, x0+TW],   j in [y0-1, y0+TH+1]
   __shared__ double su[UH * UW];
@@ -182,10 +182,13 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
 }
 
 // ---------------------------------------------------------------------------- projection + cost
-template <bool ONE>
+// The S2 partial of every 64 x 8 cost block is formed with the same operand
+// order whatever the tile height, so J does not depend on the tile choice.
+template <bool ONE, int TH>
 __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
-  constexpr int TW = TILE_W, TH = STEP_TH;
-  __shared__ double red_s[4];
+  constexpr int TW = TILE_W, NB = TH / COST_TH;
+  static_assert(TH % COST_TH == 0 && COST_TH == 8, "cost blocks are 64 x 8 (two rows per thread)");
+  __shared__ double red_s[NB][4];
   __shared__ double red_m[4];
   int item;
   const ProjArgs& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
@@ -207,7 +210,9 @@ __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
   // switches on) and linear after the second, quadratic from then on
   const double done = a.stats ? a.stats[(long)mem * STATS_STRIDE + ST_STEPS] : 1.0;
   const int order = done < 0.5 ? 0 : done < 1.5 ? 1 : 2;
-  double acc = 0.0, dmax = 0.0;
+  double acc[NB], dmax = 0.0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = 0.0;
 #pragma unroll
   for (int rr = 0; rr < TH / 4; ++rr) {
     const int r = ty + 4 * rr;
@@ -258,21 +263,27 @@ __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
       const double dv = 0.5 * (vsv + vn) - a.shv[ac];
       a.s1u[coff + ac] += du;
       a.s1v[coff + ac] += dv;
-      acc += du * du + dv * dv;
+      acc[rr >> 1] += du * du + dv * dv;  // row ty + 4 rr lies in cost block rr / 2
     }
   }
-  acc = wave_sum(acc);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = wave_sum(acc[b]);
   dmax = wave_max(dmax);
   if (tx == 0) {
-    red_s[ty] = acc;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) red_s[b][ty] = acc[b];
     red_m[ty] = dmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double s = ((red_s[0] + red_s[1]) + red_s[2]) + red_s[3];
+    if (a.s2part)
+      for (int b = 0; b < NB; ++b) {
+        if (y0 + COST_TH * b >= g.ny) break;
+        const double s = ((red_s[b][0] + red_s[b][1]) + red_s[b][2]) + red_s[b][3];
+        a.s2part[(long)mem * a.cost_ntiles + a.cost_tiling.index(x0, y0 + COST_TH * b)] += s;
+      }
     double m = red_m[0];
     for (int k = 1; k < 4; ++k) m = (red_m[k] > m || red_m[k] != red_m[k]) ? red_m[k] : m;
-    if (a.s2part) a.s2part[(long)mem * a.ntiles + tile] += s;
     atomicMax((unsigned long long*)&a.divmax[mem], dbits(m));
   }
 }
@@ -432,20 +443,35 @@ void launch_stream_copy(const void* src, void* dst, long n16, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------- launchers
+template <typename TT, int TH>
+static void launch_predictor_(const Multi<PredArgs<TT>>& m, hipStream_t s) {
+  if (m.nseg == 1)
+    hipLaunchKernelGGL((k_predictor<TT, true, TH>), dim3(m.total()), dim3(256), 0, s, m);
+  else
+    hipLaunchKernelGGL((k_predictor<TT, false, TH>), dim3(m.total()), dim3(256), 0, s, m);
+}
+// every segment of one launch shares the tile height (the host groups segments by it)
 template <typename TT>
 void launch_predictor(const Multi<PredArgs<TT>>& m, hipStream_t s) {
-  if (m.nseg == 1)
-    hipLaunchKernelGGL((k_predictor<TT, true>), dim3(m.total()), dim3(256), 0, s, m);
+  if (m.seg[0].trows == 8)
+    launch_predictor_<TT, 8>(m, s);
   else
-    hipLaunchKernelGGL((k_predictor<TT, false>), dim3(m.total()), dim3(256), 0, s, m);
+    launch_predictor_<TT, 16>(m, s);
 }
 template void launch_predictor<double>(const Multi<PredArgs<double>>&, hipStream_t);
 
-void launch_project_cost(const Multi<ProjArgs>& m, hipStream_t s) {
+template <int TH>
+static void launch_project_cost_(const Multi<ProjArgs>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL(k_project_cost<true>, dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_project_cost<true, TH>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL(k_project_cost<false>, dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_project_cost<false, TH>), dim3(m.total()), dim3(256), 0, s, m);
+}
+void launch_project_cost(const Multi<ProjArgs>& m, hipStream_t s) {
+  if (m.seg[0].trows == 8)
+    launch_project_cost_<8>(m, s);
+  else
+    launch_project_cost_<16>(m, s);
 }
 void launch_step_book(const Multi<BookArgs>& m, hipStream_t s) {
   hipLaunchKernelGGL(k_step_book, dim3(m.total()), dim3(64), 0, s, m);

@@ -20,6 +20,9 @@ REGION_COLUMN, REGION_CAVITY, REGION_BOX = 0, 1, 2
 FP64, MIXED = 0, 1
 FLAG_TIME_KERNELS = 1
 FLAG_NO_GRAPHS = 2
+FLAG_NO_TUNE = 4
+FLAG_TILES_8 = 8
+FLAG_TILES_16 = 16
 
 EXPORTS = (
     "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",
@@ -53,10 +56,13 @@ class Stats(ctypes.Structure):
         ("predictor_us", ctypes.c_double), ("pre_us", ctypes.c_double), ("post_us", ctypes.c_double),
         ("resid_us", ctypes.c_double), ("project_us", ctypes.c_double), ("vcycle_us", ctypes.c_double),
         ("timed_steps", ctypes.c_int32), ("timed_members", ctypes.c_int32),
+        ("rows_pred", ctypes.c_int32), ("rows_proj", ctypes.c_int32), ("rows_mg", ctypes.c_int32 * 4),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["rows_mg"] = list(self.rows_mg)
+        return d
 
 
 class _Job(ctypes.Structure):
