@@ -21,6 +21,9 @@ namespace envar {
 constexpr int TILE_W = 64;
 constexpr int COST_TH = 8;   // rows of a cost block: the S2 partial sums live on a fixed 64 x 8 grid
 constexpr int MG_NS = 2;     // red-black sweeps before and after the coarse correction
+// over-relaxation of the red-black sweeps on the tiled levels: measured at h = 1/128 (65 members),
+// FP64 V-cycles per step 3.04 (omega = 1) -> 2.06 (1.15) -> 3.05 (1.3); the LDS levels keep 1
+constexpr double MG_OMEGA = 1.15;
 constexpr int MG_H = 2 * MG_NS + 1;           // window halo of the multigrid kernels
 constexpr int MG_TW = 64 - 2 * MG_H;          // multigrid tile width: the window is one wave wide
 constexpr int COARSE_N = 16; // levels with inv_h <= 16 run inside one workgroup per member

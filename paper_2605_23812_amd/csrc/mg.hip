@@ -4,9 +4,9 @@
 // phi = 0 on the outflow face (mirror ghost -phi). The geometry is aligned on
 // every level down to h = 1/4, so each coarse cell has four fluid children.
 //
-// Per fine level and V-cycle two launches, both over (member, 64 x 16 tile):
+// Per fine level and V-cycle two launches, both over (member, 64 x 8 or 64 x 16 tile):
 //   pre : load phi, b with a halo of 2 NS + 1 into LDS, NS red-black
-//         Gauss-Seidel sweeps (temporal blocking: a sweep invalidates two
+//         Gauss-Seidel sweeps over-relaxed by MG_OMEGA (temporal blocking: a sweep invalidates two
 //         halo rings), residual r = b - L phi, restriction b_c = mean of the
 //         four children; writes phi and b_c.
 //   post: load phi, b with a halo of 2 NS (+1), add the bilinearly
@@ -120,7 +120,10 @@ struct Items {
     for (int c = 0; c < 2; ++c) {
 #pragma unroll
       for (int n = 0; n < W::NIT; ++n)
-        if (invd[c][n] != (T)0) sp[own0[c] + 8 * n * W::QS] = (nbsum(sp, c, n) - hb[c][n]) * invd[c][n];
+        if (invd[c][n] != (T)0) {
+          T* const o = sp + own0[c] + 8 * n * W::QS;
+          *o += (T)MG_OMEGA * ((nbsum(sp, c, n) - hb[c][n]) * invd[c][n] - *o);
+        }
       __syncthreads();
     }
   }
