@@ -113,11 +113,11 @@ typedef struct {
   double cell_steps;       /* fluid cells x steps x members */
   /* ENVAR_FLAG_TIME_KERNELS: mean device time per launch (microseconds) over
    * the sampled steps, and the number of sampled steps */
-  double predictor_us;     /* fused predictor */
+  double predictor_us;     /* predictor, fused with the previous step's projection and cost sample */
   double pre_us;           /* finest-level pre-smoothing + restriction */
   double post_us;          /* finest-level prolongation + post-smoothing (+ residual norm) */
   double resid_us;         /* FP64 refinement residual (MIXED) */
-  double project_us;       /* projection + cost accumulator */
+  double project_us;       /* 0: the projection runs inside the next predictor (one closing launch per forward) */
   double vcycle_us;        /* one full V-cycle (FP64) or refinement pass (MIXED) */
   int32_t timed_steps;
   int32_t timed_members;   /* members active in the timed cycle (all, unless converged before it) */

@@ -197,7 +197,7 @@ static int make_plan(const envar_problem* pin, Plan& P) {
 
 // workspace layout of a forward over nmem members
 struct WS {
-  size_t u, v, us, vs, tuA, tvA, tuB, tvB, phiA, phiB, phiC, phiQ, b0, e0, r0;
+  size_t u, v, us, vs, us2, vs2, tuA, tvA, tuB, tvB, phiA, phiB, phiC, phiQ, b0, e0, r0;
   size_t lphiA[MAX_LEVELS], lphiB[MAX_LEVELS], lb[MAX_LEVELS];
   size_t s1u, s1v, s2part, norms, stats, divmax;
   size_t total;
@@ -216,8 +216,10 @@ static WS make_ws(const Plan& P, int nmem) {
   const size_t vsz = P.mixed ? 4 : 8;  // V-cycle storage
   w.u = take(nmem * pl * 8);
   w.v = take(nmem * pl * 8);
-  w.us = take(nmem * pl * 8);
+  w.us = take(nmem * pl * 8);   // u*, v* of even steps
   w.vs = take(nmem * pl * 8);
+  w.us2 = take(nmem * pl * 8);  // u*, v* of odd steps (the fused predictor reads the other parity)
+  w.vs2 = take(nmem * pl * 8);
   w.tuA = take(nmem * pl * tsz);
   w.tvA = take(nmem * pl * tsz);
   w.tuB = take(nmem * pl * tsz);
@@ -363,6 +365,8 @@ struct Job {
     return at<T>(ws, off);
   }
   double* phi(int k) const { return w_<double>(k ? w.phiC : w.phiA); }
+  double* ustar(int p) const { return w_<double>(p ? w.us2 : w.us); }
+  double* vstar(int p) const { return w_<double>(p ? w.vs2 : w.vs); }
 };
 
 template <typename A>
@@ -383,10 +387,11 @@ static Multi<A> seg_begin() {
 // height (8 or 16) of the launch; k is the V-cycle pass.
 static int vidx(int rows) { return rows == 16 ? 1 : 0; }
 
-static PredArgs<double> pred_args(const Job& j, int rows) {
+static PredArgs<double> pred_args(const Job& j, int rows, bool fused) {
   const Plan& P = j.P;
   const WS& w = j.w;
   const bool even = (j.step & 1) == 0;
+  const int par = j.step & 1;
   PredArgs<double> a{};
   a.g = P.lev[0];
   a.tiling = P.sk_tl[vidx(rows)];
@@ -397,10 +402,29 @@ static PredArgs<double> pred_args(const Job& j, int rows) {
   a.nu = P.nu;
   a.dt = P.dt;
   a.cold_flag = (j.step == 0 && j.cold_first) ? at<int>(j.state, P.s_meta) : nullptr;
-  a.u = j.w_<double>(w.u);
-  a.v = j.w_<double>(w.v);
-  a.us = j.w_<double>(w.us);
-  a.vs = j.w_<double>(w.vs);
+  a.us = j.ustar(par);
+  a.vs = j.vstar(par);
+  if (fused) {  // projection of the previous step: its u*, v* and phi (the other parity)
+    a.fused = 1;
+    a.u = j.ustar(par ^ 1);
+    a.v = j.vstar(par ^ 1);
+    a.phi = j.phi(par ^ 1);
+    a.phi_next = j.phi(par);
+    a.phi_old = j.w_<double>(w.phiQ);
+    a.stats = j.w_<double>(w.stats);
+    a.shu = at<double>(j.state, P.s_shu);
+    a.shv = at<double>(j.state, P.s_shv);
+    a.s1u = j.w_<double>(w.s1u);
+    a.s1v = j.w_<double>(w.s1v);
+    a.s2part = j.w_<double>(w.s2part);
+    a.divmax = j.w_<double>(w.divmax);
+    a.cost_tiling = P.st_tl;
+    a.cost_ntiles = P.st_tiles;
+    a.cplane = P.cplane;
+  } else {
+    a.u = j.w_<double>(w.u);
+    a.v = j.w_<double>(w.v);
+  }
   a.tu_prev = j.w_<double>(even ? w.tuA : w.tuB);
   a.tv_prev = j.w_<double>(even ? w.tvA : w.tvB);
   a.tu = j.w_<double>(even ? w.tuB : w.tuA);
@@ -415,10 +439,10 @@ static PredArgs<double> pred_args(const Job& j, int rows) {
   return a;
 }
 
-static ProjArgs proj_args(const Job& j, int rows) {
+// the projection that closes a forward (cur: parity of its last step)
+static ProjArgs proj_args(const Job& j, int rows, int cur) {
   const Plan& P = j.P;
   const WS& w = j.w;
-  const int cur = j.step & 1;
   ProjArgs pj{};
   pj.g = P.lev[0];
   pj.tiling = P.sk_tl[vidx(rows)];
@@ -432,8 +456,8 @@ static ProjArgs proj_args(const Job& j, int rows) {
   pj.dt = P.dt;
   pj.u = j.w_<double>(w.u);
   pj.v = j.w_<double>(w.v);
-  pj.us = j.w_<double>(w.us);
-  pj.vs = j.w_<double>(w.vs);
+  pj.us = j.ustar(cur);
+  pj.vs = j.vstar(cur);
   pj.phi = j.phi(cur);
   pj.phi_next = j.phi(cur ^ 1);
   pj.phi_old = j.w_<double>(w.phiQ);
@@ -655,17 +679,15 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
 // One time step of every job of the batch (each at its own step index).
 template <typename TT>
 static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
+  // the first step of a job starts from u^n; later steps fuse the previous step's projection
   if (tm) tm->mark(TM_PRED, 0, st);
-  grouped<PredArgs<double>>(
-      J, [](const Job& j) { return j.rows_pred; }, [](const Job& j, int rows) { return pred_args(j, rows); },
-      [&](const Multi<PredArgs<double>>& m) { launch_predictor<double>(m, st); });
+  for (const bool fused : {false, true})
+    grouped<PredArgs<double>>(
+        J, [&](const Job& j) { return (j.step > 0) == fused ? j.rows_pred : 0; },
+        [&](const Job& j, int rows) { return pred_args(j, rows, fused); },
+        [&](const Multi<PredArgs<double>>& m) { launch_predictor<double>(m, st); });
   if (tm) tm->mark(TM_PRED, 1, st);
   batch_pressure<TT>(J, st, cap, tm);
-  if (tm) tm->mark(TM_PROJ, 0, st);
-  grouped<ProjArgs>(
-      J, [](const Job& j) { return j.rows_proj; }, [](const Job& j, int rows) { return proj_args(j, rows); },
-      [&](const Multi<ProjArgs>& m) { launch_project_cost(m, st); });
-  if (tm) tm->mark(TM_PROJ, 1, st);
   {
     auto m = seg_begin<BookArgs>();
     for (Job* j : J) {
@@ -703,6 +725,8 @@ static void init_members(const Job& j, hipStream_t s) {
   ia.v = j.w_<double>(w.v);
   ia.us = j.w_<double>(w.us);
   ia.vs = j.w_<double>(w.vs);
+  ia.us2 = j.w_<double>(w.us2);
+  ia.vs2 = j.w_<double>(w.vs2);
   ia.phi = j.w_<double>(w.phiA);
   ia.phi2 = j.w_<double>(w.phiC);
   ia.tu = j.w_<double>(w.tuA);
@@ -719,6 +743,13 @@ static void init_members(const Job& j, hipStream_t s) {
 static void finish_job(const Job& j, double* J_dev, double* fields_dev, bool spinup_store, hipStream_t s) {
   const Plan& P = j.P;
   const WS& w = j.w;
+  {
+    // the projection of the last step (earlier ones ran fused into the next predictor)
+    auto m = seg_begin<ProjArgs>();
+    const ProjArgs pj = proj_args(j, j.rows_proj, j.last_cur);
+    seg_add(m, pj, pj.ntiles * pj.nmem);
+    launch_project_cost(m, s);
+  }
   if (J_dev) {
     FinalArgs fa{};
     fa.g = P.lev[0];
@@ -1165,12 +1196,11 @@ static int tune_job(Job& j, hipStream_t s) {
     return m;
   };
   if (P.rows16) {
+    // the steady-state kernel: predictor fused with the previous projection
     float t[2];
     for (int v = 0; v < 2; ++v)
-      t[v] = timed([&] { launch_predictor<double>(one(pred_args(j, v ? 16 : 8)), s); });
-    c.pred = t[1] < t[0] ? 16 : 8;
-    for (int v = 0; v < 2; ++v) t[v] = timed([&] { launch_project_cost(one(proj_args(j, v ? 16 : 8)), s); });
-    c.proj = t[1] < t[0] ? 16 : 8;
+      t[v] = timed([&] { launch_predictor<double>(one(pred_args(j, v ? 16 : 8, true)), s); });
+    c.pred = c.proj = t[1] < t[0] ? 16 : 8;
   }
   for (int l = 0; l < P.nlev_grid; ++l) {
     const int k = (P.mixed && l == 0) ? 1 : 0;  // a first pass: no launch reads a convergence slot

@@ -60,6 +60,23 @@ struct PredArgs {
   const int* cmap;            // control index of every cell (plane layout), -1 outside
   double* norms;              // [nmem][norm_slots], cleared here
   int norm_slots;
+  // fused with the projection of the previous step: u, v above then hold u*^{n-1}, v*^{n-1};
+  // u^n = u* - dt grad phi^{n-1} is rebuilt on the halo, and the previous step's cost sample,
+  // divergence and warm start of this step's solve are produced here (see ProjArgs)
+  int fused;
+  const double* phi;          // phi^{n-1}
+  double* phi_next;           // phi^{n-2} on entry -> warm start of this step's solve
+  double* phi_old;            // phi^{n-3} on entry -> phi^{n-2}
+  const double* stats;
+  const double* shu;
+  const double* shv;
+  double* s1u;
+  double* s1v;
+  double* s2part;
+  double* divmax;
+  Tiling cost_tiling;
+  int cost_ntiles;
+  long cplane;
 };
 
 struct ProjArgs {
@@ -120,7 +137,7 @@ struct InitArgs {
   int nmem, ntiles;
   long plane, cplane;
   const double *bu, *bv, *btu, *btv, *bphi;
-  double *u, *v, *us, *vs, *phi, *phi2;
+  double *u, *v, *us, *vs, *us2, *vs2, *phi, *phi2;
   TT *tu, *tv;
   double *s1u, *s1v, *s2part, *stats, *divmax;
 };

@@ -23,15 +23,27 @@
 namespace envar {
 
 // ---------------------------------------------------------------------------- predictor
-template <typename TT, bool ONE, int TH>
+// FUSED: the projection of the previous step runs here first. The halo of
+// u^n = u*^{n-1} - dt grad phi^{n-1} is rebuilt in LDS from u*, v* and phi
+// (with the same expressions as k_project_cost, so every value is bitwise the
+// same), and the tile cells take the previous step's cost sample, divergence
+// and the warm start of this step's solve. u^n never goes to memory: the step
+// carries u* and phi, which saves the u, v store and reload and a launch.
+template <typename TT, bool ONE, int TH, bool FUSED>
 __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
   constexpr int TW = TILE_W;
   constexpr int UW = TW + 3, UH = TH + 2;  // u halo: i in [x0-1, x0+TW+1], j in [y0-1, y0+TH]
   constexpr int VW = TW + 2, VH = TH + 3;  // v halo: i in [x0-1, x0+TW],   j in [y0-1, y0+TH+1]
+  constexpr int PW = TW + 4, PH = TH + 4;  // phi halo (fused): i in [x0-2, x0+TW+1], j in [y0-2, y0+TH+1]
+  constexpr int NB = TH / COST_TH;
+  static_assert(TH % COST_TH == 0 && COST_TH == 8, "cost blocks are 64 x 8 (two rows per thread)");
   __shared__ double su[UH * UW];
   __shared__ double sv[VH * VW];
   __shared__ double sus[TH * (TW + 1)];
   __shared__ double svs[(TH + 1) * TW];
+  __shared__ double sphi[FUSED ? PH * PW : 1];
+  __shared__ double red_s[NB][4];
+  __shared__ double red_m[4];
 
   int item;
   const PredArgs<TT>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
@@ -51,6 +63,15 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
   if (tile == 0 && a.norms != nullptr)
     for (int k = tid; k < a.norm_slots; k += 256) a.norms[(long)mem * a.norm_slots + k] = 0.0;
 
+  // Every global operand of the tile besides the halo is loaded into registers
+  // right after the halo loads, so its latency overlaps the LDS phases.
+  constexpr int KU = (TH * (TW + 1) + 255) / 256, KV = ((TH + 1) * TW + 255) / 256, KR = TH / 4;
+  const bool cold = a.cold_flag != nullptr && *a.cold_flag != 0;
+  const int tx = tid % TW, ty = tid / TW;
+  const long coff = (long)mem * a.cplane;
+  TT tpu[KU], tpv[KV];         // T^{n-1} of this thread's active faces
+  int cmu[KU][2], cmv[KV][2];  // control index of the two cells of each face (-1: none)
+  double pn[KR], po[KR], s1a[KR], s1b[KR], sha[KR], shb[KR];  // fused: operands of the tile cells
   {
     // all global loads of the halo first, then the LDS stores
     constexpr int NU = (UH * UW + 255) / 256, NV = (VH * VW + 255) / 256;
@@ -67,6 +88,64 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
       const int i = x0 - 1 + k % VW, j = y0 - 1 + k / VW;
       lv[n] = (k < VH * VW && i >= 0 && i < g.nx && j >= 0 && j <= g.ny) ? v[g.at(i, j)] : 0.0;
     }
+    if (FUSED) {
+      constexpr int NP = (PH * PW + 255) / 256;
+      const double* __restrict__ ph = a.phi + off;
+      double lp[NP];
+#pragma unroll
+      for (int n = 0; n < NP; ++n) {
+        const int k = tid + 256 * n;
+        const int i = x0 - 2 + k % PW, j = y0 - 2 + k / PW;
+        lp[n] = (k < PH * PW && i >= 0 && i < g.nx && j >= 0 && j < g.ny) ? ph[g.at(i, j)] : 0.0;
+      }
+#pragma unroll
+      for (int n = 0; n < NP; ++n)
+        if (tid + 256 * n < PH * PW) sphi[tid + 256 * n] = lp[n];
+    }
+#pragma unroll
+    for (int kk = 0; kk < KU; ++kk) {
+      const int k = tid + 256 * kk;
+      const int i = x0 + k % (TW + 1), j = y0 + k / (TW + 1);
+      tpu[kk] = (TT)0;
+      cmu[kk][0] = cmu[kk][1] = -1;
+      if (k < TH * (TW + 1) && i <= g.nx && j < g.ny && g.fluid(i - 1, j) && g.fluid(i, j)) {
+        if (!cold) tpu[kk] = tup[g.at(i, j)];
+        if (f) {
+          cmu[kk][0] = a.cmap[g.at(i - 1, j)];
+          cmu[kk][1] = a.cmap[g.at(i, j)];
+        }
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KV; ++kk) {
+      const int k = tid + 256 * kk;
+      const int i = x0 + k % TW, j = y0 + k / TW;
+      tpv[kk] = (TT)0;
+      cmv[kk][0] = cmv[kk][1] = -1;
+      if (k < (TH + 1) * TW && i < g.nx && j <= g.ny && g.fluid(i, j - 1) && g.fluid(i, j)) {
+        if (!cold) tpv[kk] = tvp[g.at(i, j)];
+        if (f) {
+          cmv[kk][0] = a.cmap[g.at(i, j - 1)];
+          cmv[kk][1] = a.cmap[g.at(i, j)];
+        }
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < KR; ++rr) {
+      pn[rr] = po[rr] = s1a[rr] = s1b[rr] = sha[rr] = shb[rr] = 0.0;
+      const int i = x0 + tx, j = y0 + ty + 4 * rr;
+      if (FUSED && g.fluid(i, j)) {
+        const long at = g.at(i, j), ac = (long)j * g.nx + i;
+        if (a.phi_next) pn[rr] = a.phi_next[off + at];
+        if (a.phi_old) po[rr] = a.phi_old[off + at];
+        if (a.s1u) {
+          s1a[rr] = a.s1u[coff + ac];
+          s1b[rr] = a.s1v[coff + ac];
+          sha[rr] = a.shu[ac];
+          shb[rr] = a.shv[ac];
+        }
+      }
+    }
 #pragma unroll
     for (int n = 0; n < NU; ++n)
       if (tid + 256 * n < UH * UW) su[tid + 256 * n] = lu[n];
@@ -77,10 +156,74 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
   __syncthreads();
 #define SU(i, j) su[((j) - y0 + 1) * UW + ((i) - x0 + 1)]
 #define SV(i, j) sv[((j) - y0 + 1) * VW + ((i) - x0 + 1)]
+#define SP(i, j) sphi[((j) - y0 + 2) * PW + ((i) - x0 + 2)]
+  // face forcing (operator P): the control values behind the prefetched indices
+  double fu[KU], fv[KV];
+#pragma unroll
+  for (int kk = 0; kk < KU; ++kk)
+    fu[kk] = 0.5 * ((cmu[kk][0] >= 0 ? f[cmu[kk][0]] : 0.0) + (cmu[kk][1] >= 0 ? f[cmu[kk][1]] : 0.0));
+#pragma unroll
+  for (int kk = 0; kk < KV; ++kk)
+    fv[kk] = 0.5 * ((cmv[kk][0] >= 0 ? f[a.nctrl + cmv[kk][0]] : 0.0) +
+                    (cmv[kk][1] >= 0 ? f[a.nctrl + cmv[kk][1]] : 0.0));
+  double acc[NB], dmax = 0.0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+  if (FUSED) {
+    const double dt = a.dt, inv_h = 1.0 / g.h;
+    // u^n on the halo: active faces take the pressure gradient, the outflow face the
+    // ghost -phi, walls and the inflow keep their boundary values (held by u*)
+    for (int k = tid; k < UH * UW; k += 256) {
+      const int i = x0 - 1 + k % UW, j = y0 - 1 + k / UW;
+      if (i < 0 || i > g.nx || j < 0 || j >= g.ny) continue;
+      const bool w = g.fluid(i - 1, j), e = g.fluid(i, j);
+      if (w && e)
+        su[k] = su[k] - dt * (SP(i, j) - SP(i - 1, j)) * inv_h;
+      else if (w && i == g.nx)
+        su[k] = su[k] + 2.0 * dt * SP(i - 1, j) * inv_h;
+    }
+    for (int k = tid; k < VH * VW; k += 256) {
+      const int i = x0 - 1 + k % VW, j = y0 - 1 + k / VW;
+      if (i < 0 || i >= g.nx || j < 0 || j > g.ny) continue;
+      if (g.fluid(i, j - 1) && g.fluid(i, j)) sv[k] = sv[k] - dt * (SP(i, j) - SP(i, j - 1)) * inv_h;
+    }
+    __syncthreads();
+    // the previous step's cost sample, divergence and this step's warm start on the tile cells
+    // (thread layout and operand order of k_project_cost)
+    const double done = a.stats ? a.stats[(long)mem * STATS_STRIDE + ST_STEPS] - 1.0 : 1.0;
+    const int order = done < 0.5 ? 0 : done < 1.5 ? 1 : 2;
+#pragma unroll
+    for (int rr = 0; rr < TH / 4; ++rr) {
+      const int r = ty + 4 * rr;
+      const int i = x0 + tx, j = y0 + r;
+      if (!g.fluid(i, j)) continue;
+      const long at = g.at(i, j);
+      const double pc = SP(i, j);
+      const double uw = SU(i, j), ue = SU(i + 1, j), vsv = SV(i, j), vn = SV(i, j + 1);
+      if (a.phi_next) {
+        const double p1 = pn[rr];
+        double wn = order == 0 ? pc : 2.0 * pc - p1;
+        if (a.phi_old) {
+          if (order == 2) wn = 3.0 * (pc - p1) + po[rr];
+          a.phi_old[off + at] = p1;
+        }
+        a.phi_next[off + at] = wn;
+      }
+      const double div = fabs((ue - uw + vn - vsv) * inv_h);
+      dmax = (div > dmax || div != div) ? div : dmax;
+      if (a.s1u) {
+        const long ac = (long)j * g.nx + i;  // dense cell index
+        const double du = 0.5 * (uw + ue) - sha[rr];
+        const double dv = 0.5 * (vsv + vn) - shb[rr];
+        a.s1u[coff + ac] = s1a[rr] + du;
+        a.s1v[coff + ac] = s1b[rr] + dv;
+        acc[rr >> 1] += du * du + dv * dv;  // row ty + 4 rr lies in cost block rr / 2
+      }
+    }
+  }
 
   const TT h = (TT)g.h, inv4h = (TT)(0.25 / g.h), inv_h2 = (TT)(1.0 / (g.h * g.h)), nu = (TT)a.nu;
   const double dt = a.dt;
-  const bool cold = a.cold_flag != nullptr && *a.cold_flag != 0;
 
   // u faces i in [x0, x0+TW], j in [y0, y0+TH): the face i = x0+TW is the east
   // face of the tile, computed here for the divergence and owned by the next tile.
@@ -104,13 +247,8 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
                        ((uc + uN) * (vNW + vNE) - (uS + uc) * (vSW + vSE)) * inv4h;
         const TT T = -adv + nu * (uE + uW + uN + uS - (TT)4 * uc) * inv_h2;
         const long at = g.at(i, j);
-        const TT Tp = cold ? T : tup[at];
-        double F = 0.0;
-        if (f) {
-          const int cw = a.cmap[g.at(i - 1, j)], ce = a.cmap[g.at(i, j)];
-          F = 0.5 * ((cw >= 0 ? f[cw] : 0.0) + (ce >= 0 ? f[ce] : 0.0));
-        }
-        us = uo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + F);
+        const TT Tp = cold ? T : tpu[kk];
+        us = uo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + fu[kk]);
         if (owned) {
           a.us[off + at] = us;
           a.tu[off + at] = T;
@@ -145,13 +283,8 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
                        ((vc + vN) * (vc + vN) - (vS + vc) * (vS + vc)) * inv4h;
         const TT T = -adv + nu * (vE + vW + vN + vS - (TT)4 * vc) * inv_h2;
         const long at = g.at(i, j);
-        const TT Tp = cold ? T : tvp[at];
-        double F = 0.0;
-        if (f) {
-          const int cs = a.cmap[g.at(i, j - 1)], cn = a.cmap[g.at(i, j)];
-          F = 0.5 * ((cs >= 0 ? f[a.nctrl + cs] : 0.0) + (cn >= 0 ? f[a.nctrl + cn] : 0.0));
-        }
-        vs = vo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + F);
+        const TT Tp = cold ? T : tpv[kk];
+        vs = vo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + fv[kk]);
         if (owned) {
           a.vs[off + at] = vs;
           a.tv[off + at] = T;
@@ -177,8 +310,31 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
       a.b[off + g.at(i, j)] = bb;
     }
   }
+  if (FUSED) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = wave_sum(acc[b]);
+    dmax = wave_max(dmax);
+    if (tx == 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) red_s[b][ty] = acc[b];
+      red_m[ty] = dmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      if (a.s2part)
+        for (int b = 0; b < NB; ++b) {
+          if (y0 + COST_TH * b >= g.ny) break;
+          const double s = ((red_s[b][0] + red_s[b][1]) + red_s[b][2]) + red_s[b][3];
+          a.s2part[(long)mem * a.cost_ntiles + a.cost_tiling.index(x0, y0 + COST_TH * b)] += s;
+        }
+      double m = red_m[0];
+      for (int k = 1; k < 4; ++k) m = (red_m[k] > m || red_m[k] != red_m[k]) ? red_m[k] : m;
+      atomicMax((unsigned long long*)&a.divmax[mem], dbits(m));
+    }
+  }
 #undef SU
 #undef SV
+#undef SP
 }
 
 // ---------------------------------------------------------------------------- projection + cost
@@ -367,6 +523,8 @@ __global__ __launch_bounds__(256) void k_init_members(InitArgs<TT> a) {
     a.v[off + k] = a.bv[k];
     a.us[off + k] = a.bu[k];
     a.vs[off + k] = a.bv[k];
+    a.us2[off + k] = a.bu[k];  // both u* buffers carry the boundary values of u
+    a.vs2[off + k] = a.bv[k];
     a.tu[off + k] = (TT)a.btu[k];
     a.tv[off + k] = (TT)a.btv[k];
     a.phi[off + k] = a.bphi[k];
@@ -443,20 +601,28 @@ void launch_stream_copy(const void* src, void* dst, long n16, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------- launchers
-template <typename TT, int TH>
+template <typename TT, int TH, bool FUSED>
 static void launch_predictor_(const Multi<PredArgs<TT>>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL((k_predictor<TT, true, TH>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_predictor<TT, true, TH, FUSED>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_predictor<TT, false, TH>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_predictor<TT, false, TH, FUSED>), dim3(m.total()), dim3(256), 0, s, m);
 }
-// every segment of one launch shares the tile height (the host groups segments by it)
+// every segment of one launch shares the tile height and the fused flag (the host groups by them)
 template <typename TT>
 void launch_predictor(const Multi<PredArgs<TT>>& m, hipStream_t s) {
-  if (m.seg[0].trows == 8)
-    launch_predictor_<TT, 8>(m, s);
-  else
-    launch_predictor_<TT, 16>(m, s);
+  const bool r8 = m.seg[0].trows == 8;
+  if (m.seg[0].fused) {
+    if (r8)
+      launch_predictor_<TT, 8, true>(m, s);
+    else
+      launch_predictor_<TT, 16, true>(m, s);
+  } else {
+    if (r8)
+      launch_predictor_<TT, 8, false>(m, s);
+    else
+      launch_predictor_<TT, 16, false>(m, s);
+  }
 }
 template void launch_predictor<double>(const Multi<PredArgs<double>>&, hipStream_t);
 
