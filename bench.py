@@ -47,13 +47,12 @@ BYTES_PER_CELL = {
 
 # HBM bytes per launch from the two calibrated rocprofv3 counter passes (FETCH_SIZE x 2.000,
 # WRITE_SIZE x 1.000 against the library's streaming copy), h=1/128, 65 members, mixed precision,
-# for the kernel sources and tile choices recorded in profiles/k_project_cost_h128_65members_mixed.md.
+# for the kernel sources and tile choices recorded in profiles/k_predictor_fused_h128_65members_mixed.md.
 # Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
-    ("pre", "mixed"): None,
-    ("post", "mixed"): None,
-    ("predictor", "mixed"): None,
-    ("project", "mixed"): 606.3e6,
+    ("predictor", "mixed"): 915.2e6,
+    ("pre", "mixed"): 151.4e6,
+    ("post", "mixed"): 146.9e6,
     ("resid", "mixed"): None,
 }
 
