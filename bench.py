@@ -90,6 +90,11 @@ def roofline(st, prec, ncells, members, copy_gbs=None):
     }
     if prec == "mixed":  # the refinement residual is formed by the finest pre kernel; one more closes the step
         per_step["resid"] = st["resid_us"]
+    per_kernel = {}
+    for k in per_step:
+        us = {"predictor": st["predictor_us"], "pre": st["pre_us"], "post": st["post_us"], "resid": st["resid_us"]}[k]
+        if us > 0 and (k, prec) in BYTES_PER_CELL:
+            per_kernel[k] = round(BYTES_PER_CELL[(k, prec)] * ncells * members / (us * 1e-6) / 1e9, 1)
     name = max(per_step, key=per_step.get)
     avg_us = {"predictor": st["predictor_us"], "project": st["project_us"], "pre": st["pre_us"],
               "post": st["post_us"], "resid": st["resid_us"]}[name]
@@ -104,7 +109,89 @@ def roofline(st, prec, ncells, members, copy_gbs=None):
         "frac_of_measured_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
         "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2),
         "per_step_us": {k: round(v, 1) for k, v in per_step.items()},
+        "per_kernel_algorithmic_GBs": per_kernel,
     }
+
+
+# bytes per cell-step of the whole step (ideal fusion): the fused predictor, one refinement pass
+# (finest pre and post 25 + 25 B, the coarser tiled levels ~22 B per cell of their level, 1/4 + 1/16
+# + ... of the fine cells) per pass, and the finest pre kernel of the convergence-check pass (25 B)
+def step_bytes(prec, cycles):
+    if prec == "mixed":
+        return 150.4 + cycles * (50.0 + 22.0 / 3.0) + 25.0
+    return 150.4 + cycles * (52.0 + 44.0 / 3.0)
+
+
+def step_roofline(value, prec, cycles, copy_gbs):
+    b = step_bytes(prec, cycles)
+    at_peak = PEAK_HBM_GBS * 1e9 / b
+    return {"bytes_per_cell_step": round(b, 1), "cell_steps_per_s_at_peak": round(at_peak, 1),
+            "frac": round(value / at_peak, 4),
+            "frac_of_measured_copy": round(value / (copy_gbs * 1e9 / b), 4) if copy_gbs else None}
+
+
+def uneven_batch(torch, E, inputs, scale):
+    """Three ensembles of different grids, Reynolds numbers, sizes and horizons in one batch (FP64).
+
+    h = 1/64, 1/128, 1/256 with 32, 64, 128 members (+ centre), Re 4000, 7500, 12000 and horizons
+    5k, 10k, 20k steps x `scale`, each from a short spin-up of its own. Reported: cell-steps/s of
+    the merged batch and of the same three ensembles run one after the other.
+    """
+    spec = [(64, 4000.0, 32, 5000), (128, 7500.0, 64, 10000), (256, 12000.0, 128, 20000)]
+    jobs, work = [], 0
+    for n, Re, N, hz in spec:
+        p = E.Problem(inv_h=n, Re=Re, precision=E.FP64)
+        u0, v0 = inputs.initial_field(n, amp=1e-3)
+        state = E.state_init(p, u0, v0)
+        E.spinup(p, state, 100)
+        rows = np.vstack([np.zeros(E.control_dim(p)), inputs.grf_perturbations(N, n, ELL, SIGMA)])
+        H = max(1, int(round(hz * scale)))
+        jobs.append((p, state, torch.tensor(rows, device="cuda"), H))
+        work += E.cell_count(p) * (N + 1) * H
+    E.forward_batch([(p, s_, c, 20) for (p, s_, c, _) in jobs])  # tune every shape, warm the graphs
+    torch.cuda.synchronize()
+    t = time.time()
+    out = E.forward_batch(jobs)
+    torch.cuda.synchronize()
+    tb = time.time() - t
+    t = time.time()
+    for (p, s_, c, H) in jobs:
+        E.forward(p, s_, c, H, stats=False)
+    torch.cuda.synchronize()
+    ts = time.time() - t
+    return {"ensembles": [{"inv_h": n, "Re": Re, "members": N + 1, "horizon": j[3], "mean_vcycles":
+                           round(o[1]["mean_cycles"], 3)} for (n, Re, N, _), j, o in zip(spec, jobs, out)],
+            "cell_steps": work, "batched_cell_steps_per_s": round(work / tb, 1),
+            "sequential_cell_steps_per_s": round(work / ts, 1), "speedup": round(ts / tb, 3),
+            "all_J_finite": bool(all(np.all(np.isfinite(o[0].cpu().numpy())) for o in out))}
+
+
+def gram_sweep(torch, E):
+    """Anomaly reduction (Gram X X^T on the matrix cores, Cholesky, X^T c) timed on the device.
+
+    TFLOP/s counts the Gram's 2 N^2 m flops against the whole reduction's time (a lower bound for
+    the Gram kernel), against the dense MFMA peak of the precision: FP32 157.3, FP64 78.6 TFLOP/s.
+    """
+    out = []
+    rng = torch.Generator(device="cuda").manual_seed(5)
+    for N, m in ((64, 65536), (256, 65536), (256, 262144)):
+        ctrl = torch.randn((N + 1, m), dtype=torch.float64, device="cuda", generator=rng)
+        J = torch.randn(N + 1, dtype=torch.float64, device="cuda", generator=rng)
+        for prec, name, peak in ((E.MIXED, "fp32_mfma", 157.3), (E.FP64, "fp64_mfma", 78.6)):
+            gws = E._bytes_tensor(E.gradient_bytes(N, m, prec))
+            g = torch.empty(m, dtype=torch.float64, device="cuda")
+            E.gradient(ctrl, J, prec, ws=gws, g=g)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                E.gradient(ctrl, J, prec, ws=gws, g=g)
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3 / 5
+            tf = 2.0 * N * N * m / sec / 1e12
+            out.append({"N": N, "m": m, "precision": name, "us": round(sec * 1e6, 1), "gram_TFLOPs": round(tf, 2),
+                        "frac_of_peak": round(tf / peak, 4)})
+    return out
 
 
 def serving(torch, E, inputs, nreq, horizon_scale, seed=2605238125):
@@ -209,10 +296,10 @@ def cpu_baseline(state_host, rows, steps, procs):
 
     base = ns.State(u, v, tu, tv)
     t = time.time()
-    OE.forward(op, base, rows, steps, processes=procs)
+    Jo = OE.forward(op, base, rows, steps, processes=procs)
     dt = time.time() - t
     ncells = op.grid().ncells
-    return ncells * steps * rows.shape[0] / dt, dt
+    return ncells * steps * rows.shape[0] / dt, dt, Jo
 
 
 def main():
@@ -230,6 +317,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true", help="launch every step eagerly (profiler counter passes)")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-horizon-scale", type=float, default=0.05)
+    ap.add_argument("--uneven-scale", type=float, default=0.02, help="horizon scale of the uneven batch (0: skip)")
+    ap.add_argument("--no-gram", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the ensemble members of one MI355X "
@@ -316,7 +405,7 @@ def main():
         rate_64 = ncells * nrows * hb / t64
         rate_1 = ncells * len(sub) * hb / t1
         jm, j64 = Jm.cpu().numpy(), J64.cpu().numpy()
-        extra = {
+        extra.update({
             "baselines_horizon": hb,
             "mixed_batched_cell_steps_per_s": round(rate_m, 1),
             "fp64_batched_cell_steps_per_s": round(rate_64, 1),
@@ -326,8 +415,16 @@ def main():
             "J_rel_err_mixed_vs_fp64_max": float(np.max(np.abs(jm - j64) / np.abs(j64))),
             "fp64_mean_vcycles_per_step": round(st64["mean_cycles"], 3),
             "fp64_roofline": roofline(st64, "fp64", ncells, nrows, copy_gbs),
-        }
+            "fp64_step_roofline": step_roofline(rate_64, "fp64", st64["mean_cycles"], copy_gbs),
+        })
         log("baselines", extra)
+
+    if args.uneven_scale > 0:
+        extra["uneven_batch_fp64"] = uneven_batch(torch, E, inputs, args.uneven_scale)
+        log("uneven batch", extra["uneven_batch_fp64"])
+    if not args.no_gram:
+        extra["anomaly_reduction"] = gram_sweep(torch, E)
+        log("anomaly reduction", extra["anomaly_reduction"])
 
     serve = None
     if not args.no_serve:
@@ -339,11 +436,26 @@ def main():
         u, v, tu, tv, _ = E.state_read(E.Problem(inv_h=INV_H, Re=RE), state)
         procs = min(16, os.cpu_count() or 1)
         rows = ctrl.cpu().numpy()
-        rate, secs = cpu_baseline((u, v, tu, tv), rows, args.cpu_steps, procs)
+        rate, secs, Jo = cpu_baseline((u, v, tu, tv), rows, args.cpu_steps, procs)
         cpu = {"value": round(rate, 1), "unit": "cell-steps/s", "cores": procs, "kind": "oracle",
                "sample": f"all {nrows} members x {args.cpu_steps} steps of the same h=1/128 workload "
                          f"from the same base state ({secs:.1f}s wall, one process per member)"}
         log("cpu baseline", cpu)
+        # the same sample on the GPU against the oracle: J (relative) and the gradient (cosine, relative norm)
+        from oracle import envar as OE
+
+        go = OE.gradient(rows, Jo)
+        check = {"sample": f"{nrows} members x {args.cpu_steps} steps"}
+        for prec, name in ((E.FP64, "fp64"), (E.MIXED, "mixed")):
+            pp = E.Problem(inv_h=INV_H, Re=RE, precision=prec)
+            Jg, _, _ = E.forward(pp, state, ctrl, args.cpu_steps)
+            gg = E.gradient(ctrl, Jg, prec).cpu().numpy()
+            jg = Jg.cpu().numpy()
+            check[name] = {"J_rel_err_max": float(np.max(np.abs(jg - Jo) / np.abs(Jo))),
+                           "g_cosine": float(gg @ go / (np.linalg.norm(gg) * np.linalg.norm(go))),
+                           "g_rel_err": float(np.linalg.norm(gg - go) / np.linalg.norm(go))}
+        extra["oracle_check"] = check
+        log("oracle check", check)
 
     out = {
         "metric": "ensemble cell-steps/s, batched FP32 vs plain FP64 at J err<=1e-4; p50/p99 solve latency",
@@ -371,6 +483,7 @@ def main():
         "max_div": st["max_div"],
         "J_finite": bool(np.all(np.isfinite(J_mixed_long))),
         "roofline": roofline(st, "mixed", ncells, nrows, copy_gbs),
+        "step_roofline": step_roofline(value, "mixed", st["mean_cycles"], copy_gbs),
         "measured_copy_GBs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "serving": serve,

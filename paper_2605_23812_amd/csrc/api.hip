@@ -1414,7 +1414,7 @@ int envar_forward(const envar_problem* p, const void* state_dev, const double* c
 // ---------------------------------------------------------------------------- gradient
 namespace envar {
 struct GradLayout {
-  size_t X, Xt, dJ, rhs, partial, G, c, info, total;
+  size_t X, Xt, dJ, rhs, partial, tmp, G, c, info, total;
   int nsplit, dim;
   long kchunk;
 };
@@ -1443,6 +1443,7 @@ static GradLayout grad_layout(int n, long m, int precision) {
   L.dJ = take((size_t)n * 8);
   L.rhs = take((size_t)L.dim * 8);
   L.partial = take((size_t)L.nsplit * L.dim * L.dim * 8);
+  L.tmp = take((size_t)gram_reduce_groups(L.nsplit) * L.dim * L.dim * 8);
   L.G = take((size_t)L.dim * L.dim * 8);
   L.c = take((size_t)L.dim * 8);
   L.info = take(256);
@@ -1468,14 +1469,14 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   launch_anomaly<TX>(ctrl, J, n, m, X, dJ, s);
   if (n <= m) {
     launch_gram<TX>(X, n, m, m, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
-    launch_gram_reduce(at<double>(ws, L.partial), n, L.nsplit, G, s);
+    launch_gram_reduce(at<double>(ws, L.partial), n, L.nsplit, at<double>(ws, L.tmp), G, s);
     launch_chol_solve(G, dJ, n, at<double>(ws, L.c), at<double>(ws, L.info), s);
     launch_gemv_t<TX>(X, n, m, m, at<double>(ws, L.c), g, s);
   } else {
     TX* Xt = at<TX>(ws, L.Xt);
     launch_transpose<TX>(X, n, m, Xt, s);
     launch_gram<TX>(Xt, (int)m, n, n, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
-    launch_gram_reduce(at<double>(ws, L.partial), (int)m, L.nsplit, G, s);
+    launch_gram_reduce(at<double>(ws, L.partial), (int)m, L.nsplit, at<double>(ws, L.tmp), G, s);
     double* rhs = at<double>(ws, L.rhs);
     launch_gemv_t<TX>(X, n, m, m, dJ, rhs, s);
     launch_chol_solve(G, rhs, (int)m, g, at<double>(ws, L.info), s);

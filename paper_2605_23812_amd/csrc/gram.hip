@@ -7,9 +7,9 @@
 // G is the only dense contraction of the hot path: 2 n^2 m flops over n m
 // operands, so it runs on MFMA (v_mfma_f64_16x16x4f64, or
 // v_mfma_f32_16x16x4f32 for FP32 operands) with a split over m and FP64
-// partials reduced in a fixed order. The n x n solve is an FP64 Cholesky
-// in one workgroup; the projection g = X^T c is a bandwidth-bound GEMV with
-// FP64 accumulation.
+// partials reduced in a fixed order (two levels). The n x n solve is an FP64
+// Cholesky in one workgroup (in LDS up to n = 128); the projection g = X^T c is
+// a bandwidth-bound GEMV with FP64 accumulation.
 #include "common.h"
 #include "kernels.h"
 
@@ -53,6 +53,7 @@ struct MfmaAcc<float> {
 };
 
 constexpr int GRAM_KC = 32;
+constexpr int GRAM_REDUCE_GROUP = 32;  // splits summed per group in the first reduction level
 
 template <typename TX>
 __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, long m, long ldx,
@@ -101,6 +102,18 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
   }
 }
 
+// Fixed-order reduction of the split-K partials in two levels: groups of
+// consecutive splits summed in order, then the group sums in order.
+__global__ void k_gram_reduce_groups(const double* partial, long nn, int nsplit, int rg, double* tmp) {
+  const int grp = blockIdx.y;
+  const int p0 = grp * rg, p1 = min(nsplit, p0 + rg);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) s += partial[(long)p * nn + e];
+    tmp[(long)grp * nn + e] = s;
+  }
+}
+
 __global__ void k_gram_reduce(const double* partial, int n, int nsplit, double* G) {
   const long nn = (long)n * n;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
@@ -111,66 +124,103 @@ __global__ void k_gram_reduce(const double* partial, int n, int nsplit, double* 
 }
 
 // ---------------------------------------------------------------------------- FP64 Cholesky solve
-// Solves (G + ridge I) x = rhs in place (G lower triangle overwritten by L),
-// ridge = 1e-12 tr(G) / n; right-looking, one workgroup, fixed order.
-__global__ __launch_bounds__(1024) void k_chol_solve(double* G, const double* rhs, int n, double* x, int* info) {
+// Solves (G + ridge I) x = rhs, ridge = 1e-12 tr(G) / n, in one workgroup with
+// one barrier per column. At step k every thread updates its entries of the
+// trailing block with a_ik a_jk / a_kk from the still unscaled column k, so the
+// factor is kept as A~ (column k as it stood at step k, pivot d_k = A~_kk) and
+// G = A~ D^-1 A~^T, D = diag(d). The solves run right-looking on that form:
+// A~ z = rhs, then A~^T x = D z. Threads form a 32-wide grid over the trailing
+// block; thread j owns entry j of the vectors.
+// LDS (n <= CHOL_LDS_MAX): the matrix is staged in LDS with an odd row stride
+// (column reads hit distinct banks) and only the lower triangle is updated.
+// Otherwise it is updated in place in global memory (L2 resident for the sizes
+// allowed) as a full symmetric block, so that column k is read as row k.
+constexpr int CHOL_LDS_MAX = 128;
+constexpr int CHOL_VEC_MAX = 1024;
+
+template <bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_chol_solve(double* G, const double* rhs, int n, double* x, int* info) {
+  constexpr int RS = NT / 32;
+  __shared__ double sA[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) : 1];
+  __shared__ double sv[CHOL_VEC_MAX];  // right-hand side, then z, then x
+  __shared__ double sz[CHOL_VEC_MAX];
+  __shared__ double sdi[CHOL_VEC_MAX];  // 1 / d_k
   __shared__ double ridge;
-  __shared__ double piv;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  double* const A = LDS ? sA : G;
+  const long ld = LDS ? n + 1 : n;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  if (LDS)
+    for (int i = ty; i < n; i += RS)
+      for (int j = tx; j < n; j += 32) sA[i * ld + j] = G[(long)i * n + j];
+  for (int i = tid; i < n; i += NT) sv[i] = rhs[i];
+  __syncthreads();
   if (tid == 0) {
     double tr = 0.0;
-    for (int i = 0; i < n; ++i) tr += G[(long)i * n + i];
+    for (int i = 0; i < n; ++i) tr += A[i * ld + i];
     ridge = 1e-12 * tr / (double)n;
     *info = 0;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += nt) {
-    G[(long)i * n + i] += ridge;
-    x[i] = rhs[i];
-  }
+  for (int i = tid; i < n; i += NT) A[i * ld + i] += ridge;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double d = G[(long)k * n + k];
-      if (!(d > 0.0)) *info = k + 1;
-      piv = sqrt(d > 0.0 ? d : 1e-300);
-      G[(long)k * n + k] = piv;
-    }
-    __syncthreads();
-    for (int i = k + 1 + tid; i < n; i += nt) G[(long)i * n + k] /= piv;
-    __syncthreads();
-    const long rem = n - k - 1;
-    for (long e = tid; e < rem * rem; e += nt) {
-      const int i = k + 1 + (int)(e / rem), j = k + 1 + (int)(e % rem);
-      if (j <= i) G[(long)i * n + j] -= G[(long)i * n + k] * G[(long)j * n + k];
+    const double akk = A[k * ld + k];
+    if (tid == 0 && !(akk > 0.0)) *info = k + 1;
+    const double inv = 1.0 / (akk > 0.0 ? akk : 1e-300);
+    if (LDS) {
+      for (int i = k + 1 + ty; i < n; i += RS) {
+        const double aik = A[i * ld + k] * inv;
+        for (int j = k + 1 + tx; j <= i; j += 32) A[i * ld + j] -= aik * A[j * ld + k];
+      }
+    } else {
+      for (int i = k + 1 + ty; i < n; i += RS) {
+        const double aik = A[k * ld + i] * inv;
+        for (int j = k + 1 + tx; j < n; j += 32) A[i * ld + j] -= aik * A[k * ld + j];
+      }
     }
     __syncthreads();
   }
-  // L y = rhs
+  for (int i = tid; i < n; i += NT) {
+    const double d = A[i * ld + i];
+    sdi[i] = 1.0 / (d > 0.0 ? d : 1e-300);
+  }
+  __syncthreads();
+  // A~ z = rhs (column k of A~ read as row k in the symmetric global form)
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) x[k] /= G[(long)k * n + k];
-    __syncthreads();
-    for (int i = k + 1 + tid; i < n; i += nt) x[i] -= G[(long)i * n + k] * x[k];
+    const double zk = sv[k] * sdi[k];
+    if (tid == 0) sz[k] = zk;
+    for (int i = k + 1 + tid; i < n; i += NT) sv[i] -= (LDS ? A[i * ld + k] : A[k * ld + i]) * zk;
     __syncthreads();
   }
-  // L^T x = y
+  // A~^T x = D z: x_j = z_j - sum_{k>j} A~_kj x_k / d_j, right-looking over the rows of A~
+  for (int i = tid; i < n; i += NT) sv[i] = sz[i];
+  __syncthreads();
   for (int k = n - 1; k >= 0; --k) {
-    if (tid == 0) x[k] /= G[(long)k * n + k];
-    __syncthreads();
-    for (int i = tid; i < k; i += nt) x[i] -= G[(long)k * n + i] * x[k];
+    const double xk = sv[k];
+    for (int j = tid; j < k; j += NT) sv[j] -= A[k * ld + j] * xk * sdi[j];
     __syncthreads();
   }
+  for (int i = tid; i < n; i += NT) x[i] = sv[i];
 }
 
 // ---------------------------------------------------------------------------- GEMVs
-// g[k] = sum_i X[i][k] c[i]
+// g[k] = sum_i X[i][k] c[i]: 64 columns per block, four row groups summed in order
 template <typename TX>
-__global__ void k_gemv_t(const TX* __restrict__ X, int n, long m, long ldx, const double* __restrict__ c,
-                         double* __restrict__ g) {
-  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < m; k += (long)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_gemv_t(const TX* __restrict__ X, int n, long m, long ldx,
+                                                const double* __restrict__ c, double* __restrict__ g) {
+  __shared__ double part[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (long k0 = blockIdx.x * 64L; k0 < m; k0 += (long)gridDim.x * 64L) {
+    const long k = k0 + tx;
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += (double)X[(long)i * ldx + k] * c[i];
-    g[k] = s;
+    if (k < m) {
+#pragma unroll 4
+      for (int i = ty; i < n; i += 4) s += (double)X[(long)i * ldx + k] * c[i];
+    }
+    part[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && k < m) g[k] = ((part[0][tx] + part[1][tx]) + part[2][tx]) + part[3][tx];
+    __syncthreads();
   }
 }
 
@@ -196,21 +246,31 @@ void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nspl
   hipLaunchKernelGGL(k_gram<TX>, dim3(nsplit * nbt * nbt), dim3(256), 0, s, X, n, m, ldx, partial, nsplit, kchunk,
                      nbt);
 }
-void launch_gram_reduce(const double* partial, int n, int nsplit, double* G, hipStream_t s) {
+int gram_reduce_groups(int nsplit) { return (nsplit + GRAM_REDUCE_GROUP - 1) / GRAM_REDUCE_GROUP; }
+void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, double* G, hipStream_t s) {
   const long nn = (long)n * n;
   int bx = (int)((nn + 255) / 256);
   if (bx > 1024) bx = 1024;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(bx), dim3(256), 0, s, partial, n, nsplit, G);
+  const int ng = gram_reduce_groups(nsplit);
+  hipLaunchKernelGGL(k_gram_reduce_groups, dim3(bx, ng), dim3(256), 0, s, partial, nn, nsplit, GRAM_REDUCE_GROUP,
+                     tmp);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(bx), dim3(256), 0, s, tmp, n, ng, G);
 }
 int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work);
+  if (n > CHOL_VEC_MAX) return -1;
+  if (n <= 64)
+    hipLaunchKernelGGL((k_chol_solve<true, 256>), dim3(1), dim3(256), 0, s, G, rhs, n, x, (int*)work);
+  else if (n <= CHOL_LDS_MAX)
+    hipLaunchKernelGGL((k_chol_solve<true, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work);
+  else
+    hipLaunchKernelGGL((k_chol_solve<false, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work);
   return 0;
 }
 template <typename TX>
 void launch_gemv_t(const TX* X, int n, long m, long ldx, const double* c, double* g, hipStream_t s) {
-  int bx = (int)((m + 255) / 256);
-  if (bx > 4096) bx = 4096;
-  hipLaunchKernelGGL(k_gemv_t<TX>, dim3(bx), dim3(256), 0, s, X, n, m, ldx, c, g);
+  long bx = (m + 63) / 64;
+  if (bx > 8192) bx = 8192;
+  hipLaunchKernelGGL(k_gemv_t<TX>, dim3((unsigned)bx), dim3(256), 0, s, X, n, m, ldx, c, g);
 }
 template <typename TX>
 void launch_transpose(const TX* X, int n, long m, TX* Xt, hipStream_t s) {

@@ -245,7 +245,8 @@ template <typename TX>
 void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, double* dJ, hipStream_t s);
 template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s);
-void launch_gram_reduce(const double* partial, int n, int nsplit, double* G, hipStream_t s);
+int gram_reduce_groups(int nsplit);
+void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, double* G, hipStream_t s);
 int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s);
 template <typename TX>
 void launch_gemv_t(const TX* X, int n, long m, long ldx, const double* c, double* g, hipStream_t s);
