@@ -20,10 +20,19 @@ What it computes, and where the paper defines it:
               least-squares reduction of {delta f_i, J_i} to a gradient in
               span of the perturbations (eq. gradient_EnVar, scalar-J form),
               plus the fixed-ensemble descent loop of Fig. (envar_loop).
+* ``gn``      the vector-observation EnVar step: velocity sensors on the cavity
+              lid (Sec. 4.1), fluctuation observations, Y by finite differences
+              (eq. fdapprox), the Gauss-Newton Hessian and step (eq.
+              Hessian_EnVar, eq. update_Newton) and the posterior variance
+              (eq. posterior_covariance_matrix).
 
 Pins (tests/test_oracle_*.py): Taylor-Green linear AB2 recurrence and O(h^2)
 nonlinear decay, energy conservation of the advection operator, the discrete
 Poiseuille profile, divergence after projection, projection idempotence,
-two-pass vs brute-force cost, closed-form gradients on quadratic costs, and
-central finite differences of the Navier-Stokes cost.
+two-pass vs brute-force cost, closed-form gradients on quadratic costs,
+central finite differences of the Navier-Stokes cost; for ``gn``: exact sensor
+interpolation of linear fields, zero-mean fluctuations, a Gauss-Newton step
+landing on the minimiser of an affine model (checked against an iterative
+least-squares solver and central differences), and the prior limit and
+monotonicity of the posterior variance.
 """
