@@ -166,6 +166,48 @@ def uneven_batch(torch, E, inputs, scale):
             "all_J_finite": bool(all(np.all(np.isfinite(o[0].cpu().numpy())) for o in out))}
 
 
+def gauss_newton(torch, E, pm, state, ctrl, horizon, every=10):
+    """Vector-observation EnVar at the benchmark shape: the cost of recording the lid sensors during
+    the forward (mixed, `horizon` steps, with and without), then one Gauss-Newton step and the
+    posterior variance for the series length of the full horizon (20,000 steps sampled every
+    `every`: K = 2,000 per channel), timed on the device with synthetic series of that shape."""
+    nrows, m = ctrl.shape
+    ws = E._bytes_tensor(E.workspace_bytes(pm, nrows))
+    E.forward(pm, state, ctrl, 20, ws=ws, stats=False)
+    E.forward_obs(pm, state, ctrl, 20, ws=ws, stats=False)
+    torch.cuda.synchronize()
+    t = time.time()
+    E.forward(pm, state, ctrl, horizon, ws=ws, stats=False)
+    torch.cuda.synchronize()
+    t_plain = time.time() - t
+    t = time.time()
+    E.forward_obs(pm, state, ctrl, horizon, ws=ws, stats=False)
+    torch.cuda.synchronize()
+    t_obs = time.time() - t
+    K = 20000 // every
+    g = torch.Generator(device="cuda").manual_seed(3)
+    series = 3.0 + torch.randn((nrows, E.OBS_CHANNELS, K), dtype=torch.float64, device="cuda", generator=g)
+    series[1:] = series[0] + 1e-4 * torch.randn((nrows - 1, E.OBS_CHANNELS, K), dtype=torch.float64,
+                                                device="cuda", generator=g)
+    w = torch.zeros(nrows - 1, dtype=torch.float64, device="cuda")
+    gws = E._bytes_tensor(E.lib().envar_gn_bytes(nrows - 1, K))
+    dw, H, jw = E.gn_step(series, 1e-4, w, ws=gws)
+    E.posterior_var(ctrl, 1e-4, H)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(5):
+        dw, H, jw = E.gn_step(series, 1e-4, w, ws=gws)
+    e1.record()
+    for _ in range(5):
+        E.posterior_var(ctrl, 1e-4, H)
+    e2.record()
+    torch.cuda.synchronize()
+    return {"sensor_recording_us_per_step": round((t_obs - t_plain) / horizon * 1e6, 2),
+            "forward_us_per_step": round(t_plain / horizon * 1e6, 1),
+            "gn_step_us": round(e0.elapsed_time(e1) * 1e3 / 5, 1), "posterior_variance_us": round(e1.elapsed_time(e2) * 1e3 / 5, 1),
+            "members": nrows - 1, "samples_per_channel": K, "n_obs": E.OBS_CHANNELS * K, "m": m}
+
+
 def gram_sweep(torch, E):
     """Anomaly reduction (Gram X X^T on the matrix cores, Cholesky, X^T c) timed on the device.
 
@@ -425,6 +467,8 @@ def main():
     if not args.no_gram:
         extra["anomaly_reduction"] = gram_sweep(torch, E)
         log("anomaly reduction", extra["anomaly_reduction"])
+        extra["gauss_newton"] = gauss_newton(torch, E, pm, state, ctrl, args.baseline_horizon)
+        log("gauss newton", extra["gauss_newton"])
 
     serve = None
     if not args.no_serve:

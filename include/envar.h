@@ -210,6 +210,50 @@ size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
 int envar_gradient(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
                    int32_t precision, void* ws_dev, size_t ws_bytes, double* g_dev, void* stream);
 
+/* ---- Vector-observation EnVar (Sec. 3.3.1, with the observation of Sec. 4.1) ----
+ * The observation H q(f) is the velocity fluctuation u' = u - u_bar at four sensors on
+ * the cavity lid, x = x_cav + 1/5, 2/5, 3/5, 4/5, y = 0 (the paper places its cavity at
+ * x = 0), both components, sampled at the end of steps every, 2 every, ...: eight
+ * channels (channel c = 2 s + component of sensor s), each component interpolated
+ * bilinearly from its own MAC positions; u_bar is the time mean of the member's own
+ * samples; R = I and y = 0. */
+
+/* Forward ensemble as envar_forward, also recording the sensor series into obs_dev
+ * [n_rows][8][horizon / every] (FP64, device, caller-owned; samples of the projected
+ * velocity, before the fluctuation is formed). Requires the cavity geometry. Errors:
+ * EINVAL (bad sizes, every outside [1, horizon], channel geometry), ENOMEM, EDIVERGED. */
+int envar_forward_obs(const envar_problem* p, const void* state_dev, const double* controls_dev,
+                      int32_t n_rows, int64_t m, int32_t horizon, int32_t every, void* ws_dev,
+                      size_t ws_bytes, double* J_dev, double* obs_dev, envar_stats* stats, void* stream);
+
+/* Workspace bytes of envar_gn_step for n members and K samples per channel (0 = invalid). */
+size_t envar_gn_bytes(int32_t n, int64_t K);
+
+/* Gauss-Newton step in ensemble space (eq. gradient_EnVar, eq. Hessian_EnVar,
+ * eq. update_Newton) from the series of envar_forward_obs: series_dev [n+1][8][K]
+ * (row 0 the centre f^(e) + E w, row i the member f^(e) + E w + eps E_i). With d_i the
+ * fluctuations of row i: Y_i = (d_i - d_0) / eps, H_GN = Y^T Y + (n - 1) I (Gram on the
+ * FP64 matrix cores), dJ/dw = Y^T d_0 + (n - 1) w (w_dev [n], the current weights),
+ * dw_dev [n] <- -H_GN^-1 dJ/dw (FP64 Cholesky), hgn_dev [n][n] <- H_GN (input of
+ * envar_posterior_var), jw_dev [2] <- (1/2 |d_0|^2, 1/2 (n - 1) |w|^2), the two terms of
+ * J(w) in eq. (J_w). All pointers device. Errors: EINVAL (n < 1, n > 1024, K < 1,
+ * eps <= 0), ENOMEM. */
+int envar_gn_step(const double* series_dev, int32_t n, int64_t K, double eps, const double* w_dev,
+                  void* ws_dev, size_t ws_bytes, double* dw_dev, double* hgn_dev, double* jw_dev,
+                  void* stream);
+
+/* Workspace bytes of envar_posterior_var (0 = invalid). */
+size_t envar_posterior_bytes(int32_t n);
+
+/* Diagonal of the posterior covariance B_post = E H_GN^-1 E^T (eq.
+ * posterior_covariance_matrix) with E_i = (f_i - f_0) / eps from controls_dev [n+1][m]
+ * and H_GN from envar_gn_step: var_dev [m] (device). H_GN is inverted in one workgroup
+ * by Gauss-Jordan sweeps (n <= 128). Errors: EINVAL (n < 1, n > 128, m < 1, eps <= 0),
+ * ENOMEM. */
+int envar_posterior_var(const double* controls_dev, int32_t n, int64_t m, double eps,
+                        const double* hgn_dev, void* ws_dev, size_t ws_bytes, double* var_dev,
+                        void* stream);
+
 /* Line search and iteration parameters of envar_iterate (Armijo, eq. update_BFGS). */
 typedef struct {
   int32_t iters;          /* descent iterations */

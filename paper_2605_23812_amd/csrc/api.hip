@@ -72,7 +72,41 @@ struct Plan {
   // state layout
   size_t s_meta, s_u, s_v, s_tu, s_tv, s_phi, s_shu, s_shv, s_cmap, s_ainv, s_aidx, s_total;
   size_t s_code[MAX_LEVELS];  // per-level Poisson diagonal codes (levels 0..nlev_grid)
+  // velocity sensors on the cavity lid (vector observation): bilinear stencils per channel
+  bool obs_ok = false;
+  int obs_fi[OBS_CHANNELS][4], obs_fj[OBS_CHANNELS][4];
+  double obs_tx[OBS_CHANNELS], obs_ty[OBS_CHANNELS];
 };
+
+// The four sensors x = x_cav + 1/5 .. 4/5 on the cavity lid y = 0 (Sec. 4.1). Each
+// component is interpolated bilinearly from its own MAC positions: u faces at
+// (i h, y0 + (j + 1/2) h), v faces at ((i + 1/2) h, y0 + j h). Every stencil face must
+// be an active face (it is for the cavity geometry).
+static void make_sensors(Plan& P) {
+  const Geo& g = P.lev[0];
+  P.obs_ok = P.p.geometry == ENVAR_CAVITY;
+  if (!P.obs_ok) return;
+  const double h = g.h, y0 = -1.0;
+  for (int s = 0; s < 4; ++s) {
+    const double xs = P.p.x_cav + (s + 1) / 5.0, ys = 0.0;
+    for (int comp = 0; comp < 2; ++comp) {
+      const int c = 2 * s + comp;
+      const double ox = comp == 0 ? 0.0 : 0.5 * h, oy = comp == 0 ? y0 + 0.5 * h : y0;
+      const double fx = (xs - ox) / h, fy = (ys - oy) / h;
+      const int i = (int)std::floor(fx), j = (int)std::floor(fy);
+      P.obs_tx[c] = fx - i;
+      P.obs_ty[c] = fy - j;
+      const int di[4] = {0, 1, 0, 1}, dj[4] = {0, 0, 1, 1};
+      for (int q = 0; q < 4; ++q) {
+        const int fi = i + di[q], fj = j + dj[q];
+        P.obs_fi[c][q] = fi;
+        P.obs_fj[c][q] = fj;
+        const bool active = comp == 0 ? (g.fluid(fi - 1, fj) && g.fluid(fi, fj)) : (g.fluid(fi, fj - 1) && g.fluid(fi, fj));
+        if (!active) P.obs_ok = false;
+      }
+    }
+  }
+}
 
 static Geo make_geo(int n, int geometry, double x_cav) {
   Geo g;
@@ -163,6 +197,7 @@ static int make_plan(const envar_problem* pin, Plan& P) {
       if (in) P.ctrl_cells.push_back(j * g.nx + i);
     }
   P.m = 2 * (long)P.ctrl_cells.size();
+  make_sensors(P);
   // coarsest level
   Geo gc = P.lev[nl];
   for (int l = 1; l < P.ncoarse; ++l) gc = gc.coarser();
@@ -357,6 +392,9 @@ struct Job {
   int step = 0;            // steps launched so far
   bool cold_first = true;  // the state's cold-start flag applies to step 0
   int last_cur = 0;        // pressure buffer of the last solved step
+  // sensor series of the vector observation: obs[nmem][OBS_CHANNELS][obs_K], a sample every obs_every steps
+  double* obs = nullptr;
+  int obs_K = 0, obs_every = 1;
   // tile heights (8 | 16) of the predictor, the projection and each tiled multigrid level
   int rows_pred = 8, rows_proj = 8;
   int rows_mg[MAX_LEVELS] = {16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16};
@@ -688,6 +726,32 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer
         [&](const Multi<PredArgs<double>>& m) { launch_predictor<double>(m, st); });
   if (tm) tm->mark(TM_PRED, 1, st);
   batch_pressure<TT>(J, st, cap, tm);
+  {
+    auto m = seg_begin<SensorArgs>();
+    for (Job* j : J) {
+      if (!j->obs) continue;
+      const Plan& P = j->P;
+      const int par = j->step & 1;
+      SensorArgs a{};
+      a.g = P.lev[0];
+      a.nmem = j->nmem;
+      a.plane = P.lev[0].plane();
+      a.dt = P.dt;
+      a.us = j->ustar(par);
+      a.vs = j->vstar(par);
+      a.phi = j->phi(par);
+      a.stats = j->w_<double>(j->w.stats);
+      a.obs = j->obs;
+      a.K = j->obs_K;
+      a.every = j->obs_every;
+      std::memcpy(a.fi, P.obs_fi, sizeof a.fi);
+      std::memcpy(a.fj, P.obs_fj, sizeof a.fj);
+      std::memcpy(a.tx, P.obs_tx, sizeof a.tx);
+      std::memcpy(a.ty, P.obs_ty, sizeof a.ty);
+      seg_add(m, a, (j->nmem * OBS_CHANNELS + 63) / 64);
+    }
+    if (m.nseg) launch_sensors(m, st);
+  }
   {
     auto m = seg_begin<BookArgs>();
     for (Job* j : J) {
@@ -1318,10 +1382,15 @@ static int make_job(const Plan& P, const void* state_dev, const double* controls
 
 static int forward_impl(const Plan& P, const void* state_dev, const double* controls_dev, int n_rows, int horizon,
                         void* ws_dev, size_t ws_bytes, double* J_dev, double* fields_dev, envar_stats* stats,
-                        hipStream_t s, bool spinup_store) {
+                        hipStream_t s, bool spinup_store, double* obs_dev = nullptr, int obs_every = 1) {
   std::vector<Job> jobs(1);
   int rc = make_job(P, state_dev, controls_dev, n_rows, horizon, ws_dev, ws_bytes, jobs[0]);
   if (rc) return rc;
+  if (obs_dev) {
+    jobs[0].obs = obs_dev;
+    jobs[0].obs_every = obs_every;
+    jobs[0].obs_K = horizon / obs_every;
+  }
   std::vector<JobOut> outs(1);
   outs[0].J = J_dev;
   outs[0].fields = fields_dev;
@@ -1407,6 +1476,22 @@ int envar_forward(const envar_problem* p, const void* state_dev, const double* c
   if (horizon < 1) return fail(ENVAR_EINVAL, "horizon must be >= 1");
   return forward_impl(P, state_dev, controls_dev, n_rows, horizon, ws_dev, ws_bytes, J_dev, fields_dev, stats,
                       (hipStream_t)stream, false);
+}
+
+int envar_forward_obs(const envar_problem* p, const void* state_dev, const double* controls_dev, int32_t n_rows,
+                      int64_t m, int32_t horizon, int32_t every, void* ws_dev, size_t ws_bytes, double* J_dev,
+                      double* obs_dev, envar_stats* stats, void* stream) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!state_dev || !ws_dev || !J_dev || !controls_dev || !obs_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  if (n_rows < 1) return fail(ENVAR_EINVAL, "n_rows must be >= 1");
+  if (m != P.m) return fail(ENVAR_EINVAL, "m = %lld but the control region has m = %ld", (long long)m, P.m);
+  if (horizon < 1) return fail(ENVAR_EINVAL, "horizon must be >= 1");
+  if (every < 1 || horizon / every < 1) return fail(ENVAR_EINVAL, "every must be in [1, horizon]");
+  if (!P.obs_ok) return fail(ENVAR_EINVAL, "the lid sensors need the cavity geometry");
+  return forward_impl(P, state_dev, controls_dev, n_rows, horizon, ws_dev, ws_bytes, J_dev, nullptr, stats,
+                      (hipStream_t)stream, false, obs_dev, every);
 }
 
 }  // extern "C"
@@ -1498,6 +1583,99 @@ extern "C" int envar_gradient(const double* controls_dev, const double* J_dev, i
   if (precision == ENVAR_MIXED)
     return gradient_impl<float>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
   return gradient_impl<double>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------- vector-observation EnVar step
+namespace envar {
+struct GNLayout {
+  size_t D, Y, partial, tmp, G, grad, neg, Hc, info, total;
+  int nsplit;
+  long kchunk;
+};
+
+static GNLayout gn_layout(int n, long n_obs) {
+  GNLayout L{};
+  const int nbt = (n + 63) / 64;
+  long want = std::max(1L, 512L / (nbt * nbt));
+  long chunk = (n_obs + want - 1) / want;
+  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
+  L.kchunk = chunk;
+  L.nsplit = (int)((n_obs + chunk - 1) / chunk);
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t a = o;
+    o = align256(o + b);
+    return a;
+  };
+  L.D = take((size_t)(n + 1) * n_obs * 8);
+  L.Y = take((size_t)n * n_obs * 8);
+  L.partial = take((size_t)L.nsplit * n * n * 8);
+  L.tmp = take((size_t)gram_reduce_groups(L.nsplit) * n * n * 8);
+  L.G = take((size_t)n * n * 8);
+  L.grad = take((size_t)n * 8);
+  L.neg = take((size_t)n * 8);
+  L.Hc = take((size_t)n * n * 8);
+  L.info = take(256);
+  L.total = o;
+  return L;
+}
+}  // namespace envar
+
+extern "C" size_t envar_gn_bytes(int32_t n, int64_t K) {
+  if (n < 1 || K < 1) return 0;
+  return gn_layout(n, (long)K * OBS_CHANNELS).total;
+}
+
+extern "C" int envar_gn_step(const double* series_dev, int32_t n, int64_t K, double eps, const double* w_dev,
+                             void* ws_dev, size_t ws_bytes, double* dw_dev, double* hgn_dev, double* jw_dev,
+                             void* stream) {
+  if (n < 1 || K < 1) return fail(ENVAR_EINVAL, "n and K must be >= 1");
+  if (n > 1024) return fail(ENVAR_EINVAL, "n = %d exceeds 1024", n);
+  if (!(eps > 0.0)) return fail(ENVAR_EINVAL, "eps must be positive");
+  if (!series_dev || !w_dev || !ws_dev || !dw_dev || !hgn_dev || !jw_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  const long n_obs = (long)K * OBS_CHANNELS;
+  const GNLayout L = gn_layout(n, n_obs);
+  if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = ws_dev;
+  double* D = at<double>(ws, L.D);
+  double* Y = at<double>(ws, L.Y);
+  double* G = at<double>(ws, L.G);
+  double* grad = at<double>(ws, L.grad);
+  const double shift = (double)(n - 1);  // (N_ens - 1) with N_ens = n members
+  launch_obs_fluct(series_dev, n + 1, OBS_CHANNELS, (long)K, D, s);
+  launch_yrows(D, n, n_obs, eps, Y, s);
+  launch_gram<double>(Y, n, n_obs, n_obs, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
+  launch_gram_reduce(at<double>(ws, L.partial), n, L.nsplit, at<double>(ws, L.tmp), G, s);
+  launch_rowdot(Y, D, n, n_obs, 1.0, w_dev, shift, grad, s);  // Y^T d_0 + (N - 1) w
+  launch_rowdot(D, D, 1, n_obs, 0.5, nullptr, 0.0, jw_dev, s);  // 1/2 |d_0|^2
+  launch_rowdot(w_dev, w_dev, 1, n, 0.5 * shift, nullptr, 0.0, jw_dev + 1, s);  // 1/2 (N - 1) |w|^2
+  launch_shift_diag(G, n, shift, hgn_dev, grad, at<double>(ws, L.neg), s);
+  HIP_OK(hipMemcpyAsync(at<double>(ws, L.Hc), hgn_dev, (size_t)n * n * 8, hipMemcpyDeviceToDevice, s));
+  launch_chol_solve(at<double>(ws, L.Hc), at<double>(ws, L.neg), n, dw_dev, at<double>(ws, L.info), s, 0.0);
+  HIP_OK(hipGetLastError());
+  return ENVAR_OK;
+}
+
+extern "C" size_t envar_posterior_bytes(int32_t n) {
+  if (n < 1) return 0;
+  return align256((size_t)n * n * 8) + 256;
+}
+
+extern "C" int envar_posterior_var(const double* controls_dev, int32_t n, int64_t m, double eps, const double* hgn_dev,
+                                   void* ws_dev, size_t ws_bytes, double* var_dev, void* stream) {
+  if (n < 1 || m < 1) return fail(ENVAR_EINVAL, "n and m must be >= 1");
+  if (n > 128) return fail(ENVAR_EINVAL, "n = %d exceeds 128", n);
+  if (!(eps > 0.0)) return fail(ENVAR_EINVAL, "eps must be positive");
+  if (!controls_dev || !hgn_dev || !ws_dev || !var_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  if (ws_bytes < envar_posterior_bytes(n)) return fail(ENVAR_ENOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  double* C = (double*)ws_dev;
+  double* info = at<double>(ws_dev, align256((size_t)n * n * 8));
+  launch_spd_inverse(hgn_dev, n, C, info, s);
+  launch_post_var(controls_dev, n, (long)m, eps, C, var_dev, s);
+  HIP_OK(hipGetLastError());
+  return ENVAR_OK;
 }
 
 // ---------------------------------------------------------------------------- iterate

@@ -124,7 +124,7 @@ __global__ void k_gram_reduce(const double* partial, int n, int nsplit, double* 
 }
 
 // ---------------------------------------------------------------------------- FP64 Cholesky solve
-// Solves (G + ridge I) x = rhs, ridge = 1e-12 tr(G) / n, in one workgroup with
+// Solves (G + ridge I) x = rhs, ridge = ridge_rel tr(G) / n, in one workgroup with
 // one barrier per column. At step k every thread updates its entries of the
 // trailing block with a_ik a_jk / a_kk from the still unscaled column k, so the
 // factor is kept as A~ (column k as it stood at step k, pivot d_k = A~_kk) and
@@ -139,7 +139,8 @@ constexpr int CHOL_LDS_MAX = 128;
 constexpr int CHOL_VEC_MAX = 1024;
 
 template <bool LDS, int NT>
-__global__ __launch_bounds__(NT) void k_chol_solve(double* G, const double* rhs, int n, double* x, int* info) {
+__global__ __launch_bounds__(NT) void k_chol_solve(double* G, const double* rhs, int n, double* x, int* info,
+                                                   double ridge_rel) {
   constexpr int RS = NT / 32;
   __shared__ double sA[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) : 1];
   __shared__ double sv[CHOL_VEC_MAX];  // right-hand side, then z, then x
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(NT) void k_chol_solve(double* G, const double* rhs,
   if (tid == 0) {
     double tr = 0.0;
     for (int i = 0; i < n; ++i) tr += A[i * ld + i];
-    ridge = 1e-12 * tr / (double)n;
+    ridge = ridge_rel * tr / (double)n;
     *info = 0;
   }
   __syncthreads();
@@ -256,14 +257,145 @@ void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, d
                      tmp);
   hipLaunchKernelGGL(k_gram_reduce, dim3(bx), dim3(256), 0, s, tmp, n, ng, G);
 }
-int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s) {
+int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s, double ridge_rel) {
   if (n > CHOL_VEC_MAX) return -1;
   if (n <= 64)
-    hipLaunchKernelGGL((k_chol_solve<true, 256>), dim3(1), dim3(256), 0, s, G, rhs, n, x, (int*)work);
+    hipLaunchKernelGGL((k_chol_solve<true, 256>), dim3(1), dim3(256), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
   else if (n <= CHOL_LDS_MAX)
-    hipLaunchKernelGGL((k_chol_solve<true, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work);
+    hipLaunchKernelGGL((k_chol_solve<true, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
   else
-    hipLaunchKernelGGL((k_chol_solve<false, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work);
+    hipLaunchKernelGGL((k_chol_solve<false, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------- vector-observation EnVar step
+// Fluctuations about each channel's time mean: one workgroup per (row, channel), the
+// mean summed in a fixed order (per-thread strided sums, then waves, then workgroup).
+__global__ __launch_bounds__(256) void k_obs_fluct(const double* series, long K, double* D) {
+  __shared__ double red[4];
+  const long base = (long)blockIdx.x * K;  // row r, channel c: blockIdx.x = r * channels + c
+  double s = 0.0;
+  for (long t = threadIdx.x; t < K; t += 256) s += series[base + t];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double mean = (((red[0] + red[1]) + red[2]) + red[3]) / (double)K;
+  for (long t = threadIdx.x; t < K; t += 256) D[base + t] = series[base + t] - mean;
+}
+
+// Y rows (n x n_obs): Y_i = (d_i - d_0) / eps, i = 1 .. n
+__global__ void k_yrows(const double* D, int n, long n_obs, double inv_eps, double* Y) {
+  const int i = blockIdx.y;
+  for (long o = blockIdx.x * (long)blockDim.x + threadIdx.x; o < n_obs; o += (long)gridDim.x * blockDim.x)
+    Y[(long)i * n_obs + o] = (D[(long)(i + 1) * n_obs + o] - D[o]) * inv_eps;
+}
+
+// out[i] = scale * sum_o A[i][o] B[o] + add_coef * add[i] (one workgroup per row, fixed order)
+__global__ __launch_bounds__(256) void k_rowdot(const double* A, const double* B, long len, double scale,
+                                                const double* add, double add_coef, double* out) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (long o = threadIdx.x; o < len; o += 256) s += A[(long)i * len + o] * B[o];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[i] = scale * (((red[0] + red[1]) + red[2]) + red[3]) + (add ? add_coef * add[i] : 0.0);
+}
+
+// H = G + shift I (n x n), and rhs = -grad
+__global__ void k_shift_diag(const double* G, int n, double shift, double* H, const double* grad, double* neg) {
+  const long nn = (long)n * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    H[e] = G[e] + (i == j ? shift : 0.0);
+  }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) neg[i] = -grad[i];
+}
+
+// ---------------------------------------------------------------------------- posterior variance
+// Inverse of an SPD matrix by in-place Gauss-Jordan sweeps in LDS (no pivoting: the
+// pivots of an SPD matrix stay positive): for each k, with d = a_kk, the other entries
+// take a_ij - a_ik a_kj / d, then row k is divided by d, column k by -d and a_kk = 1 / d.
+constexpr int SPD_INV_MAX = 128;
+__global__ __launch_bounds__(1024) void k_spd_inverse(const double* H, int n, double* C, int* info) {
+  __shared__ double sA[SPD_INV_MAX * (SPD_INV_MAX + 1)];
+  const long ld = n + 1;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  for (int i = ty; i < n; i += 32)
+    for (int j = tx; j < n; j += 32) sA[i * ld + j] = H[(long)i * n + j];
+  if (tid == 0) *info = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double d = sA[k * ld + k];
+    if (tid == 0 && !(d > 0.0)) *info = k + 1;
+    const double inv = 1.0 / d;
+    for (int i = ty; i < n; i += 32) {
+      if (i == k) continue;
+      const double aik = sA[i * ld + k] * inv;
+      for (int j = tx; j < n; j += 32)
+        if (j != k) sA[i * ld + j] -= aik * sA[k * ld + j];
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += 1024)
+      if (j != k) {
+        sA[k * ld + j] *= inv;
+        sA[j * ld + k] *= -inv;
+      }
+    if (tid == 0) sA[k * ld + k] = inv;
+    __syncthreads();
+  }
+  for (int i = ty; i < n; i += 32)
+    for (int j = tx; j < n; j += 32) C[(long)i * n + j] = sA[i * ld + j];
+}
+
+// var[k] = e_k^T C e_k with e_k[a] = (ctrl[a + 1][k] - ctrl[0][k]) / eps: 64 columns per
+// workgroup staged in LDS, four row groups summed in a fixed order
+__global__ __launch_bounds__(256) void k_post_var(const double* ctrl, int n, long m, double inv_eps,
+                                                  const double* __restrict__ C, double* var) {
+  __shared__ double sE[SPD_INV_MAX * 64];
+  __shared__ double part[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const long k = blockIdx.x * 64L + tx;
+  for (int a = ty; a < n; a += 4) sE[a * 64 + tx] = k < m ? (ctrl[(long)(a + 1) * m + k] - ctrl[k]) * inv_eps : 0.0;
+  __syncthreads();
+  double acc = 0.0;
+  for (int a = ty; a < n; a += 4) {
+    double t = 0.0;
+    for (int b = 0; b < n; ++b) t += C[(long)a * n + b] * sE[b * 64 + tx];
+    acc += sE[a * 64 + tx] * t;
+  }
+  part[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && k < m) var[k] = ((part[0][tx] + part[1][tx]) + part[2][tx]) + part[3][tx];
+}
+
+void launch_obs_fluct(const double* series, int rows, int channels, long K, double* D, hipStream_t s) {
+  hipLaunchKernelGGL(k_obs_fluct, dim3(rows * channels), dim3(256), 0, s, series, K, D);
+}
+void launch_yrows(const double* D, int n, long n_obs, double eps, double* Y, hipStream_t s) {
+  long bx = (n_obs + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_yrows, dim3((unsigned)bx, n), dim3(256), 0, s, D, n, n_obs, 1.0 / eps, Y);
+}
+void launch_rowdot(const double* A, const double* B, int rows, long len, double scale, const double* add,
+                   double add_coef, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowdot, dim3(rows), dim3(256), 0, s, A, B, len, scale, add, add_coef, out);
+}
+void launch_shift_diag(const double* G, int n, double shift, double* H, const double* grad, double* neg, hipStream_t s) {
+  long bx = ((long)n * n + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_shift_diag, dim3((unsigned)bx), dim3(256), 0, s, G, n, shift, H, grad, neg);
+}
+int launch_spd_inverse(const double* H, int n, double* C, double* work, hipStream_t s) {
+  if (n > SPD_INV_MAX) return -1;
+  hipLaunchKernelGGL(k_spd_inverse, dim3(1), dim3(1024), 0, s, H, n, C, (int*)work);
+  return 0;
+}
+int launch_post_var(const double* ctrl, int n, long m, double eps, const double* C, double* var, hipStream_t s) {
+  if (n > SPD_INV_MAX) return -1;
+  hipLaunchKernelGGL(k_post_var, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, ctrl, n, m, 1.0 / eps, C, var);
   return 0;
 }
 template <typename TX>

@@ -226,6 +226,26 @@ void launch_fields_out(const Geo& g, long plane, int nmem, const double* u, cons
 void launch_clear_flag(int* flag, hipStream_t s);
 void launch_stream_copy(const void* src, void* dst, long n16, hipStream_t s);
 
+// velocity sensors (the vector observation): channel c = 2 s + component of sensor s;
+// each sample is the bilinear combination of four active faces of its component,
+// ((1 - ty) ((1 - tx) f00 + tx f01) + ty ((1 - tx) f10 + tx f11)), of the projected velocity
+constexpr int OBS_CHANNELS = 8;
+struct SensorArgs {
+  Geo g;
+  int nmem;
+  long plane;
+  double dt;
+  const double* us;     // u*, v* of the step
+  const double* vs;
+  const double* phi;    // its solved pressure
+  const double* stats;  // steps done (the sample index)
+  double* obs;          // [nmem][OBS_CHANNELS][K]
+  int K, every;
+  int fi[OBS_CHANNELS][4], fj[OBS_CHANNELS][4];  // face (i, j) of f00, f01, f10, f11
+  double tx[OBS_CHANNELS], ty[OBS_CHANNELS];
+};
+void launch_sensors(const Multi<SensorArgs>& m, hipStream_t s);
+
 template <typename T>
 void launch_mg_pre(const Multi<MGArgs<T>>& m, hipStream_t s);
 template <typename T>
@@ -247,7 +267,16 @@ template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s);
 int gram_reduce_groups(int nsplit);
 void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, double* G, hipStream_t s);
-int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s);
+int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s,
+                      double ridge_rel = 1e-12);
+// vector-observation EnVar step and posterior variance
+void launch_obs_fluct(const double* series, int rows, int channels, long K, double* D, hipStream_t s);
+void launch_yrows(const double* D, int n, long n_obs, double eps, double* Y, hipStream_t s);
+void launch_rowdot(const double* A, const double* B, int rows, long len, double scale, const double* add,
+                   double add_coef, double* out, hipStream_t s);
+void launch_shift_diag(const double* G, int n, double shift, double* H, const double* grad, double* neg, hipStream_t s);
+int launch_spd_inverse(const double* H, int n, double* C, double* work, hipStream_t s);
+int launch_post_var(const double* ctrl, int n, long m, double eps, const double* C, double* var, hipStream_t s);
 template <typename TX>
 void launch_gemv_t(const TX* X, int n, long m, long ldx, const double* c, double* g, hipStream_t s);
 template <typename TX>

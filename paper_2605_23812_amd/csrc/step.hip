@@ -444,6 +444,38 @@ __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
   }
 }
 
+// ---------------------------------------------------------------------------- velocity sensors
+// After the pressure solve of a step: the projected velocity u = u* - dt grad phi at the
+// sixteen active faces around the four sensors, combined bilinearly (the operand order is
+// fixed by SensorArgs). Samples are taken at the end of steps every, 2 every, ...; the
+// sample index comes from the member's step counter, so captured graphs stay valid.
+__global__ void k_sensors(Multi<SensorArgs> ms) {
+  int blk;
+  const SensorArgs& a = ms.template pick<false>(blockIdx.x, blk);
+  const int t = blk * blockDim.x + threadIdx.x;
+  if (t >= a.nmem * OBS_CHANNELS) return;
+  const int mem = t / OBS_CHANNELS, c = t % OBS_CHANNELS;
+  const int n1 = (int)a.stats[(long)mem * STATS_STRIDE + ST_STEPS] + 1;  // this step's end state is u^{n1}
+  if (n1 % a.every != 0) return;
+  const int sidx = n1 / a.every - 1;
+  if (sidx >= a.K) return;
+  const Geo& g = a.g;
+  const long off = (long)mem * a.plane;
+  const double inv_h = 1.0 / g.h;
+  double f[4];
+  for (int q = 0; q < 4; ++q) {
+    const int i = a.fi[c][q], j = a.fj[c][q];
+    const long at = off + g.at(i, j);
+    if ((c & 1) == 0)
+      f[q] = a.us[at] - a.dt * (a.phi[at] - a.phi[off + g.at(i - 1, j)]) * inv_h;
+    else
+      f[q] = a.vs[at] - a.dt * (a.phi[at] - a.phi[off + g.at(i, j - 1)]) * inv_h;
+  }
+  const double tx = a.tx[c], ty = a.ty[c];
+  a.obs[((long)mem * OBS_CHANNELS + c) * a.K + sidx] =
+      (1 - ty) * ((1 - tx) * f[0] + tx * f[1]) + ty * ((1 - tx) * f[2] + tx * f[3]);
+}
+
 // ---------------------------------------------------------------------------- per-step bookkeeping
 // norms[mem][k] holds dt*max|r| after cycle k; a skipped cycle carries the
 // previous value, so the first slot at or below tol ends the solve. Records
@@ -638,6 +670,9 @@ void launch_project_cost(const Multi<ProjArgs>& m, hipStream_t s) {
     launch_project_cost_<8>(m, s);
   else
     launch_project_cost_<16>(m, s);
+}
+void launch_sensors(const Multi<SensorArgs>& m, hipStream_t s) {
+  hipLaunchKernelGGL(k_sensors, dim3(m.total()), dim3(64), 0, s, m);
 }
 void launch_step_book(const Multi<BookArgs>& m, hipStream_t s) {
   hipLaunchKernelGGL(k_step_book, dim3(m.total()), dim3(64), 0, s, m);

@@ -30,7 +30,9 @@ EXPORTS = (
     "envar_gradient_bytes", "envar_gradient", "envar_iterate_bytes", "envar_iterate",
     "envar_last_error", "envar_version", "envar_stream_copy",
     "envar_request_bytes", "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
+    "envar_forward_obs", "envar_gn_bytes", "envar_gn_step", "envar_posterior_bytes", "envar_posterior_var",
 )
+OBS_CHANNELS = 8  # four lid sensors x two velocity components
 
 
 class EnvarError(RuntimeError):
@@ -177,12 +179,19 @@ def lib():
     L.envar_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, dp, ctypes.POINTER(RequestStats)]
     L.envar_server_destroy.argtypes = [vp]
     L.envar_stream_copy.argtypes = [vp, vp, sz, vp]
+    L.envar_forward_obs.argtypes = [P, vp, dp, i32, i64, i32, i32, vp, sz, dp, dp, ctypes.POINTER(Stats), vp]
+    L.envar_gn_bytes.argtypes = [i32, i64]
+    L.envar_gn_bytes.restype = sz
+    L.envar_gn_step.argtypes = [dp, i32, i64, ctypes.c_double, dp, vp, sz, dp, dp, dp, vp]
+    L.envar_posterior_bytes.argtypes = [i32]
+    L.envar_posterior_bytes.restype = sz
+    L.envar_posterior_var.argtypes = [dp, i32, i64, ctypes.c_double, dp, vp, sz, dp, vp]
     L.envar_last_error.restype = ctypes.c_char_p
     L.envar_version.restype = ctypes.c_char_p
     for name in ("envar_control_dim", "envar_cell_count", "envar_state_init", "envar_state_read",
                  "envar_spinup", "envar_forward", "envar_forward_batch", "envar_gradient", "envar_iterate",
                  "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
-                 "envar_stream_copy"):
+                 "envar_stream_copy", "envar_forward_obs", "envar_gn_step", "envar_posterior_var"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -354,6 +363,59 @@ def gradient(controls, J, precision=FP64, ws=None, g=None):
         g = torch.empty(m, dtype=torch.float64, device=controls.device)
     _check(lib().envar_gradient(_ptr(controls), _ptr(J), n, m, precision, _ptr(ws), ws.numel(), _ptr(g), _stream()))
     return g
+
+
+def forward_obs(p, state, controls, horizon, every=1, ws=None, J=None, stats=True):
+    """J [n_rows] and the lid-sensor series [n_rows, 8, horizon // every] (torch FP64 on the device)."""
+    import torch
+
+    n_rows, m = controls.shape
+    assert controls.dtype == torch.float64 and controls.is_cuda and controls.is_contiguous()
+    if ws is None:
+        ws = _bytes_tensor(workspace_bytes(p, n_rows))
+    if J is None:
+        J = torch.empty(n_rows, dtype=torch.float64, device=controls.device)
+    obs = torch.empty((n_rows, OBS_CHANNELS, horizon // every), dtype=torch.float64, device=controls.device)
+    st = Stats() if stats else None
+    rc = lib().envar_forward_obs(ctypes.byref(p.c()), _ptr(state), _ptr(controls), n_rows, m, horizon, every,
+                                 _ptr(ws), ws.numel(), _ptr(J), _ptr(obs),
+                                 ctypes.byref(st) if st is not None else None, _stream())
+    if rc == EDIVERGED:
+        return J, obs, st.as_dict()
+    _check(rc)
+    return J, obs, (st.as_dict() if st is not None else None)
+
+
+def gn_step(series, eps, w, ws=None):
+    """Gauss-Newton step from the sensor series [n+1, 8, K]: (dw [n], H_GN [n, n], (J_obs, J_prior))."""
+    import torch
+
+    rows, ch, K = series.shape
+    assert ch == OBS_CHANNELS and series.dtype == torch.float64 and series.is_contiguous()
+    n = rows - 1
+    w = w.contiguous()
+    if ws is None:
+        ws = _bytes_tensor(lib().envar_gn_bytes(n, K))
+    dw = torch.empty(n, dtype=torch.float64, device=series.device)
+    H = torch.empty((n, n), dtype=torch.float64, device=series.device)
+    jw = torch.empty(2, dtype=torch.float64, device=series.device)
+    _check(lib().envar_gn_step(_ptr(series), n, K, float(eps), _ptr(w), _ptr(ws), ws.numel(), _ptr(dw), _ptr(H),
+                               _ptr(jw), _stream()))
+    return dw, H, jw
+
+
+def posterior_var(controls, eps, H, ws=None):
+    """diag(E H^-1 E^T) [m] with E_i = (f_i - f_0) / eps from controls [n+1, m] (device FP64)."""
+    import torch
+
+    rows, m = controls.shape
+    n = rows - 1
+    if ws is None:
+        ws = _bytes_tensor(lib().envar_posterior_bytes(n))
+    var = torch.empty(m, dtype=torch.float64, device=controls.device)
+    _check(lib().envar_posterior_var(_ptr(controls), n, m, float(eps), _ptr(H.contiguous()), _ptr(ws), ws.numel(),
+                                     _ptr(var), _stream()))
+    return var
 
 
 def iterate(p, state, f, perturb, horizon, iters=1, max_trials=8, c1=1e-4, shrink=0.5, alpha0=0.0,
