@@ -24,7 +24,8 @@ What it computes, and where the paper defines it:
               lid (Sec. 4.1), fluctuation observations, Y by finite differences
               (eq. fdapprox), the Gauss-Newton Hessian and step (eq.
               Hessian_EnVar, eq. update_Newton) and the posterior variance
-              (eq. posterior_covariance_matrix).
+              (eq. posterior_covariance_matrix), and the EnVar loop over w with
+              the Gauss-Newton or L-BFGS update (eq. update_Newton, update_BFGS).
 
 Pins (tests/test_oracle_*.py): Taylor-Green linear AB2 recurrence and O(h^2)
 nonlinear decay, energy conservation of the advection operator, the discrete
@@ -33,6 +34,9 @@ two-pass vs brute-force cost, closed-form gradients on quadratic costs,
 central finite differences of the Navier-Stokes cost; for ``gn``: exact sensor
 interpolation of linear fields, zero-mean fluctuations, a Gauss-Newton step
 landing on the minimiser of an affine model (checked against an iterative
-least-squares solver and central differences), and the prior limit and
-monotonicity of the posterior variance.
+least-squares solver and central differences), the prior limit and
+monotonicity of the posterior variance, the Gauss-Newton loop solving an
+affine model in one step, the L-BFGS loop decreasing monotonically to the
+same minimiser, and the two-loop recursion against the dense inverse-BFGS
+update.
 """

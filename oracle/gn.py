@@ -18,6 +18,10 @@ TEST INFRASTRUCTURE ONLY (see the package header).
                        J(w) = 1/2 |d_0|^2 + 1/2 (N - 1) |w|^2.
 * ``posterior_variance``: the diagonal of eq. (posterior_covariance_matrix),
                        B_post = E H_GN^-1 E^T with E_i = (f_i - f_0) / eps.
+* ``iterate_ens``    : the EnVar loop over w (ensemble fixed, Sec. 3.3.3) with the
+                       Gauss-Newton update of eq. (update_Newton) or the L-BFGS update of
+                       eq. (update_BFGS) and its Armijo line search; ``lbfgs_direction`` is
+                       the two-loop recursion.
 """
 import numpy as np
 
@@ -104,3 +108,81 @@ def posterior_variance(controls, eps, H):
     E = ((controls[1:] - controls[0]) / eps).T       # m x N
     C = np.linalg.inv(np.asarray(H, dtype=np.float64))
     return np.einsum("ka,ab,kb->k", E, C, E)
+
+
+# ---------------------------------------------------------------------------- the EnVar loop over w
+def lbfgs_direction(g, S, Yh):
+    """-H^-1 g by the two-loop recursion over the stored pairs (s_k, y_k), oldest first, with the
+    initial Hessian scaled by s^T y / y^T y of the newest pair (Nocedal and Wright, Alg. 7.4)."""
+    q = np.array(g, dtype=np.float64)
+    alphas = []
+    for s, y in zip(reversed(S), reversed(Yh)):
+        rho = 1.0 / float(y @ s)
+        a = rho * float(s @ q)
+        q -= a * y
+        alphas.append((rho, a, s, y))
+    gamma = float(S[-1] @ Yh[-1]) / float(Yh[-1] @ Yh[-1]) if S else 1.0
+    r = gamma * q
+    for rho, a, s, y in reversed(alphas):
+        b = rho * float(y @ r)
+        r += (a - b) * s
+    return -r
+
+
+def iterate_ens(observe, fe, Ecols, eps, iters, method="gn", memory=5, c1=1e-4, shrink=0.5, max_trials=10,
+                w0=None):
+    """EnVar minimisation of J(w) over the ensemble weights (eq. J_w), the ensemble held fixed.
+
+    ``observe(rows)`` returns the raw sensor series [len(rows), N_CHANNELS, K] of the forward runs
+    of the control rows. Every iteration runs the centre f = f^(e) + E w and the N members
+    f + eps E_i (eq. fdapprox), forms the gradient and H_GN (``gn_step``) and updates w:
+    method "gn": w += dw (eq. update_Newton, unit step); method "lbfgs": w += alpha d with
+    d = -H_BFGS^-1 dJ/dw (eq. update_BFGS, ``memory`` pairs) and alpha the first of 1, shrink,
+    shrink^2, ... meeting the Armijo condition J(w + alpha d) <= J(w) + c1 alpha g.d (each trial
+    one centre run); the pair (s, y) is stored when s.y > 0. Returns the final w and a record per
+    iteration (J, J_obs, J_prior, |g|, alpha, trials)."""
+    Ecols = np.asarray(Ecols, dtype=np.float64)          # N x m, row i = E_(:, i)
+    fe = np.asarray(fe, dtype=np.float64)
+    N = Ecols.shape[0]
+    w = np.zeros(N) if w0 is None else np.array(w0, dtype=np.float64)
+    S, Yh, hist = [], [], []
+
+    def J_of(wv):
+        d0 = observations(observe((fe + wv @ Ecols)[None, :]))[0]
+        return 0.5 * float(d0 @ d0) + 0.5 * (N - 1) * float(wv @ wv)
+
+    g_prev, w_prev = None, None
+    for _ in range(iters):
+        f = fe + w @ Ecols
+        rows = np.vstack([f, f + eps * Ecols])
+        out = gn_step(observations(observe(rows)), eps, w)
+        g, J = out["grad"], out["J_obs"] + out["J_prior"]
+        if g_prev is not None:
+            s, y = w - w_prev, g - g_prev
+            if float(s @ y) > 0.0:
+                S.append(s)
+                Yh.append(y)
+                if len(S) > memory:
+                    S.pop(0)
+                    Yh.pop(0)
+        if method == "gn":
+            alpha, trials, step = 1.0, 0, out["dw"]
+        else:
+            d = lbfgs_direction(g, S, Yh)
+            gd = float(g @ d)
+            alpha, trials, step = 1.0, 0, None
+            while trials < max_trials:
+                trials += 1
+                if J_of(w + alpha * d) <= J + c1 * alpha * gd:
+                    step = alpha * d
+                    break
+                alpha *= shrink
+            if step is None:
+                alpha, step = 0.0, np.zeros(N)
+        hist.append(dict(J=J, J_obs=out["J_obs"], J_prior=out["J_prior"], gnorm=float(np.linalg.norm(g)),
+                         alpha=alpha, trials=trials))
+        g_prev, w_prev = g, w.copy()
+        w = w + step
+        if method != "gn" and alpha == 0.0:
+            break
+    return w, hist

@@ -95,3 +95,73 @@ def test_recording_the_sensors_keeps_the_cost():
     J, series = gn.forward_member_obs(p, base, f, 6, every=2)
     assert series.shape == (gn.N_CHANNELS, 3)
     assert J == OE.forward_member(p, base, f, 6)
+
+
+def _affine_observer(A, dc, Ecols, fe):
+    """Sensor series of an affine model: channel-major series whose fluctuations are dc + A w
+    for the control f = fe + E w (w recovered from f by least squares)."""
+    K = A.shape[0] // gn.N_CHANNELS
+    pinv = np.linalg.pinv(Ecols.T)
+
+    def observe(rows):
+        out = []
+        for f in rows:
+            wv = pinv @ (f - fe)
+            d = dc + A @ wv
+            out.append(d.reshape(gn.N_CHANNELS, K) + 7.0)  # a constant offset: removed by the time mean
+        return np.array(out)
+
+    return observe
+
+
+def _affine_problem(N, seed):
+    rng = np.random.default_rng(seed)
+    K, m = 6, 3 * N + 4
+    A = rng.standard_normal((gn.N_CHANNELS * K, N))
+    dc = rng.standard_normal(gn.N_CHANNELS * K)
+    # fluctuations have zero time mean per channel: project both onto that subspace
+    Z = lambda x: (x.reshape(gn.N_CHANNELS, K, -1) - x.reshape(gn.N_CHANNELS, K, -1).mean(axis=1, keepdims=True)
+                   ).reshape(gn.N_CHANNELS * K, -1)
+    A, dc = Z(A), Z(dc[:, None])[:, 0]
+    Ecols = rng.standard_normal((N, m))
+    fe = rng.standard_normal(m)
+    return A, dc, Ecols, fe
+
+
+@pytest.mark.parametrize("N", [3, 6])
+def test_gauss_newton_loop_solves_the_affine_problem_in_one_step(N):
+    A, dc, Ecols, fe = _affine_problem(N, 10 + N)
+    w, hist = gn.iterate_ens(_affine_observer(A, dc, Ecols, fe), fe, Ecols, 1e-4, 2, method="gn")
+    ref = np.linalg.lstsq(np.vstack([A, np.sqrt(N - 1.0) * np.eye(N)]), np.concatenate([-dc, np.zeros(N)]),
+                          rcond=None)[0]
+    assert np.abs(w - ref).max() < 1e-6 * (1 + np.abs(ref).max())
+    assert hist[1]["gnorm"] < 1e-6 * hist[0]["gnorm"]
+
+
+@pytest.mark.parametrize("N", [3, 6])
+def test_lbfgs_loop_decreases_and_converges_on_the_affine_problem(N):
+    A, dc, Ecols, fe = _affine_problem(N, 20 + N)
+    w, hist = gn.iterate_ens(_affine_observer(A, dc, Ecols, fe), fe, Ecols, 1e-4, 4 * N, method="lbfgs", memory=8)
+    J = [h["J"] for h in hist]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(J, J[1:]))  # Armijo: monotone decrease
+    ref = np.linalg.lstsq(np.vstack([A, np.sqrt(N - 1.0) * np.eye(N)]), np.concatenate([-dc, np.zeros(N)]),
+                          rcond=None)[0]
+    assert np.abs(w - ref).max() < 1e-5 * (1 + np.abs(ref).max())
+
+
+def test_lbfgs_two_loop_matches_the_dense_bfgs_inverse():
+    """With exact pairs of a quadratic, the two-loop product equals the dense inverse-BFGS update."""
+    rng = np.random.default_rng(4)
+    n = 5
+    M = rng.standard_normal((n, n))
+    H = M @ M.T + n * np.eye(n)
+    S = [rng.standard_normal(n) for _ in range(3)]
+    Yh = [H @ s for s in S]
+    g = rng.standard_normal(n)
+    gamma = float(S[-1] @ Yh[-1]) / float(Yh[-1] @ Yh[-1])
+    Binv = gamma * np.eye(n)
+    for s, y in zip(S, Yh):
+        rho = 1.0 / float(y @ s)
+        V = np.eye(n) - rho * np.outer(y, s)
+        Binv = V.T @ Binv @ V + rho * np.outer(s, s)
+    assert np.allclose(gn.lbfgs_direction(g, S, Yh), -Binv @ g, rtol=1e-10, atol=1e-12)
