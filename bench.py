@@ -208,6 +208,42 @@ def gauss_newton(torch, E, pm, state, ctrl, horizon, every=10):
             "members": nrows - 1, "samples_per_channel": K, "n_obs": E.OBS_CHANNELS * K, "m": m}
 
 
+def ens_loop(torch, E, p64, state, ctrl, horizon, every=10):
+    """One iteration of the EnVar loop over the ensemble weights at the benchmark shape (FP64:
+    the finite differences of eq. fdapprox need it): Gauss-Newton, and L-BFGS with its Armijo
+    trials batched as rows of one forward and one at a time, against the n + 1 forwards with
+    sensors alone."""
+    nrows, m = ctrl.shape
+    fe = ctrl[0].contiguous()
+    Ed = (ctrl[1:] - ctrl[0]).contiguous()
+    ws = E._bytes_tensor(E.ens_bytes(p64, nrows - 1, m, horizon, every))
+    fws = E._bytes_tensor(E.workspace_bytes(p64, nrows))
+    def best_of(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t = time.time()
+            r = fn()
+            torch.cuda.synchronize()
+            best = min(best or 1e30, time.time() - t)
+        return best, r
+
+    t_fwd, _ = best_of(lambda: E.forward_obs(p64, state, ctrl, horizon, every, ws=fws, stats=False))
+    del fws
+    out = {"members": nrows - 1, "horizon": horizon, "every": every,
+           "forwards_with_sensors_ms": round(t_fwd * 1e3, 1)}
+    for name, method, tb in (("gn", E.GN, 8), ("lbfgs", E.LBFGS, 8), ("lbfgs_one_trial_per_forward", E.LBFGS, 1)):
+        dt, (_, rec) = best_of(lambda: E.ens_iterate(p64, state, fe, Ed, horizon, iters=1, method=method,
+                                                      every=every, trial_batch=tb, ws=ws))
+        out[f"{name}_iteration_ms"] = round(dt * 1e3, 1)
+        if method == E.LBFGS:
+            out[f"{name}_trials"] = rec[0]["trials"]
+            out[f"{name}_trial_rows"] = rec[0]["trial_rows"]
+    out["gn_overhead_beyond_forwards_ms"] = round(out["gn_iteration_ms"] - out["forwards_with_sensors_ms"], 1)
+    return out
+
+
 def gram_sweep(torch, E):
     """Anomaly reduction (Gram X X^T on the matrix cores, Cholesky, X^T c) timed on the device.
 
@@ -469,6 +505,8 @@ def main():
         log("anomaly reduction", extra["anomaly_reduction"])
         extra["gauss_newton"] = gauss_newton(torch, E, pm, state, ctrl, args.baseline_horizon)
         log("gauss newton", extra["gauss_newton"])
+        extra["ens_loop_fp64"] = ens_loop(torch, E, p64, state, ctrl, args.baseline_horizon)
+        log("EnVar loop", extra["ens_loop_fp64"])
 
     serve = None
     if not args.no_serve:

@@ -254,6 +254,56 @@ int envar_posterior_var(const double* controls_dev, int32_t n, int64_t m, double
                         const double* hgn_dev, void* ws_dev, size_t ws_bytes, double* var_dev,
                         void* stream);
 
+/* ---------------------------------------------------------------- EnVar loop over w
+ * Minimisation of J(w) (eq. J_w) over the ensemble weights with the ensemble held fixed
+ * (Sec. 3.3.3), the vector observation of envar_forward_obs and R = I, y = 0. */
+enum { ENVAR_GN = 0, ENVAR_LBFGS = 1 };
+
+typedef struct {
+  int32_t method;      /* ENVAR_GN: w += dw (eq. update_Newton, unit step);
+                          ENVAR_LBFGS: w += alpha d, d = -H_BFGS^-1 dJ/dw (eq. update_BFGS) */
+  int32_t iters;       /* outer iterations (each runs the n + 1 forwards) */
+  int32_t memory;      /* L-BFGS pairs kept; <= 0: 5 */
+  int32_t max_trials;  /* Armijo trials per search (one centre forward each); <= 0: 10 */
+  int32_t every;       /* sensor sampling interval in steps; <= 0: 1 */
+  int32_t trial_batch; /* line-search trials evaluated per batched forward (min with n + 1); <= 0: 8 */
+  double eps;          /* finite-difference scale of eq. (fdapprox); <= 0: 1e-4 */
+  double c1;           /* sufficient-decrease constant; <= 0: 1e-4 */
+  double shrink;       /* step reduction per trial, in (0, 1); otherwise 0.5 */
+} envar_ens_params;
+
+/* Per-iteration record of envar_ens_iterate (NaN entries after an early stop). */
+typedef struct {
+  double J;        /* J(w) at the start of the iteration = J_obs + J_prior */
+  double J_obs;    /* 1/2 |d_0|^2 */
+  double J_prior;  /* 1/2 (n - 1) |w|^2 */
+  double gnorm;    /* |dJ/dw| (eq. gradient_EnVar) */
+  double alpha;    /* accepted step: 1 for Gauss-Newton; 0 = no sufficient decrease, loop stopped */
+  int32_t trials;      /* line-search trials up to the accepted one (0 for Gauss-Newton) */
+  int32_t trial_rows;  /* forward rows the search ran (>= trials: trials are batched) */
+} envar_ens_record;
+
+/* Workspace bytes of envar_ens_iterate (0 = invalid). */
+size_t envar_ens_bytes(const envar_problem* p, int32_t n, int64_t m, int32_t horizon, int32_t every);
+
+/* Each iteration builds on the device the centre f = f^(e) + E w and the members
+ * f + eps E_i (eq. fdapprox), runs their n + 1 forwards recording the lid sensors, forms
+ * dJ/dw and H_GN as envar_gn_step does, and updates w by the chosen method; the L-BFGS pair
+ * (s, y) of consecutive iterates is stored when s.y > 0, and the direction comes from the
+ * two-loop recursion with the initial scaling s.y / y.y of the newest pair. The line search
+ * takes the first of 1, shrink, shrink^2, ... meeting J(w + alpha d) <= J(w) + c1 alpha g.d;
+ * when none does, that record has alpha = 0, w keeps its value and the loop stops. The trial
+ * steps run trial_batch at a time as rows of one forward (each row's result does not depend on
+ * its batch), which gives the same accepted step as trying them one at a time.
+ * fe_dev [m] = f^(e), E_dev [n][m] (row i = E_i), w_dev [n] (in: w_0, out: the final w), all
+ * device; records (host, `iters` entries) may be NULL. Needs the cavity geometry.
+ * Synchronous: the update decisions read J and dJ/dw on the host. Errors: EINVAL (bad
+ * sizes, unknown method, no cavity), ENOMEM, EDIVERGED (non-finite gradient). */
+int envar_ens_iterate(const envar_problem* p, const void* state_dev, const double* fe_dev,
+                      const double* E_dev, int32_t n, int64_t m, int32_t horizon,
+                      const envar_ens_params* params, double* w_dev, void* ws_dev, size_t ws_bytes,
+                      envar_ens_record* records, void* stream);
+
 /* Line search and iteration parameters of envar_iterate (Armijo, eq. update_BFGS). */
 typedef struct {
   int32_t iters;          /* descent iterations */

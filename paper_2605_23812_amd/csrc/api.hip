@@ -1626,18 +1626,12 @@ extern "C" size_t envar_gn_bytes(int32_t n, int64_t K) {
   return gn_layout(n, (long)K * OBS_CHANNELS).total;
 }
 
-extern "C" int envar_gn_step(const double* series_dev, int32_t n, int64_t K, double eps, const double* w_dev,
-                             void* ws_dev, size_t ws_bytes, double* dw_dev, double* hgn_dev, double* jw_dev,
-                             void* stream) {
-  if (n < 1 || K < 1) return fail(ENVAR_EINVAL, "n and K must be >= 1");
-  if (n > 1024) return fail(ENVAR_EINVAL, "n = %d exceeds 1024", n);
-  if (!(eps > 0.0)) return fail(ENVAR_EINVAL, "eps must be positive");
-  if (!series_dev || !w_dev || !ws_dev || !dw_dev || !hgn_dev || !jw_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
-  const long n_obs = (long)K * OBS_CHANNELS;
+namespace envar {
+// Gauss-Newton step on the device; the gradient stays in the workspace at L.grad
+static int gn_step_impl(const double* series_dev, int n, long K, double eps, const double* w_dev, void* ws,
+                        double* dw_dev, double* hgn_dev, double* jw_dev, hipStream_t s) {
+  const long n_obs = K * OBS_CHANNELS;
   const GNLayout L = gn_layout(n, n_obs);
-  if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
-  hipStream_t s = (hipStream_t)stream;
-  void* ws = ws_dev;
   double* D = at<double>(ws, L.D);
   double* Y = at<double>(ws, L.Y);
   double* G = at<double>(ws, L.G);
@@ -1654,6 +1648,237 @@ extern "C" int envar_gn_step(const double* series_dev, int32_t n, int64_t K, dou
   HIP_OK(hipMemcpyAsync(at<double>(ws, L.Hc), hgn_dev, (size_t)n * n * 8, hipMemcpyDeviceToDevice, s));
   launch_chol_solve(at<double>(ws, L.Hc), at<double>(ws, L.neg), n, dw_dev, at<double>(ws, L.info), s, 0.0);
   HIP_OK(hipGetLastError());
+  return ENVAR_OK;
+}
+}  // namespace envar
+
+extern "C" int envar_gn_step(const double* series_dev, int32_t n, int64_t K, double eps, const double* w_dev,
+                             void* ws_dev, size_t ws_bytes, double* dw_dev, double* hgn_dev, double* jw_dev,
+                             void* stream) {
+  if (n < 1 || K < 1) return fail(ENVAR_EINVAL, "n and K must be >= 1");
+  if (n > 1024) return fail(ENVAR_EINVAL, "n = %d exceeds 1024", n);
+  if (!(eps > 0.0)) return fail(ENVAR_EINVAL, "eps must be positive");
+  if (!series_dev || !w_dev || !ws_dev || !dw_dev || !hgn_dev || !jw_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  const GNLayout L = gn_layout(n, (long)K * OBS_CHANNELS);
+  if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+  return gn_step_impl(series_dev, n, (long)K, eps, w_dev, ws_dev, dw_dev, hgn_dev, jw_dev, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------- EnVar loop over w
+namespace envar {
+struct EnsLayout {
+  size_t rows, series, J, fws, gws, w, dw, H, jw, wt, jt, total;
+  size_t fws_bytes, gws_bytes;
+  long K;
+};
+static EnsLayout ens_layout(const Plan& P, int n, long m, int horizon, int every) {
+  EnsLayout L{};
+  L.K = horizon / every;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t a = o;
+    o = align256(o + b);
+    return a;
+  };
+  L.rows = take((size_t)(n + 1) * m * 8);
+  L.series = take((size_t)(n + 1) * OBS_CHANNELS * L.K * 8);
+  L.J = take((size_t)(n + 1) * 8);
+  L.fws_bytes = make_ws(P, n + 1).total;
+  L.fws = take(L.fws_bytes);
+  L.gws_bytes = gn_layout(n, L.K * OBS_CHANNELS).total;
+  L.gws = take(L.gws_bytes);
+  L.w = take((size_t)n * 8);
+  L.dw = take((size_t)n * 8);
+  L.H = take((size_t)n * n * 8);
+  L.jw = take(2 * 8);
+  L.wt = take((size_t)(n + 1) * n * 8);
+  L.jt = take((size_t)(n + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+// -H^-1 g by the two-loop recursion over the stored pairs (oldest first), initial scaling s.y / y.y
+static std::vector<double> lbfgs_dir(const std::vector<double>& g, const std::deque<std::vector<double>>& S,
+                                     const std::deque<std::vector<double>>& Yh) {
+  const size_t n = g.size(), k = S.size();
+  auto dot = [&](const std::vector<double>& a, const std::vector<double>& b) {
+    double t = 0.0;
+    for (size_t i = 0; i < n; ++i) t += a[i] * b[i];
+    return t;
+  };
+  std::vector<double> q = g, alpha(k), rho(k);
+  for (size_t kk = k; kk-- > 0;) {
+    rho[kk] = 1.0 / dot(Yh[kk], S[kk]);
+    alpha[kk] = rho[kk] * dot(S[kk], q);
+    for (size_t i = 0; i < n; ++i) q[i] -= alpha[kk] * Yh[kk][i];
+  }
+  const double gamma = k ? dot(S[k - 1], Yh[k - 1]) / dot(Yh[k - 1], Yh[k - 1]) : 1.0;
+  for (size_t i = 0; i < n; ++i) q[i] *= gamma;
+  for (size_t kk = 0; kk < k; ++kk) {
+    const double b = rho[kk] * dot(Yh[kk], q);
+    for (size_t i = 0; i < n; ++i) q[i] += (alpha[kk] - b) * S[kk][i];
+  }
+  for (size_t i = 0; i < n; ++i) q[i] = -q[i];
+  return q;
+}
+}  // namespace envar
+
+extern "C" size_t envar_ens_bytes(const envar_problem* p, int32_t n, int64_t m, int32_t horizon, int32_t every) {
+  Plan P;
+  if (make_plan(p, P) != ENVAR_OK || n < 1 || m != P.m || horizon < 1) return 0;
+  if (every < 1) every = 1;
+  if (horizon / every < 1) return 0;
+  return ens_layout(P, n, (long)m, horizon, every).total;
+}
+
+extern "C" int envar_ens_iterate(const envar_problem* p, const void* state_dev, const double* fe_dev,
+                                 const double* E_dev, int32_t n, int64_t m, int32_t horizon,
+                                 const envar_ens_params* prm_in, double* w_dev, void* ws_dev, size_t ws_bytes,
+                                 envar_ens_record* recs, void* stream) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  if (!state_dev || !fe_dev || !E_dev || !w_dev || !ws_dev || !prm_in) return fail(ENVAR_EINVAL, "NULL pointer");
+  if (n < 1 || n > 1024) return fail(ENVAR_EINVAL, "n must be in [1, 1024]");
+  if (m != P.m) return fail(ENVAR_EINVAL, "m = %lld but the control region has m = %ld", (long long)m, P.m);
+  if (horizon < 1) return fail(ENVAR_EINVAL, "horizon must be >= 1");
+  if (!P.obs_ok) return fail(ENVAR_EINVAL, "the lid sensors need the cavity geometry");
+  envar_ens_params prm = *prm_in;
+  if (prm.method != ENVAR_GN && prm.method != ENVAR_LBFGS) return fail(ENVAR_EINVAL, "unknown method %d", prm.method);
+  if (prm.iters < 1) return fail(ENVAR_EINVAL, "iters must be >= 1");
+  if (prm.memory <= 0) prm.memory = 5;
+  if (prm.max_trials <= 0) prm.max_trials = 10;
+  if (!(prm.eps > 0.0)) prm.eps = 1e-4;
+  if (!(prm.c1 > 0.0)) prm.c1 = 1e-4;
+  if (!(prm.shrink > 0.0) || prm.shrink >= 1.0) prm.shrink = 0.5;
+  if (prm.every <= 0) prm.every = 1;
+  if (prm.trial_batch <= 0) prm.trial_batch = 8;
+  if (horizon / prm.every < 1) return fail(ENVAR_EINVAL, "every must be in [1, horizon]");
+  const EnsLayout L = ens_layout(P, n, (long)m, horizon, prm.every);
+  if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = ws_dev;
+  double* rows = at<double>(ws, L.rows);
+  double* series = at<double>(ws, L.series);
+  double* wd = at<double>(ws, L.w);
+  const size_t nb = (size_t)n * 8;
+  std::vector<double> w(n), g(n), dw(n), jw(2), gprev, wprev;
+  HIP_OK(hipMemcpyAsync(w.data(), w_dev, nb, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  std::deque<std::vector<double>> S, Yh;
+  const double shift = (double)(n - 1);
+  auto wdot = [&](const std::vector<double>& a) {
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += a[i] * a[i];
+    return t;
+  };
+  // J(w_t) of several trial weights W [nt][n] in one batched forward (rows independent)
+  std::vector<double> jt(n + 1);
+  auto J_trials = [&](const std::vector<double>& W, int nt) -> int {
+    HIP_OK(hipMemcpyAsync(at<double>(ws, L.wt), W.data(), (size_t)nt * nb, hipMemcpyHostToDevice, s));
+    launch_combine_rows(fe_dev, E_dev, n, (long)m, at<double>(ws, L.wt), nt, rows, s);
+    int r = forward_impl(P, state_dev, rows, nt, horizon, at<double>(ws, L.fws), L.fws_bytes, at<double>(ws, L.J),
+                         nullptr, nullptr, s, false, series, prm.every);
+    if (r) return r;
+    double* D = at<double>(ws, L.gws);  // the step's fluctuation buffer, reused
+    launch_obs_fluct(series, nt, OBS_CHANNELS, L.K, D, s);
+    launch_rowdot(D, D, nt, L.K * OBS_CHANNELS, 0.5, nullptr, 0.0, at<double>(ws, L.jt), s, true);  // 1/2 |d_t|^2
+    HIP_OK(hipMemcpyAsync(jt.data(), at<double>(ws, L.jt), (size_t)nt * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return ENVAR_OK;
+  };
+  for (int it = 0; it < prm.iters; ++it) {
+    HIP_OK(hipMemcpyAsync(wd, w.data(), nb, hipMemcpyHostToDevice, s));
+    launch_build_rows(fe_dev, E_dev, n, (long)m, wd, prm.eps, n + 1, rows, s);
+    rc = forward_impl(P, state_dev, rows, n + 1, horizon, at<double>(ws, L.fws), L.fws_bytes, at<double>(ws, L.J),
+                      nullptr, nullptr, s, false, series, prm.every);
+    if (rc) return rc;
+    rc = gn_step_impl(series, n, L.K, prm.eps, wd, at<double>(ws, L.gws), at<double>(ws, L.dw),
+                      at<double>(ws, L.H), at<double>(ws, L.jw), s);
+    if (rc) return rc;
+    const GNLayout GL = gn_layout(n, L.K * OBS_CHANNELS);
+    HIP_OK(hipMemcpyAsync(g.data(), at<double>(at<char>(ws, L.gws), GL.grad), nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(dw.data(), at<double>(ws, L.dw), nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(jw.data(), at<double>(ws, L.jw), 2 * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(g[i])) return fail(ENVAR_EDIVERGED, "non-finite gradient at iteration %d", it);
+    if (!gprev.empty()) {
+      std::vector<double> sv(n), yv(n);
+      double sy = 0.0;
+      for (int i = 0; i < n; ++i) {
+        sv[i] = w[i] - wprev[i];
+        yv[i] = g[i] - gprev[i];
+        sy += sv[i] * yv[i];
+      }
+      if (sy > 0.0) {
+        S.push_back(sv);
+        Yh.push_back(yv);
+        if ((int)S.size() > prm.memory) {
+          S.pop_front();
+          Yh.pop_front();
+        }
+      }
+    }
+    const double J = jw[0] + jw[1];
+    double alpha = 1.0;
+    int trials = 0, trial_rows = 0;
+    std::vector<double> step(n, 0.0);
+    if (prm.method == ENVAR_GN) {
+      step = dw;
+    } else {
+      const std::vector<double> d = lbfgs_dir(g, S, Yh);
+      double gd = 0.0;
+      for (int i = 0; i < n; ++i) gd += g[i] * d[i];
+      bool ok = false;
+      // the trial steps 1, shrink, shrink^2, ... are evaluated trial_batch at a time; the first
+      // one meeting the Armijo condition is taken, as a one-at-a-time search would
+      const int B = std::min(prm.trial_batch, n + 1);
+      double a = 1.0;
+      while (trials < prm.max_trials && !ok) {
+        const int nt = std::min(B, prm.max_trials - trials);
+        std::vector<double> W((size_t)nt * n), at_(nt);
+        for (int t = 0; t < nt; ++t) {
+          at_[t] = a;
+          for (int i = 0; i < n; ++i) W[(size_t)t * n + i] = w[i] + a * d[i];
+          a *= prm.shrink;
+        }
+        rc = J_trials(W, nt);
+        if (rc) return rc;
+        trial_rows += nt;
+        for (int t = 0; t < nt && !ok; ++t) {
+          ++trials;
+          double p2 = 0.0;
+          for (int i = 0; i < n; ++i) p2 += W[(size_t)t * n + i] * W[(size_t)t * n + i];
+          const double Jt = jt[t] + 0.5 * shift * p2;
+          if (Jt <= J + prm.c1 * at_[t] * gd) {
+            ok = true;
+            alpha = at_[t];
+            for (int i = 0; i < n; ++i) step[i] = alpha * d[i];
+          }
+        }
+      }
+      if (!ok) alpha = 0.0;
+    }
+    if (recs) {
+      recs[it].J = J;
+      recs[it].J_obs = jw[0];
+      recs[it].J_prior = jw[1];
+      recs[it].gnorm = std::sqrt(wdot(g));
+      recs[it].alpha = alpha;
+      recs[it].trials = trials;
+      recs[it].trial_rows = trial_rows;
+    }
+    gprev = g;
+    wprev = w;
+    for (int i = 0; i < n; ++i) w[i] += step[i];
+    if (prm.method == ENVAR_LBFGS && alpha == 0.0) {
+      for (int k = it + 1; k < prm.iters && recs; ++k) recs[k] = envar_ens_record{NAN, NAN, NAN, NAN, 0.0, 0, 0};  // not run
+      break;
+    }
+  }
+  HIP_OK(hipMemcpyAsync(w_dev, w.data(), nb, hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
   return ENVAR_OK;
 }
 

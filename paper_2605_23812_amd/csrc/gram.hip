@@ -417,12 +417,13 @@ __global__ void k_yrows(const double* D, int n, long n_obs, double inv_eps, doub
 }
 
 // out[i] = scale * sum_o A[i][o] B[o] + add_coef * add[i] (one workgroup per row, fixed order)
-__global__ __launch_bounds__(256) void k_rowdot(const double* A, const double* B, long len, double scale,
-                                                const double* add, double add_coef, double* out) {
+__global__ __launch_bounds__(256) void k_rowdot(const double* A, const double* B, long bstride, long len,
+                                                double scale, const double* add, double add_coef, double* out) {
   __shared__ double red[4];
   const int i = blockIdx.x;
+  const double* b = B + (long)i * bstride;
   double s = 0.0;
-  for (long o = threadIdx.x; o < len; o += 256) s += A[(long)i * len + o] * B[o];
+  for (long o = threadIdx.x; o < len; o += 256) s += A[(long)i * len + o] * b[o];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -497,6 +498,45 @@ __global__ __launch_bounds__(256) void k_post_var(const double* ctrl, int n, lon
   if (ty == 0 && k < m) var[k] = ((part[0][tx] + part[1][tx]) + part[2][tx]) + part[3][tx];
 }
 
+// one column k per thread: the centre sums the members in index order, then each member row
+// adds its own scaled direction to that centre
+__global__ __launch_bounds__(256) void k_build_rows(const double* __restrict__ fe, const double* __restrict__ E,
+                                                   int n, long m, const double* __restrict__ w, double eps,
+                                                   int nrows, double* __restrict__ rows) {
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < m; k += (long)gridDim.x * 256) {
+    double f = fe[k];
+    for (int i = 0; i < n; ++i) f = fma(w[i], E[(long)i * m + k], f);
+    rows[k] = f;
+    for (int i = 0; i + 1 < nrows; ++i) rows[(long)(i + 1) * m + k] = fma(eps, E[(long)i * m + k], f);
+  }
+}
+
+// rows[t] = fe + sum_i W[t][i] E_i for t < nw (the same summation order as the centre above)
+__global__ __launch_bounds__(256) void k_combine_rows(const double* __restrict__ fe, const double* __restrict__ E,
+                                                     int n, long m, const double* __restrict__ W, int nw,
+                                                     double* __restrict__ rows) {
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < m; k += (long)gridDim.x * 256)
+    for (int t = 0; t < nw; ++t) {
+      double f = fe[k];
+      for (int i = 0; i < n; ++i) f = fma(W[(long)t * n + i], E[(long)i * m + k], f);
+      rows[(long)t * m + k] = f;
+    }
+}
+
+void launch_combine_rows(const double* fe, const double* E, int n, long m, const double* W, int nw, double* rows,
+                         hipStream_t s) {
+  long bx = (m + 255) / 256;
+  if (bx > 2048) bx = 2048;
+  hipLaunchKernelGGL(k_combine_rows, dim3((unsigned)bx), dim3(256), 0, s, fe, E, n, m, W, nw, rows);
+}
+
+void launch_build_rows(const double* fe, const double* E, int n, long m, const double* w, double eps, int nrows,
+                       double* rows, hipStream_t s) {
+  long bx = (m + 255) / 256;
+  if (bx > 2048) bx = 2048;
+  hipLaunchKernelGGL(k_build_rows, dim3((unsigned)bx), dim3(256), 0, s, fe, E, n, m, w, eps, nrows, rows);
+}
+
 void launch_obs_fluct(const double* series, int rows, int channels, long K, double* D, hipStream_t s) {
   hipLaunchKernelGGL(k_obs_fluct, dim3(rows * channels), dim3(256), 0, s, series, K, D);
 }
@@ -506,8 +546,9 @@ void launch_yrows(const double* D, int n, long n_obs, double eps, double* Y, hip
   hipLaunchKernelGGL(k_yrows, dim3((unsigned)bx, n), dim3(256), 0, s, D, n, n_obs, 1.0 / eps, Y);
 }
 void launch_rowdot(const double* A, const double* B, int rows, long len, double scale, const double* add,
-                   double add_coef, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowdot, dim3(rows), dim3(256), 0, s, A, B, len, scale, add, add_coef, out);
+                   double add_coef, double* out, hipStream_t s, bool per_row_b) {
+  hipLaunchKernelGGL(k_rowdot, dim3(rows), dim3(256), 0, s, A, B, per_row_b ? len : 0L, len, scale, add, add_coef,
+                     out);
 }
 void launch_shift_diag(const double* G, int n, double shift, double* H, const double* grad, double* neg, hipStream_t s) {
   long bx = ((long)n * n + 255) / 256;

@@ -272,11 +272,18 @@ int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* wo
 // vector-observation EnVar step and posterior variance
 void launch_obs_fluct(const double* series, int rows, int channels, long K, double* D, hipStream_t s);
 void launch_yrows(const double* D, int n, long n_obs, double eps, double* Y, hipStream_t s);
+// out[i] = scale * A_i . B_i + add_coef * add[i], with B_i = B (shared) or row i of B (per_row_b)
 void launch_rowdot(const double* A, const double* B, int rows, long len, double scale, const double* add,
-                   double add_coef, double* out, hipStream_t s);
+                   double add_coef, double* out, hipStream_t s, bool per_row_b = false);
 void launch_shift_diag(const double* G, int n, double shift, double* H, const double* grad, double* neg, hipStream_t s);
 int launch_spd_inverse(const double* H, int n, double* C, double* work, hipStream_t s);
 int launch_post_var(const double* ctrl, int n, long m, double eps, const double* C, double* var, hipStream_t s);
+// rows[0] = fe + sum_i w_i E_i, rows[1 + i] = rows[0] + eps E_i for i < nrows - 1
+// rows[t] = fe + sum_i W[t][i] E_i for t < nw
+void launch_combine_rows(const double* fe, const double* E, int n, long m, const double* W, int nw, double* rows,
+                         hipStream_t s);
+void launch_build_rows(const double* fe, const double* E, int n, long m, const double* w, double eps, int nrows,
+                       double* rows, hipStream_t s);
 template <typename TX>
 void launch_gemv_t(const TX* X, int n, long m, long ldx, const double* c, double* g, hipStream_t s);
 template <typename TX>

@@ -31,7 +31,9 @@ EXPORTS = (
     "envar_last_error", "envar_version", "envar_stream_copy",
     "envar_request_bytes", "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
     "envar_forward_obs", "envar_gn_bytes", "envar_gn_step", "envar_posterior_bytes", "envar_posterior_var",
+    "envar_ens_bytes", "envar_ens_iterate",
 )
+GN, LBFGS = 0, 1
 OBS_CHANNELS = 8  # four lid sensors x two velocity components
 
 
@@ -106,6 +108,20 @@ class LSParams(ctypes.Structure):
 class IterRecord(ctypes.Structure):
     _fields_ = [("J0", ctypes.c_double), ("gnorm", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("J_trial", ctypes.c_double)]
+
+
+class EnsParams(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32), ("iters", ctypes.c_int32), ("memory", ctypes.c_int32),
+        ("max_trials", ctypes.c_int32), ("every", ctypes.c_int32), ("trial_batch", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("c1", ctypes.c_double), ("shrink", ctypes.c_double),
+    ]
+
+
+class EnsRecord(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_double), ("J_obs", ctypes.c_double), ("J_prior", ctypes.c_double),
+                ("gnorm", ctypes.c_double), ("alpha", ctypes.c_double), ("trials", ctypes.c_int32),
+                ("trial_rows", ctypes.c_int32)]
 
 
 @dataclass
@@ -186,12 +202,17 @@ def lib():
     L.envar_posterior_bytes.argtypes = [i32]
     L.envar_posterior_bytes.restype = sz
     L.envar_posterior_var.argtypes = [dp, i32, i64, ctypes.c_double, dp, vp, sz, dp, vp]
+    L.envar_ens_bytes.argtypes = [P, i32, i64, i32, i32]
+    L.envar_ens_bytes.restype = sz
+    L.envar_ens_iterate.argtypes = [P, vp, dp, dp, i32, i64, i32, ctypes.POINTER(EnsParams), dp, vp, sz,
+                                    ctypes.POINTER(EnsRecord), vp]
     L.envar_last_error.restype = ctypes.c_char_p
     L.envar_version.restype = ctypes.c_char_p
     for name in ("envar_control_dim", "envar_cell_count", "envar_state_init", "envar_state_read",
                  "envar_spinup", "envar_forward", "envar_forward_batch", "envar_gradient", "envar_iterate",
                  "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
-                 "envar_stream_copy", "envar_forward_obs", "envar_gn_step", "envar_posterior_var"):
+                 "envar_stream_copy", "envar_forward_obs", "envar_gn_step", "envar_posterior_var",
+                 "envar_ens_iterate"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -416,6 +437,35 @@ def posterior_var(controls, eps, H, ws=None):
     _check(lib().envar_posterior_var(_ptr(controls), n, m, float(eps), _ptr(H.contiguous()), _ptr(ws), ws.numel(),
                                      _ptr(var), _stream()))
     return var
+
+
+def ens_bytes(p, n, m, horizon, every=1):
+    return lib().envar_ens_bytes(ctypes.byref(p.c()), n, m, horizon, every)
+
+
+def ens_iterate(p, state, fe, E, horizon, iters=1, method=GN, w=None, memory=5, max_trials=10, every=1,
+                eps=1e-4, c1=1e-4, shrink=0.5, trial_batch=8, ws=None):
+    """EnVar loop over the ensemble weights (device FP64 fe [m], E [n, m]). Returns (w [n] on the
+    device, per-iteration records up to an early stop)."""
+    import torch
+
+    n, m = E.shape
+    assert fe.dtype == E.dtype == torch.float64 and fe.is_contiguous() and E.is_contiguous()
+    if ws is None:
+        ws = _bytes_tensor(ens_bytes(p, n, m, horizon, every))
+    w = (torch.zeros(n, dtype=torch.float64, device=E.device) if w is None
+         else w.to(device=E.device, dtype=torch.float64).clone().contiguous())
+    prm = EnsParams(method, iters, memory, max_trials, every, trial_batch, eps, c1, shrink)
+    recs = (EnsRecord * iters)()
+    _check(lib().envar_ens_iterate(ctypes.byref(p.c()), _ptr(state), _ptr(fe), _ptr(E), n, m, horizon,
+                                   ctypes.byref(prm), _ptr(w), _ptr(ws), ws.numel(), recs, _stream()))
+    out = []
+    for r in recs:
+        out.append(dict(J=r.J, J_obs=r.J_obs, J_prior=r.J_prior, gnorm=r.gnorm, alpha=r.alpha, trials=r.trials,
+                        trial_rows=r.trial_rows))
+        if method == LBFGS and r.alpha == 0.0:
+            break
+    return w, out
 
 
 def iterate(p, state, f, perturb, horizon, iters=1, max_trials=8, c1=1e-4, shrink=0.5, alpha0=0.0,
