@@ -26,6 +26,11 @@ What it computes, and where the paper defines it:
               Hessian_EnVar, eq. update_Newton) and the posterior variance
               (eq. posterior_covariance_matrix), and the EnVar loop over w with
               the Gauss-Newton or L-BFGS update (eq. update_Newton, update_BFGS).
+* ``eigen``   the deterministic eigen-ensemble of Sec. 3.3.2: the tapered
+              Gaussian covariance B of eq. (covarianceB) with the parameters of
+              Sec. 4.2, its leading eigenpairs by a dense symmetric
+              eigensolver, E = V_N mu_N^(1/2) sqrt(N - 1) (eq. eigenvm1), and the
+              reconstruction error of App. A (eq. reconstruction_error).
 
 Pins (tests/test_oracle_*.py): Taylor-Green linear AB2 recurrence and O(h^2)
 nonlinear decay, energy conservation of the advection operator, the discrete
@@ -38,5 +43,9 @@ least-squares solver and central differences), the prior limit and
 monotonicity of the posterior variance, the Gauss-Newton loop solving an
 affine model in one step, the L-BFGS loop decreasing monotonically to the
 same minimiser, and the two-loop recursion against the dense inverse-BFGS
-update.
+update; for ``eigen``: the two-point closed form, the Kronecker spectrum of a
+uniform-variance rectangle, E E^T / (N - 1) = B with every mode kept and the
+Eckart-Young error when truncated, the taper's centre, corners and symmetry,
+the separable product against the dense B, and the limits of the
+reconstruction error.
 """
