@@ -304,6 +304,60 @@ int envar_ens_iterate(const envar_problem* p, const void* state_dev, const doubl
                       const envar_ens_params* params, double* w_dev, void* ws_dev, size_t ws_bytes,
                       envar_ens_record* records, void* stream);
 
+/* ---------------------------------------------------------------- eigen-ensemble
+ * The deterministic ensemble of Sec. 3.3.2: the N leading eigenvectors of the prior covariance
+ * B_ij = sigma_i sigma_j exp(-(x_i - x_j)^2 / a_x^2 - (y_i - y_j)^2 / a_y^2) of eq. (covarianceB)
+ * (c_xy = infinity, the value of Sec. 4.2) over the control cells, as members
+ * E = U_N Sigma_N^(1/2) sqrt(N - 1) (eq. eigenvm1). With M_f = h^2 I the M_f-orthonormal
+ * eigenvectors are U = V / h with Sigma = h^2 mu (V, mu: the orthonormal eigenpairs of the matrix
+ * B), so E = V_N mu_N^(1/2) sqrt(N - 1). */
+enum { ENVAR_TAPER_NONE = 0, ENVAR_TAPER_ELLIPSE = 1 };
+
+typedef struct {
+  double a_x, a_y;      /* correlation lengths; <= 0: 0.07 (Sec. 4.2) */
+  double sigma2_max;    /* largest variance sigma_i^2; <= 0: 0.01 (Sec. 4.2) */
+  double tol;           /* stop when |B v_k - mu_k v_k| <= tol mu_1 for every k < N; <= 0: 1e-10 */
+  int32_t taper;        /* ENVAR_TAPER_ELLIPSE: sigma_i^2 = sigma2_max (1 - r^2)^2 inside the ellipse
+                           inscribed in the bounding rectangle of the control cells (r = 1 on the
+                           ellipse), 0 outside; ENVAR_TAPER_NONE: sigma2_max on every control cell */
+  int32_t component;    /* forcing component the members drive: 0 = x, 1 = y (Sec. 4.1: y only) */
+  int32_t oversample;   /* subspace vectors beyond N; <= 0: max(8, N / 2); N + oversample <= 512 */
+  int32_t max_iters;    /* subspace iterations; <= 0: 500 */
+  uint64_t seed;        /* start block */
+} envar_eigen_params;
+
+typedef struct {
+  int32_t iters;      /* subspace iterations run */
+  int32_t converged;  /* 1 when every kept residual met tol */
+  int32_t block;      /* subspace size b = N + oversample (reduced to the cells with sigma > 0) */
+  int32_t reserved;
+  double max_resid;   /* max over k < N of |B v_k - mu_k v_k| / mu_1 at exit */
+  double orth_err;    /* max |V V^T - I| of the kept directions */
+} envar_eigen_info;
+
+/* Workspace bytes of envar_eigen_ensemble (0 = invalid). */
+size_t envar_eigen_bytes(const envar_problem* p, int32_t N, const envar_eigen_params* params);
+
+/* E_dev [N][m] (device): row k the k-th member, nonzero only in params->component (the other
+ * component's half of the row is 0); mu_dev [N] (device): the eigenvalues mu_k of B, decreasing.
+ * The sign of each member, and the basis inside an eigenspace of a repeated eigenvalue, are not
+ * fixed; E E^T is. Block subspace iteration on the matrix cores (B applied through the separable
+ * kernel on the region's bounding rectangle); info (host) may be NULL. Synchronous. Errors: EINVAL
+ * (N < 2, N above the number of cells with sigma > 0 or above 448, bad lengths), ENOMEM. An
+ * iteration limit reached before tol is not an error: info->converged = 0. */
+int envar_eigen_ensemble(const envar_problem* p, int32_t N, const envar_eigen_params* params, double* E_dev,
+                         double* mu_dev, void* ws_dev, size_t ws_bytes, envar_eigen_info* info, void* stream);
+
+/* Workspace bytes of envar_recon_error. */
+size_t envar_recon_bytes(int32_t N, int64_t m);
+
+/* Reconstruction error of App. A (eq. reconstruction_error): the share of |f|^2 outside the span of
+ * the members, |f - V V^T f|^2 / |f|^2 with V the normalised rows of E_dev [N][m] (orthogonal rows,
+ * as envar_eigen_ensemble returns; M_f = h^2 I cancels). f_dev [m], out_dev [1], all device.
+ * Errors: EINVAL (N < 1, m < 1), ENOMEM. */
+int envar_recon_error(const double* E_dev, int32_t N, int64_t m, const double* f_dev, void* ws_dev,
+                      size_t ws_bytes, double* out_dev, void* stream);
+
 /* Line search and iteration parameters of envar_iterate (Armijo, eq. update_BFGS). */
 typedef struct {
   int32_t iters;          /* descent iterations */

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libenvar.so")
-SOURCES = ["api.hip", "step.hip", "mg.hip", "gram.hip"]
+SOURCES = ["api.hip", "step.hip", "mg.hip", "gram.hip", "eigen.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -1882,6 +1882,269 @@ extern "C" int envar_ens_iterate(const envar_problem* p, const void* state_dev, 
   return ENVAR_OK;
 }
 
+// ---------------------------------------------------------------------------- eigen-ensemble
+namespace envar {
+struct EigSetup {
+  envar_eigen_params prm;
+  int i0, j0, nxb, nyb, ncc, npos, N, b;
+  long M;
+  std::vector<int> bidx;  // rectangle index of each control cell, in control order
+};
+
+static int eig_setup(const Plan& P, int N, const envar_eigen_params* in, EigSetup& S) {
+  envar_eigen_params prm{};
+  if (in) prm = *in;
+  if (!(prm.a_x > 0.0)) prm.a_x = 0.07;
+  if (!(prm.a_y > 0.0)) prm.a_y = 0.07;
+  if (!(prm.sigma2_max > 0.0)) prm.sigma2_max = 0.01;
+  if (!(prm.tol > 0.0)) prm.tol = 1e-10;
+  if (prm.max_iters <= 0) prm.max_iters = 500;
+  if (prm.taper != ENVAR_TAPER_NONE && prm.taper != ENVAR_TAPER_ELLIPSE)
+    return fail(ENVAR_EINVAL, "unknown taper %d", prm.taper);
+  if (prm.component != 0 && prm.component != 1) return fail(ENVAR_EINVAL, "component must be 0 (x) or 1 (y)");
+  if (N < 2 || N > 448) return fail(ENVAR_EINVAL, "N = %d must be in [2, 448]", N);
+  const Geo& g = P.lev[0];
+  int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
+  for (int c : P.ctrl_cells) {
+    const int i = c % g.nx, j = c / g.nx;
+    imin = std::min(imin, i);
+    imax = std::max(imax, i);
+    jmin = std::min(jmin, j);
+    jmax = std::max(jmax, j);
+  }
+  S.ncc = (int)P.ctrl_cells.size();
+  if (S.ncc < 2) return fail(ENVAR_EINVAL, "the control region has %d cell(s)", S.ncc);
+  S.i0 = imin;
+  S.j0 = jmin;
+  S.nxb = imax - imin + 1;
+  S.nyb = jmax - jmin + 1;
+  S.M = (long)S.nxb * S.nyb;
+  S.bidx.resize(S.ncc);
+  S.npos = 0;
+  for (int k = 0; k < S.ncc; ++k) {
+    const int i = P.ctrl_cells[k] % g.nx - imin, j = P.ctrl_cells[k] / g.nx - jmin;
+    S.bidx[k] = j * S.nxb + i;
+    bool pos = true;
+    if (prm.taper == ENVAR_TAPER_ELLIPSE) {  // the same test as the device's taper
+      const double ex = ((i + 0.5) * g.h - 0.5 * S.nxb * g.h) / (0.5 * S.nxb * g.h);
+      const double ey = ((j + 0.5) * g.h - 0.5 * S.nyb * g.h) / (0.5 * S.nyb * g.h);
+      pos = ex * ex + ey * ey < 1.0;
+    }
+    S.npos += pos;
+  }
+  if (N > S.npos) return fail(ENVAR_EINVAL, "N = %d exceeds the %d control cells with sigma > 0", N, S.npos);
+  if (prm.oversample <= 0) prm.oversample = std::max(8, N / 2);
+  S.b = std::min(std::min(N + prm.oversample, 512), S.npos);
+  S.N = N;
+  S.prm = prm;
+  return ENVAR_OK;
+}
+
+struct EigLayout {
+  size_t sig, Kx, Ky, bidx, QZ, W1, T1, UV, partial, tmp, G2, Ts, ZZ, QQ, Wm, Wt, M1, Pm, Gy, Pg, Pgt, Sm, Cm, theta,
+      lam, ninv, dv, resid, jac, total;
+  int nsplit;
+  long kchunk;
+};
+
+static EigLayout eig_layout(const EigSetup& S) {
+  EigLayout L{};
+  const int b = S.b, n2 = 2 * b;
+  const int nbt = (n2 + 63) / 64;
+  long want = std::max(1L, 512L / (nbt * nbt));
+  long chunk = (S.M + want - 1) / want;
+  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
+  L.kchunk = chunk;
+  L.nsplit = (int)((S.M + chunk - 1) / chunk);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t a = o;
+    o = align256(o + bytes);
+    return a;
+  };
+  const size_t bb = (size_t)b * b * 8, bm = (size_t)b * S.M * 8;
+  L.sig = take((size_t)S.M * 8);
+  L.Kx = take((size_t)S.nxb * S.nxb * 8);
+  L.Ky = take((size_t)S.nyb * S.nyb * 8);
+  L.bidx = take((size_t)S.ncc * 4);
+  L.QZ = take(2 * bm);
+  L.W1 = take(bm);
+  L.T1 = take(bm);
+  L.UV = take(2 * bm);
+  L.partial = take((size_t)L.nsplit * n2 * n2 * 8);
+  L.tmp = take((size_t)gram_reduce_groups(L.nsplit) * n2 * n2 * 8);
+  L.G2 = take((size_t)n2 * n2 * 8);
+  L.Ts = take(bb);
+  L.ZZ = take(bb);
+  L.QQ = take(bb);
+  L.Wm = take(bb);
+  L.Wt = take(bb);
+  L.M1 = take(bb);
+  L.Pm = take(bb);
+  L.Gy = take(bb);
+  L.Pg = take(bb);
+  L.Pgt = take(bb);
+  L.Sm = take(bb);
+  L.Cm = take(bb);
+  L.theta = take((size_t)b * 8);
+  L.lam = take((size_t)b * 8);
+  L.ninv = take((size_t)b * 8);
+  L.dv = take((size_t)b * 8);
+  L.resid = take((size_t)b * 8);
+  L.jac = take(std::max<size_t>(8, jacobi_scratch_doubles(b) * 8));
+  L.total = o;
+  return L;
+}
+}  // namespace envar
+
+extern "C" size_t envar_eigen_bytes(const envar_problem* p, int32_t N, const envar_eigen_params* params) {
+  Plan P;
+  if (make_plan(p, P) != ENVAR_OK) return 0;
+  EigSetup S;
+  if (eig_setup(P, N, params, S) != ENVAR_OK) return 0;
+  return eig_layout(S).total;
+}
+
+extern "C" int envar_eigen_ensemble(const envar_problem* p, int32_t N, const envar_eigen_params* params,
+                                    double* E_dev, double* mu_dev, void* ws_dev, size_t ws_bytes,
+                                    envar_eigen_info* info, void* stream) {
+  Plan P;
+  int rc = make_plan(p, P);
+  if (rc) return rc;
+  EigSetup S;
+  rc = eig_setup(P, N, params, S);
+  if (rc) return rc;
+  if (!E_dev || !mu_dev || !ws_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  const EigLayout L = eig_layout(S);
+  if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = ws_dev;
+  const int b = S.b;
+  const long M = S.M;
+  const double h = P.lev[0].h;
+  double* sig = at<double>(ws, L.sig);
+  double* Kx = at<double>(ws, L.Kx);
+  double* Ky = at<double>(ws, L.Ky);
+  int* bidx = at<int>(ws, L.bidx);
+  double* Q = at<double>(ws, L.QZ);
+  double* Z = Q + (size_t)b * M;
+  double* W1 = at<double>(ws, L.W1);
+  double* T1 = at<double>(ws, L.T1);
+  double* U = at<double>(ws, L.UV);
+  double* Vv = U + (size_t)b * M;
+  double* G2 = at<double>(ws, L.G2);
+  auto d = [&](size_t off) { return at<double>(ws, off); };
+  HIP_OK(hipMemcpyAsync(bidx, S.bidx.data(), (size_t)S.ncc * 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(sig, 0, (size_t)M * 8, s));
+  launch_eig_sigma(bidx, S.ncc, S.nxb, S.nyb, h, S.prm.sigma2_max, S.prm.taper, sig, s);
+  launch_kernel1d(S.nxb, h, S.prm.a_x, Kx, s);
+  launch_kernel1d(S.nyb, h, S.prm.a_y, Ky, s);
+  // Z = B Q = D (Ky kron Kx) D Q, rows of Q as ny x nx grids
+  auto apply_B = [&]() {
+    launch_scale_rows(Q, sig, b, M, W1, s);
+    launch_dgemm(b * S.nyb, S.nxb, S.nxb, W1, S.nxb, 0, Kx, S.nxb, 0, T1, S.nxb, 0, 1, nullptr, 0, s);
+    launch_dgemm(S.nyb, S.nxb, S.nyb, Ky, S.nyb, 0, T1, S.nxb, M, Z, S.nxb, M, b, sig, S.nxb, s);
+  };
+  auto gram2 = [&](int rows) {  // G2 = X X^T over the first `rows` rows of [Q; Z]
+    launch_gram<double>(Q, rows, M, M, d(L.partial), L.nsplit, L.kchunk, s);
+    launch_gram_reduce(d(L.partial), rows, L.nsplit, d(L.tmp), G2, s);
+  };
+  auto jacobi = [&](const double* A, double* ev, double* Wc, double* Wr) -> int {
+    if (launch_jacobi(A, b, b, ev, Wc, Wr, d(L.jac), s)) return fail(ENVAR_EDEVICE, "Jacobi launch failed");
+    return ENVAR_OK;
+  };
+  // start block: random on the cells with sigma > 0, orthonormalised (Loewdin): Q = G^-1/2 Q0
+  launch_eig_random(Z, b, M, sig, S.prm.seed ? S.prm.seed : 0x5EEDull, s);
+  launch_gram<double>(Z, b, M, M, d(L.partial), L.nsplit, L.kchunk, s);
+  launch_gram_reduce(d(L.partial), b, L.nsplit, d(L.tmp), d(L.Gy), s);
+  if ((rc = jacobi(d(L.Gy), d(L.lam), d(L.Pg), d(L.Pgt)))) return rc;
+  launch_eig_rsqrt(d(L.lam), b, d(L.dv), s);
+  launch_small_gemm(b, d(L.Pg), 0, d(L.Pgt), 0, d(L.dv), d(L.Sm), s);
+  launch_dgemm(b, (int)M, b, d(L.Sm), b, 0, Z, M, 0, Q, M, 0, 1, nullptr, 0, s);
+  HIP_OK(hipGetLastError());
+  std::vector<double> th(b), res(S.N);
+  int it = 0;
+  bool conv = false;
+  double maxr = 0.0;
+  for (it = 1; it <= S.prm.max_iters; ++it) {
+    apply_B();
+    gram2(2 * b);
+    launch_eig_blocks(G2, b, d(L.Ts), d(L.ZZ), d(L.QQ), s);
+    if ((rc = jacobi(d(L.Ts), d(L.theta), d(L.Wm), d(L.Wt)))) return rc;
+    // Ritz vectors and images: [U; V] = W^T [Q; Z]
+    launch_dgemm(b, (int)M, b, d(L.Wt), b, 0, Q, M, (long)b * M, U, M, (long)b * M, 2, nullptr, 0, s);
+    launch_eig_resid(U, Vv, d(L.theta), S.N, M, d(L.resid), s);
+    HIP_OK(hipMemcpyAsync(th.data(), d(L.theta), (size_t)b * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(res.data(), d(L.resid), (size_t)S.N * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    maxr = 0.0;
+    for (int k = 0; k < S.N; ++k) maxr = std::max(maxr, res[k]);
+    maxr = th[0] > 0.0 ? maxr / th[0] : INFINITY;
+    if (!std::isfinite(maxr)) return fail(ENVAR_EDIVERGED, "non-finite Ritz values at iteration %d", it);
+    if (maxr <= S.prm.tol) {
+      conv = true;
+      break;
+    }
+    if (it == S.prm.max_iters) break;
+    // next Q: Loewdin orthonormalisation of the unit-norm rows of V = W^T Z,
+    // Q = Gy^-1/2 Dn^-1 W^T Z with P = W^T (Z Z^T) W, Dn = diag(P)^1/2, Gy = Dn^-1 P Dn^-1
+    launch_small_gemm(b, d(L.ZZ), 0, d(L.Wm), 0, nullptr, d(L.M1), s);
+    launch_small_gemm(b, d(L.Wt), 0, d(L.M1), 0, nullptr, d(L.Pm), s);
+    launch_eig_unit_gram(d(L.Pm), b, d(L.Gy), d(L.ninv), s);
+    if ((rc = jacobi(d(L.Gy), d(L.lam), d(L.Pg), d(L.Pgt)))) return rc;
+    launch_eig_rsqrt(d(L.lam), b, d(L.dv), s);
+    launch_small_gemm(b, d(L.Pg), 0, d(L.Pgt), 0, d(L.dv), d(L.Sm), s);
+    launch_small_gemm(b, d(L.Sm), 0, d(L.Wt), 0, d(L.ninv), d(L.Cm), s);
+    launch_dgemm(b, (int)M, b, d(L.Cm), b, 0, Z, M, 0, Q, M, 0, 1, nullptr, 0, s);
+    HIP_OK(hipGetLastError());
+  }
+  launch_eig_extract(U, d(L.theta), S.N, M, bidx, S.ncc, S.prm.component, E_dev, mu_dev, s);
+  HIP_OK(hipGetLastError());
+  if (info) {
+    // orthonormality of the kept Ritz vectors: W^T (Q Q^T) W
+    launch_small_gemm(b, d(L.QQ), 0, d(L.Wm), 0, nullptr, d(L.M1), s);
+    launch_small_gemm(b, d(L.Wt), 0, d(L.M1), 0, nullptr, d(L.Pm), s);
+    std::vector<double> pm((size_t)b * b);
+    HIP_OK(hipMemcpyAsync(pm.data(), d(L.Pm), pm.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double oe = 0.0;
+    for (int i = 0; i < S.N; ++i)
+      for (int j = 0; j < S.N; ++j) oe = std::max(oe, std::fabs(pm[(size_t)i * b + j] - (i == j ? 1.0 : 0.0)));
+    info->iters = std::min(it, S.prm.max_iters);
+    info->converged = conv;
+    info->block = b;
+    info->reserved = 0;
+    info->max_resid = maxr;
+    info->orth_err = oe;
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  return ENVAR_OK;
+}
+
+extern "C" size_t envar_recon_bytes(int32_t N, int64_t m) {
+  if (N < 1 || m < 1) return 0;
+  return align256((size_t)N * 8) * 3 + align256((size_t)recon_blocks(m) * 16);
+}
+
+extern "C" int envar_recon_error(const double* E_dev, int32_t N, int64_t m, const double* f_dev, void* ws_dev,
+                                 size_t ws_bytes, double* out_dev, void* stream) {
+  if (N < 1 || m < 1) return fail(ENVAR_EINVAL, "N and m must be >= 1");
+  if (!E_dev || !f_dev || !ws_dev || !out_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  const size_t need = envar_recon_bytes(N, m);
+  if (ws_bytes < need) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t a = align256((size_t)N * 8);
+  double* ef = at<double>(ws_dev, 0);
+  double* ee = at<double>(ws_dev, a);
+  double* coef = at<double>(ws_dev, 2 * a);
+  double* part = at<double>(ws_dev, 3 * a);
+  launch_rowdot(E_dev, f_dev, N, (long)m, 1.0, nullptr, 0.0, ef, s);
+  launch_rowdot(E_dev, E_dev, N, (long)m, 1.0, nullptr, 0.0, ee, s, true);
+  launch_recon(E_dev, N, (long)m, f_dev, ef, ee, coef, part, out_dev, s);
+  HIP_OK(hipGetLastError());
+  return ENVAR_OK;
+}
+
 extern "C" size_t envar_posterior_bytes(int32_t n) {
   if (n < 1) return 0;
   return align256((size_t)n * n * 8) + 256;

@@ -279,6 +279,29 @@ void launch_shift_diag(const double* G, int n, double shift, double* H, const do
 int launch_spd_inverse(const double* H, int n, double* C, double* work, hipStream_t s);
 int launch_post_var(const double* ctrl, int n, long m, double eps, const double* C, double* var, hipStream_t s);
 // rows[0] = fe + sum_i w_i E_i, rows[1 + i] = rows[0] + eps E_i for i < nrows - 1
+// eigen-ensemble of the tapered Gaussian covariance (csrc/eigen.hip)
+void launch_eig_sigma(const int* bidx, int ncc, int nxb, int nyb, double h, double sig2max, int taper, double* sig,
+                      hipStream_t s);
+void launch_kernel1d(int n, double h, double a, double* K, hipStream_t s);
+void launch_eig_random(double* Q, int b, long M, const double* sig, unsigned long long seed, hipStream_t s);
+void launch_scale_rows(const double* Q, const double* sig, int rows, long M, double* W, hipStream_t s);
+void launch_dgemm(int M, int N, int K, const double* A, long lda, long sA, const double* B, long ldb, long sB,
+                  double* C, long ldc, long sC, int batch, const double* S, long lds, hipStream_t s);
+size_t jacobi_scratch_doubles(int n);
+int launch_jacobi(const double* A, int lda, int n, double* evals, double* W, double* Wt, double* scratch,
+                  hipStream_t s);
+void launch_small_gemm(int n, const double* A, int ta, const double* B, int tb, const double* d, double* C,
+                       hipStream_t s);
+void launch_eig_blocks(const double* G, int b, double* T, double* ZZ, double* QQ, hipStream_t s);
+void launch_eig_unit_gram(const double* P, int n, double* Gy, double* ninv, hipStream_t s);
+void launch_eig_rsqrt(const double* lam, int n, double* d, hipStream_t s);
+void launch_eig_resid(const double* U, const double* V, const double* theta, int N, long M, double* out,
+                      hipStream_t s);
+void launch_eig_extract(const double* U, const double* theta, int N, long M, const int* bidx, int ncc, int comp,
+                        double* E, double* mu, hipStream_t s);
+long recon_blocks(long m);
+void launch_recon(const double* E, int N, long m, const double* f, const double* ef, const double* ee, double* coef,
+                  double* part, double* out, hipStream_t s);
 // rows[t] = fe + sum_i W[t][i] E_i for t < nw
 void launch_combine_rows(const double* fe, const double* E, int n, long m, const double* W, int nw, double* rows,
                          hipStream_t s);

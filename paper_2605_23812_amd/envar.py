@@ -32,8 +32,10 @@ EXPORTS = (
     "envar_request_bytes", "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
     "envar_forward_obs", "envar_gn_bytes", "envar_gn_step", "envar_posterior_bytes", "envar_posterior_var",
     "envar_ens_bytes", "envar_ens_iterate",
+    "envar_eigen_bytes", "envar_eigen_ensemble", "envar_recon_bytes", "envar_recon_error",
 )
 GN, LBFGS = 0, 1
+TAPER_NONE, TAPER_ELLIPSE = 0, 1
 OBS_CHANNELS = 8  # four lid sensors x two velocity components
 
 
@@ -124,6 +126,22 @@ class EnsRecord(ctypes.Structure):
                 ("trial_rows", ctypes.c_int32)]
 
 
+class EigenParams(ctypes.Structure):
+    _fields_ = [
+        ("a_x", ctypes.c_double), ("a_y", ctypes.c_double), ("sigma2_max", ctypes.c_double), ("tol", ctypes.c_double),
+        ("taper", ctypes.c_int32), ("component", ctypes.c_int32), ("oversample", ctypes.c_int32),
+        ("max_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
+    ]
+
+
+class EigenInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("max_resid", ctypes.c_double), ("orth_err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 @dataclass
 class Problem:
     """Python mirror of envar_problem (fields <= 0 take the library defaults)."""
@@ -206,13 +224,20 @@ def lib():
     L.envar_ens_bytes.restype = sz
     L.envar_ens_iterate.argtypes = [P, vp, dp, dp, i32, i64, i32, ctypes.POINTER(EnsParams), dp, vp, sz,
                                     ctypes.POINTER(EnsRecord), vp]
+    L.envar_eigen_bytes.argtypes = [P, i32, ctypes.POINTER(EigenParams)]
+    L.envar_eigen_bytes.restype = sz
+    L.envar_eigen_ensemble.argtypes = [P, i32, ctypes.POINTER(EigenParams), dp, dp, vp, sz, ctypes.POINTER(EigenInfo),
+                                       vp]
+    L.envar_recon_bytes.argtypes = [i32, i64]
+    L.envar_recon_bytes.restype = sz
+    L.envar_recon_error.argtypes = [dp, i32, i64, dp, vp, sz, dp, vp]
     L.envar_last_error.restype = ctypes.c_char_p
     L.envar_version.restype = ctypes.c_char_p
     for name in ("envar_control_dim", "envar_cell_count", "envar_state_init", "envar_state_read",
                  "envar_spinup", "envar_forward", "envar_forward_batch", "envar_gradient", "envar_iterate",
                  "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
                  "envar_stream_copy", "envar_forward_obs", "envar_gn_step", "envar_posterior_var",
-                 "envar_ens_iterate"):
+                 "envar_ens_iterate", "envar_eigen_ensemble", "envar_recon_error"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -437,6 +462,49 @@ def posterior_var(controls, eps, H, ws=None):
     _check(lib().envar_posterior_var(_ptr(controls), n, m, float(eps), _ptr(H.contiguous()), _ptr(ws), ws.numel(),
                                      _ptr(var), _stream()))
     return var
+
+
+def eigen_params(a_x=0.07, a_y=0.07, sigma2_max=0.01, taper=TAPER_ELLIPSE, component=1, oversample=0, max_iters=0,
+                 tol=0.0, seed=0):
+    return EigenParams(a_x, a_y, sigma2_max, tol, taper, component, oversample, max_iters, seed)
+
+
+def eigen_bytes(p, N, prm=None):
+    prm = prm or eigen_params()
+    return lib().envar_eigen_bytes(ctypes.byref(p.c()), N, ctypes.byref(prm))
+
+
+def eigen_ensemble(p, N, ws=None, **kw):
+    """Deterministic eigen-ensemble: (E [N, m] device FP64 members, mu [N] eigenvalues of B, info)."""
+    import torch
+
+    prm = eigen_params(**kw)
+    if ws is None:
+        nb = eigen_bytes(p, N, prm)
+        if nb == 0:
+            _check(lib().envar_eigen_ensemble(ctypes.byref(p.c()), N, ctypes.byref(prm), None, None, None, 0, None,
+                                              _stream()))
+        ws = _bytes_tensor(nb)
+    m = control_dim(p)
+    E = torch.empty((N, m), dtype=torch.float64, device="cuda")
+    mu = torch.empty(N, dtype=torch.float64, device="cuda")
+    info = EigenInfo()
+    _check(lib().envar_eigen_ensemble(ctypes.byref(p.c()), N, ctypes.byref(prm), _ptr(E), _ptr(mu), _ptr(ws),
+                                      ws.numel(), ctypes.byref(info), _stream()))
+    return E, mu, info.as_dict()
+
+
+def recon_error(E, f, ws=None):
+    """Reconstruction error of f [m] in the span of the rows of E [N, m] (device; a 1-element tensor)."""
+    import torch
+
+    N, m = E.shape
+    if ws is None:
+        ws = _bytes_tensor(lib().envar_recon_bytes(N, m))
+    out = torch.empty(1, dtype=torch.float64, device=E.device)
+    _check(lib().envar_recon_error(_ptr(E.contiguous()), N, m, _ptr(f.contiguous()), _ptr(ws), ws.numel(), _ptr(out),
+                                   _stream()))
+    return out
 
 
 def ens_bytes(p, n, m, horizon, every=1):
