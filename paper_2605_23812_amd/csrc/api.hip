@@ -1990,7 +1990,7 @@ static EigLayout eig_layout(const EigSetup& S) {
   L.lam = take((size_t)b * 8);
   L.ninv = take((size_t)b * 8);
   L.dv = take((size_t)b * 8);
-  L.resid = take((size_t)b * 8);
+  L.resid = take((size_t)b * eig_resid_split() * 8);
   L.jac = take(std::max<size_t>(8, jacobi_scratch_doubles(b) * 8));
   L.total = o;
   return L;
@@ -2053,16 +2053,19 @@ extern "C" int envar_eigen_ensemble(const envar_problem* p, int32_t N, const env
     if (launch_jacobi(A, b, b, ev, Wc, Wr, d(L.jac), s)) return fail(ENVAR_EDEVICE, "Jacobi launch failed");
     return ENVAR_OK;
   };
-  // start block: random on the cells with sigma > 0, orthonormalised (Loewdin): Q = G^-1/2 Q0
+  auto chol_inv = [&](const double* G, double* Li) -> int {
+    if (launch_chol_inv(G, b, Li, d(L.jac), s)) return fail(ENVAR_EDEVICE, "Cholesky launch failed");
+    return ENVAR_OK;
+  };
+  // start block: random on the cells with sigma > 0, orthonormalised: Q = L^-1 Q0 with L L^T = Q0 Q0^T
   launch_eig_random(Z, b, M, sig, S.prm.seed ? S.prm.seed : 0x5EEDull, s);
   launch_gram<double>(Z, b, M, M, d(L.partial), L.nsplit, L.kchunk, s);
   launch_gram_reduce(d(L.partial), b, L.nsplit, d(L.tmp), d(L.Gy), s);
-  if ((rc = jacobi(d(L.Gy), d(L.lam), d(L.Pg), d(L.Pgt)))) return rc;
-  launch_eig_rsqrt(d(L.lam), b, d(L.dv), s);
-  launch_small_gemm(b, d(L.Pg), 0, d(L.Pgt), 0, d(L.dv), d(L.Sm), s);
+  if ((rc = chol_inv(d(L.Gy), d(L.Sm)))) return rc;
   launch_dgemm(b, (int)M, b, d(L.Sm), b, 0, Z, M, 0, Q, M, 0, 1, nullptr, 0, s);
   HIP_OK(hipGetLastError());
-  std::vector<double> th(b), res(S.N);
+  const int rsplit = eig_resid_split();
+  std::vector<double> th(b), res((size_t)S.N * rsplit);
   int it = 0;
   bool conv = false;
   double maxr = 0.0;
@@ -2075,10 +2078,14 @@ extern "C" int envar_eigen_ensemble(const envar_problem* p, int32_t N, const env
     launch_dgemm(b, (int)M, b, d(L.Wt), b, 0, Q, M, (long)b * M, U, M, (long)b * M, 2, nullptr, 0, s);
     launch_eig_resid(U, Vv, d(L.theta), S.N, M, d(L.resid), s);
     HIP_OK(hipMemcpyAsync(th.data(), d(L.theta), (size_t)b * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(res.data(), d(L.resid), (size_t)S.N * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(res.data(), d(L.resid), res.size() * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     maxr = 0.0;
-    for (int k = 0; k < S.N; ++k) maxr = std::max(maxr, res[k]);
+    for (int k = 0; k < S.N; ++k) {
+      double r2 = 0.0;
+      for (int q = 0; q < rsplit; ++q) r2 += res[(size_t)k * rsplit + q];
+      maxr = std::max(maxr, std::sqrt(r2));
+    }
     maxr = th[0] > 0.0 ? maxr / th[0] : INFINITY;
     if (!std::isfinite(maxr)) return fail(ENVAR_EDIVERGED, "non-finite Ritz values at iteration %d", it);
     if (maxr <= S.prm.tol) {
@@ -2086,14 +2093,12 @@ extern "C" int envar_eigen_ensemble(const envar_problem* p, int32_t N, const env
       break;
     }
     if (it == S.prm.max_iters) break;
-    // next Q: Loewdin orthonormalisation of the unit-norm rows of V = W^T Z,
-    // Q = Gy^-1/2 Dn^-1 W^T Z with P = W^T (Z Z^T) W, Dn = diag(P)^1/2, Gy = Dn^-1 P Dn^-1
+    // next Q: Cholesky orthonormalisation of the unit-norm rows of V = W^T Z (in decreasing Ritz
+    // value), Q = L^-1 Dn^-1 W^T Z with P = W^T (Z Z^T) W, Dn = diag(P)^1/2, L L^T = Dn^-1 P Dn^-1
     launch_small_gemm(b, d(L.ZZ), 0, d(L.Wm), 0, nullptr, d(L.M1), s);
     launch_small_gemm(b, d(L.Wt), 0, d(L.M1), 0, nullptr, d(L.Pm), s);
     launch_eig_unit_gram(d(L.Pm), b, d(L.Gy), d(L.ninv), s);
-    if ((rc = jacobi(d(L.Gy), d(L.lam), d(L.Pg), d(L.Pgt)))) return rc;
-    launch_eig_rsqrt(d(L.lam), b, d(L.dv), s);
-    launch_small_gemm(b, d(L.Pg), 0, d(L.Pgt), 0, d(L.dv), d(L.Sm), s);
+    if ((rc = chol_inv(d(L.Gy), d(L.Sm)))) return rc;
     launch_small_gemm(b, d(L.Sm), 0, d(L.Wt), 0, d(L.ninv), d(L.Cm), s);
     launch_dgemm(b, (int)M, b, d(L.Cm), b, 0, Z, M, 0, Q, M, 0, 1, nullptr, 0, s);
     HIP_OK(hipGetLastError());

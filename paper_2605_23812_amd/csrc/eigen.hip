@@ -11,10 +11,11 @@
 // iteration. Per iteration, with Q [b][M] orthonormal rows:
 //   Z = B Q;  G = [Q; Z][Q; Z]^T (MFMA Gram);  T = sym(Q Z^T) = W diag(theta) W^T (Jacobi);
 //   U = W^T Q, V = W^T Z (Ritz vectors and their images), residuals |V_k - theta_k U_k|;
-//   next Q = the symmetric (Loewdin) orthonormalisation of V with rows scaled to unit norm, formed
-//   from the b x b blocks of G without another pass over M.
-// The b x b symmetric eigenproblems are solved by cyclic Jacobi in one workgroup (parallel
-// round-robin ordering, A and the rotations in LDS up to b = 96).
+//   next Q = the Cholesky orthonormalisation of V with rows scaled to unit norm (rows in decreasing
+//   Ritz value), formed from the b x b blocks of G without another pass over M.
+// The b x b symmetric eigenproblem is solved by cyclic Jacobi in one workgroup (parallel round-robin
+// ordering, the matrix and the rotations in LDS up to b = 96); the Cholesky factor and its inverse
+// also in one workgroup.
 #include "common.h"
 #include "kernels.h"
 
@@ -122,10 +123,11 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, const double
 
 // ---------------------------------------------------------------------------- b x b work
 // Cyclic Jacobi for a symmetric n x n matrix in one workgroup: n (padded to even) indices in n - 1
-// rounds of n / 2 disjoint pairs (round-robin), each round a rotation angle per pair, then the row
-// and the column rotations (and the eigenvector columns). Stops when the off-diagonal Frobenius norm
-// is below 1e-15 of the diagonal's. Outputs the eigenvalues in decreasing order, W with eigenvector
-// k in column k, and its transpose Wt.
+// rounds of n / 2 disjoint pairs (round-robin), each round a rotation angle per pair, then J^T A J
+// in one pass over the 2 x 2 blocks of pair pairs (and the eigenvector columns). A pair is rotated unless |a_pq| is below
+// n ulp of sqrt(|a_pp a_qq|) or of the largest diagonal entry; the iteration ends before a sweep in
+// which no pair would rotate. Outputs the eigenvalues in decreasing order, W with eigenvector k in column k, and its
+// transpose Wt.
 constexpr int JAC_LDS_MAX = 96;
 constexpr int JAC_MAX = 512;
 
@@ -143,88 +145,96 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ Ain,
                                                  double* __restrict__ evals, double* __restrict__ W,
                                                  double* __restrict__ Wt, double* __restrict__ gscratch) {
   extern __shared__ double dyn[];
-  __shared__ double cs[JAC_MAX];
-  __shared__ double dg[JAC_MAX];
+  __shared__ double cs[JAC_MAX];  // (c, s) per pair; the sorted diagonal at the end
+  __shared__ int pq[JAC_MAX];     // (p, q) per pair
   __shared__ int rk[JAC_MAX];
-  __shared__ double red[2][16];
-  const int tid = threadIdx.x;
+  __shared__ double red[16];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int ne = n + (n & 1);
+  const int ld = ne + 1;  // odd row stride: a column walk touches every LDS bank
   double* A = ne <= JAC_LDS_MAX ? dyn : gscratch;
-  double* V = A + (long)ne * ne;
-  const int nn = ne * ne;
-  for (int e = tid; e < nn; e += 1024) {
-    const int i = e / ne, j = e % ne;
-    A[e] = (i < n && j < n) ? Ain[(long)i * lda + j] : 0.0;
-    V[e] = i == j ? 1.0 : 0.0;
-  }
+  double* V = A + (long)ne * ld;
+  for (int i = wave; i < ne; i += 16)
+    for (int j = lane; j < ne; j += 64) {
+      A[i * ld + j] = (i < n && j < n) ? Ain[(long)i * lda + j] : 0.0;
+      V[i * ld + j] = i == j ? 1.0 : 0.0;
+    }
+  if (tid == 0) rotated = 0;
   __syncthreads();
   const int half = ne / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int e = tid; e < nn; e += 1024) {
-      const double v = A[e];
-      if (e / ne == e % ne)
-        dia += v * v;
-      else
-        off += v * v;
-    }
-    off = wave_sum(off);
-    dia = wave_sum(dia);
-    if ((tid & 63) == 0) {
-      red[0][tid >> 6] = off;
-      red[1][tid >> 6] = dia;
+    // largest |diagonal| of this sweep: the absolute floor of the rotation test
+    double dmax = 0.0;
+    for (int k = tid; k < ne; k += 1024) dmax = fmax(dmax, fabs(A[k * ld + k]));
+    dmax = wave_max(dmax);
+    if (lane == 0) red[wave] = dmax;
+    __syncthreads();
+    dmax = 0.0;
+    for (int w = 0; w < 16; ++w) dmax = fmax(dmax, red[w]);
+    // skip the sweep when no pair would rotate (a converged matrix costs one scan, not a sweep)
+    const double tol = ne * 1.1102230246251565e-16;
+    for (int e = tid; e < ne * ne; e += 1024) {
+      const int i = e / ne, j = e % ne;
+      const double a = fabs(A[i * ld + j]);
+      if (i != j && a > tol * dmax && a > tol * sqrt(fabs(A[i * ld + i] * A[j * ld + j]))) rotated = 1;
     }
     __syncthreads();
-    off = 0.0;
-    dia = 0.0;
-    for (int w = 0; w < 16; ++w) {
-      off += red[0][w];
-      dia += red[1][w];
-    }
+    const int need = rotated;
     __syncthreads();
-    if (!(off > 1e-30 * dia)) break;  // also stops on a zero matrix
+    if (tid == 0) rotated = 0;
+    if (!need) break;
     for (int t = 0; t < ne - 1; ++t) {
       if (tid < half) {
         int p, q;
         jac_pair(t, tid, ne, p, q);
-        const double apq = A[p * ne + q];
+        const double apq = A[p * ld + q];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double th = (A[q * ne + q] - A[p * ne + p]) / (2.0 * apq);
+        // rotate unless a_pq is at the rounding level (n ulp) of sqrt(|a_pp a_qq|) or of the largest
+        // diagonal entry (the floor for pairs of near-zero eigenvalues)
+        if (fabs(apq) > tol * dmax && fabs(apq) > tol * sqrt(fabs(A[p * ld + p] * A[q * ld + q]))) {
+          const double th = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
           const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
           c = 1.0 / sqrt(1.0 + tt * tt);
           s = tt * c;
         }
         cs[2 * tid] = c;
         cs[2 * tid + 1] = s;
+        pq[2 * tid] = p;
+        pq[2 * tid + 1] = q;
       }
       __syncthreads();
-      for (int e = tid; e < half * ne; e += 1024) {  // rows p, q <- J^T A
-        const int k = e / ne, j = e % ne;
-        int p, q;
-        jac_pair(t, k, ne, p, q);
-        const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double ap = A[p * ne + j], aq = A[q * ne + j];
-        A[p * ne + j] = c * ap - s * aq;
-        A[q * ne + j] = s * ap + c * aq;
+      // A <- J^T A J block by block: the 2 x 2 block of rows (p, q) of pair a and columns (p', q') of
+      // pair b only needs its own four old entries, so rows and columns rotate in one pass
+      for (int e = tid; e < half * half; e += 1024) {
+        const int a = e / half, bb = e % half;
+        const int p = pq[2 * a], q = pq[2 * a + 1], r = pq[2 * bb], u = pq[2 * bb + 1];
+        const double c1 = cs[2 * a], s1 = cs[2 * a + 1], c2 = cs[2 * bb], s2 = cs[2 * bb + 1];
+        const double apr = A[p * ld + r], apu = A[p * ld + u], aqr = A[q * ld + r], aqu = A[q * ld + u];
+        // rows: (p, q) <- (c1 p - s1 q, s1 p + c1 q)
+        const double bpr = c1 * apr - s1 * aqr, bpu = c1 * apu - s1 * aqu;
+        const double bqr = s1 * apr + c1 * aqr, bqu = s1 * apu + c1 * aqu;
+        // columns: (r, u) <- (c2 r - s2 u, s2 r + c2 u)
+        A[p * ld + r] = c2 * bpr - s2 * bpu;
+        A[p * ld + u] = s2 * bpr + c2 * bpu;
+        A[q * ld + r] = c2 * bqr - s2 * bqu;
+        A[q * ld + u] = s2 * bqr + c2 * bqu;
       }
-      __syncthreads();
-      for (int e = tid; e < half * ne; e += 1024) {  // columns p, q <- A J, V J
-        const int k = e / ne, i = e % ne;
-        int p, q;
-        jac_pair(t, k, ne, p, q);
+      for (int k = wave; k < half; k += 16) {  // eigenvector columns p, q <- V J
+        const int p = pq[2 * k], q = pq[2 * k + 1];
         const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double ap = A[i * ne + p], aq = A[i * ne + q];
-        A[i * ne + p] = c * ap - s * aq;
-        A[i * ne + q] = s * ap + c * aq;
-        const double vp = V[i * ne + p], vq = V[i * ne + q];
-        V[i * ne + p] = c * vp - s * vq;
-        V[i * ne + q] = s * vp + c * vq;
+        if (s == 0.0) continue;
+        for (int i = lane; i < ne; i += 64) {
+          const double vp = V[i * ld + p], vq = V[i * ld + q];
+          V[i * ld + p] = c * vp - s * vq;
+          V[i * ld + q] = s * vp + c * vq;
+        }
       }
       __syncthreads();
     }
   }
-  for (int k = tid; k < n; k += 1024) dg[k] = A[k * ne + k];
+  double* dg = cs;
+  for (int k = tid; k < n; k += 1024) dg[k] = A[k * ld + k];
   __syncthreads();
   for (int k = tid; k < n; k += 1024) {
     const double lk = dg[k];
@@ -234,11 +244,79 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ Ain,
     evals[r] = lk;
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += 1024) {
-    const int i = e / n, k = e % n;
-    const double v = V[i * ne + k];
-    W[(long)i * n + rk[k]] = v;
-    Wt[(long)rk[k] * n + i] = v;
+  for (int i = wave; i < n; i += 16)
+    for (int k = lane; k < n; k += 64) {
+      const double v = V[i * ld + k];
+      W[(long)i * n + rk[k]] = v;
+      Wt[(long)rk[k] * n + i] = v;
+    }
+}
+
+// Cholesky G = L L^T and Linv = L^-1 for an n x n SPD matrix in one workgroup (in LDS up to
+// n = 96). Factor: one barrier per column, the trailing update from the unscaled column
+// (a_ij -= a_ik a_jk / a_kk), the columns scaled at the end. Inverse: forward substitution on the
+// identity, one barrier per row, rows scaled at the end. A pivot below 1e-20 of the largest diagonal
+// entry drops its direction (that row of Linv is 0).
+__global__ __launch_bounds__(1024) void k_chol_inv(const double* __restrict__ G, int n, double* __restrict__ Linv,
+                                                   double* __restrict__ gscratch) {
+  extern __shared__ double dyn[];
+  __shared__ double piv[JAC_MAX];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ld = n + 1;
+  double* A = n <= JAC_LDS_MAX ? dyn : gscratch;
+  double* X = A + (long)n * ld;
+  double dm = 0.0;
+  for (int i = wave; i < n; i += 16)
+    for (int j = lane; j < n; j += 64) {
+      const double g = G[(long)i * n + j];
+      A[i * ld + j] = g;
+      X[i * ld + j] = i == j ? 1.0 : 0.0;
+      if (i == j) dm = fmax(dm, fabs(g));
+    }
+  dm = wave_max(dm);
+  if (lane == 0) red[wave] = dm;
+  __syncthreads();
+  dm = 0.0;
+  for (int w = 0; w < 16; ++w) dm = fmax(dm, red[w]);
+  const double floor_ = 1e-20 * dm;
+  for (int k = 0; k < n; ++k) {
+    const double akk = A[k * ld + k];
+    const bool ok = akk > floor_;
+    if (tid == 0) piv[k] = ok ? akk : 0.0;
+    if (ok) {
+      const double inv = 1.0 / akk;
+      const int m = n - k - 1;
+      for (int e = tid; e < m * m; e += 1024) {  // lower triangle of the trailing block
+        const int i = k + 1 + e / m, j = k + 1 + e % m;
+        if (j <= i) A[i * ld + j] -= A[i * ld + k] * A[j * ld + k] * inv;
+      }
+    }
+    __syncthreads();
+  }
+  // L = lower(A) with column k scaled by 1 / sqrt(piv_k); rows of dropped pivots are zero
+  for (int i = wave; i < n; i += 16)
+    for (int j = lane; j <= i; j += 64) {
+      const double pj = piv[j];
+      A[i * ld + j] = pj > 0.0 ? A[i * ld + j] / sqrt(pj) : 0.0;
+    }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {  // rows i > k of X -= L_ik / L_kk * X_k (X_k not yet scaled)
+    const double lkk = A[k * ld + k];
+    if (lkk > 0.0) {
+      const double inv = 1.0 / lkk;
+      const int m = n - k - 1;
+      for (int e = tid; e < m * (k + 1); e += 1024) {
+        const int i = k + 1 + e / (k + 1), c = e % (k + 1);
+        X[i * ld + c] -= A[i * ld + k] * inv * X[k * ld + c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = wave; i < n; i += 16) {
+    const double lii = A[i * ld + i];
+    for (int c = lane; c < n; c += 64)
+      Linv[(long)i * n + c] = (lii > 0.0 && c <= i) ? X[i * ld + c] / lii : 0.0;
   }
 }
 
@@ -290,22 +368,26 @@ __global__ void k_eig_rsqrt(const double* __restrict__ lam, int n, double* __res
     d[k] = lam[k] > 1e-14 * lam[0] ? 1.0 / sqrt(lam[k]) : 0.0;
 }
 
-// |V_k - theta_k U_k| for k < N (one workgroup per k)
+// partial sums of |V_k - theta_k U_k|^2 for k < N over EIG_RSPLIT slices of M (workgroup (k, slice));
+// the host adds the slices in order
+constexpr int EIG_RSPLIT = 16;
 __global__ __launch_bounds__(256) void k_eig_resid(const double* __restrict__ U, const double* __restrict__ V,
                                                    const double* __restrict__ theta, long M,
                                                    double* __restrict__ out) {
   __shared__ double red[4];
-  const int k = blockIdx.x;
+  const int k = blockIdx.x / EIG_RSPLIT, sl = blockIdx.x % EIG_RSPLIT;
   const double th = theta[k];
+  const long chunk = (M + EIG_RSPLIT - 1) / EIG_RSPLIT;
+  const long i0 = sl * chunk, i1 = i0 + chunk < M ? i0 + chunk : M;
   double s = 0.0;
-  for (long i = threadIdx.x; i < M; i += 256) {
+  for (long i = i0 + threadIdx.x; i < i1; i += 256) {
     const double r = V[(long)k * M + i] - th * U[(long)k * M + i];
     s += r * r;
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[k] = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
+  if (threadIdx.x == 0) out[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // control rows E[k] (component `comp` = U_k sqrt(theta_k (N - 1)) on the region's cells, other
@@ -407,21 +489,34 @@ void launch_dgemm(int M, int N, int K, const double* A, long lda, long sA, const
 }
 size_t jacobi_scratch_doubles(int n) {
   const int ne = n + (n & 1);
-  return ne <= JAC_LDS_MAX ? 0 : 2 * (size_t)ne * ne;
+  return ne <= JAC_LDS_MAX ? 0 : 2 * (size_t)ne * (ne + 1);
 }
 int launch_jacobi(const double* A, int lda, int n, double* evals, double* W, double* Wt, double* scratch,
                   hipStream_t s) {
   if (n < 1 || n > JAC_MAX) return -1;
   const int ne = n + (n & 1);
-  const size_t dyn = ne <= JAC_LDS_MAX ? 2 * (size_t)ne * ne * sizeof(double) : 0;
+  const size_t dyn = ne <= JAC_LDS_MAX ? 2 * (size_t)ne * (ne + 1) * sizeof(double) : 0;
   static bool attr = false;
   if (!attr) {
     if (hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            2 * JAC_LDS_MAX * JAC_LDS_MAX * (int)sizeof(double)) != hipSuccess)
+                            2 * JAC_LDS_MAX * (JAC_LDS_MAX + 1) * (int)sizeof(double)) != hipSuccess)
       return -2;
     attr = true;
   }
   hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), dyn, s, A, lda, n, 40, evals, W, Wt, scratch);
+  return 0;
+}
+int launch_chol_inv(const double* G, int n, double* Linv, double* scratch, hipStream_t s) {
+  if (n < 1 || n > JAC_MAX) return -1;
+  const size_t dyn = n <= JAC_LDS_MAX ? 2 * (size_t)n * (n + 1) * sizeof(double) : 0;
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * JAC_LDS_MAX * (JAC_LDS_MAX + 1) * (int)sizeof(double)) != hipSuccess)
+      return -2;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), dyn, s, G, n, Linv, scratch);
   return 0;
 }
 void launch_small_gemm(int n, const double* A, int ta, const double* B, int tb, const double* d, double* C,
@@ -439,8 +534,9 @@ void launch_eig_rsqrt(const double* lam, int n, double* d, hipStream_t s) {
 }
 void launch_eig_resid(const double* U, const double* V, const double* theta, int N, long M, double* out,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_eig_resid, dim3(N), dim3(256), 0, s, U, V, theta, M, out);
+  hipLaunchKernelGGL(k_eig_resid, dim3(N * EIG_RSPLIT), dim3(256), 0, s, U, V, theta, M, out);
 }
+int eig_resid_split() { return EIG_RSPLIT; }
 void launch_eig_extract(const double* U, const double* theta, int N, long M, const int* bidx, int ncc, int comp,
                         double* E, double* mu, hipStream_t s) {
   hipLaunchKernelGGL(k_eig_extract, dim3(grid_for((long)N * ncc)), dim3(256), 0, s, U, theta, N, M, bidx, ncc, comp,

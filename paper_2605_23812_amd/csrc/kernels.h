@@ -290,6 +290,7 @@ void launch_dgemm(int M, int N, int K, const double* A, long lda, long sA, const
 size_t jacobi_scratch_doubles(int n);
 int launch_jacobi(const double* A, int lda, int n, double* evals, double* W, double* Wt, double* scratch,
                   hipStream_t s);
+int launch_chol_inv(const double* G, int n, double* Linv, double* scratch, hipStream_t s);
 void launch_small_gemm(int n, const double* A, int ta, const double* B, int tb, const double* d, double* C,
                        hipStream_t s);
 void launch_eig_blocks(const double* G, int b, double* T, double* ZZ, double* QQ, hipStream_t s);
@@ -297,6 +298,7 @@ void launch_eig_unit_gram(const double* P, int n, double* Gy, double* ninv, hipS
 void launch_eig_rsqrt(const double* lam, int n, double* d, hipStream_t s);
 void launch_eig_resid(const double* U, const double* V, const double* theta, int N, long M, double* out,
                       hipStream_t s);
+int eig_resid_split();  // slices per residual (partial sums of squares [N][slices])
 void launch_eig_extract(const double* U, const double* theta, int N, long M, const int* bidx, int ncc, int comp,
                         double* E, double* mu, hipStream_t s);
 long recon_blocks(long m);
