@@ -270,6 +270,60 @@ def eigen_ensemble(torch, E):
     return out
 
 
+def paper_geometry(torch, E, inputs):
+    """The paper's configuration (channel height 1/2, uniform inflow, slip top and outer lower wall,
+    y-only forcing on the actuation window): the batched mixed forward at the benchmark shape
+    (65 members, h = 1/128, 200 steps), and a regime check at h = 1/64 for Re = 6250 and 14000 (one
+    member from rest plus noise, 40 time units of spin-up, then the lid sensors over 20 time units:
+    rms of the transverse velocity and the dominant frequency of the most downstream sensor)."""
+    window = (1.25 - 0.32, 1.25 + 0.15, -0.60, 0.15)
+    out = {}
+    pm = E.Problem(inv_h=INV_H, Re=6250.0, precision=E.MIXED, geometry=E.CAVITY_PAPER, region=E.REGION_BOX,
+                   box=window)
+    u0, v0 = inputs.initial_field(INV_H, amp=1e-3, geometry="paper")
+    state = E.state_init(pm, u0, v0)
+    E.spinup(pm, state, 2000)
+    m = E.control_dim(pm)
+    rng = np.random.default_rng(11)
+    rows = np.zeros((N_MEMBERS + 1, m))
+    rows[1:, m // 2:] = 1e-2 * rng.standard_normal((N_MEMBERS, m // 2))
+    ctrl = torch.tensor(rows, device="cuda")
+    ws = E._bytes_tensor(E.workspace_bytes(pm, N_MEMBERS + 1))
+    E.forward(pm, state, ctrl, 20, ws=ws, stats=False)
+    torch.cuda.synchronize()
+    t = time.time()
+    _, _, st = E.forward(pm, state, ctrl, 200, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    ncells = E.cell_count(pm)
+    out["cells"] = ncells
+    out["mixed_batched_cell_steps_per_s"] = round(ncells * (N_MEMBERS + 1) * 200 / dt, 1)
+    out["mean_vcycles_per_step"] = round(st["mean_cycles"], 3)
+    regimes = []
+    n = 64
+    for Re in (6250.0, 14000.0):
+        p = E.Problem(inv_h=n, Re=Re, precision=E.FP64, geometry=E.CAVITY_PAPER, region=E.REGION_BOX, box=window)
+        u0, v0 = inputs.initial_field(n, amp=1e-2, geometry="paper")
+        stt = E.state_init(p, u0, v0)
+        steps_per_unit = int(round(1.0 / (0.064 / n)))
+        t = time.time()
+        E.spinup(p, stt, 40 * steps_per_unit)
+        every = 10
+        horizon = 20 * steps_per_unit
+        _, series, _ = E.forward_obs(p, stt, torch.zeros((1, E.control_dim(p)), dtype=torch.float64, device="cuda"),
+                                     horizon, every)
+        torch.cuda.synchronize()
+        s = series.cpu().numpy()[0]
+        vy = s[7] - s[7].mean()  # v at the most downstream sensor
+        spec = np.abs(np.fft.rfft(vy)) ** 2
+        freq = np.fft.rfftfreq(vy.size, d=every * 0.064 / n)
+        k = int(np.argmax(spec[1:])) + 1
+        regimes.append({"Re": Re, "inv_h": n, "sensor_v_rms": float(np.sqrt(np.mean(vy ** 2))),
+                        "dominant_frequency": float(freq[k]), "seconds": round(time.time() - t, 2)})
+    out["regimes"] = regimes
+    return out
+
+
 def gram_sweep(torch, E):
     """Anomaly reduction (Gram X X^T on the matrix cores, Cholesky, X^T c) timed on the device.
 
@@ -535,6 +589,8 @@ def main():
         log("EnVar loop", extra["ens_loop_fp64"])
         extra["eigen_ensemble"] = eigen_ensemble(torch, E)
         log("eigen ensemble", extra["eigen_ensemble"])
+        extra["paper_geometry"] = paper_geometry(torch, E, inputs)
+        log("paper geometry", extra["paper_geometry"])
 
     serve = None
     if not args.no_serve:

@@ -49,7 +49,12 @@ enum {
   ENVAR_ETIMEOUT = 7     /* envar_wait timed out */
 };
 
-enum { ENVAR_CAVITY = 0, ENVAR_CHANNEL = 1 };
+/* ENVAR_CAVITY_PAPER: the configuration of Sec. 2 (Table tabgeometry) with the boundary
+ * conditions of Sec. 4.4 on this grid: a channel of height 1/2 over the unit cavity (NY =
+ * inv_h + inv_h / 2), uniform inflow u = 1, a symmetry (slip) top wall, a lower wall that is no-slip
+ * for x_cav - 0.4 <= x <= x_cav + 1.75 and slip beyond, no-slip cavity walls; the outlet keeps the
+ * convective condition, with the inflow's bulk speed 1. */
+enum { ENVAR_CAVITY = 0, ENVAR_CHANNEL = 1, ENVAR_CAVITY_PAPER = 2 };
 /* Control regions (cells whose centre lies inside):
  *  COLUMN: x in [x_cav, x_cav + 1], all y (cavity + channel column above it), 2 / h^2 cells
  *  CAVITY: the cavity cells only, 1 / h^2 cells
@@ -65,7 +70,7 @@ enum { ENVAR_FP64 = 0, ENVAR_MIXED = 1 };
 /* One forward problem, passed by value-pointer; fields <= 0 take defaults. */
 typedef struct {
   int32_t inv_h;       /* 1/h; a multiple of 16 (cavity aligned down to h = 1/4) */
-  int32_t geometry;    /* ENVAR_CAVITY | ENVAR_CHANNEL */
+  int32_t geometry;    /* ENVAR_CAVITY | ENVAR_CHANNEL | ENVAR_CAVITY_PAPER */
   int32_t region;      /* ENVAR_REGION_* */
   int32_t precision;   /* ENVAR_FP64 | ENVAR_MIXED */
   double Re;           /* U D / nu with U = inflow centreline speed, D = cavity depth (Sec. 2) */

@@ -26,6 +26,10 @@ What it computes, and where the paper defines it:
               Hessian_EnVar, eq. update_Newton) and the posterior variance
               (eq. posterior_covariance_matrix), and the EnVar loop over w with
               the Gauss-Newton or L-BFGS update (eq. update_Newton, update_BFGS).
+* ``geometry`` also carries the paper's configuration (Sec. 2, Table
+              tabgeometry, boundary conditions of Sec. 4.4): channel height
+              1/2, uniform inflow, symmetry top, slip lower wall outside the
+              no-slip segments next to the cavity.
 * ``eigen``   the deterministic eigen-ensemble of Sec. 3.3.2: the tapered
               Gaussian covariance B of eq. (covarianceB) with the parameters of
               Sec. 4.2, its leading eigenpairs by a dense symmetric
@@ -47,5 +51,8 @@ update; for ``eigen``: the two-point closed form, the Kronecker spectrum of a
 uniform-variance rectangle, E E^T / (N - 1) = B with every mode kept and the
 Eckart-Young error when truncated, the taper's centre, corners and symmetry,
 the separable product against the dense B, and the limits of the
-reconstruction error.
+reconstruction error; for the paper geometry: the viscous term of a uniform
+stream on each kind of wall (0 on slip walls, -2 nu / h^2 on no-slip ones,
+-nu / h^2 over the cavity) and a short forward that stays divergence-free with
+the free stream kept at the symmetry top.
 """

@@ -8,7 +8,12 @@ x in [0, L] x y in [0, 1] over a square cavity x in [x_cav, x_cav + 1] x
 y in [-1, 0], lengths scaled by the cavity depth D = 1 (Re = U D / nu, Sec. 2).
 Two test geometries reuse the same operators: a plain channel (no cavity, for
 the plane Poiseuille pin) and a doubly periodic box [0, 2 pi]^2 (for the
-Taylor-Green pins).
+Taylor-Green pins). The "paper" geometry takes the configuration of Sec. 2 and
+the boundary conditions of Sec. 4.4 as far as they differ from the simplified
+one: a channel of height H = 0.5 (Table tabgeometry) over the unit cavity, a
+uniform inflow u = 1, a symmetry (slip) top wall, and a lower wall that is
+no-slip only on L_1,slip = 0.4 upstream and L_2,slip = 0.75 downstream of the
+cavity and slip beyond (Fig. cavity_tikz); the cavity walls are no-slip.
 
 Layout (all arrays are numpy, y-row major, x fastest):
   cells   (NY, NX)      cell (i, j) centre ((i + 1/2) h, y0 + (j + 1/2) h)
@@ -23,6 +28,10 @@ import numpy as np
 
 SOLID, ACTIVE, WALL, INFLOW, OUTFLOW = 0, 1, 2, 3, 4
 
+PAPER_HEIGHT = 0.5       # H of Table tabgeometry
+PAPER_NOSLIP_UP = 0.4    # L_1,slip: no-slip lower wall for x_cav - 0.4 <= x <= x_cav
+PAPER_NOSLIP_DOWN = 0.75  # L_2,slip: no-slip lower wall for x_cav + 1 <= x <= x_cav + 1.75
+
 
 class Grid:
     """Uniform MAC grid of spacing h = 1/inv_h (2 pi / inv_h when periodic)."""
@@ -34,13 +43,16 @@ class Grid:
         if geometry == "periodic":
             self.h = 2.0 * np.pi / n
             self.NX, self.NY, self.y0 = n, n, 0.0
-        elif geometry in ("cavity", "channel"):
+        elif geometry in ("cavity", "channel", "paper"):
             self.h = 1.0 / n
             self.NX = int(round(length * n))
             if abs(self.NX - length * n) > 1e-9:
                 raise ValueError("channel length must be a multiple of h")
-            if geometry == "cavity":
-                self.NY, self.y0 = 2 * n, -1.0
+            if geometry in ("cavity", "paper"):
+                height = 1.0 if geometry == "cavity" else PAPER_HEIGHT
+                if (n * height) % 1 != 0:
+                    raise ValueError("the channel height must be a multiple of h")
+                self.NY, self.y0 = n + int(n * height), -1.0
                 self.ic0 = int(round(x_cav * n))
                 if abs(self.ic0 - x_cav * n) > 1e-9:
                     raise ValueError("cavity edge must lie on a grid line")
@@ -58,7 +70,7 @@ class Grid:
         self.xc = (np.arange(NX) + 0.5) * h
         self.yc = self.y0 + (np.arange(NY) + 0.5) * h
         fluid = np.ones((NY, NX), dtype=bool)
-        if geometry == "cavity":
+        if geometry in ("cavity", "paper"):
             below = self.yc < 0.0
             inside = (np.arange(NX) >= self.ic0) & (np.arange(NX) < self.ic1)
             fluid[below, :] = False
@@ -102,11 +114,30 @@ class Grid:
         self.ucls, self.vcls = ucls, vcls
         self.ncells = int(fluid.sum())
 
+        # sign of the mirrored u value across a wall parallel to x (the u face beyond is SOLID or
+        # outside the box): -1 no-slip (u = 0 half a cell away), +1 slip (du/dy = 0)
+        self.mirror_S = -np.ones((NY, NX + 1))
+        self.mirror_N = -np.ones((NY, NX + 1))
+        self.inflow = "parabola"
+        self.u_convective = 2.0 / 3.0  # bulk speed of the parabola 4 y (1 - y)
+        if geometry == "paper":
+            self.inflow = "uniform"
+            self.u_convective = 1.0
+            self.mirror_N[NY - 1, :] = 1.0  # symmetry top
+            jc = n  # first channel row
+            xs0, xs1 = x_cav - PAPER_NOSLIP_UP, x_cav + 1.0 + PAPER_NOSLIP_DOWN
+            for i in range(NX + 1):
+                x = i * h
+                if (x < xs0 or x > xs1) and ucls[jc - 1, i] == SOLID:
+                    self.mirror_S[jc, i] = 1.0
+
     # ------------------------------------------------------------------ inflow
     def inflow_profile(self):
-        """Parabolic inflow u = 4 y (1 - y), unit centreline speed, on the x = 0 faces."""
+        """Inflow on the x = 0 faces: the parabola u = 4 y (1 - y) (unit centreline speed), or
+        u = 1 (the paper geometry's uniform inflow, Sec. 4.4)."""
         y = self.yc
-        return np.where(self.ucls[:, 0] == INFLOW, 4.0 * y * (1.0 - y), 0.0)
+        prof = np.ones_like(y) if self.inflow == "uniform" else 4.0 * y * (1.0 - y)
+        return np.where(self.ucls[:, 0] == INFLOW, prof, 0.0)
 
 
 def control_cells(grid, region="column", box=None):

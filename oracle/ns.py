@@ -13,13 +13,16 @@ on a finite-element mesh, is replaced by an explicit scheme on a uniform grid):
 
   T^n   = -div_h(u u)^n + nu lap_h u^n                      (active faces)
   u*    = u^n + dt (3/2 T^n - 1/2 T^{n-1} + F)               (AB2; T^{-1} = T^0 on a cold start)
-  u*_b  = u^n_b - dt U_c (u^n_b - u^n_{b-1}) / h             (outflow faces, U_c = 2/3)
+  u*_b  = u^n_b - dt U_c (u^n_b - u^n_{b-1}) / h             (outflow faces, U_c = the inflow's
+                                                             bulk speed: 2/3 parabola, 1 uniform)
   L_h phi = div_h u* / dt                                    (sparse direct LU)
   u^{n+1} = u* - dt grad_h phi                               (active and outflow faces)
 
 Neighbour rules at an active face: a stored face value (active, wall = 0,
 inflow, outflow) is used as is; a SOLID face or one outside the box mirrors the
-own value with a sign flip (no-slip wall half a cell away); the v value beyond
+own value with a sign flip (no-slip wall half a cell away), or without one across
+a slip wall (the paper geometry's symmetry top and outer lower wall, du/dy = 0);
+the v value beyond
 the outflow copies the own value (zero normal gradient of the tangential
 velocity at the outlet, as the paper's outlet condition of Sec. 4.4).
 Poisson: homogeneous Neumann on walls and inflow, phi = 0 on the outflow face
@@ -31,7 +34,6 @@ import scipy.sparse.linalg as spla
 
 from .geometry import ACTIVE, INFLOW, OUTFLOW, SOLID, WALL
 
-U_CONVECTIVE = 2.0 / 3.0  # bulk velocity of the parabola 4y(1-y)
 
 
 # --------------------------------------------------------------------------- neighbours
@@ -43,11 +45,12 @@ def _neighbours_bounded(g, u, v):
     uE = np.zeros_like(u)
     uW[:, 1:] = u[:, :-1]
     uE[:, :-1] = u[:, 1:]
-    # y neighbours: mirror when the neighbour face is SOLID or outside the box
-    uS = -u.copy()
-    uN = -u.copy()
-    uS[1:, :] = np.where(g.ucls[:-1, :] == SOLID, -u[1:, :], u[:-1, :])
-    uN[:-1, :] = np.where(g.ucls[1:, :] == SOLID, -u[:-1, :], u[1:, :])
+    # y neighbours: mirror when the neighbour face is SOLID or outside the box, with the sign of
+    # the wall (no-slip -u, slip +u)
+    uS = g.mirror_S * u
+    uN = g.mirror_N * u
+    uS[1:, :] = np.where(g.ucls[:-1, :] == SOLID, g.mirror_S[1:, :] * u[1:, :], u[:-1, :])
+    uN[:-1, :] = np.where(g.ucls[1:, :] == SOLID, g.mirror_N[:-1, :] * u[:-1, :], u[1:, :])
     # v at the four corners of a u face (i, j): v[j][i-1], v[j][i], v[j+1][i-1], v[j+1][i]
     vSW = np.zeros_like(u)
     vSE = np.zeros_like(u)
@@ -325,7 +328,7 @@ def step(g, poisson, st, nu, dt, Fu=None, Fv=None):
         vs[g.NY, :] = vs[0, :]
     else:
         ob = g.ucls[:, -1] == OUTFLOW
-        us[ob, -1] = u[ob, -1] - dt * U_CONVECTIVE * (u[ob, -1] - u[ob, -2]) / g.h
+        us[ob, -1] = u[ob, -1] - dt * g.u_convective * (u[ob, -1] - u[ob, -2]) / g.h
     un, vn, phi = project(g, poisson, us, vs, dt)
     return State(un, vn, Tu, Tv), phi, us, vs
 

@@ -84,7 +84,7 @@ struct Plan {
 // be an active face (it is for the cavity geometry).
 static void make_sensors(Plan& P) {
   const Geo& g = P.lev[0];
-  P.obs_ok = P.p.geometry == ENVAR_CAVITY;
+  P.obs_ok = P.p.geometry == ENVAR_CAVITY || P.p.geometry == ENVAR_CAVITY_PAPER;
   if (!P.obs_ok) return;
   const double h = g.h, y0 = -1.0;
   for (int s = 0; s < 4; ++s) {
@@ -113,8 +113,12 @@ static Geo make_geo(int n, int geometry, double x_cav) {
   g.n = n;
   g.nx = 4 * n;
   g.h = 1.0 / n;
-  if (geometry == ENVAR_CAVITY) {
-    g.ny = 2 * n;
+  g.slip_top = 0;
+  g.slip_i0 = -1;
+  g.slip_i1 = 1 << 30;
+  g.uconv = 2.0 / 3.0;  // bulk speed of the parabola 4 y (1 - y)
+  if (geometry == ENVAR_CAVITY || geometry == ENVAR_CAVITY_PAPER) {
+    g.ny = geometry == ENVAR_CAVITY ? 2 * n : n + n / 2;
     g.jc = n;
     g.ic0 = (int)std::lround(x_cav * n);
     g.ic1 = g.ic0 + n;
@@ -122,6 +126,17 @@ static Geo make_geo(int n, int geometry, double x_cav) {
     g.ny = n;
     g.jc = 0;
     g.ic0 = g.ic1 = 0;
+  }
+  if (geometry == ENVAR_CAVITY_PAPER) {
+    // symmetry top; lower wall no-slip for x_cav - 0.4 <= x <= x_cav + 1.75, slip beyond
+    g.slip_top = 1;
+    g.uconv = 1.0;
+    const double xs0 = x_cav - 0.4, xs1 = x_cav + 1.0 + 0.75;
+    for (int i = 0; i <= g.nx; ++i) {
+      const double x = i * g.h;
+      if (x < xs0) g.slip_i0 = i;
+      if (x > xs1 && g.slip_i1 > g.nx) g.slip_i1 = i;
+    }
   }
   g.pitch = ((g.nx + 1 + 15) / 16) * 16;
   g.rows = g.ny + 1;
@@ -134,7 +149,7 @@ static int make_plan(const envar_problem* pin, Plan& P) {
   envar_problem& p = P.p;
   if (p.inv_h < 16 || p.inv_h % 16 != 0 || p.inv_h > 2048)
     return fail(ENVAR_EINVAL, "inv_h must be a multiple of 16 in [16, 2048], got %d", p.inv_h);
-  if (p.geometry != ENVAR_CAVITY && p.geometry != ENVAR_CHANNEL)
+  if (p.geometry != ENVAR_CAVITY && p.geometry != ENVAR_CHANNEL && p.geometry != ENVAR_CAVITY_PAPER)
     return fail(ENVAR_EINVAL, "unknown geometry %d", p.geometry);
   if (p.precision != ENVAR_FP64 && p.precision != ENVAR_MIXED)
     return fail(ENVAR_EINVAL, "unknown precision %d", p.precision);
@@ -184,7 +199,7 @@ static int make_plan(const envar_problem* pin, Plan& P) {
     for (int i = 0; i < g.nx; ++i) {
       if (!g.fluid(i, j)) continue;
       const double x = (i + 0.5) * g.h;
-      const double y = (p.geometry == ENVAR_CAVITY ? -1.0 : 0.0) + (j + 0.5) * g.h;
+      const double y = (p.geometry == ENVAR_CHANNEL ? 0.0 : -1.0) + (j + 0.5) * g.h;
       bool in = false;
       if (p.region == ENVAR_REGION_COLUMN)
         in = x > p.x_cav && x < p.x_cav + 1.0;
@@ -1082,7 +1097,8 @@ int envar_state_init(const envar_problem* p, const double* u, const double* v, c
   const long pl = g.plane();
   const int NX = g.nx, NY = g.ny;
   std::vector<double> bu(pl, 0.0), bv(pl, 0.0), btu(pl, 0.0), btv(pl, 0.0), bphi(pl, 0.0);
-  const double y0 = p->geometry == ENVAR_CAVITY ? -1.0 : 0.0;
+  const double y0 = p->geometry == ENVAR_CHANNEL ? 0.0 : -1.0;
+  const bool uniform = p->geometry == ENVAR_CAVITY_PAPER;  // the paper geometry's uniform inflow
   for (int j = 0; j < NY; ++j)
     for (int i = 0; i <= NX; ++i) {
       const bool w = g.fluid(i - 1, j), e = g.fluid(i, j);
@@ -1091,7 +1107,7 @@ int envar_state_init(const envar_problem* p, const double* u, const double* v, c
       else if (i == NX && w) val = u[(size_t)j * (NX + 1) + i];
       else if (i == 0 && e) {
         const double y = y0 + (j + 0.5) * g.h;
-        val = 4.0 * y * (1.0 - y);
+        val = uniform ? 1.0 : 4.0 * y * (1.0 - y);
       }
       if (!std::isfinite(val)) return fail(ENVAR_EINVAL, "non-finite u at (%d, %d)", i, j);
       bu[g.at(i, j)] = val;

@@ -30,7 +30,6 @@ constexpr int COARSE_N = 16; // levels with inv_h <= 16 run inside one workgroup
 constexpr int MAX_LEVELS = 12;
 constexpr int MAX_COARSE_UNKNOWNS = 128;
 constexpr int COARSE_INV_MAX = 8192;  // LDS budget for the coarsest inverse (nc^2 doubles)
-constexpr double U_CONVECTIVE = 2.0 / 3.0;  // bulk speed of the 4y(1-y) inflow
 
 struct Geo {
   int nx, ny;    // bounding box in cells
@@ -40,6 +39,10 @@ struct Geo {
   int rows;      // rows per plane
   int n;         // cells per unit length at this level
   double h;
+  // momentum boundary kinds (finest level): slip top wall, slip lower channel wall for u faces
+  // i <= slip_i0 or i >= slip_i1, convective outflow speed (the inflow's bulk speed)
+  int slip_top, slip_i0, slip_i1;
+  double uconv;
 
   __host__ __device__ __forceinline__ long plane() const { return (long)pitch * rows; }
   __host__ __device__ __forceinline__ long at(int i, int j) const { return (long)j * pitch + i; }
@@ -54,6 +57,13 @@ struct Geo {
   // v face (i, j) lies between cells (i, j-1) and (i, j)
   __host__ __device__ __forceinline__ bool v_solid(int i, int j) const {
     return !(fluid(i, j - 1) || fluid(i, j));
+  }
+  // sign of the mirrored u across the SOLID u face (i, jn) next to an active face: -1 no-slip
+  // (u = 0 half a cell away), +1 slip (du/dy = 0)
+  __host__ __device__ __forceinline__ double u_wall_sign(int i, int jn) const {
+    if (jn >= ny) return slip_top ? 1.0 : -1.0;
+    if (jn == jc - 1 && (i <= slip_i0 || i >= slip_i1)) return 1.0;
+    return -1.0;
   }
   // number of Poisson neighbours (+2 for the Dirichlet outflow face)
   __host__ __device__ __forceinline__ int diag_count(int i, int j) const {

@@ -10,7 +10,8 @@
 //   b     = div_h u* / dt                      (Poisson right-hand side)
 //   u^{n+1} = u* - dt grad_h phi               (active and outflow faces; phi = 0 on the outflow face)
 // Neighbour rules: a wall face holds 0, a face with no fluid cell on either
-// side mirrors the own value (no-slip wall half a cell away), the v value
+// side mirrors the own value (no-slip wall half a cell away; without the sign
+// flip across a slip wall), the v value
 // west of the inflow mirrors (v = 0 at the inlet) and east of the outflow
 // copies (zero normal gradient of v at the outlet).
 //
@@ -240,8 +241,8 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
       const bool owned = (c < TW) || (i == g.nx);
       if (w && e) {
         const TT uc = (TT)uo, uE = (TT)SU(i + 1, j), uW = (TT)SU(i - 1, j);
-        const TT uN = g.u_solid(i, j + 1) ? -uc : (TT)SU(i, j + 1);
-        const TT uS = g.u_solid(i, j - 1) ? -uc : (TT)SU(i, j - 1);
+        const TT uN = g.u_solid(i, j + 1) ? (TT)g.u_wall_sign(i, j + 1) * uc : (TT)SU(i, j + 1);
+        const TT uS = g.u_solid(i, j - 1) ? (TT)g.u_wall_sign(i, j - 1) * uc : (TT)SU(i, j - 1);
         const TT vSW = (TT)SV(i - 1, j), vSE = (TT)SV(i, j), vNW = (TT)SV(i - 1, j + 1), vNE = (TT)SV(i, j + 1);
         const TT adv = ((uc + uE) * (uc + uE) - (uW + uc) * (uW + uc)) * inv4h +
                        ((uc + uN) * (vNW + vNE) - (uS + uc) * (vSW + vSE)) * inv4h;
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
           a.tu[off + at] = T;
         }
       } else if (w && i == g.nx) {
-        us = uo - dt * U_CONVECTIVE * (uo - SU(i - 1, j)) / g.h;
+        us = uo - dt * g.uconv * (uo - SU(i - 1, j)) / g.h;
         if (owned) a.us[off + g.at(i, j)] = us;
       } else {
         us = uo;  // wall (0) or inflow profile

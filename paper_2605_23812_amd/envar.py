@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libenvar.so")
 
 OK, EINVAL, ENOMEM, EDIVERGED, EDEVICE, EBUSY, ECANCELLED, ETIMEOUT = range(8)
-CAVITY, CHANNEL = 0, 1
+CAVITY, CHANNEL, CAVITY_PAPER = 0, 1, 2
 REGION_COLUMN, REGION_CAVITY, REGION_BOX = 0, 1, 2
 FP64, MIXED = 0, 1
 FLAG_TIME_KERNELS = 1
@@ -172,7 +172,7 @@ class Problem:
 
     def box_dims(self):
         n = self.inv_h
-        return (4 * n, 2 * n) if self.geometry == CAVITY else (4 * n, n)
+        return {CAVITY: (4 * n, 2 * n), CAVITY_PAPER: (4 * n, n + n // 2)}.get(self.geometry, (4 * n, n))
 
 
 _lib = None

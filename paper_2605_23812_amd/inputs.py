@@ -69,21 +69,25 @@ def grf_perturbations(n_members, inv_h, ell, sigma, seed=DEFAULT_SEED, region="c
 
 
 def box_dims(inv_h, geometry="cavity", length=4.0):
-    """(NX, NY, y0) of the bounding box of the MAC grid."""
+    """(NX, NY, y0) of the bounding box of the MAC grid ("paper": a channel of height 1/2 over the
+    unit cavity)."""
     n = int(inv_h)
     if geometry == "cavity":
         return int(round(length * n)), 2 * n, -1.0
+    if geometry == "paper":
+        return int(round(length * n)), n + n // 2, -1.0
     if geometry == "channel":
         return int(round(length * n)), n, 0.0
     raise ValueError(geometry)
 
 
 def initial_field(inv_h, amp=1e-3, seed=DEFAULT_SEED, geometry="cavity", length=4.0):
-    """(u0 (NY, NX+1), v0 (NY+1, NX)) raw initial face fields before boundary values."""
+    """(u0 (NY, NX+1), v0 (NY+1, NX)) raw initial face fields before boundary values: the inflow
+    profile (parabola, or uniform for "paper") in the channel plus seeded noise of size amp."""
     NX, NY, y0 = box_dims(inv_h, geometry, length)
     h = 1.0 / inv_h
     y = y0 + (np.arange(NY) + 0.5) * h
-    prof = np.where(y > 0.0, 4.0 * y * (1.0 - y), 0.0)
+    prof = np.where(y > 0.0, 1.0 if geometry == "paper" else 4.0 * y * (1.0 - y), 0.0)
     rng = _rng(seed, 1 << 20)
     u0 = prof[:, None] + amp * rng.standard_normal((NY, NX + 1))
     v0 = amp * rng.standard_normal((NY + 1, NX))

@@ -146,3 +146,60 @@ def test_iterate_armijo_invariants():
     rows = np.vstack([f0, f0 + pert])
     g = envar.gradient(rows, envar.forward(p, base, rows, 12))
     assert np.array_equal(h0["f"], f0 - h0["alpha"] * g)
+
+
+# ---------------------------------------------------------------------------- the paper's geometry
+def test_paper_geometry_wall_kinds_in_the_viscous_term():
+    """Sec. 2 / Sec. 4.4: H = 1/2, symmetry top, lower wall no-slip only on [x_cav - 0.4, x_cav + 1.75].
+    With u = 1 on the channel faces, 0 in the cavity and v = 0, the viscous term of the first channel
+    row is nu (uE + uW + uN + uS - 4 u) / h^2 with uS the cavity face (0) above the cavity, the mirrored
+    +1 on a slip wall and -1 on a no-slip wall; the top row sees a slip wall above (0)."""
+    from oracle import ns
+    from oracle.geometry import ACTIVE, Grid
+
+    n, x_cav, nu = 16, 1.25, 0.01
+    g = Grid(n, "paper", x_cav, 4.0)
+    assert g.NY == n + n // 2 and g.y0 == -1.0 and g.u_convective == 1.0
+    u = np.where((g.yc > 0.0)[:, None], 1.0, 0.0) * np.ones((g.NY, g.NX + 1))
+    v = np.zeros((g.NY + 1, g.NX))
+    Tu, _ = ns.tendency(g, u, v, nu)
+    h = g.h
+    jc = n
+    for i in range(2, g.NX - 1):  # interior faces of the first channel row (away from in/outflow)
+        x = i * h
+        if x_cav < x < x_cav + 1.0:
+            want = -1.0      # the cavity face below holds 0
+        elif x_cav - 0.4 <= x <= x_cav + 1.75:
+            want = -2.0      # no-slip: mirrored -1
+        else:
+            want = 0.0       # slip: mirrored +1
+        if abs(x - x_cav) < 1e-12 or abs(x - x_cav - 1.0) < 1e-12:
+            want = -1.0      # the faces on the cavity's side walls' top corners see the wall face (0)
+        assert g.ucls[jc, i] == ACTIVE
+        assert abs(Tu[jc, i] - nu * want / (h * h)) < 1e-9, (i, x, Tu[jc, i] * h * h / nu)
+    top = g.NY - 1
+    assert np.abs(Tu[top, 2:g.NX - 1]).max() < 1e-9  # symmetry top: no shear stress
+    prof = g.inflow_profile()
+    assert np.all(prof[g.yc > 0] == 1.0) and np.all(prof[g.yc < 0] == 0.0)
+
+
+def test_paper_geometry_forward_keeps_divergence_and_slip_top():
+    """A short forward in the paper geometry: discretely divergence-free; with the uniform inflow the
+    velocity at the symmetry top stays at the free-stream value while the no-slip segments slow it."""
+    from oracle import ns
+    from paper_2605_23812_amd import inputs
+
+    p = Problem(inv_h=16, Re=6250.0, geometry="paper")
+    u0, v0 = inputs.initial_field(16, amp=0.0, geometry="paper")
+    st = initial_state(p, u0, v0)
+    g, P = p.grid(), p.poisson()
+    for _ in range(20):
+        st, *_ = ns.step(g, P, st, p.nu, p.step_dt)
+    div = ns.divergence(g, st.u, st.v)
+    assert np.abs(div[g.fluid]).max() < 1e-10
+    top = st.u[g.NY - 1, 8:g.NX - 8]
+    assert np.abs(top - 1.0).max() < 0.05
+    jc = 16
+    i_ns = int(round((1.25 - 0.2) * 16))   # a no-slip face just upstream of the cavity
+    i_sl = int(round(0.4 * 16))            # a slip face near the inlet
+    assert st.u[jc, i_ns] < st.u[jc, i_sl]
