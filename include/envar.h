@@ -94,15 +94,18 @@ enum {
    * the steady steps (for comparisons; results are identical). */
   ENVAR_FLAG_NO_GRAPHS = 2,
   /* Tile heights. By default the first call for a (grid, geometry,
-   * precision, member count) times 8- and 16-row tiles for the predictor,
-   * the projection and every tiled multigrid level on the call's workspace
+   * precision, member count) times 8- and 16-row tiles for the predictor and
+   * the projection and 8-, 16- and 32-row tiles for every tiled multigrid
+   * level (32 where the cavity rows take whole tiles) on the call's workspace
    * (before the members are initialised) and keeps the fastest for the
    * process. The results do not depend on the choice (the cost partial sums
    * live on fixed 64 x 8 blocks; the multigrid windows reproduce the global
    * red-black sweep). These flags bypass the tuner: */
   ENVAR_FLAG_NO_TUNE = 4,   /* 8-row step tiles, 16-row multigrid tiles */
   ENVAR_FLAG_TILES_8 = 8,   /* 8 rows everywhere */
-  ENVAR_FLAG_TILES_16 = 16  /* 16 rows everywhere (step tiles only where the rows align) */
+  ENVAR_FLAG_TILES_16 = 16, /* 16 rows everywhere (step tiles only where the rows align) */
+  ENVAR_FLAG_TILES_32 = 32  /* 32-row multigrid tiles where the cavity rows take whole tiles
+                               (16 elsewhere), 16-row step tiles where the rows align */
 };
 
 /* Per-call statistics (filled only when a non-NULL pointer is passed; then the
@@ -126,7 +129,7 @@ typedef struct {
   double vcycle_us;        /* one full V-cycle (FP64) or refinement pass (MIXED) */
   int32_t timed_steps;
   int32_t timed_members;   /* members active in the timed cycle (all, unless converged before it) */
-  /* tile heights in use (8 | 16): predictor, projection, tiled multigrid levels 0..3 (0 = none) */
+  /* tile heights in use: predictor and projection 8 | 16, tiled multigrid levels 0..3 8 | 16 | 32 (0 = none) */
   int32_t rows_pred, rows_proj, rows_mg[4];
 } envar_stats;
 

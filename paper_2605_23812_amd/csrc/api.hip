@@ -56,8 +56,8 @@ struct Plan {
   int nlev_grid;        // levels run by the tiled kernels (inv_h > 16)
   int ncoarse;          // levels run by the LDS kernel (top inv_h <= 16 .. 4)
   Geo lev[MAX_LEVELS];  // lev[nlev_grid] is the top of the LDS part
-  Tiling mg_tl[2][MAX_LEVELS];  // [8 | 16 rows][level]
-  int mg_tiles[2][MAX_LEVELS];
+  Tiling mg_tl[3][MAX_LEVELS];  // [8 | 16 | 32 rows][level]
+  int mg_tiles[3][MAX_LEVELS];
   Tiling sk_tl[2];              // predictor / projection tiles, 8 | 16 rows
   int sk_tiles[2];
   bool rows16;                  // 16-row step tiles align with the cavity and channel rows
@@ -177,8 +177,8 @@ static int make_plan(const envar_problem* pin, Plan& P) {
   if (ntop != 16 || P.ncoarse != 3 || P.lev[nl].nx != 64 || P.lev[nl].ny > 32)
     return fail(ENVAR_EINVAL, "internal: the LDS levels must be 16, 8, 4 on a 64 x (<= 32) top box");
   for (int l = 0; l < nl; ++l)
-    for (int v = 0; v < 2; ++v) {
-      P.mg_tl[v][l] = Tiling::make(P.lev[l], v ? 16 : 8, MG_TW);
+    for (int v = 0; v < 3; ++v) {
+      P.mg_tl[v][l] = Tiling::make(P.lev[l], 8 << v, MG_TW);
       P.mg_tiles[v][l] = P.mg_tl[v][l].count();
     }
   const Geo& g = P.lev[0];
@@ -439,6 +439,7 @@ static Multi<A> seg_begin() {
 // Builders shared by the time step and the tile tuner. `rows` is the tile
 // height (8 or 16) of the launch; k is the V-cycle pass.
 static int vidx(int rows) { return rows == 16 ? 1 : 0; }
+static int mg_vidx(int rows) { return rows == 32 ? 2 : rows == 16 ? 1 : 0; }
 
 static PredArgs<double> pred_args(const Job& j, int rows, bool fused) {
   const Plan& P = j.P;
@@ -530,9 +531,9 @@ static MGArgs<T> level_args(const Job& j, int l, int k, int rows) {
   MGArgs<T> a{};
   a.g = P.lev[l];
   a.gc = P.lev[l + 1];
-  a.tiling = P.mg_tl[vidx(rows)][l];
+  a.tiling = P.mg_tl[mg_vidx(rows)][l];
   a.trows = rows;
-  a.ntiles = P.mg_tiles[vidx(rows)][l];
+  a.ntiles = P.mg_tiles[mg_vidx(rows)][l];
   a.nmem = j.nmem;
   a.plane = P.lev[l].plane();
   a.cplane_c = P.lev[l + 1].plane();
@@ -657,7 +658,7 @@ static ResidArgs resid_args(const Job& j, int k) {
 // phase, or 0 when the job has no work in it.
 template <typename A, typename RowsOf, typename Make, typename Launch>
 static void grouped(const std::vector<Job*>& J, RowsOf rows_of, Make make, Launch launch) {
-  for (int rows : {8, 16}) {
+  for (int rows : {8, 16, 32}) {
     auto m = seg_begin<A>();
     for (Job* j : J)
       if (rows_of(*j) == rows) {
@@ -1229,10 +1230,10 @@ static int tune_job(Job& j, hipStream_t s) {
   const Plan& P = j.P;
   const int fl = P.p.flags;
   TileChoice c;
-  if (fl & (ENVAR_FLAG_TILES_8 | ENVAR_FLAG_TILES_16)) {
-    const int r = (fl & ENVAR_FLAG_TILES_16) ? 16 : 8;
-    c.pred = c.proj = (r == 16 && P.rows16) ? 16 : 8;
-    for (int l = 0; l < MAX_LEVELS; ++l) c.mg[l] = r;
+  if (fl & (ENVAR_FLAG_TILES_8 | ENVAR_FLAG_TILES_16 | ENVAR_FLAG_TILES_32)) {
+    const int r = (fl & ENVAR_FLAG_TILES_32) ? 32 : (fl & ENVAR_FLAG_TILES_16) ? 16 : 8;
+    c.pred = c.proj = (r >= 16 && P.rows16) ? 16 : 8;
+    for (int l = 0; l < MAX_LEVELS; ++l) c.mg[l] = (r == 32 && l < P.nlev_grid && P.lev[l].jc % 32) ? 16 : r;
     apply_choice(j, c);
     return ENVAR_OK;
   }
@@ -1284,15 +1285,19 @@ static int tune_job(Job& j, hipStream_t s) {
   }
   for (int l = 0; l < P.nlev_grid; ++l) {
     const int k = (P.mixed && l == 0) ? 1 : 0;  // a first pass: no launch reads a convergence slot
-    float t[2];
-    for (int v = 0; v < 2; ++v) {
-      const int rows = v ? 16 : 8;
+    // 32-row tiles only where the cavity rows take whole tiles
+    const int nv = P.lev[l].jc % 32 == 0 ? 3 : 2;
+    float t[3];
+    int best = 0;
+    for (int v = 0; v < nv; ++v) {
+      const int rows = 8 << v;
       t[v] = timed([&] {
         launch_mg_pre<T>(one(pre_args<T>(j, l, k, rows)), s);
         launch_mg_post<T>(one(post_args<T>(j, l, 0, rows)), l == 0 && !P.mixed, s);
       });
+      if (t[v] < t[best]) best = v;
     }
-    c.mg[l] = t[0] < t[1] ? 8 : 16;
+    c.mg[l] = 8 << best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

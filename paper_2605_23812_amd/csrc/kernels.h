@@ -149,7 +149,7 @@ struct MGArgs {
   const unsigned char* code;   // this level: Poisson diagonal count of every cell (0 = not fluid), plane layout
   const unsigned char* codec;  // the coarser level
   Tiling tiling;
-  int trows;          // tile height of `tiling` (8 or 16): selects the kernel instance
+  int trows;          // tile height of `tiling` (8, 16 or 32): selects the kernel instance
   int ntiles, nmem;
   long plane, cplane_c;  // plane of this level and of the coarse level
   const T* phi_in;    // [nmem][plane] read (halo included); never written by this launch

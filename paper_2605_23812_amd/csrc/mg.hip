@@ -4,7 +4,7 @@
 // phi = 0 on the outflow face (mirror ghost -phi). The geometry is aligned on
 // every level down to h = 1/4, so each coarse cell has four fluid children.
 //
-// Per fine level and V-cycle two launches, both over (member, 64 x 8 or 64 x 16 tile):
+// Per fine level and V-cycle two launches, both over (member, 64-wide tile of 8, 16 or 32 rows):
 //   pre : load phi, b with a halo of 2 NS + 1 into LDS, NS red-black
 //         Gauss-Seidel sweeps over-relaxed by MG_OMEGA (temporal blocking: a sweep invalidates two
 //         halo rings), residual r = b - L phi, restriction b_c = mean of the
@@ -769,8 +769,10 @@ template <typename T, bool REF>
 static void launch_mg_pre_rows(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.seg[0].trows == 8)
     launch_mg_pre_<T, REF, 8>(m, s);
-  else
+  else if (m.seg[0].trows == 16)
     launch_mg_pre_<T, REF, 16>(m, s);
+  else
+    launch_mg_pre_<T, REF, 32>(m, s);
 }
 template <>
 void launch_mg_pre<double>(const Multi<MGArgs<double>>& m, hipStream_t s) {
@@ -793,17 +795,21 @@ static void launch_mg_post_(const Multi<MGArgs<T>>& m, hipStream_t s) {
 }
 template <typename T>
 void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s) {
-  const bool r8 = m.seg[0].trows == 8;
+  const int tr = m.seg[0].trows;
   if (write_norm) {
-    if (r8)
+    if (tr == 8)
       launch_mg_post_<T, 1, 8>(m, s);
-    else
+    else if (tr == 16)
       launch_mg_post_<T, 1, 16>(m, s);
-  } else {
-    if (r8)
-      launch_mg_post_<T, 0, 8>(m, s);
     else
+      launch_mg_post_<T, 1, 32>(m, s);
+  } else {
+    if (tr == 8)
+      launch_mg_post_<T, 0, 8>(m, s);
+    else if (tr == 16)
       launch_mg_post_<T, 0, 16>(m, s);
+    else
+      launch_mg_post_<T, 0, 32>(m, s);
   }
 }
 template <typename T>
