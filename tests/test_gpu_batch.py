@@ -2,7 +2,8 @@
 horizons advance together in merged launches (needs an MI355X).
 
 Each ensemble's costs must equal those of its own envar_forward call bitwise
-(per-member convergence, fixed-order reductions), in FP64 and in mixed precision.
+(per-member convergence, fixed-order reductions), in FP64 and in mixed precision,
+also when the jobs mix the simplified and the paper's cavity geometry.
 """
 import numpy as np
 import pytest
@@ -14,14 +15,16 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _job(n, Re, N, horizon, precision, seed):
-    p = E.Problem(inv_h=n, Re=Re, precision=precision)
-    p64 = E.Problem(inv_h=n, Re=Re)
-    u0, v0 = inputs.initial_field(n, amp=1e-3, seed=seed)
+def _job(n, Re, N, horizon, precision, seed, paper=False):
+    geo = dict(geometry=E.CAVITY_PAPER) if paper else {}
+    p = E.Problem(inv_h=n, Re=Re, precision=precision, **geo)
+    p64 = E.Problem(inv_h=n, Re=Re, **geo)
+    u0, v0 = inputs.initial_field(n, amp=1e-3, seed=seed, geometry="paper" if paper else "cavity")
     state = E.state_init(p64, u0, v0)
     E.spinup(p64, state, 30)
     m = E.control_dim(p)
-    rows = np.vstack([np.zeros(m), inputs.grf_perturbations(N - 1, n, 0.05, 5e-3, seed=seed)])
+    shape = (n + n // 2, n) if paper else None  # the column region spans the channel's height
+    rows = np.vstack([np.zeros(m), inputs.grf_perturbations(N - 1, n, 0.05, 5e-3, seed=seed, shape=shape)])
     return p, state, torch.tensor(rows, dtype=torch.float64, device="cuda"), horizon
 
 
@@ -40,6 +43,26 @@ def test_uneven_batch_equals_separate_forwards(precision):
         torch.cuda.synchronize()
         a, b = Jb.cpu().numpy(), Js.cpu().numpy()
         print("batch", p.inv_h, horizon, a, b, st["mean_cycles"], sts["mean_cycles"], flush=True)
+        assert np.array_equal(a, b)
+        assert st["unconverged"] == 0 and st["steps"] == horizon
+
+
+@pytest.mark.parametrize("precision", [E.FP64, E.MIXED])
+def test_batch_mixing_the_two_cavity_geometries(precision):
+    """Jobs of the simplified and of the paper's geometry (different heights, wall kinds, inflow and
+    outflow speed) share the merged launches and still equal their own forwards bitwise."""
+    jobs = [
+        _job(64, 6250.0, 4, 30, precision, 5, paper=True),
+        _job(64, 7500.0, 3, 25, precision, 6),
+        _job(32, 14000.0, 5, 41, precision, 7, paper=True),
+    ]
+    out = E.forward_batch(jobs)
+    torch.cuda.synchronize()
+    for (p, state, ctrl, horizon), (Jb, st) in zip(jobs, out):
+        Js, _, _ = E.forward(p, state, ctrl, horizon)
+        torch.cuda.synchronize()
+        a, b = Jb.cpu().numpy(), Js.cpu().numpy()
+        print("geometry", p.geometry, p.inv_h, a, b, flush=True)
         assert np.array_equal(a, b)
         assert st["unconverged"] == 0 and st["steps"] == horizon
 
