@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
       tpu[kk] = (TT)0;
       cmu[kk][0] = cmu[kk][1] = -1;
       if (k < TH * (TW + 1) && i <= g.nx && j < g.ny && g.fluid(i - 1, j) && g.fluid(i, j)) {
-        if (!cold) tpu[kk] = tup[g.at(i, j)];
+        if (!cold) tpu[kk] = __builtin_nontemporal_load(&tup[g.at(i, j)]);
         if (f) {
           cmu[kk][0] = a.cmap[g.at(i - 1, j)];
           cmu[kk][1] = a.cmap[g.at(i, j)];
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
       tpv[kk] = (TT)0;
       cmv[kk][0] = cmv[kk][1] = -1;
       if (k < (TH + 1) * TW && i < g.nx && j <= g.ny && g.fluid(i, j - 1) && g.fluid(i, j)) {
-        if (!cold) tpv[kk] = tvp[g.at(i, j)];
+        if (!cold) tpv[kk] = __builtin_nontemporal_load(&tvp[g.at(i, j)]);
         if (f) {
           cmv[kk][0] = a.cmap[g.at(i, j - 1)];
           cmv[kk][1] = a.cmap[g.at(i, j)];
@@ -138,10 +138,10 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
       if (FUSED && g.fluid(i, j)) {
         const long at = g.at(i, j), ac = (long)j * g.nx + i;
         if (a.phi_next) pn[rr] = a.phi_next[off + at];
-        if (a.phi_old) po[rr] = a.phi_old[off + at];
+        if (a.phi_old) po[rr] = __builtin_nontemporal_load(&a.phi_old[off + at]);
         if (a.s1u) {
-          s1a[rr] = a.s1u[coff + ac];
-          s1b[rr] = a.s1v[coff + ac];
+          s1a[rr] = __builtin_nontemporal_load(&a.s1u[coff + ac]);
+          s1b[rr] = __builtin_nontemporal_load(&a.s1v[coff + ac]);
           sha[rr] = a.shu[ac];
           shb[rr] = a.shv[ac];
         }
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
         double wn = order == 0 ? pc : 2.0 * pc - p1;
         if (a.phi_old) {
           if (order == 2) wn = 3.0 * (pc - p1) + po[rr];
-          a.phi_old[off + at] = p1;
+          __builtin_nontemporal_store(p1, &a.phi_old[off + at]);
         }
         a.phi_next[off + at] = wn;
       }
@@ -216,8 +216,8 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
         const long ac = (long)j * g.nx + i;  // dense cell index
         const double du = 0.5 * (uw + ue) - sha[rr];
         const double dv = 0.5 * (vsv + vn) - shb[rr];
-        a.s1u[coff + ac] = s1a[rr] + du;
-        a.s1v[coff + ac] = s1b[rr] + dv;
+        __builtin_nontemporal_store(s1a[rr] + du, &a.s1u[coff + ac]);
+        __builtin_nontemporal_store(s1b[rr] + dv, &a.s1v[coff + ac]);
         acc[rr >> 1] += du * du + dv * dv;  // row ty + 4 rr lies in cost block rr / 2
       }
     }
@@ -251,8 +251,8 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
         const TT Tp = cold ? T : tpu[kk];
         us = uo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + fu[kk]);
         if (owned) {
-          a.us[off + at] = us;
-          a.tu[off + at] = T;
+          __builtin_nontemporal_store(us, &a.us[off + at]);
+          __builtin_nontemporal_store(T, &a.tu[off + at]);
         }
       } else if (w && i == g.nx) {
         us = uo - dt * g.uconv * (uo - SU(i - 1, j)) / g.h;
@@ -287,8 +287,8 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
         const TT Tp = cold ? T : tpv[kk];
         vs = vo + dt * ((double)((TT)1.5 * T - (TT)0.5 * Tp) + fv[kk]);
         if (owned) {
-          a.vs[off + at] = vs;
-          a.tv[off + at] = T;
+          __builtin_nontemporal_store(vs, &a.vs[off + at]);
+          __builtin_nontemporal_store(T, &a.tv[off + at]);
         }
       } else {
         vs = vo;  // wall
