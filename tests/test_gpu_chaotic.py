@@ -1,0 +1,79 @@
+"""The chaotic configurations over horizons shorter than their predictability time (needs an MI355X;
+calls the C ABI through the binding).
+
+* the chaotic workload's grid and Reynolds number (h = 1/256, Re = 12000, 1024 x 256 channel cells
+  over a 256 x 256 cavity): the GPU forward in FP64 against the oracle at the 1e-10 bar and in mixed
+  precision at the 1e-6 bar, each side integrating its own spin-up;
+* the paper's geometry at Re = 14000, where the flow is unsteady at the sensors: after a spin-up of
+  20 convective times, FP64 and mixed precision keep the sensor series together pointwise over the
+  next 10 (a 1e-10 forcing perturbation grows by orders of magnitude over that time but stays far
+  below the signal), and the series' time means and standard deviations agree.
+"""
+import numpy as np
+import pytest
+
+from oracle import envar as OE
+from paper_2605_23812_amd import envar as E
+from paper_2605_23812_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("precision,tol", [(E.FP64, 1e-10), (E.MIXED, 1e-6)])
+def test_chaotic_configuration_h256_matches_oracle(precision, tol):
+    n, Re, spin, horizon = 256, 12000.0, 12, 6
+    op = OE.Problem(inv_h=n, Re=Re)
+    u0, v0 = inputs.initial_field(n, amp=1e-3)
+    _say("oracle spin-up at h = 1/256 ...")
+    st = OE.spinup(op, OE.initial_state(op, u0, v0), spin)
+    rows = np.vstack([np.zeros(op.m), inputs.grf_perturbations(1, n, 0.05, 5e-3, seed=21)])
+    p = E.Problem(inv_h=n, Re=Re, precision=precision)
+    state = E.state_init(E.Problem(inv_h=n, Re=Re), st.u, st.v, st.Tu_prev, st.Tv_prev)
+    J, F, stats = E.forward(p, state, torch.tensor(rows, device="cuda"), horizon, fields=True)
+    torch.cuda.synchronize()
+    J = J.cpu().numpy()
+    u, v = E.split_fields(p, F)
+    for i in range(rows.shape[0]):
+        Jr, sr = OE.forward_member(op, st, rows[i], horizon, return_state=True)
+        _say(" member", i, "J", J[i], "oracle", Jr, "rel", abs(J[i] - Jr) / abs(Jr),
+             "u", np.abs(u[i] - sr.u).max() / np.abs(sr.u).max())
+        assert abs(J[i] - Jr) <= tol * abs(Jr)
+        assert np.abs(u[i] - sr.u).max() <= tol * np.abs(sr.u).max()
+        assert np.abs(v[i] - sr.v).max() <= tol * np.abs(sr.u).max()
+    assert stats["unconverged"] == 0
+
+
+def test_paper_regime_re14000_fp64_and_mixed_before_divergence():
+    n, Re = 64, 14000.0
+    steps_per_unit = int(round(n / 0.064))
+    p64 = E.Problem(inv_h=n, Re=Re, geometry=E.CAVITY_PAPER)
+    pmx = E.Problem(inv_h=n, Re=Re, geometry=E.CAVITY_PAPER, precision=E.MIXED)
+    u0, v0 = inputs.initial_field(n, amp=1e-2, geometry="paper")
+    state = E.state_init(p64, u0, v0)
+    E.spinup(p64, state, 20 * steps_per_unit)
+    m = E.control_dim(p64)
+    rows = np.zeros((2, m))
+    rows[1, m // 2:] = 1e-10  # a tiny y-forcing: the growth of its effect gauges the sensitivity
+    ctrl = torch.tensor(rows, device="cuda")
+    every = 10
+    J64, S64, _ = E.forward_obs(p64, state, ctrl, 10 * steps_per_unit, every)
+    Jmx, Smx, _ = E.forward_obs(pmx, state, ctrl, 10 * steps_per_unit, every)
+    torch.cuda.synchronize()
+    a, c, b = S64.cpu().numpy()[0], S64.cpu().numpy()[1], Smx.cpu().numpy()[0]
+    std = a.std(axis=1)
+    scale = std.max()
+    d_mixed = np.abs(a - b).max(axis=0) / scale
+    d_pert = np.abs(a - c).max(axis=0) / scale
+    _say("sensor std", np.round(std, 4), "mixed vs FP64 max", d_mixed.max(), "perturbation first / last",
+         d_pert[0], d_pert[-1])
+    assert scale > 1e-2  # the sensors see an unsteady flow
+    assert d_mixed.max() <= 1e-6
+    assert d_pert[-1] > 100 * d_pert[0] and d_pert.max() < 1e-3  # growing, still far below the signal
+    assert np.abs(a.mean(axis=1) - b.mean(axis=1)).max() <= 1e-6 * scale
+    assert np.abs(std - b.std(axis=1)).max() <= 1e-6 * scale
+    assert abs(Jmx.cpu().numpy()[0] - J64.cpu().numpy()[0]) <= 1e-6 * J64.cpu().numpy()[0]
