@@ -214,7 +214,11 @@ size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
  * g = X^+ dJ = X^T (X X^T)^{-1} dJ (n <= m; n > m uses (X^T X)^{-1} X^T dJ).
  * The Gram X X^T runs on the matrix cores (FP64 MFMA, or FP32 MFMA with
  * precision = ENVAR_MIXED); the n x n solve is an FP64 Cholesky with a
- * relative ridge 1e-12 tr(G)/n. Errors: EINVAL (n < 1, m < 1), ENOMEM. */
+ * relative ridge 1e-12 tr(G)/n (a rank-deficient X, e.g. repeated members, then gives the
+ * minimum-norm solution up to that ridge). Synchronous (the solve is checked on the host).
+ * Errors: EINVAL (n < 1, m < 1, min(n, m) > 1024), ENOMEM, EDIVERGED (a pivot not positive
+ * after the ridge, or a non-finite solution, e.g. from a non-finite cost; g_dev is then
+ * undefined). */
 int envar_gradient(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
                    int32_t precision, void* ws_dev, size_t ws_bytes, double* g_dev, void* stream);
 

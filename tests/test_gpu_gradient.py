@@ -2,8 +2,9 @@
 
 g = X^+ dJ for X_i = f_i - f_0: compared with numpy.linalg.lstsq on the same
 seeded rows (FP64 MFMA: 1e-10 relative; FP32 MFMA: cosine >= 0.999999), for
-n <= m (Gram path) and n > m (normal-equation path), and the closed form of
-an antithetic quadratic cost.
+n <= m (Gram path) and n > m (normal-equation path), the closed form of
+an antithetic quadratic cost, repeated members (rank-deficient X: the
+minimum-norm solution) and a non-finite cost (reported, not returned).
 """
 import numpy as np
 import pytest
@@ -60,3 +61,32 @@ def test_gradient_exact_on_antithetic_quadratic():
     g = _run(rows, J, E.FP64)
     grad = Q @ f0 + b
     assert np.abs(g - grad).max() <= 1e-9 * np.abs(grad).max()
+
+
+@pytest.mark.parametrize("precision,tol", [(E.FP64, 1e-8), (E.MIXED, 1e-5)])
+def test_gradient_with_repeated_members_is_minimum_norm(precision, tol):
+    rng = np.random.default_rng(77)
+    n, m = 12, 3000
+    rows = rng.standard_normal((n + 1, m)) * 1e-2
+    rows[7] = rows[3]  # a repeated member with the same cost: X has rank n - 1
+    rows[11] = rows[2]
+    J = rng.standard_normal(n + 1)
+    J[7], J[11] = J[3], J[2]
+    g = _run(rows, J, precision)
+    X = rows[1:] - rows[0]
+    ref, *_ = np.linalg.lstsq(X, J[1:] - J[0], rcond=None)  # minimum-norm solution
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print("repeated members", precision, err, flush=True)
+    assert err <= tol
+
+
+def test_gradient_reports_a_non_finite_cost():
+    rng = np.random.default_rng(5)
+    rows = rng.standard_normal((9, 500)) * 1e-2
+    J = rng.standard_normal(9)
+    J[4] = np.nan
+    for precision in (E.FP64, E.MIXED):
+        with pytest.raises(E.EnvarError) as ei:
+            _run(rows, J, precision)
+        assert ei.value.code == E.EDIVERGED
+    assert np.all(np.isfinite(_run(rows[:4], J[:4], E.FP64)))  # the library still works
