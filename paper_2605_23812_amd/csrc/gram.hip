@@ -56,37 +56,82 @@ constexpr int GRAM_KC = 32;
 constexpr int GRAM_REDUCE_GROUP = 32;  // splits summed per group in the first reduction level
 
 template <typename TX>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float __attribute__((ext_vector_type(4))) T;
+};
+template <>
+struct Vec16<double> {
+  typedef double __attribute__((ext_vector_type(2))) T;
+};
+
+// Only the tile pairs bi <= bj are computed; an off-diagonal tile is written twice (as G[I][J] and
+// transposed as G[J][I]), so G is exactly symmetric. The X rows are fetched as 16-byte vectors into
+// registers one chunk ahead of the MFMA work on the chunk in LDS (a diagonal tile fetches its rows
+// once and uses them for both operands).
+template <typename TX>
 __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, long m, long ldx,
                                               double* __restrict__ partial, int nsplit, long kchunk, int nbt) {
   typedef typename MfmaAcc<TX>::V V;
+  typedef typename Vec16<TX>::T VT;
   constexpr int KC = GRAM_KC, LDR = KC + 1;
+  constexpr int VW = 16 / sizeof(TX);      // elements per vector
+  constexpr int VPR = KC / VW;             // vectors per row and chunk
+  constexpr int NV = 64 * VPR / 256;       // vectors per thread and operand
   __shared__ TX sa[64 * LDR];
   __shared__ TX sb[64 * LDR];
   const int split = blockIdx.x % nsplit;
-  const int pair = blockIdx.x / nsplit;
-  const int bi = pair / nbt, bj = pair % nbt;
+  int pair = blockIdx.x / nsplit;
+  int bi = 0;
+  while (pair >= nbt - bi) {
+    pair -= nbt - bi;
+    ++bi;
+  }
+  const int bj = bi + pair;
+  const bool diag = bi == bj;
   const int I0 = bi * 64, J0 = bj * 64;
   const long kbeg = (long)split * kchunk;
   long kend = kbeg + kchunk;
   if (kend > m) kend = m;
+  const bool vec = ldx % VW == 0;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  VT ra[NV], rb[NV];
+  auto load = [&](int row, long k) -> VT {
+    VT v;
+    if (row < n && vec && k + VW <= kend) return *(const VT*)(X + (long)row * ldx + k);
+    for (int e = 0; e < VW; ++e) v[e] = (row < n && k + e < kend) ? X[(long)row * ldx + k + e] : (TX)0;
+    return v;
+  };
+  auto fetch = [&](long k0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int q = threadIdx.x + 256 * v, r = q / VPR, c = (q % VPR) * VW;
+      ra[v] = load(I0 + r, k0 + c);
+      if (!diag) rb[v] = load(J0 + r, k0 + c);
+    }
+  };
   V acc[4];
   for (int t = 0; t < 4; ++t) acc[t] = V{0, 0, 0, 0};
+  if (kbeg < kend) fetch(kbeg);
   for (long k0 = kbeg; k0 < kend; k0 += KC) {
-    // stage 64 rows x KC columns of both row blocks (zero outside X)
-    for (int q = threadIdx.x; q < 64 * KC; q += 256) {
-      const int r = q / KC, c = q % KC;
-      const long k = k0 + c;
-      const int ra = I0 + r, rb = J0 + r;
-      sa[r * LDR + c] = (ra < n && k < kend) ? X[(long)ra * ldx + k] : (TX)0;
-      sb[r * LDR + c] = (rb < n && k < kend) ? X[(long)rb * ldx + k] : (TX)0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int q = threadIdx.x + 256 * v, r = q / VPR, c = (q % VPR) * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        sa[r * LDR + c + e] = ra[v][e];
+        if (!diag) sb[r * LDR + c + e] = rb[v][e];
+      }
     }
     __syncthreads();
+    if (k0 + KC < kend) fetch(k0 + KC);  // the next chunk's loads overlap this chunk's MFMA work
+    const TX* sB = diag ? sa : sb;
     const int row = 16 * wave + lane % 16;
     for (int kk = 0; kk < KC; kk += 4) {
       const TX a = sa[row * LDR + kk + lane / 16];
       for (int t = 0; t < 4; ++t) {
-        const TX b = sb[(16 * t + lane % 16) * LDR + kk + lane / 16];
+        const TX b = sB[(16 * t + lane % 16) * LDR + kk + lane / 16];
         acc[t] = MfmaAcc<TX>::mma(a, b, acc[t]);
       }
     }
@@ -97,7 +142,10 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
     const int j = J0 + 16 * t + lane % 16;
     for (int r = 0; r < 4; ++r) {
       const int i = I0 + 16 * wave + MfmaAcc<TX>::row(lane, r);
-      if (i < n && j < n) P[(long)i * n + j] = (double)acc[t][r];
+      if (i < n && j < n) {
+        P[(long)i * n + j] = (double)acc[t][r];
+        if (!diag) P[(long)j * n + i] = (double)acc[t][r];
+      }
     }
   }
 }
@@ -367,8 +415,8 @@ void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, d
 template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s) {
   const int nbt = (n + 63) / 64;
-  hipLaunchKernelGGL(k_gram<TX>, dim3(nsplit * nbt * nbt), dim3(256), 0, s, X, n, m, ldx, partial, nsplit, kchunk,
-                     nbt);
+  hipLaunchKernelGGL(k_gram<TX>, dim3(nsplit * nbt * (nbt + 1) / 2), dim3(256), 0, s, X, n, m, ldx, partial, nsplit,
+                     kchunk, nbt);
 }
 int gram_reduce_groups(int nsplit) { return (nsplit + GRAM_REDUCE_GROUP - 1) / GRAM_REDUCE_GROUP; }
 void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, double* G, hipStream_t s) {
