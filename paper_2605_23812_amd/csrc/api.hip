@@ -1576,7 +1576,8 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   if (n <= m) {
     launch_gram<TX>(X, n, m, m, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
     launch_gram_reduce(at<double>(ws, L.partial), n, L.nsplit, at<double>(ws, L.tmp), G, s);
-    launch_chol_solve(G, dJ, n, at<double>(ws, L.c), at<double>(ws, L.info), s);
+    if (launch_chol_solve(G, dJ, n, at<double>(ws, L.c), at<double>(ws, L.info), s))
+      return fail(ENVAR_EDEVICE, "Cholesky launch failed (n = %d)", n);
     launch_gemv_t<TX>(X, n, m, m, at<double>(ws, L.c), g, s);
   } else {
     TX* Xt = at<TX>(ws, L.Xt);
@@ -1585,7 +1586,8 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
     launch_gram_reduce(at<double>(ws, L.partial), (int)m, L.nsplit, at<double>(ws, L.tmp), G, s);
     double* rhs = at<double>(ws, L.rhs);
     launch_gemv_t<TX>(X, n, m, m, dJ, rhs, s);
-    launch_chol_solve(G, rhs, (int)m, g, at<double>(ws, L.info), s);
+    if (launch_chol_solve(G, rhs, (int)m, g, at<double>(ws, L.info), s))
+      return fail(ENVAR_EDEVICE, "Cholesky launch failed (m = %ld)", m);
   }
   HIP_OK(hipGetLastError());
   // a pivot that is not positive after the ridge (a non-finite Gram) or a non-finite solution
@@ -1678,7 +1680,8 @@ static int gn_step_impl(const double* series_dev, int n, long K, double eps, con
   launch_rowdot(w_dev, w_dev, 1, n, 0.5 * shift, nullptr, 0.0, jw_dev + 1, s);  // 1/2 (N - 1) |w|^2
   launch_shift_diag(G, n, shift, hgn_dev, grad, at<double>(ws, L.neg), s);
   HIP_OK(hipMemcpyAsync(at<double>(ws, L.Hc), hgn_dev, (size_t)n * n * 8, hipMemcpyDeviceToDevice, s));
-  launch_chol_solve(at<double>(ws, L.Hc), at<double>(ws, L.neg), n, dw_dev, at<double>(ws, L.info), s, 0.0);
+  if (launch_chol_solve(at<double>(ws, L.Hc), at<double>(ws, L.neg), n, dw_dev, at<double>(ws, L.info), s, 0.0))
+    return fail(ENVAR_EDEVICE, "Cholesky launch failed (n = %d)", n);
   HIP_OK(hipGetLastError());
   return ENVAR_OK;
 }

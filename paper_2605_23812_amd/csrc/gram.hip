@@ -8,8 +8,9 @@
 // operands, so it runs on MFMA (v_mfma_f64_16x16x4f64, or
 // v_mfma_f32_16x16x4f32 for FP32 operands) with a split over m and FP64
 // partials reduced in a fixed order (two levels). The n x n solve is an FP64
-// Cholesky in one workgroup (in LDS up to n = 128); the projection g = X^T c is
-// a bandwidth-bound GEMV with FP64 accumulation.
+// Cholesky in one workgroup (in the registers of one wave up to n = 64, in
+// 64-column panels up to n = 256); the projection g = X^T c is a
+// bandwidth-bound GEMV with FP64 accumulation.
 #include "common.h"
 #include "kernels.h"
 
@@ -173,34 +174,26 @@ __global__ void k_gram_reduce(const double* partial, int n, int nsplit, double* 
 
 // ---------------------------------------------------------------------------- FP64 Cholesky solve
 // Solves (G + ridge I) x = rhs, ridge = ridge_rel tr(G) / n, in one workgroup with
-// one barrier per column. At step k every thread updates its entries of the
-// trailing block with a_ik a_jk / a_kk from the still unscaled column k, so the
-// factor is kept as A~ (column k as it stood at step k, pivot d_k = A~_kk) and
-// G = A~ D^-1 A~^T, D = diag(d). The solves run right-looking on that form:
-// A~ z = rhs, then A~^T x = D z. Threads form a 32-wide grid over the trailing
-// block; thread j owns entry j of the vectors.
-// LDS (n <= CHOL_LDS_MAX): the matrix is staged in LDS with an odd row stride
-// (column reads hit distinct banks) and only the lower triangle is updated.
-// Otherwise it is updated in place in global memory (L2 resident for the sizes
-// allowed) as a full symmetric block, so that column k is read as row k.
-constexpr int CHOL_LDS_MAX = 128;
+// one barrier per column (the fallback for n > CHOL_BLK_MAX). At step k every thread
+// updates its entries of the trailing block with a_ik a_jk / a_kk from the still
+// unscaled column k, so the factor is kept as A~ (column k as it stood at step k,
+// pivot d_k = A~_kk) and G = A~ D^-1 A~^T, D = diag(d). The solves run right-looking
+// on that form: A~ z = rhs, then A~^T x = D z. Threads form a 32-wide grid over the
+// trailing block; thread j owns entry j of the vectors. The matrix is updated in place
+// in global memory (L2 resident for the sizes allowed) as a full symmetric block, so
+// that column k is read as row k.
 constexpr int CHOL_VEC_MAX = 1024;
 
-template <bool LDS, int NT>
-__global__ __launch_bounds__(NT) void k_chol_solve(double* G, const double* rhs, int n, double* x, int* info,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_chol_solve(double* A, const double* rhs, int n, double* x, int* info,
                                                    double ridge_rel) {
   constexpr int RS = NT / 32;
-  __shared__ double sA[LDS ? CHOL_LDS_MAX * (CHOL_LDS_MAX + 1) : 1];
   __shared__ double sv[CHOL_VEC_MAX];  // right-hand side, then z, then x
   __shared__ double sz[CHOL_VEC_MAX];
   __shared__ double sdi[CHOL_VEC_MAX];  // 1 / d_k
   __shared__ double ridge;
-  double* const A = LDS ? sA : G;
-  const long ld = LDS ? n + 1 : n;
+  const long ld = n;
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  if (LDS)
-    for (int i = ty; i < n; i += RS)
-      for (int j = tx; j < n; j += 32) sA[i * ld + j] = G[(long)i * n + j];
   for (int i = tid; i < n; i += NT) sv[i] = rhs[i];
   __syncthreads();
   if (tid == 0) {
@@ -216,16 +209,9 @@ __global__ __launch_bounds__(NT) void k_chol_solve(double* G, const double* rhs,
     const double akk = A[k * ld + k];
     if (tid == 0 && !(akk > 0.0)) *info = k + 1;
     const double inv = 1.0 / (akk > 0.0 ? akk : 1e-300);
-    if (LDS) {
-      for (int i = k + 1 + ty; i < n; i += RS) {
-        const double aik = A[i * ld + k] * inv;
-        for (int j = k + 1 + tx; j <= i; j += 32) A[i * ld + j] -= aik * A[j * ld + k];
-      }
-    } else {
-      for (int i = k + 1 + ty; i < n; i += RS) {
-        const double aik = A[k * ld + i] * inv;
-        for (int j = k + 1 + tx; j < n; j += 32) A[i * ld + j] -= aik * A[k * ld + j];
-      }
+    for (int i = k + 1 + ty; i < n; i += RS) {
+      const double aik = A[k * ld + i] * inv;
+      for (int j = k + 1 + tx; j < n; j += 32) A[i * ld + j] -= aik * A[k * ld + j];
     }
     __syncthreads();
   }
@@ -234,11 +220,11 @@ __global__ __launch_bounds__(NT) void k_chol_solve(double* G, const double* rhs,
     sdi[i] = 1.0 / (d > 0.0 ? d : 1e-300);
   }
   __syncthreads();
-  // A~ z = rhs (column k of A~ read as row k in the symmetric global form)
+  // A~ z = rhs (column k of A~ read as row k of the symmetric form)
   for (int k = 0; k < n; ++k) {
     const double zk = sv[k] * sdi[k];
     if (tid == 0) sz[k] = zk;
-    for (int i = k + 1 + tid; i < n; i += NT) sv[i] -= (LDS ? A[i * ld + k] : A[k * ld + i]) * zk;
+    for (int i = k + 1 + tid; i < n; i += NT) sv[i] -= A[k * ld + i] * zk;
     __syncthreads();
   }
   // A~^T x = D z: x_j = z_j - sum_{k>j} A~_kj x_k / d_j, right-looking over the rows of A~
@@ -296,7 +282,7 @@ __global__ __launch_bounds__(CHOL_BLK_NT) void k_chol_blocked(double* A, const d
     for (int r = ty; r < rows; r += RS)
       if (tx < kw) P[r * CHOL_PS + tx] = A[(k0 + r) * ld + k0 + tx];
     __syncthreads();
-    // the panel's columns one barrier each, all threads, unscaled (as in k_chol_solve):
+    // the panel's columns one barrier each, all threads, unscaled:
     // a_rj -= a_rc a_jc / a_cc for c < j <= r, j < kw; then column c scaled by 1 / sqrt(a_cc)
     for (int c = 0; c < kw; ++c) {
       const double d = P[c * CHOL_PS + c];
@@ -375,6 +361,355 @@ __global__ __launch_bounds__(CHOL_BLK_NT) void k_chol_blocked(double* A, const d
   for (int i = tid; i < n; i += CHOL_BLK_NT) x[i] = sv[i];
 }
 
+// ---------------------------------------------------------------------------- one-wave and 64-panel Cholesky
+// Same system, (G + ridge I) x = rhs, as the kernels above, through the plain
+// factor G + ridge I = L L^T.
+//
+// lane l's value of v (l wave-uniform), as a scalar
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// wave_chol64_panels factors a symmetric 64 x 64 block (the leading n x n part; the rest
+// is the identity, which stays the identity) held one column per lane of one wave,
+// b[i] = A[i][lane], in registers, with no workgroup barrier. Step k scales row k by
+// 1 / sqrt(a_kk) (l_j = a_kj / sqrt(a_kk), lanes j > k) and broadcasts it through LDS,
+// and every lane j > k subtracts l_i l_j from its entries i > k; lanes j <= k multiply
+// by zero instead of branching, so that a step is one basic block and the next pivot's
+// chain overlaps the updates. The fused product is the same for (i, j) and (j, i), so
+// the trailing block stays exactly symmetric, and the next pivot is lane k + 1's own
+// diagonal update, bit for bit the value the update loop leaves, read without LDS.
+// The steps run as a loop over panels of eight (unrolled within a panel): straight-line
+// code for all 64 steps is some 60 KB, executed once, and runs at the speed of
+// instruction fetch. After a panel the finished rows go to LDS and the column shifts
+// down by eight, so register indices stay static (rows past 63 are zero and take
+// broadcasts of zero); only ceil(n / 8) panels run. On return sT[k * 64 + j] holds lane
+// j's entry of row k after step k: L[j][k] for j > k, the pivot for j = k, and for j < k
+// the trailing entry A^(j)[k][j], so that L[k][j] = sT[k][j] * rs_j bit for bit;
+// rs = 1 / L[j][j] (rsqrt of the pivot) and sq = L[j][j] (pivot * rs). Returns
+// (wave-uniform) the first step whose pivot is not positive, plus one, or 0.
+__device__ __forceinline__ int wave_chol64_panels(double (&b)[64], int n, double& sq, double& rs, double* cb,
+                                                  double* sT) {
+  const int lane = threadIdx.x & 63;
+  int bad = 0;
+  sq = 1.0;
+  rs = 1.0;
+  cb[64 + lane] = 0.0;  // broadcast slots for rows past 63, both buffers
+  cb[192 + lane] = 0.0;
+  double piv = readlane_d(b[0], 0);
+  const int np = (n + 7) >> 3;
+  for (int pn = 0; pn < np; ++pn) {
+    const int k0 = 8 * pn;
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int k = k0 + st;
+      if (!(piv > 0.0) && bad == 0) bad = k + 1;
+      const double pv = piv > 0.0 ? piv : 1e-300;
+      const double r = rsqrt(pv);
+      double* const c = cb + (st & 1) * 128 + k0;  // c[i] is row k0 + i's broadcast
+      const double t = b[st] * r;
+      c[lane - k0] = t;
+      wave_sync();
+      const double tt = lane > k ? t : 0.0;
+      piv = readlane_d(fma(-t, tt, b[st + 1]), (k + 1) & 63);  // unused after the last step
+      sq = lane == k ? pv * r : sq;
+      rs = lane == k ? r : rs;
+      b[st] = lane > k ? t : b[st];
+#pragma unroll
+      for (int i = st + 1; i < 64; ++i) b[i] = fma(-c[i], tt, b[i]);
+    }
+#pragma unroll
+    for (int st = 0; st < 8; ++st) sT[(k0 + st) * 64 + lane] = b[st];
+#pragma unroll
+    for (int i = 0; i < 56; ++i) b[i] = b[i + 8];
+#pragma unroll
+    for (int i = 56; i < 64; ++i) b[i] = 0.0;
+  }
+  wave_sync();
+  return bad;
+}
+
+// wave_chol64: the same steps with all 64 unrolled and the finished rows kept in the
+// registers, for the 64-column blocks of k_chol_p64 (measured on gfx950 with the other
+// phases of that kernel: 415 us at n = 256 against 530 us for a variant built on the panel
+// loop). On return lane j holds L[j][k] in a[k] for k < j, its pivot in a[j] and the
+// trailing entries A^(j)[i][j] below (i > j), with sq and rs as in wave_chol64_panels.
+__device__ __forceinline__ int wave_chol64(double (&a)[64], double& sq, double& rs, double* colk) {
+  const int lane = threadIdx.x & 63;
+  int bad = 0;
+  sq = 1.0;
+  rs = 1.0;
+  double piv = readlane_d(a[0], 0);
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    if (!(piv > 0.0) && bad == 0) bad = k + 1;
+    const double p = piv > 0.0 ? piv : 1e-300;
+    const double r = rsqrt(p);
+    double* const c = colk + (k & 1) * 64;  // two buffers: one wave sync per step
+    const double t = a[k] * r;
+    c[lane] = t;
+    wave_sync();
+    // lanes <= k multiply by zero instead of branching, so that a step is one basic block and
+    // the next pivot's chain overlaps this step's updates. That pivot is lane k + 1's own
+    // diagonal update (c[k + 1] is its t), bit for bit the value the loop below leaves.
+    const double tt = lane > k ? t : 0.0;
+    if (k + 1 < 64) piv = readlane_d(fma(-t, tt, a[k + 1]), k + 1);
+    sq = lane == k ? p * r : sq;
+    rs = lane == k ? r : rs;
+    a[k] = lane > k ? t : a[k];
+#pragma unroll
+    for (int i = k + 1; i < 64; ++i) a[i] = fma(-c[i], tt, a[i]);
+  }
+  return bad;
+}
+
+// n <= 64: one wave, the column in registers. The solves are rolled loops over the rows
+// kept in LDS: L y = rhs uses sT[k][j] = L[j][k] (j > k), L^T x = y uses
+// L[k][j] = sT[k][j] * rs_j (k > j), the pivots and the running right-hand side read
+// across lanes.
+__global__ __launch_bounds__(64) void k_chol_wave(const double* G, const double* rhs, int n, double* x, int* info,
+                                                  double ridge_rel) {
+  __shared__ double cb[256];
+  __shared__ double sT[64 * 64];
+  const int lane = threadIdx.x;
+  const double dg = lane < n ? G[(long)lane * n + lane] : 0.0;
+  double tr = 0.0;
+  for (int i = 0; i < n; ++i) tr += readlane_d(dg, i);
+  const double ridge = ridge_rel * tr / (double)n;
+  double a[64];
+  // lower triangle only, mirrored: the factored matrix is symmetric by construction. Every
+  // load is unconditional (clamped address) and masked arithmetically, fma(g, 1, ridge or 0)
+  // or fma(g, 0, 1 or 0): a select on the loaded value is turned into a branch around each
+  // load, and the 64 loads then run one after another.
+  const int lc = min(lane, n - 1);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const int ic = min(i, n - 1);
+    const double g = G[(long)max(ic, lc) * n + min(ic, lc)];
+    const bool in = i < n && lane < n;
+    a[i] = fma(g, in ? 1.0 : 0.0, i == lane ? (in ? ridge : 1.0) : 0.0);
+  }
+  double sq, rs;
+  const int bad = wave_chol64_panels(a, n, sq, rs, cb, sT);
+  if (lane == 0) *info = bad <= n ? bad : 0;
+  const double b = rhs[lc];
+  double v = lane < n ? b : 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double yk = readlane_d(v * rs, k);
+    const double l = sT[k * 64 + lane];
+    v = lane == k ? yk : lane > k ? fma(-l, yk, v) : v;
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double xk = readlane_d(v * rs, k);
+    const double l = sT[k * 64 + lane] * rs;
+    v = lane == k ? xk : lane < k ? fma(-l, xk, v) : v;
+  }
+  if (lane < n) x[lane] = v;
+}
+
+// 64 < n <= CHOL_P64_MAX: right-looking in 64-column panels, the matrix in
+// global memory (L2 resident; lower triangle kept) and one workgroup. Per panel:
+// wave 0 factors the diagonal block (wave_chol64) and stores L11; every thread
+// takes one row of the panel below and solves L11 l^T = a^T right-looking (column
+// c final once scaled, then 63 - c independent updates) with L11 broadcast from
+// LDS; the panel, transposed in LDS, then takes the trailing lower triangle
+// A22 -= L21 L21^T in 4 x 4 register tiles. The solves are blocked the same way:
+// the diagonal blocks by wave 0 with the block in registers and the pivots and
+// running right-hand side read across lanes, the off-diagonal blocks as GEMVs by
+// all threads.
+constexpr int CHOL_P64_MAX = 256;
+constexpr int CHOL_P64_NT = 512;                 // eight waves: 256 VGPRs for wave 0's 64-double column
+constexpr int CHOL_P64_PR = CHOL_P64_MAX - 64;   // rows of the transposed panel
+constexpr int CHOL_P64_LDS = 64 * CHOL_P64_PR * (int)sizeof(double);  // dynamic part: the transposed panel
+
+__global__ __launch_bounds__(CHOL_P64_NT) void k_chol_p64(double* A, const double* rhs, int n, double* x, int* info,
+                                                      double ridge_rel) {
+  // the small buffers are static so that their constant offsets fold into the LDS
+  // instructions (offsets into the dynamic block are materialised one register each)
+  __shared__ double sL[64 * 65];  // L11, row stride 65
+  __shared__ double sR[64];       // 1 / L11[c][c]
+  __shared__ double colk[128];
+  __shared__ double sv[CHOL_P64_MAX];  // rhs -> y -> x
+  extern __shared__ double Pt[];       // Pt[c * PR + r] = L21[r][c]
+  constexpr int PR = CHOL_P64_PR;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long ld = n;
+  if (wave == 0) {  // trace: strided partial sums, then a fixed shuffle tree
+    double tr = 0.0;
+    for (int i = lane; i < n; i += 64) tr += A[i * ld + i];
+    tr = wave_sum(tr);
+    if (lane == 0) {
+      colk[0] = ridge_rel * tr / (double)n;
+      *info = 0;
+    }
+  }
+  __syncthreads();
+  const double ridge = colk[0];
+  for (int i = tid; i < n; i += CHOL_P64_NT) A[i * ld + i] += ridge;
+  __threadfence_block();
+  __syncthreads();
+  for (int i = tid; i < n; i += CHOL_P64_NT) sv[i] = rhs[i];
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    const int kw = min(64, n - k0), rows = n - k0 - kw;
+    double* const Ak = A + (long)k0 * ld + k0;
+    if (wave == 0) {
+      double a[64];
+      const int lc = min(lane, kw - 1);
+#pragma unroll
+      for (int i = 0; i < 64; ++i) {  // unconditional loads, masked arithmetically (as in k_chol_wave)
+        const int ic = min(i, kw - 1);
+        const double g = Ak[max(ic, lc) * ld + min(ic, lc)];
+        const bool in = i < kw && lane < kw;
+        a[i] = fma(g, in ? 1.0 : 0.0, (i == lane && !in) ? 1.0 : 0.0);
+      }
+      double sq, rs;
+      const int bad = wave_chol64(a, sq, rs, colk);
+      if (lane == 0 && bad != 0 && bad <= kw && *info == 0) *info = k0 + bad;
+#pragma unroll
+      for (int k = 0; k < 64; ++k) sL[lane * 65 + k] = k < lane ? a[k] : k == lane ? sq : 0.0;
+      sR[lane] = rs;
+      // row lane of L11 back to memory (lower triangle) from LDS, without per-element branches
+      // on the register array
+      wave_sync();
+      for (int e = lane; e < kw * kw; e += 64) {
+        const int i = e / kw, k = e - i * kw;
+        if (k <= i) Ak[i * ld + k] = sL[i * 65 + k];
+      }
+    }
+    __syncthreads();
+    const int rows4 = (rows + 3) & ~3;
+    // a panel with rows below it is full (kw = 64); rows4 <= PR < CHOL_P64_NT: one row per thread
+    if (tid < rows4) {
+      const int r = tid;
+      double* const src = Ak + (long)(kw + r) * ld;
+      const double* const srow = Ak + (long)(kw + min(r, rows - 1)) * ld;
+      double ar[64];
+      const double keep = r < rows ? 1.0 : 0.0;
+#pragma unroll
+      for (int c = 0; c < 64; ++c) ar[c] = srow[c] * keep;
+      // right-looking: column c is final once scaled, then leaves the 63 - c independent updates
+#pragma unroll
+      for (int c = 0; c < 64; ++c) {
+        ar[c] *= sR[c];
+#pragma unroll
+        for (int k = c + 1; k < 64; ++k) ar[k] = fma(-sL[k * 65 + c], ar[c], ar[k]);
+      }
+      if (r < rows) {
+#pragma unroll
+        for (int c = 0; c < 64; ++c) src[c] = ar[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 64; ++c) Pt[c * PR + r] = ar[c];
+    }
+    __syncthreads();
+    const int T = rows4 >> 2, ntile = T * (T + 1) / 2;
+    double* const A22 = Ak + (long)kw * ld + kw;
+    for (int idx = tid; idx < ntile; idx += CHOL_P64_NT) {
+      int ti = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+      while (ti * (ti + 1) / 2 > idx) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= idx) ++ti;
+      const int tj = idx - ti * (ti + 1) / 2;
+      double acc[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+      const double* const pi = Pt + 4 * ti;
+      const double* const pj = Pt + 4 * tj;
+#pragma unroll 4
+      for (int c = 0; c < kw; ++c) {
+        const double2 i01 = *(const double2*)(pi + c * PR), i23 = *(const double2*)(pi + c * PR + 2);
+        const double2 j01 = *(const double2*)(pj + c * PR), j23 = *(const double2*)(pj + c * PR + 2);
+        const double li[4] = {i01.x, i01.y, i23.x, i23.y}, lj[4] = {j01.x, j01.y, j23.x, j23.y};
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[p][q] = fma(li[p], lj[q], acc[p][q]);
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int i = 4 * ti + p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = 4 * tj + q;
+          if (i < rows && j <= i) A22[i * ld + j] -= acc[p][q];
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // L y = rhs
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    const int kw = min(64, n - k0);
+    const double* const Ak = A + (long)k0 * ld + k0;
+    if (wave == 0) {
+      double a[64];
+      const int lc = min(lane, kw - 1);
+      // unmasked: only k < lane is used by a lane below kw; padding lanes start at zero and
+      // their broadcasts reach padding lanes only
+#pragma unroll
+      for (int k = 0; k < 64; ++k) a[k] = Ak[lc * ld + min(k, kw - 1)];
+      const double dg = Ak[lc * ld + lc], b = sv[k0 + lc];
+      const double rs = lane < kw ? 1.0 / dg : 1.0;
+      double v = lane < kw ? b : 0.0;
+#pragma unroll
+      for (int k = 0; k < 64; ++k) {
+        const double yk = readlane_d(v * rs, k);
+        if (lane == k)
+          v = yk;
+        else if (lane > k)
+          v = fma(-a[k], yk, v);
+      }
+      if (lane < kw) sv[k0 + lane] = v;
+    }
+    __syncthreads();
+    for (int i = k0 + kw + tid; i < n; i += CHOL_P64_NT) {
+      const double* const Li = A + (long)i * ld + k0;
+      double t = sv[i];
+      for (int c = 0; c < kw; ++c) t = fma(-Li[c], sv[k0 + c], t);
+      sv[i] = t;
+    }
+    __syncthreads();
+  }
+  // L^T x = y
+  for (int k0 = ((n - 1) / 64) * 64; k0 >= 0; k0 -= 64) {
+    const int kw = min(64, n - k0);
+    const double* const Ak = A + (long)k0 * ld + k0;
+    if (wave == 0) {
+      double a[64];
+      const int lc = min(lane, kw - 1);
+      // unmasked: a padding lane k >= kw keeps v = 0 (its updates are finite entries times
+      // zero), so x_k = 0 and the clamped entries it meets change nothing
+#pragma unroll
+      for (int k = 0; k < 64; ++k) a[k] = Ak[min(k, kw - 1) * ld + lc];
+      const double dg = Ak[lc * ld + lc], b = sv[k0 + lc];
+      const double rs = lane < kw ? 1.0 / dg : 1.0;
+      double v = lane < kw ? b : 0.0;
+#pragma unroll
+      for (int k = 63; k >= 0; --k) {
+        const double xk = readlane_d(v * rs, k);
+        if (lane == k)
+          v = xk;
+        else if (lane < k)
+          v = fma(-a[k], xk, v);
+      }
+      if (lane < kw) sv[k0 + lane] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < k0; i += CHOL_P64_NT) {
+      double t = sv[i];
+      for (int c = 0; c < kw; ++c) t = fma(-A[(long)(k0 + c) * ld + i], sv[k0 + c], t);
+      sv[i] = t;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += CHOL_P64_NT) x[i] = sv[i];
+}
+
 // ---------------------------------------------------------------------------- GEMVs
 // g[k] = sum_i X[i][k] c[i]: 64 columns per block, four row groups summed in order
 template <typename TX>
@@ -430,15 +765,21 @@ void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, d
 }
 int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s, double ridge_rel) {
   if (n > CHOL_VEC_MAX) return -1;
-  // measured on gfx950: n = 64 unblocked LDS 73 us, blocked 75 us; n = 256 unblocked global 2.4 ms, blocked 0.68 ms
-  if (n <= 64)
-    hipLaunchKernelGGL((k_chol_solve<true, 256>), dim3(1), dim3(256), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
-  else if (n <= CHOL_LDS_MAX)
-    hipLaunchKernelGGL((k_chol_solve<true, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
-  else if (n <= CHOL_BLK_MAX)
+  if (n <= 64) {
+    hipLaunchKernelGGL(k_chol_wave, dim3(1), dim3(64), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
+  } else if (n <= CHOL_P64_MAX) {
+    static bool attr = false;
+    if (!attr) {
+      if (hipFuncSetAttribute((const void*)k_chol_p64, hipFuncAttributeMaxDynamicSharedMemorySize, CHOL_P64_LDS) !=
+          hipSuccess)
+        return -2;
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_chol_p64, dim3(1), dim3(CHOL_P64_NT), CHOL_P64_LDS, s, G, rhs, n, x, (int*)work, ridge_rel);
+  } else if (n <= CHOL_BLK_MAX)
     hipLaunchKernelGGL(k_chol_blocked, dim3(1), dim3(CHOL_BLK_NT), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
   else
-    hipLaunchKernelGGL((k_chol_solve<false, 1024>), dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
+    hipLaunchKernelGGL(k_chol_solve<1024>, dim3(1), dim3(1024), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
   return 0;
 }
 
