@@ -477,6 +477,8 @@ def main():
     ap.add_argument("--serve-horizon-scale", type=float, default=0.05)
     ap.add_argument("--uneven-scale", type=float, default=0.02, help="horizon scale of the uneven batch (0: skip)")
     ap.add_argument("--no-gram", action="store_true")
+    ap.add_argument("--anomaly-only", action="store_true",
+                    help="run only the anomaly-reduction sweep and print it as one JSON line (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the ensemble members of one MI355X "
@@ -490,6 +492,9 @@ def main():
 
     E.lib()
     torch.cuda.init()
+    if args.anomaly_only:
+        print(json.dumps({"anomaly_reduction": gram_sweep(torch, E)}), flush=True)
+        return
     # measured streaming-copy ceiling (and the reference for traffic counters)
     src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
