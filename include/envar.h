@@ -218,7 +218,7 @@ size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
  * minimum-norm solution up to that ridge). Synchronous (the solve is checked on the host).
  * Errors: EINVAL (n < 1, m < 1, min(n, m) > 1024), ENOMEM, EDIVERGED (a pivot not positive
  * after the ridge, or a non-finite solution, e.g. from a non-finite cost; g_dev is then
- * undefined). */
+ * undefined), EDEVICE (a launch failed). */
 int envar_gradient(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
                    int32_t precision, void* ws_dev, size_t ws_bytes, double* g_dev, void* stream);
 
@@ -249,7 +249,7 @@ size_t envar_gn_bytes(int32_t n, int64_t K);
  * dw_dev [n] <- -H_GN^-1 dJ/dw (FP64 Cholesky), hgn_dev [n][n] <- H_GN (input of
  * envar_posterior_var), jw_dev [2] <- (1/2 |d_0|^2, 1/2 (n - 1) |w|^2), the two terms of
  * J(w) in eq. (J_w). All pointers device. Errors: EINVAL (n < 1, n > 1024, K < 1,
- * eps <= 0), ENOMEM. */
+ * eps <= 0), ENOMEM, EDEVICE (a launch failed). */
 int envar_gn_step(const double* series_dev, int32_t n, int64_t K, double eps, const double* w_dev,
                   void* ws_dev, size_t ws_bytes, double* dw_dev, double* hgn_dev, double* jw_dev,
                   void* stream);
