@@ -78,7 +78,10 @@ typedef struct {
   double x_cav;        /* <= 0: 1.25 */
   double box[4];       /* x0, x1, y0, y1 for ENVAR_REGION_BOX */
   double penalty;      /* lambda of the penalty lambda h^2 |f|^2; < 0: 1e-3 */
-  double div_tol;      /* pressure solve stops when dt * max|b - L phi| <= div_tol; <= 0: 1e-12 FP64, 1e-10 MIXED */
+  double div_tol;      /* bound on the divergence after projection: the pressure solve stops when
+                          dt * max|b - L phi| <= 0.999 div_tol (the margin covers rounding between
+                          the residual and the divergence of the projected velocities);
+                          <= 0: 1e-12 FP64, 1e-10 MIXED */
   int32_t max_cycles;  /* cap on V-cycles (FP64) or refinement passes (MIXED) per step; <= 0: 30 */
   int32_t flags;       /* ENVAR_FLAG_* bits, 0 = none */
 } envar_problem;

@@ -20,12 +20,22 @@ namespace envar {
 // Tiles of the stencil kernels: 64 cells (one wave) wide.
 constexpr int TILE_W = 64;
 constexpr int COST_TH = 8;   // rows of a cost block: the S2 partial sums live on a fixed 64 x 8 grid
-constexpr int MG_NS = 2;     // red-black sweeps before and after the coarse correction
+// Red-black sweeps before and after the coarse correction, by the V-cycle's element type:
+// two for FP64 V-cycles, one for the FP32 V-cycles inside FP64 refinement (mixed precision).
+// Measured at h = 1/128, 65 members, 20,000 steps: mixed 9.28e9 cell-steps/s with two sweeps
+// (1.25 refinement passes per step) -> 1.05e10 with one (1.30 passes, each cheaper, and a
+// wider tile); FP64 6.52e9 with two (2.09 V-cycles per step) -> 5.92e9 with one (3.11).
+template <typename T>
+__host__ __device__ constexpr int mg_ns() { return sizeof(T) == sizeof(float) ? 1 : 2; }
+// window halo of the multigrid kernels: a sweep invalidates two rings, the residual one more
+template <typename T>
+__host__ __device__ constexpr int mg_h() { return 2 * mg_ns<T>() + 1; }
+// multigrid tile width: the window is one wave wide
+template <typename T>
+__host__ __device__ constexpr int mg_tw() { return 64 - 2 * mg_h<T>(); }
 // over-relaxation of the red-black sweeps on the tiled levels: measured at h = 1/128 (65 members),
 // FP64 V-cycles per step 3.04 (omega = 1) -> 2.06 (1.15) -> 3.05 (1.3); the LDS levels keep 1
 constexpr double MG_OMEGA = 1.15;
-constexpr int MG_H = 2 * MG_NS + 1;           // window halo of the multigrid kernels
-constexpr int MG_TW = 64 - 2 * MG_H;          // multigrid tile width: the window is one wave wide
 constexpr int COARSE_N = 16; // levels with inv_h <= 16 run inside one workgroup per member
 constexpr int MAX_LEVELS = 12;
 constexpr int MAX_COARSE_UNKNOWNS = 128;

@@ -59,7 +59,7 @@ __device__ __forceinline__ bool mg_skip(const MGArgs<T>& a, int mem, int tile) {
 // (ox + oy) is even, so a cell's colour is (r + col) & 1 in window coordinates.
 template <typename T, int TR>
 struct Win {
-  static constexpr int H = MG_H, LW = 64, TWI = MG_TW, TH = TR, LH = TH + 2 * H;
+  static constexpr int H = mg_h<T>(), LW = 64, TWI = mg_tw<T>(), TH = TR, LH = TH + 2 * H;
   static constexpr int QS = 34;                 // padded row stride of a colour plane (32 cells)
   static constexpr int CS = (LH + 2) * QS;      // padded colour plane
   static constexpr int NR = (LH + 3) / 4;       // window rows per wave
@@ -760,9 +760,9 @@ __global__ __launch_bounds__(256) void k_resid64(Multi<ResidArgs> ms) {
 template <typename T, bool REF, int TR>
 static void launch_mg_pre_(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_pre<T, mg_ns<T>(), REF, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_mg_pre<T, MG_NS, REF, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_pre<T, mg_ns<T>(), REF, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
 }
 // every segment of one launch shares the tile height (the host groups segments by it)
 template <typename T, bool REF>
@@ -789,9 +789,9 @@ void launch_mg_pre<float>(const Multi<MGArgs<float>>& m, hipStream_t s) {
 template <typename T, int NORM, int TR>
 static void launch_mg_post_(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL((k_mg_post<T, MG_NS, NORM, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_post<T, mg_ns<T>(), NORM, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_mg_post<T, MG_NS, NORM, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_post<T, mg_ns<T>(), NORM, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
 }
 template <typename T>
 void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s) {
