@@ -2,7 +2,8 @@
 
 g = X^+ dJ for X_i = f_i - f_0: compared with numpy.linalg.lstsq on the same
 seeded rows (FP64 MFMA: 1e-10 relative; FP32 MFMA: cosine >= 0.999999), for
-n <= m (Gram path) and n > m (normal-equation path), the closed form of
+n <= m (Gram path) and n > m (normal-equation path), at the size edges of the
+Cholesky variants and at the largest supported system (1024), the closed form of
 an antithetic quadratic cost, repeated members (rank-deficient X: the
 minimum-norm solution) and a non-finite cost (reported, not returned).
 """
@@ -36,6 +37,22 @@ def test_gradient_fp64_matches_lstsq(n, m):
     ref, *_ = np.linalg.lstsq(X, J[1:] - J[0], rcond=None)
     print("fp64 gradient", n, m, np.abs(g - ref).max() / np.abs(ref).max(), flush=True)
     assert np.abs(g - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+# the edges of the Cholesky variants (one wave <= 64 < 64-column blocks <= 256 < 32-column panels
+# <= 448 < unblocked) and the largest supported system, in the Gram (n <= m) and normal-equation
+# (n > m) forms
+@pytest.mark.parametrize("n,m", [(65, 200), (257, 600), (448, 900), (449, 900), (1024, 2048), (1100, 1024)])
+def test_gradient_fp64_at_solver_size_edges(n, m):
+    rng = np.random.default_rng(7 * n + m)
+    rows = rng.standard_normal((n + 1, m)) * 1e-2
+    J = rng.standard_normal(n + 1)
+    g = _run(rows, J, E.FP64)
+    X = rows[1:] - rows[0]
+    ref, *_ = np.linalg.lstsq(X, J[1:] - J[0], rcond=None)
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print("fp64 gradient at size edge", n, m, err, flush=True)
+    assert err <= 1e-9
 
 
 @pytest.mark.parametrize("n,m", [(8, 4096), (64, 65536), (256, 65536)])
