@@ -1594,16 +1594,15 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   }
   HIP_OK(hipGetLastError());
   // a pivot that is not positive after the ridge (a non-finite Gram) or a non-finite solution
-  // (a non-finite cost) is reported instead of returning garbage
-  const int dim = L.dim;
-  std::vector<double> sol(dim);
-  int info = 0;
-  HIP_OK(hipMemcpyAsync(&info, at<int>(ws, L.info), sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(sol.data(), n <= m ? at<double>(ws, L.c) : g, (size_t)dim * 8, hipMemcpyDeviceToHost, s));
+  // (a non-finite cost) is reported instead of returning garbage: the solve leaves both in one
+  // word, read through a pinned word of this host thread (allocated once, kept for the process)
+  static thread_local int* flag = nullptr;
+  if (!flag) HIP_OK(hipHostMalloc((void**)&flag, sizeof(int), hipHostMallocDefault));
+  HIP_OK(hipMemcpyAsync(flag, at<int>(ws, L.info), sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  if (info != 0) return fail(ENVAR_EDIVERGED, "the ensemble Gram is not positive definite (pivot %d)", info);
-  for (int i = 0; i < dim; ++i)
-    if (!std::isfinite(sol[i])) return fail(ENVAR_EDIVERGED, "non-finite least-squares solution (a cost is not finite?)");
+  const int info = *flag;
+  if (info > 0) return fail(ENVAR_EDIVERGED, "the ensemble Gram is not positive definite (pivot %d)", info);
+  if (info < 0) return fail(ENVAR_EDIVERGED, "non-finite least-squares solution (a cost is not finite?)");
   return ENVAR_OK;
 }
 

@@ -235,7 +235,12 @@ __global__ __launch_bounds__(NT) void k_chol_solve(double* A, const double* rhs,
     for (int j = tid; j < k; j += NT) sv[j] -= A[k * ld + j] * xk * sdi[j];
     __syncthreads();
   }
-  for (int i = tid; i < n; i += NT) x[i] = sv[i];
+  bool nonfinite = false;
+  for (int i = tid; i < n; i += NT) {
+    x[i] = sv[i];
+    nonfinite = nonfinite || !isfinite(sv[i]);
+  }
+  if (__syncthreads_or(nonfinite) && tid == 0 && *info == 0) *info = -1;
 }
 
 // Blocked variant (n <= CHOL_BLK_MAX), same system: right-looking Cholesky G = L L^T in
@@ -358,7 +363,12 @@ __global__ __launch_bounds__(CHOL_BLK_NT) void k_chol_blocked(double* A, const d
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += CHOL_BLK_NT) x[i] = sv[i];
+  bool nonfinite = false;
+  for (int i = tid; i < n; i += CHOL_BLK_NT) {
+    x[i] = sv[i];
+    nonfinite = nonfinite || !isfinite(sv[i]);
+  }
+  if (__syncthreads_or(nonfinite) && tid == 0 && *info == 0) *info = -1;
 }
 
 // ---------------------------------------------------------------------------- one-wave and 64-panel Cholesky
@@ -494,7 +504,6 @@ __global__ __launch_bounds__(64) void k_chol_wave(const double* G, const double*
   }
   double sq, rs;
   const int bad = wave_chol64_panels(a, n, sq, rs, cb, sT);
-  if (lane == 0) *info = bad <= n ? bad : 0;
   const double b = rhs[lc];
   double v = lane < n ? b : 0.0;
   for (int k = 0; k < n; ++k) {
@@ -508,6 +517,8 @@ __global__ __launch_bounds__(64) void k_chol_wave(const double* G, const double*
     v = lane == k ? xk : lane < k ? fma(-l, xk, v) : v;
   }
   if (lane < n) x[lane] = v;
+  const bool nonfinite = __any(lane < n && !isfinite(v));
+  if (lane == 0) *info = (bad != 0 && bad <= n) ? bad : nonfinite ? -1 : 0;
 }
 
 // 64 < n <= CHOL_P64_MAX: right-looking in 64-column panels, the matrix in
@@ -707,7 +718,12 @@ __global__ __launch_bounds__(CHOL_P64_NT) void k_chol_p64(double* A, const doubl
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += CHOL_P64_NT) x[i] = sv[i];
+  bool nonfinite = false;
+  for (int i = tid; i < n; i += CHOL_P64_NT) {
+    x[i] = sv[i];
+    nonfinite = nonfinite || !isfinite(sv[i]);
+  }
+  if (__syncthreads_or(nonfinite) && tid == 0 && *info == 0) *info = -1;
 }
 
 // ---------------------------------------------------------------------------- GEMVs

@@ -267,6 +267,9 @@ template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s);
 int gram_reduce_groups(int nsplit);
 void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, double* G, hipStream_t s);
+// (G + ridge_rel tr(G)/n I) x = rhs; G may be overwritten (n > 64). work[0] (int) <- 0, the first
+// pivot that is not positive (1-based), or -1 when the pivots are fine but x is not finite.
+// Returns 0, or -1 for n > 1024 and -2 when the launch could not be configured.
 int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s,
                       double ridge_rel = 1e-12);
 // vector-observation EnVar step and posterior variance
