@@ -2203,7 +2203,8 @@ extern "C" int envar_posterior_var(const double* controls_dev, int32_t n, int64_
   double* C = (double*)ws_dev;
   double* info = at<double>(ws_dev, align256((size_t)n * n * 8));
   launch_spd_inverse(hgn_dev, n, C, info, s);
-  launch_post_var(controls_dev, n, (long)m, eps, C, var_dev, s);
+  if (launch_post_var(controls_dev, n, (long)m, eps, C, var_dev, s))
+    return fail(ENVAR_EDEVICE, "posterior variance launch failed (n = %d)", n);
   HIP_OK(hipGetLastError());
   return ENVAR_OK;
 }

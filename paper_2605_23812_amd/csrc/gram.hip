@@ -882,25 +882,54 @@ __global__ __launch_bounds__(1024) void k_spd_inverse(const double* H, int n, do
     for (int j = tx; j < n; j += 32) C[(long)i * n + j] = sA[i * ld + j];
 }
 
-// var[k] = e_k^T C e_k with e_k[a] = (ctrl[a + 1][k] - ctrl[0][k]) / eps: 64 columns per
-// workgroup staged in LDS, four row groups summed in a fixed order
-__global__ __launch_bounds__(256) void k_post_var(const double* ctrl, int n, long m, double inv_eps,
-                                                  const double* __restrict__ C, double* var) {
-  __shared__ double sE[SPD_INV_MAX * 64];
-  __shared__ double part[4][64];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const long k = blockIdx.x * 64L + tx;
-  for (int a = ty; a < n; a += 4) sE[a * 64 + tx] = k < m ? (ctrl[(long)(a + 1) * m + k] - ctrl[k]) * inv_eps : 0.0;
-  __syncthreads();
-  double acc = 0.0;
-  for (int a = ty; a < n; a += 4) {
-    double t = 0.0;
-    for (int b = 0; b < n; ++b) t += C[(long)a * n + b] * sE[b * 64 + tx];
-    acc += sE[a * 64 + tx] * t;
+// var[k] = e_k^T C e_k with e_k[a] = (ctrl[a + 1][k] - ctrl[0][k]) / eps: one workgroup per 64
+// columns, the E block (rows padded to a multiple of 16 with zeros) staged in LDS; wave w forms
+// V = C E for columns 16w .. 16w + 15 on the FP64 matrix cores (16 x 16 tiles over all row
+// blocks, v_mfma_f64_16x16x4f64), then each lane sums E o V over its rows (l/16 + 4r of every row
+// block) and the four lanes of a column are added in a fixed order. Every load is unconditional
+// and masked arithmetically, so the loads of a loop overlap.
+constexpr int POST_COLS = 64;
+__global__ __launch_bounds__(256) void k_post_var(const double* __restrict__ ctrl, int n, long m, double inv_eps,
+                                                  const double* __restrict__ C, double* __restrict__ var) {
+  extern __shared__ double sE[];  // [np][POST_COLS]
+  const int np = (n + 15) & ~15;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long c0 = (long)blockIdx.x * POST_COLS;
+  {
+    const long col = c0 + lane, colc = col < m ? col : m - 1;
+    const double base = ctrl[colc];
+#pragma unroll 4
+    for (int a = w; a < np; a += 4) {
+      const int ac = a < n ? a : n - 1;
+      const double x = (ctrl[(long)(ac + 1) * m + colc] - base) * inv_eps;
+      sE[a * POST_COLS + lane] = x * ((a < n && col < m) ? 1.0 : 0.0);
+    }
   }
-  part[ty][tx] = acc;
   __syncthreads();
-  if (ty == 0 && k < m) var[k] = ((part[0][tx] + part[1][tx]) + part[2][tx]) + part[3][tx];
+  const int lr = lane & 15, lq = lane >> 4, cw = 16 * w + lr;
+  double part = 0.0;
+  for (int R = 0; R < np; R += 16) {
+    MfmaAcc<double>::V acc = {0.0, 0.0, 0.0, 0.0};
+    const int row = R + lr, rowc = row < n ? row : n - 1;
+    // np is a multiple of 16: four MFMA steps per trip, their operands loaded first (the
+    // instruction is convergent, so the compiler does not unroll a loop that might leave a remainder)
+    for (int k0 = 0; k0 < np; k0 += 16) {
+      double a_op[4], b_op[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k0 + 4 * u + lq, kc = kk < n ? kk : n - 1;
+        a_op[u] = C[(long)rowc * n + kc] * ((row < n && kk < n) ? 1.0 : 0.0);
+        b_op[u] = sE[kk * POST_COLS + cw];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = MfmaAcc<double>::mma(a_op[u], b_op[u], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part = fma(sE[(R + lq + 4 * r) * POST_COLS + cw], acc[r], part);
+  }
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  if (lq == 0 && c0 + cw < m) var[c0 + cw] = part;
 }
 
 // one column k per thread: the centre sums the members in index order, then each member row
@@ -966,8 +995,17 @@ int launch_spd_inverse(const double* H, int n, double* C, double* work, hipStrea
   return 0;
 }
 int launch_post_var(const double* ctrl, int n, long m, double eps, const double* C, double* var, hipStream_t s) {
-  if (n > SPD_INV_MAX) return -1;
-  hipLaunchKernelGGL(k_post_var, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, ctrl, n, m, 1.0 / eps, C, var);
+  if (n < 1 || n > SPD_INV_MAX) return -1;
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void*)k_post_var, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            SPD_INV_MAX * POST_COLS * (int)sizeof(double)) != hipSuccess)
+      return -2;
+    attr = true;
+  }
+  const size_t dyn = (size_t)((n + 15) & ~15) * POST_COLS * sizeof(double);
+  hipLaunchKernelGGL(k_post_var, dim3((unsigned)((m + POST_COLS - 1) / POST_COLS)), dim3(256), dyn, s, ctrl, n, m,
+                     1.0 / eps, C, var);
   return 0;
 }
 template <typename TX>
