@@ -92,16 +92,36 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, const double
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   V4 acc[4];
   for (int t = 0; t < 4; ++t) acc[t] = V4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += DG_KC) {
-    for (int q = threadIdx.x; q < 64 * DG_KC; q += 256) {
-      const int r = q / DG_KC, c = q % DG_KC;
-      sa[r * DG_LDA + c] = (I0 + r < M && k0 + c < K) ? A[(long)(I0 + r) * lda + k0 + c] : 0.0;
+  // A 64 x 32 and B 32 x 64 chunk: eight values of each per thread, loaded into registers one
+  // chunk ahead of the MFMA work; every load is unconditional (clamped address, arithmetic mask):
+  // a select on the loaded value becomes a branch around each load, and the loads then run one
+  // after another
+  constexpr int NQ = 64 * DG_KC / 256;
+  double va[NQ], vb[NQ];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q = threadIdx.x + 256 * i, r = q / DG_KC, c = q % DG_KC;
+      const int rr = min(I0 + r, M - 1), cc = min(k0 + c, K - 1);
+      va[i] = A[(long)rr * lda + cc] * ((I0 + r < M && k0 + c < K) ? 1.0 : 0.0);
     }
-    for (int q = threadIdx.x; q < DG_KC * 64; q += 256) {
-      const int r = q >> 6, c = q & 63;
-      sb[r * DG_LDB + c] = (k0 + r < K && J0 + c < N) ? B[(long)(k0 + r) * ldb + J0 + c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q = threadIdx.x + 256 * i, r = q >> 6, c = q & 63;
+      const int rr = min(k0 + r, K - 1), cc = min(J0 + c, N - 1);
+      vb[i] = B[(long)rr * ldb + cc] * ((k0 + r < K && J0 + c < N) ? 1.0 : 0.0);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += DG_KC) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q = threadIdx.x + 256 * i;
+      sa[(q / DG_KC) * DG_LDA + q % DG_KC] = va[i];
+      sb[(q >> 6) * DG_LDB + (q & 63)] = vb[i];
     }
     __syncthreads();
+    if (k0 + DG_KC < K) fetch(k0 + DG_KC);
     const int row = 16 * wave + (lane & 15);
     for (int kk = 0; kk < DG_KC; kk += 4) {
       const double a = sa[row * DG_LDA + kk + (lane >> 4)];
