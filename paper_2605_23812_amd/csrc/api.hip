@@ -2102,7 +2102,20 @@ extern "C" int envar_eigen_ensemble(const envar_problem* p, int32_t N, const env
   launch_dgemm(b, (int)M, b, d(L.Sm), b, 0, Z, M, 0, Q, M, 0, 1, nullptr, 0, s);
   HIP_OK(hipGetLastError());
   const int rsplit = eig_resid_split();
-  std::vector<double> th(b), res((size_t)S.N * rsplit);
+  // the Ritz values and residual partials come back every iteration for the convergence test:
+  // through one pinned buffer of this host thread (kept for the process), not pageable memory
+  static thread_local double* pin = nullptr;
+  static thread_local size_t pin_n = 0;
+  const size_t need = (size_t)b + (size_t)S.N * rsplit;
+  if (pin_n < need) {
+    if (pin) (void)hipHostFree(pin);
+    pin = nullptr;
+    pin_n = 0;
+    HIP_OK(hipHostMalloc((void**)&pin, need * sizeof(double), hipHostMallocDefault));
+    pin_n = need;
+  }
+  const double* const th = pin;
+  const double* const res = pin + b;
   int it = 0;
   bool conv = false;
   double maxr = 0.0;
@@ -2114,8 +2127,8 @@ extern "C" int envar_eigen_ensemble(const envar_problem* p, int32_t N, const env
     // Ritz vectors and images: [U; V] = W^T [Q; Z]
     launch_dgemm(b, (int)M, b, d(L.Wt), b, 0, Q, M, (long)b * M, U, M, (long)b * M, 2, nullptr, 0, s);
     launch_eig_resid(U, Vv, d(L.theta), S.N, M, d(L.resid), s);
-    HIP_OK(hipMemcpyAsync(th.data(), d(L.theta), (size_t)b * 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipMemcpyAsync(res.data(), d(L.resid), res.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(pin, d(L.theta), (size_t)b * 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(pin + b, d(L.resid), (size_t)S.N * rsplit * 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     maxr = 0.0;
     for (int k = 0; k < S.N; ++k) {
