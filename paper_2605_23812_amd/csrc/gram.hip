@@ -392,9 +392,10 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // chain overlaps the updates. The fused product is the same for (i, j) and (j, i), so
 // the trailing block stays exactly symmetric, and the next pivot is lane k + 1's own
 // diagonal update, bit for bit the value the update loop leaves, read without LDS.
-// The steps run as a loop over panels of eight (unrolled within a panel): straight-line
-// code for all 64 steps is some 60 KB, executed once, and runs at the speed of
-// instruction fetch. After a panel the finished rows go to LDS and the column shifts
+// The steps run as a loop over panels of eight (unrolled within a panel), 17 KB of code
+// against 68 KB for all 64 steps unrolled, at the same measured speed (each step waits
+// on its LDS broadcast and the pivot's rsqrt chain). After a panel the finished rows go
+// to LDS and the column shifts
 // down by eight, so register indices stay static (rows past 63 are zero and take
 // broadcasts of zero); only ceil(n / 8) panels run. On return sT[k * 64 + j] holds lane
 // j's entry of row k after step k: L[j][k] for j > k, the pivot for j = k, and for j < k
