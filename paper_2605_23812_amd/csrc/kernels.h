@@ -67,6 +67,7 @@ struct PredArgs {
   const double* phi;          // phi^{n-1}
   double* phi_next;           // phi^{n-2} on entry -> warm start of this step's solve
   double* phi_old;            // phi^{n-3} on entry -> phi^{n-2}
+  double* phi_old2;           // phi^{n-4} on entry -> phi^{n-3} (cubic warm start; NULL: quadratic)
   const double* stats;
   const double* shu;
   const double* shv;
@@ -98,6 +99,8 @@ struct ProjArgs {
   // phi_old holds phi^{n-2} on entry and receives phi^{n-1}
   double* phi_next;
   double* phi_old;
+  // phi^{n-3} on entry, receives phi^{n-2}: the cubic warm start (NULL: quadratic)
+  double* phi_old2;
   const double* stats;  // [nmem][STATS_STRIDE]: steps done so far select the extrapolation order
   const double* shu;  // cost shift (dense cells, shared by members)
   const double* shv;

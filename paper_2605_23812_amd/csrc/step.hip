@@ -30,7 +30,9 @@ namespace envar {
 // same), and the tile cells take the previous step's cost sample, divergence
 // and the warm start of this step's solve. u^n never goes to memory: the step
 // carries u* and phi, which saves the u, v store and reload and a launch.
-template <typename TT, bool ONE, int TH, bool FUSED>
+// CUBIC: the fused warm start extrapolates from a third history plane (FP64 jobs); the mixed
+// instance is compiled without it, so it carries none of its registers
+template <typename TT, bool ONE, int TH, bool FUSED, bool CUBIC>
 __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
   constexpr int TW = TILE_W;
   constexpr int UW = TW + 3, UH = TH + 2;  // u halo: i in [x0-1, x0+TW+1], j in [y0-1, y0+TH]
@@ -60,6 +62,7 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
   const TT* __restrict__ tvp = a.tv_prev + off;
   const double* __restrict__ f = a.ctrl ? a.ctrl + (long)mem * a.m : nullptr;
   const int tid = threadIdx.x;
+  double* const phi_old2 = CUBIC ? a.phi_old2 : nullptr;
 
   if (tile == 0 && a.norms != nullptr)
     for (int k = tid; k < a.norm_slots; k += 256) a.norms[(long)mem * a.norm_slots + k] = 0.0;
@@ -72,7 +75,7 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
   const long coff = (long)mem * a.cplane;
   TT tpu[KU], tpv[KV];         // T^{n-1} of this thread's active faces
   int cmu[KU][2], cmv[KV][2];  // control index of the two cells of each face (-1: none)
-  double pn[KR], po[KR], s1a[KR], s1b[KR], sha[KR], shb[KR];  // fused: operands of the tile cells
+  double pn[KR], po[KR], pr[KR], s1a[KR], s1b[KR], sha[KR], shb[KR];  // fused: operands of the tile cells
   {
     // all global loads of the halo first, then the LDS stores
     constexpr int NU = (UH * UW + 255) / 256, NV = (VH * VW + 255) / 256;
@@ -133,12 +136,13 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
     }
 #pragma unroll
     for (int rr = 0; rr < KR; ++rr) {
-      pn[rr] = po[rr] = s1a[rr] = s1b[rr] = sha[rr] = shb[rr] = 0.0;
+      pn[rr] = po[rr] = pr[rr] = s1a[rr] = s1b[rr] = sha[rr] = shb[rr] = 0.0;
       const int i = x0 + tx, j = y0 + ty + 4 * rr;
       if (FUSED && g.fluid(i, j)) {
         const long at = g.at(i, j), ac = (long)j * g.nx + i;
         if (a.phi_next) pn[rr] = a.phi_next[off + at];
         if (a.phi_old) po[rr] = __builtin_nontemporal_load(&a.phi_old[off + at]);
+        if (phi_old2) pr[rr] = __builtin_nontemporal_load(&phi_old2[off + at]);
         if (a.s1u) {
           s1a[rr] = __builtin_nontemporal_load(&a.s1u[coff + ac]);
           s1b[rr] = __builtin_nontemporal_load(&a.s1v[coff + ac]);
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
     // the previous step's cost sample, divergence and this step's warm start on the tile cells
     // (thread layout and operand order of k_project_cost)
     const double done = a.stats ? a.stats[(long)mem * STATS_STRIDE + ST_STEPS] - 1.0 : 1.0;
-    const int order = done < 0.5 ? 0 : done < 1.5 ? 1 : 2;
+    const int order = done < 0.5 ? 0 : done < 1.5 ? 1 : done < 2.5 ? 2 : 3;
 #pragma unroll
     for (int rr = 0; rr < TH / 4; ++rr) {
       const int r = ty + 4 * rr;
@@ -205,7 +209,9 @@ __global__ __launch_bounds__(256) void k_predictor(Multi<PredArgs<TT>> ms) {
         const double p1 = pn[rr];
         double wn = order == 0 ? pc : 2.0 * pc - p1;
         if (a.phi_old) {
-          if (order == 2) wn = 3.0 * (pc - p1) + po[rr];
+          if (order == 2 || (order == 3 && !phi_old2)) wn = 3.0 * (pc - p1) + po[rr];
+          if (order == 3 && phi_old2) wn = (4.0 * (pc + po[rr]) - 6.0 * p1) - pr[rr];
+          if (phi_old2) __builtin_nontemporal_store(po[rr], &phi_old2[off + at]);
           __builtin_nontemporal_store(p1, &a.phi_old[off + at]);
         }
         a.phi_next[off + at] = wn;
@@ -364,9 +370,12 @@ __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
   const double dt = a.dt, inv_h = 1.0 / g.h;
   const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
   // extrapolation order of the warm start: constant after the first step (where the forcing
-  // switches on) and linear after the second, quadratic from then on
+  // switches on), linear after the second, quadratic after the third, then cubic when a third
+  // history plane is given (FP64: the solves are tight enough that truncation dominates; in
+  // mixed precision the amplified convergence error of the previous solves does, and the
+  // quadratic order converges in fewer passes)
   const double done = a.stats ? a.stats[(long)mem * STATS_STRIDE + ST_STEPS] : 1.0;
-  const int order = done < 0.5 ? 0 : done < 1.5 ? 1 : 2;
+  const int order = done < 0.5 ? 0 : done < 1.5 ? 1 : done < 2.5 ? 2 : 3;
   double acc[NB], dmax = 0.0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -407,7 +416,10 @@ __global__ __launch_bounds__(256) void k_project_cost(Multi<ProjArgs> ms) {
       const double p1 = a.phi_next[off + at];
       double wn = order == 0 ? pc : 2.0 * pc - p1;
       if (a.phi_old) {
-        if (order == 2) wn = 3.0 * (pc - p1) + a.phi_old[off + at];
+        const double p2 = a.phi_old[off + at];
+        if (order == 2 || (order == 3 && !a.phi_old2)) wn = 3.0 * (pc - p1) + p2;
+        if (order == 3 && a.phi_old2) wn = (4.0 * (pc + p2) - 6.0 * p1) - a.phi_old2[off + at];
+        if (a.phi_old2) a.phi_old2[off + at] = p2;
         a.phi_old[off + at] = p1;
       }
       a.phi_next[off + at] = wn;
@@ -634,22 +646,24 @@ void launch_stream_copy(const void* src, void* dst, long n16, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------- launchers
-template <typename TT, int TH, bool FUSED>
+template <typename TT, int TH, bool FUSED, bool CUBIC = false>
 static void launch_predictor_(const Multi<PredArgs<TT>>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL((k_predictor<TT, true, TH, FUSED>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_predictor<TT, true, TH, FUSED, CUBIC>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_predictor<TT, false, TH, FUSED>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_predictor<TT, false, TH, FUSED, CUBIC>), dim3(m.total()), dim3(256), 0, s, m);
 }
 // every segment of one launch shares the tile height and the fused flag (the host groups by them)
 template <typename TT>
 void launch_predictor(const Multi<PredArgs<TT>>& m, hipStream_t s) {
   const bool r8 = m.seg[0].trows == 8;
   if (m.seg[0].fused) {
+    // one precision per batch, so every segment has the third history plane or none does
+    const bool cubic = m.seg[0].phi_old2 != nullptr;
     if (r8)
-      launch_predictor_<TT, 8, true>(m, s);
+      cubic ? launch_predictor_<TT, 8, true, true>(m, s) : launch_predictor_<TT, 8, true>(m, s);
     else
-      launch_predictor_<TT, 16, true>(m, s);
+      cubic ? launch_predictor_<TT, 16, true, true>(m, s) : launch_predictor_<TT, 16, true>(m, s);
   } else {
     if (r8)
       launch_predictor_<TT, 8, false>(m, s);
