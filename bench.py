@@ -32,8 +32,9 @@ ELL, SIGMA = 0.05, 5e-3
 BYTES_PER_CELL = {
     # predictor fused with the previous step's projection: u*, v* of the previous step (16) + phi (8)
     # + T^{n-1} (16) + forcing on 2/5 of the cells (6.4) + cost sums S1 read and written (32) + warm start:
-    # phi^{n-2}, phi^{n-3} in, guess and phi^{n-2} out (32) -> u*, v* (16) + T^n (16) + b (8)
-    ("predictor", "fp64"): 150.4, ("predictor", "mixed"): 150.4,
+    # phi^{n-2}, phi^{n-3} in, guess and phi^{n-2} out (32) -> u*, v* (16) + T^n (16) + b (8);
+    # FP64 jobs warm-start from one more pressure (cubic): phi^{n-4} in, phi^{n-3} out (+16)
+    ("predictor", "fp64"): 166.4, ("predictor", "mixed"): 150.4,
     # phi in/out (8 + 8) + b (8) + coarse rhs (8/4)              | mixed: phi64 (8) + b64 (8) -> r (4) + e (4) + coarse (1)
     ("pre", "fp64"): 26.0, ("pre", "mixed"): 25.0,
     # phi in/out (8 + 8) + b (8) + coarse correction (8/4)       | mixed: e (4) + r (4) + coarse (1) + phi64 in/out (16)
@@ -41,8 +42,8 @@ BYTES_PER_CELL = {
     # phi64 (8) + b64 (8) -> r32 (4)
     ("resid", "mixed"): 20.0,
     # u*, v* (16) + phi (8) -> u, v (16) + cost sums S1 in/out (32) + warm start: phi^{n-1} in / guess out (16)
-    # + phi^{n-2} in / phi^{n-1} out (16)
-    ("project", "fp64"): 104.0, ("project", "mixed"): 104.0,
+    # + phi^{n-2} in / phi^{n-1} out (16); FP64: + phi^{n-3} in / phi^{n-2} out (16)
+    ("project", "fp64"): 120.0, ("project", "mixed"): 104.0,
 }
 
 # HBM bytes per launch from the two calibrated rocprofv3 counter passes (FETCH_SIZE x 2.000,
@@ -119,7 +120,7 @@ def roofline(st, prec, ncells, members, copy_gbs=None):
 def step_bytes(prec, cycles):
     if prec == "mixed":
         return 150.4 + cycles * (50.0 + 22.0 / 3.0) + 25.0
-    return 150.4 + cycles * (52.0 + 44.0 / 3.0)
+    return 166.4 + cycles * (52.0 + 44.0 / 3.0)
 
 
 def step_roofline(value, prec, cycles, copy_gbs):
