@@ -41,6 +41,7 @@ OBS_CHANNELS = 8  # four lid sensors x two velocity components
 
 
 class EnvarError(RuntimeError):
+    """A library call failed: `code` is the ENVAR_E* status, the message that of envar_last_error."""
     def __init__(self, code, msg):
         super().__init__(f"envar error {code}: {msg}")
         self.code = code
@@ -56,6 +57,7 @@ class _Problem(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
+    """envar_stats: convergence and throughput statistics of a forward or a spin-up."""
     _fields_ = [
         ("max_resid", ctypes.c_double), ("max_div", ctypes.c_double), ("mean_cycles", ctypes.c_double),
         ("max_cycles_used", ctypes.c_int32), ("unconverged", ctypes.c_int32), ("diverged", ctypes.c_int32),
@@ -92,6 +94,7 @@ class _Request(ctypes.Structure):
 
 
 class RequestStats(ctypes.Structure):
+    """envar_request_stats: timings (seconds since the server started) and status of a served request."""
     _fields_ = [("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
                 ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double), ("cell_steps", ctypes.c_double),
                 ("status", ctypes.c_int32), ("peak_jobs", ctypes.c_int32)]
@@ -101,6 +104,7 @@ class RequestStats(ctypes.Structure):
 
 
 class LSParams(ctypes.Structure):
+    """envar_ls_params: Armijo line search of envar_iterate (fields <= 0 take the defaults)."""
     _fields_ = [
         ("iters", ctypes.c_int32), ("max_trials", ctypes.c_int32), ("c1", ctypes.c_double),
         ("shrink", ctypes.c_double), ("alpha0", ctypes.c_double), ("search_every", ctypes.c_int32),
@@ -109,11 +113,13 @@ class LSParams(ctypes.Structure):
 
 
 class IterRecord(ctypes.Structure):
+    """envar_iter_record: one iteration of envar_iterate (J at the centre, |g|, step, cost at the step)."""
     _fields_ = [("J0", ctypes.c_double), ("gnorm", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("J_trial", ctypes.c_double)]
 
 
 class EnsParams(ctypes.Structure):
+    """envar_ens_params: the loop over the ensemble weights (GN or L-BFGS; fields <= 0 take the defaults)."""
     _fields_ = [
         ("method", ctypes.c_int32), ("iters", ctypes.c_int32), ("memory", ctypes.c_int32),
         ("max_trials", ctypes.c_int32), ("every", ctypes.c_int32), ("trial_batch", ctypes.c_int32),
@@ -122,12 +128,14 @@ class EnsParams(ctypes.Structure):
 
 
 class EnsRecord(ctypes.Structure):
+    """envar_ens_record: one iteration of envar_ens_iterate (J, its two terms, |dJ/dw|, step, trials)."""
     _fields_ = [("J", ctypes.c_double), ("J_obs", ctypes.c_double), ("J_prior", ctypes.c_double),
                 ("gnorm", ctypes.c_double), ("alpha", ctypes.c_double), ("trials", ctypes.c_int32),
                 ("trial_rows", ctypes.c_int32)]
 
 
 class EigenParams(ctypes.Structure):
+    """envar_eigen_params: the tapered Gaussian prior covariance and the subspace iteration."""
     _fields_ = [
         ("a_x", ctypes.c_double), ("a_y", ctypes.c_double), ("sigma2_max", ctypes.c_double), ("tol", ctypes.c_double),
         ("taper", ctypes.c_int32), ("component", ctypes.c_int32), ("oversample", ctypes.c_int32),
@@ -136,6 +144,7 @@ class EigenParams(ctypes.Structure):
 
 
 class EigenInfo(ctypes.Structure):
+    """envar_eigen_info: iterations, convergence, block size, largest kept residual, orthonormality error."""
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("max_resid", ctypes.c_double), ("orth_err", ctypes.c_double)]
 
@@ -273,30 +282,36 @@ def _hptr(a):
 
 # ---------------------------------------------------------------------------- sizes
 def control_dim(p):
+    """m, the length of a control row (both forcing components over the control cells)."""
     m = ctypes.c_int64()
     _check(lib().envar_control_dim(ctypes.byref(p.c()), ctypes.byref(m)))
     return m.value
 
 
 def cell_count(p):
+    """Fluid cells of the finest grid."""
     n = ctypes.c_int64()
     _check(lib().envar_cell_count(ctypes.byref(p.c()), ctypes.byref(n)))
     return n.value
 
 
 def state_bytes(p):
+    """Device bytes of the resident base state."""
     return lib().envar_state_bytes(ctypes.byref(p.c()))
 
 
 def workspace_bytes(p, n_rows):
+    """Device workspace bytes of a forward over n_rows control rows."""
     return lib().envar_workspace_bytes(ctypes.byref(p.c()), n_rows)
 
 
 def gradient_bytes(n, m, precision=FP64):
+    """Device workspace bytes of envar_gradient for n perturbed rows of length m."""
     return lib().envar_gradient_bytes(n, m, precision)
 
 
 def iterate_bytes(p, n, m):
+    """Device workspace bytes of envar_iterate with n perturbations of length m."""
     return lib().envar_iterate_bytes(ctypes.byref(p.c()), n, m)
 
 
@@ -317,6 +332,7 @@ def state_init(p, u, v, tu_prev=None, tv_prev=None, phi=None, state=None):
 
 
 def state_read(p, state):
+    """Host copies (u, v, T_u, T_v, phi) of a device base state, in the oracle layout."""
     NX, NY = p.box_dims()
     u = np.empty((NY, NX + 1))
     v = np.empty((NY + 1, NX))
@@ -331,6 +347,7 @@ def state_read(p, state):
 
 
 def spinup(p, state, steps, ws=None):
+    """Advance the base state in place by `steps` unforced steps (envar_spinup); returns the statistics."""
     if ws is None:
         ws = _bytes_tensor(workspace_bytes(p, 1))
     st = Stats()
@@ -467,10 +484,12 @@ def posterior_var(controls, eps, H, ws=None):
 
 def eigen_params(a_x=0.07, a_y=0.07, sigma2_max=0.01, taper=TAPER_ELLIPSE, component=1, oversample=0, max_iters=0,
                  tol=0.0, seed=0):
+    """EigenParams with the paper's taper and length scales as defaults."""
     return EigenParams(a_x, a_y, sigma2_max, tol, taper, component, oversample, max_iters, seed)
 
 
 def eigen_bytes(p, N, prm=None):
+    """Device workspace bytes of envar_eigen_ensemble for N members."""
     prm = prm or eigen_params()
     return lib().envar_eigen_bytes(ctypes.byref(p.c()), N, ctypes.byref(prm))
 
@@ -509,6 +528,7 @@ def recon_error(E, f, ws=None):
 
 
 def ens_bytes(p, n, m, horizon, every=1):
+    """Device workspace bytes of envar_ens_iterate."""
     return lib().envar_ens_bytes(ctypes.byref(p.c()), n, m, horizon, every)
 
 
@@ -556,6 +576,7 @@ def iterate(p, state, f, perturb, horizon, iters=1, max_trials=8, c1=1e-4, shrin
 
 
 def request_bytes(p, n_rows):
+    """Pool bytes one served request of n_rows rows occupies (its admission footprint)."""
     return lib().envar_request_bytes(ctypes.byref(p.c()), n_rows)
 
 
@@ -608,8 +629,10 @@ class Server:
 
 
 def stream_copy(src, dst):
+    """The library's streaming copy (the bandwidth reference of the benchmark and the counters)."""
     _check(lib().envar_stream_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), _stream()))
 
 
 def version():
+    """Library version string (name, version, target architecture)."""
     return lib().envar_version().decode()
