@@ -483,7 +483,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the ensemble members of one MI355X "
-              "(multi-GPU member sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding the members over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
