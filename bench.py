@@ -47,14 +47,18 @@ BYTES_PER_CELL = {
 }
 
 # HBM bytes per launch from the two calibrated rocprofv3 counter passes (FETCH_SIZE x 2.000,
-# WRITE_SIZE x 1.000 against the library's streaming copy), h=1/128, 65 members, mixed precision,
-# for the kernel sources and tile choices recorded in profiles/k_predictor_fused_h128_65members_mixed.md.
+# WRITE_SIZE x 1.000 against the library's streaming copy), h=1/128, 65 members, for the kernel
+# sources and tile choices recorded in profiles/k_predictor_fused_h128_65members_mixed.md (mixed
+# precision) and profiles/k_predictor_fused_h128_65members_fp64.md (FP64).
 # Set an entry to None when its kernel changes.
 MEASURED_TRAFFIC = {
     ("predictor", "mixed"): 923.9e6,
     ("pre", "mixed"): 144.2e6,
     ("post", "mixed"): 143.0e6,
     ("resid", "mixed"): None,
+    ("predictor", "fp64"): 1030.2e6,
+    ("pre", "fp64"): 156.4e6,
+    ("post", "fp64"): 159.5e6,
 }
 
 
