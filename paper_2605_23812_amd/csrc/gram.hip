@@ -8,7 +8,7 @@
 // operands, so it runs on MFMA (v_mfma_f64_16x16x4f64, or
 // v_mfma_f32_16x16x4f32 for FP32 operands) with a split over m and FP64
 // partials reduced in a fixed order (two levels). The n x n solve is an FP64
-// Cholesky in one workgroup (in the registers of one wave up to n = 64, in
+// Cholesky in one workgroup (in the registers of four waves up to n = 64, in
 // 64-column panels up to n = 256); the projection g = X^T c is a
 // bandwidth-bound GEMV with FP64 accumulation.
 #include "common.h"
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(CHOL_BLK_NT) void k_chol_blocked(double* A, const d
   if (__syncthreads_or(nonfinite) && tid == 0 && *info == 0) *info = -1;
 }
 
-// ---------------------------------------------------------------------------- one-wave and 64-panel Cholesky
+// ---------------------------------------------------------------------------- register Cholesky (n <= 64) and 64-column panels
 // Same system, (G + ridge I) x = rhs, as the kernels above, through the plain
 // factor G + ridge I = L L^T.
 //
@@ -383,71 +383,16 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// wave_chol64_panels factors a symmetric 64 x 64 block (the leading n x n part; the rest
-// is the identity, which stays the identity) held one column per lane of one wave,
-// b[i] = A[i][lane], in registers, with no workgroup barrier. Step k scales row k by
-// 1 / sqrt(a_kk) (l_j = a_kj / sqrt(a_kk), lanes j > k) and broadcasts it through LDS,
-// and every lane j > k subtracts l_i l_j from its entries i > k; lanes j <= k multiply
-// by zero instead of branching, so that a step is one basic block and the next pivot's
-// chain overlaps the updates. The fused product is the same for (i, j) and (j, i), so
-// the trailing block stays exactly symmetric, and the next pivot is lane k + 1's own
-// diagonal update, bit for bit the value the update loop leaves, read without LDS.
-// The steps run as a loop over panels of eight (unrolled within a panel), 17 KB of code
-// against 68 KB for all 64 steps unrolled, at the same measured speed (each step waits
-// on its LDS broadcast and the pivot's rsqrt chain). After a panel the finished rows go
-// to LDS and the column shifts
-// down by eight, so register indices stay static (rows past 63 are zero and take
-// broadcasts of zero); only ceil(n / 8) panels run. On return sT[k * 64 + j] holds lane
-// j's entry of row k after step k: L[j][k] for j > k, the pivot for j = k, and for j < k
-// the trailing entry A^(j)[k][j], so that L[k][j] = sT[k][j] * rs_j bit for bit;
-// rs = 1 / L[j][j] (rsqrt of the pivot) and sq = L[j][j] (pivot * rs). Returns
+// wave_chol64 factors a symmetric 64 x 64 block held one column per lane of one wave,
+// a[i] = A[i][lane], with no workgroup barrier, for the 64-column blocks of k_chol_p64. Step k
+// scales row k by 1 / sqrt(a_kk) (l_j = a_kj / sqrt(a_kk), lanes j > k), broadcasts it through
+// LDS, and every lane j > k subtracts l_i l_j from its entries i > k; lanes j <= k multiply by
+// zero instead of branching, so that a step is one basic block and the next pivot's chain
+// overlaps the updates. All 64 steps are unrolled (measured with the other phases of that
+// kernel: 415 us at n = 256 against 530 us for a loop over panels of eight). On return lane j
+// holds L[j][k] in a[k] for k < j, its pivot in a[j] and the trailing entries A^(j)[i][j] below
+// (i > j); rs = 1 / L[j][j] (rsqrt of the pivot) and sq = L[j][j] (pivot * rs). Returns
 // (wave-uniform) the first step whose pivot is not positive, plus one, or 0.
-__device__ __forceinline__ int wave_chol64_panels(double (&b)[64], int n, double& sq, double& rs, double* cb,
-                                                  double* sT) {
-  const int lane = threadIdx.x & 63;
-  int bad = 0;
-  sq = 1.0;
-  rs = 1.0;
-  cb[64 + lane] = 0.0;  // broadcast slots for rows past 63, both buffers
-  cb[192 + lane] = 0.0;
-  double piv = readlane_d(b[0], 0);
-  const int np = (n + 7) >> 3;
-  for (int pn = 0; pn < np; ++pn) {
-    const int k0 = 8 * pn;
-#pragma unroll
-    for (int st = 0; st < 8; ++st) {
-      const int k = k0 + st;
-      if (!(piv > 0.0) && bad == 0) bad = k + 1;
-      const double pv = piv > 0.0 ? piv : 1e-300;
-      const double r = rsqrt(pv);
-      double* const c = cb + (st & 1) * 128 + k0;  // c[i] is row k0 + i's broadcast
-      const double t = b[st] * r;
-      c[lane - k0] = t;
-      wave_sync();
-      const double tt = lane > k ? t : 0.0;
-      piv = readlane_d(fma(-t, tt, b[st + 1]), (k + 1) & 63);  // unused after the last step
-      sq = lane == k ? pv * r : sq;
-      rs = lane == k ? r : rs;
-      b[st] = lane > k ? t : b[st];
-#pragma unroll
-      for (int i = st + 1; i < 64; ++i) b[i] = fma(-c[i], tt, b[i]);
-    }
-#pragma unroll
-    for (int st = 0; st < 8; ++st) sT[(k0 + st) * 64 + lane] = b[st];
-#pragma unroll
-    for (int i = 0; i < 56; ++i) b[i] = b[i + 8];
-#pragma unroll
-    for (int i = 56; i < 64; ++i) b[i] = 0.0;
-  }
-  wave_sync();
-  return bad;
-}
-
-// wave_chol64: the same steps with all 64 unrolled and the finished rows kept in the
-// registers, for the 64-column blocks of k_chol_p64 (measured on gfx950 with the other
-// phases of that kernel: 415 us at n = 256 against 530 us for a variant built on the panel
-// loop). On return lane j holds L[j][k] in a[k] for k < j, its pivot in a[j] and the
-// trailing entries A^(j)[i][j] below (i > j), with sq and rs as in wave_chol64_panels.
 __device__ __forceinline__ int wave_chol64(double (&a)[64], double& sq, double& rs, double* colk) {
   const int lane = threadIdx.x & 63;
   int bad = 0;
@@ -477,34 +422,81 @@ __device__ __forceinline__ int wave_chol64(double (&a)[64], double& sq, double& 
   return bad;
 }
 
-// n <= 64: one wave, the column in registers. The solves are rolled loops over the rows
-// kept in LDS: L y = rhs uses sT[k][j] = L[j][k] (j > k), L^T x = y uses
-// L[k][j] = sT[k][j] * rs_j (k > j), the pivots and the running right-hand side read
-// across lanes.
-__global__ __launch_bounds__(64) void k_chol_wave(const double* G, const double* rhs, int n, double* x, int* info,
-                                                  double ridge_rel) {
-  __shared__ double cb[256];
+// n <= 64: four waves, wave w holding rows 16w..16w+15 of every column (lane j: column j).
+// Step k: the wave that holds row k reads the pivot from lane k (its own register, updated in
+// its previous step), scales row k by rsqrt(a_kk) (l_j = a_kj / sqrt(a_kk) for lanes j > k)
+// and broadcasts it through LDS with zeros for j <= k; after one workgroup barrier every wave
+// subtracts l_i l_j from its rows, where the zeros leave finished rows and finished columns as
+// they are. The product is the same for (i, j) and (j, i), so the trailing block stays exactly
+// symmetric. Against the one-wave form (one lane holding a whole column, 64 updates per lane per
+// step) each step costs 16 updates per lane and one barrier: 27 against 37 us at n = 64 for the
+// factor and both solves. Afterwards row k holds, for lane j,
+// L[j][k] (j > k), the pivot (j = k) or the trailing entry A^(j)[k][j] (j < k), so that
+// L[k][j] = row_k[j] / L[j][j]; wave 0 then runs both solves with the rows in LDS, the pivots'
+// reciprocals and the running right-hand side read across lanes.
+__global__ __launch_bounds__(256) void k_chol_wave(const double* G, const double* rhs, int n, double* x, int* info,
+                                                   double ridge_rel) {
+  __shared__ double cb[2][64];
   __shared__ double sT[64 * 64];
-  const int lane = threadIdx.x;
+  __shared__ double srs[64];
+  __shared__ int sbad[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const double dg = lane < n ? G[(long)lane * n + lane] : 0.0;
   double tr = 0.0;
   for (int i = 0; i < n; ++i) tr += readlane_d(dg, i);
   const double ridge = ridge_rel * tr / (double)n;
-  double a[64];
   // lower triangle only, mirrored: the factored matrix is symmetric by construction. Every
   // load is unconditional (clamped address) and masked arithmetically, fma(g, 1, ridge or 0)
   // or fma(g, 0, 1 or 0): a select on the loaded value is turned into a branch around each
-  // load, and the 64 loads then run one after another.
+  // load, and the loads then run one after another.
   const int lc = min(lane, n - 1);
+  double a[16];
 #pragma unroll
-  for (int i = 0; i < 64; ++i) {
+  for (int r = 0; r < 16; ++r) {
+    const int i = 16 * w + r;
     const int ic = min(i, n - 1);
     const double g = G[(long)max(ic, lc) * n + min(ic, lc)];
     const bool in = i < n && lane < n;
-    a[i] = fma(g, in ? 1.0 : 0.0, i == lane ? (in ? ridge : 1.0) : 0.0);
+    a[r] = fma(g, in ? 1.0 : 0.0, i == lane ? (in ? ridge : 1.0) : 0.0);
   }
-  double sq, rs;
-  const int bad = wave_chol64_panels(a, n, sq, rs, cb, sT);
+  int bad = 0;
+  const double* const crow = &cb[0][16 * w];
+  // steps k = 16 blk + st: wave blk holds row k in a[st] (a static register index)
+  const int nblk = (n + 15) >> 4;
+  for (int blk = 0; blk < nblk; ++blk) {
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int k = 16 * blk + st;
+      if (k < n) {  // workgroup-uniform
+        if (w == blk) {
+          const double piv = readlane_d(a[st], k);
+          if (!(piv > 0.0) && bad == 0) bad = k + 1;
+          const double pv = piv > 0.0 ? piv : 1e-300;
+          const double r = rsqrt(pv);
+          const double t = a[st] * r;
+          cb[st & 1][lane] = lane > k ? t : 0.0;
+          if (lane == k) srs[k] = r;
+          a[st] = lane > k ? t : a[st];
+        }
+        __syncthreads();  // two broadcast buffers: a wave still reading step k - 1's is past this barrier
+        // every wave updates all its rows: the zero multipliers of rows i <= k leave them as they
+        // are, and a test per row or per wave costs more than the updates it saves (27 against
+        // 30 to 40 us at n = 64)
+        const double tt = cb[st & 1][lane];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) a[r] = fma(-crow[(st & 1) * 64 + r], tt, a[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sT[(16 * w + r) * 64 + lane] = a[r];
+  if (lane == 0) sbad[w] = bad;
+  __syncthreads();
+  if (w != 0) return;
+  int first = 0;  // the first failing step over the waves (each tests only its own rows)
+  for (int q = 0; q < 4; ++q)
+    if (sbad[q] != 0 && (first == 0 || sbad[q] < first)) first = sbad[q];
+  const double rs = lane < n ? srs[lane] : 1.0;
   const double b = rhs[lc];
   double v = lane < n ? b : 0.0;
   for (int k = 0; k < n; ++k) {
@@ -519,7 +511,7 @@ __global__ __launch_bounds__(64) void k_chol_wave(const double* G, const double*
   }
   if (lane < n) x[lane] = v;
   const bool nonfinite = __any(lane < n && !isfinite(v));
-  if (lane == 0) *info = (bad != 0 && bad <= n) ? bad : nonfinite ? -1 : 0;
+  if (lane == 0) *info = first != 0 ? first : nonfinite ? -1 : 0;
 }
 
 // 64 < n <= CHOL_P64_MAX: right-looking in 64-column panels, the matrix in
@@ -783,7 +775,7 @@ void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, d
 int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* work, hipStream_t s, double ridge_rel) {
   if (n > CHOL_VEC_MAX) return -1;
   if (n <= 64) {
-    hipLaunchKernelGGL(k_chol_wave, dim3(1), dim3(64), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
+    hipLaunchKernelGGL(k_chol_wave, dim3(1), dim3(256), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
   } else if (n <= CHOL_P64_MAX) {
     static bool attr = false;
     if (!attr) {
