@@ -163,6 +163,36 @@ __global__ void k_gram_reduce_groups(const double* partial, long nn, int nsplit,
   }
 }
 
+// Both levels in one launch when there are at most 16 groups (the split count stays below
+// 512 for every layout here): a workgroup takes 16 consecutive entries, thread t sums group
+// t / 16 of entry t % 16 with its 32 loads unrolled (clamped addresses, masked by a factor
+// 0 or 1, so that no branch separates them), and 16 threads add the group sums from LDS.
+// The order of the additions is the two-level order above, so the result is bitwise the same.
+__global__ __launch_bounds__(256) void k_gram_reduce_fused(const double* partial, long nn, int nsplit,
+                                                           double* G) {
+  __shared__ double gs[16][16];
+  const int t = threadIdx.x, el = t & 15, g = t >> 4;
+  const long e = (long)blockIdx.x * 16 + el;
+  const long ec = e < nn ? e : nn - 1;
+  double sum = 0.0;
+  if (g * GRAM_REDUCE_GROUP < nsplit) {
+    double v[GRAM_REDUCE_GROUP];  // all loads first, then the additions in order
+#pragma unroll
+    for (int q = 0; q < GRAM_REDUCE_GROUP; ++q)
+      v[q] = __builtin_nontemporal_load(&partial[(long)min(g * GRAM_REDUCE_GROUP + q, nsplit - 1) * nn + ec]);
+#pragma unroll
+    for (int q = 0; q < GRAM_REDUCE_GROUP; ++q) sum += v[q] * (g * GRAM_REDUCE_GROUP + q < nsplit ? 1.0 : 0.0);
+  }
+  gs[g][el] = sum;
+  __syncthreads();
+  if (t < 16 && e < nn) {
+    const int ng = (nsplit + GRAM_REDUCE_GROUP - 1) / GRAM_REDUCE_GROUP;
+    double s = 0.0;
+    for (int q = 0; q < ng; ++q) s += gs[q][t];
+    G[e] = s;
+  }
+}
+
 __global__ void k_gram_reduce(const double* partial, int n, int nsplit, double* G) {
   const long nn = (long)n * n;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn; e += (long)gridDim.x * blockDim.x) {
@@ -768,6 +798,11 @@ void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, d
   int bx = (int)((nn + 255) / 256);
   if (bx > 1024) bx = 1024;
   const int ng = gram_reduce_groups(nsplit);
+  if (ng <= 16) {
+    hipLaunchKernelGGL(k_gram_reduce_fused, dim3((unsigned)((nn + 15) / 16)), dim3(256), 0, s, partial, nn, nsplit,
+                       G);
+    return;
+  }
   hipLaunchKernelGGL(k_gram_reduce_groups, dim3(bx, ng), dim3(256), 0, s, partial, nn, nsplit, GRAM_REDUCE_GROUP,
                      tmp);
   hipLaunchKernelGGL(k_gram_reduce, dim3(bx), dim3(256), 0, s, tmp, n, ng, G);
