@@ -878,6 +878,8 @@ __global__ void k_shift_diag(const double* G, int n, double shift, double* H, co
 // Inverse of an SPD matrix by in-place Gauss-Jordan sweeps in LDS (no pivoting: the
 // pivots of an SPD matrix stay positive): for each k, with d = a_kk, the other entries
 // take a_ij - a_ik a_kj / d, then row k is divided by d, column k by -d and a_kk = 1 / d.
+// (A variant keeping each thread's entries in registers and passing only row and column k
+// through LDS measured slower at n = 64: 94 against 68 us.)
 constexpr int SPD_INV_MAX = 128;
 __global__ __launch_bounds__(1024) void k_spd_inverse(const double* H, int n, double* C, int* info) {
   __shared__ double sA[SPD_INV_MAX * (SPD_INV_MAX + 1)];
@@ -1018,7 +1020,7 @@ void launch_shift_diag(const double* G, int n, double shift, double* H, const do
   hipLaunchKernelGGL(k_shift_diag, dim3((unsigned)bx), dim3(256), 0, s, G, n, shift, H, grad, neg);
 }
 int launch_spd_inverse(const double* H, int n, double* C, double* work, hipStream_t s) {
-  if (n > SPD_INV_MAX) return -1;
+  if (n < 1 || n > SPD_INV_MAX) return -1;
   hipLaunchKernelGGL(k_spd_inverse, dim3(1), dim3(1024), 0, s, H, n, C, (int*)work);
   return 0;
 }
