@@ -46,7 +46,9 @@ enum {
   ENVAR_EDEVICE = 4,     /* a HIP runtime call failed */
   ENVAR_EBUSY = 5,       /* serving queue is full */
   ENVAR_ECANCELLED = 6,  /* request cancelled before completion */
-  ENVAR_ETIMEOUT = 7     /* envar_wait timed out */
+  ENVAR_ETIMEOUT = 7,    /* envar_wait timed out */
+  ENVAR_EUNCONVERGED = 8 /* served request: >= 1 member-step's pressure solve stopped at the pass cap
+                            before div_tol; the costs are returned */
 };
 
 /* ENVAR_CAVITY_PAPER: the configuration of Sec. 2 (Table tabgeometry) with the boundary
@@ -195,6 +197,7 @@ typedef struct {
   size_t ws_bytes;
   double* J_dev;             /* [n_rows] */
   envar_stats* stats;        /* optional (the call then synchronises) */
+  double* fields_dev;        /* optional: final u, v of every member, layout as in envar_forward */
 } envar_job;
 
 /* Uneven batching: up to 8 ensembles that differ in grid size, Reynolds
@@ -439,8 +442,19 @@ typedef struct {
   double latency_s;   /* done_s - submit_s */
   double queue_s;     /* start_s - submit_s */
   double cell_steps;  /* fluid cells x horizon x n_rows */
-  int32_t status;     /* ENVAR_OK, ENVAR_EDIVERGED (some J non-finite) or ENVAR_ECANCELLED */
+  int32_t status;     /* ENVAR_OK, ENVAR_EDIVERGED (some J non-finite), ENVAR_EUNCONVERGED (see
+                         `unconverged`), ENVAR_EDEVICE (a HIP call of the worker failed; the server
+                         stops) or ENVAR_ECANCELLED */
   int32_t peak_jobs;  /* largest batch this request shared launches with */
+  double max_div;     /* largest max|div_h u| after projection over the request's member-steps */
+  double mean_cycles; /* refinement passes (MIXED) or V-cycles (FP64) per member-step */
+  int32_t unconverged;/* member-steps whose pressure solve stopped at the pass cap before div_tol.
+                         A member that meets div_tol within the cap at every step does the same
+                         arithmetic in any batch (it skips the passes after its own convergence);
+                         the cap follows the batch's recent needs with one pass of headroom and is
+                         lifted to max_cycles after a cut, so a cut member's result can depend on
+                         the requests it shared launches with */
+  int32_t reserved;
 } envar_request_stats;
 
 /* Pool bytes one request occupies while resident. */
@@ -455,7 +469,9 @@ int envar_submit(envar_server* srv, const envar_request* req, uint64_t* ticket);
 
 /* Wait up to timeout_s (< 0: forever) for a ticket; copies its n_rows costs
  * into J_host (may be NULL) and fills stats (may be NULL). Each ticket can be
- * waited on once. Errors: EINVAL (unknown ticket), ETIMEOUT. */
+ * waited on once. Returns the request's status (the costs and stats are copied
+ * for EDIVERGED and EUNCONVERGED too). Errors: EINVAL (unknown ticket),
+ * ETIMEOUT, ECANCELLED, EDEVICE. */
 int envar_wait(envar_server* srv, uint64_t ticket, double timeout_s, double* J_host, envar_request_stats* stats);
 
 /* Stop the worker (pending requests complete as ENVAR_ECANCELLED) and free

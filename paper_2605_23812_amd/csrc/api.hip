@@ -678,63 +678,79 @@ static void grouped(const std::vector<Job*>& J, RowsOf rows_of, Make make, Launc
   }
 }
 
+// A job runs at most its own max_cycles passes whatever the batch's cap (its norm slots are
+// sized by it).
+static int job_cap(const Job& j, int cap) { return std::min(cap, j.P.cap_max); }
+
 template <typename TT>
 static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
   typedef TT T;  // V-cycle type
   const bool mixed = J[0]->P.mixed;
-  int Lmax = 0;
-  for (Job* j : J) Lmax = std::max(Lmax, j->P.nlev_grid);
   const int k_timed = mixed ? 1 : 0;
-  auto vcycle = [&](int k) {
+  // jobs that run pass k (FP64: k = 0 .. cap-1; mixed: k = 1 .. cap)
+  auto in_pass = [&](int k) {
+    std::vector<Job*> Jk;
+    for (Job* j : J)
+      if (mixed ? k <= job_cap(*j, cap) : k < job_cap(*j, cap)) Jk.push_back(j);
+    return Jk;
+  };
+  auto vcycle = [&](int k, const std::vector<Job*>& Jk) {
+    int Lmax = 0;
+    for (Job* j : Jk) Lmax = std::max(Lmax, j->P.nlev_grid);
     const bool timed = tm && k == k_timed;
     if (timed) tm->mark(TM_CYCLE, 0, st);
     for (int l = 0; l < Lmax; ++l) {
       if (timed && l == 0) tm->mark(TM_PRE, 0, st);
       grouped<MGArgs<T>>(
-          J, [&](const Job& j) { return l < j.P.nlev_grid ? j.rows_mg[l] : 0; },
+          Jk, [&](const Job& j) { return l < j.P.nlev_grid ? j.rows_mg[l] : 0; },
           [&](const Job& j, int rows) { return pre_args<T>(j, l, k, rows); },
           [&](const Multi<MGArgs<T>>& m) { launch_mg_pre<T>(m, st); });
       if (timed && l == 0) tm->mark(TM_PRE, 1, st);
     }
     {
       auto m = seg_begin<CoarseArgs>();
-      for (Job* j : J) seg_add(m, coarse_args<T>(*j, k), j->nmem);
+      for (Job* j : Jk) seg_add(m, coarse_args<T>(*j, k), j->nmem);
       launch_mg_coarse<T>(m, st);
     }
     for (int l = Lmax - 1; l >= 0; --l) {
       if (timed && l == 0) tm->mark(TM_POST, 0, st);
       grouped<MGArgs<T>>(
-          J, [&](const Job& j) { return l < j.P.nlev_grid ? j.rows_mg[l] : 0; },
+          Jk, [&](const Job& j) { return l < j.P.nlev_grid ? j.rows_mg[l] : 0; },
           [&](const Job& j, int rows) { return post_args<T>(j, l, k, rows); },
           [&](const Multi<MGArgs<T>>& m) { launch_mg_post<T>(m, l == 0 && !mixed, st); });
       if (timed && l == 0) tm->mark(TM_POST, 1, st);
     }
     if (timed && !mixed) tm->mark(TM_CYCLE, 1, st);
   };
-  // standalone FP64 residual into slot k: for every job when `all`, else only for
-  // jobs whose finest level runs in the one-workgroup coarse kernel (the tiled
-  // finest pre kernel forms it otherwise)
-  auto resid = [&](int k, bool all) {
+  // standalone FP64 residual into slot k (k < 0: each job's last slot, its own cap): for every
+  // job when `all`, else only for jobs whose finest level runs in the one-workgroup coarse
+  // kernel (the tiled finest pre kernel forms it otherwise)
+  auto resid = [&](int k, const std::vector<Job*>& Jk, bool all) {
     auto m = seg_begin<ResidArgs>();
-    for (Job* j : J) {
+    for (Job* j : Jk) {
       if (!all && j->P.nlev_grid > 0) continue;
-      const ResidArgs r = resid_args(*j, k);
+      const ResidArgs r = resid_args(*j, k < 0 ? job_cap(*j, cap) : k);
       seg_add(m, r, r.ntiles * r.nmem);
     }
     if (m.nseg > 0) launch_resid64(m, st);
   };
   if (!mixed) {
-    for (int k = 0; k < cap; ++k) vcycle(k);
+    for (int k = 0; k < cap; ++k) {
+      const std::vector<Job*> Jk = in_pass(k);
+      if (!Jk.empty()) vcycle(k, Jk);
+    }
   } else {
-    // slot k - 1 is written by pass k (its finest pre kernel), slot cap by the last residual
-    resid(0, false);
+    // slot k - 1 is written by pass k (its finest pre kernel), slot cap_j by the last residual
+    resid(0, J, false);
     for (int k = 1; k <= cap; ++k) {
-      vcycle(k);
-      if (k < cap) resid(k, false);
+      const std::vector<Job*> Jk = in_pass(k);
+      if (Jk.empty()) break;
+      vcycle(k, Jk);
+      resid(k, in_pass(k + 1), false);
       if (tm && k == k_timed) tm->mark(TM_CYCLE, 1, st);
     }
     if (tm) tm->mark(TM_RESID, 0, st);
-    resid(cap, true);
+    resid(-1, J, true);
     if (tm) tm->mark(TM_RESID, 1, st);
   }
 }
@@ -783,7 +799,7 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer
       BookArgs bk{};
       bk.nmem = j->nmem;
       bk.norm_slots = j->P.norm_slots;
-      bk.cap = cap;
+      bk.cap = job_cap(*j, cap);
       bk.slot_base = j->P.mixed ? 1 : 0;
       bk.tol = j->P.tol;
       bk.norms = j->w_<double>(j->w.norms);
@@ -874,25 +890,106 @@ static void finish_job(const Job& j, double* J_dev, double* fields_dev, bool spi
   }
 }
 
+// Graph executables, their graphs and capture streams may still have launches
+// queued on the stream that replays them when they are retired (a re-key of the
+// cycle cap or of the job set, or the end of a call that returns before its
+// stream drains). They are kept here with an event recorded on that stream
+// after their last launch and destroyed once it has completed.
+struct Retired {
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t x = nullptr;
+  hipGraph_t g = nullptr;
+  hipStream_t cs = nullptr;
+};
+static std::mutex g_retired_mu;
+static std::vector<Retired> g_retired;
+
+static void destroy_retired(const Retired& r) {
+  if (r.x) (void)hipGraphExecDestroy(r.x);
+  if (r.g) (void)hipGraphDestroy(r.g);
+  if (r.cs) (void)hipStreamDestroy(r.cs);
+  if (r.ev) (void)hipEventDestroy(r.ev);
+}
+
+// destroy every retired object whose launches have completed
+static void reap_retired() {
+  std::vector<Retired> done;
+  {
+    std::lock_guard<std::mutex> lk(g_retired_mu);
+    for (size_t k = 0; k < g_retired.size();) {
+      const hipError_t q = hipEventQuery(g_retired[k].ev);
+      if (q == hipErrorNotReady) {
+        ++k;
+        continue;
+      }
+      done.push_back(g_retired[k]);  // completed (or the event failed: nothing left to wait for)
+      g_retired[k] = g_retired.back();
+      g_retired.pop_back();
+    }
+  }
+  for (const Retired& r : done) destroy_retired(r);
+  (void)hipGetLastError();
+}
+
+// retire objects whose last launch was queued on `s`
+static void retire(Retired r, hipStream_t s) {
+  if (!r.x && !r.g && !r.cs) return;
+  if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(r.ev, s) != hipSuccess) {
+    // no event: wait for the stream instead, then destroy at once
+    if (r.ev) (void)hipEventDestroy(r.ev);
+    r.ev = nullptr;
+    (void)hipStreamSynchronize(s);
+    destroy_retired(r);
+    (void)hipGetLastError();
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_retired_mu);
+    g_retired.push_back(r);
+  }
+  reap_retired();
+}
+
 // Captured batch steps. All jobs advance together, so a step's launch
 // sequence depends on the job set, the step parities and the cycle cap: two
-// graphs (one per parity) are kept per (job set, cap) and replayed.
+// graphs (one per parity) are kept per (job set, cap) and replayed on `ls`.
 struct StepGraphs {
-  hipStream_t cs = nullptr;
+  hipStream_t cs = nullptr;  // capture stream
+  hipStream_t ls = nullptr;  // stream the executables are launched on
   hipGraph_t g[2] = {nullptr, nullptr};
   hipGraphExec_t x[2] = {nullptr, nullptr};
   long key[2] = {-1, -1};
   void drop(int p) {
-    if (x[p]) (void)hipGraphExecDestroy(x[p]);
-    if (g[p]) (void)hipGraphDestroy(g[p]);
+    Retired r;
+    r.x = x[p];
+    r.g = g[p];
+    retire(r, ls);
     x[p] = nullptr;
     g[p] = nullptr;
     key[p] = -1;
   }
+  // destroy everything now: the caller has synchronised the launch stream
+  void destroy_drained() {
+    for (int p = 0; p < 2; ++p) {
+      Retired r;
+      r.x = x[p];
+      r.g = g[p];
+      destroy_retired(r);
+      x[p] = nullptr;
+      g[p] = nullptr;
+      key[p] = -1;
+    }
+    Retired r;
+    r.cs = cs;
+    destroy_retired(r);
+    cs = nullptr;
+  }
   ~StepGraphs() {
     drop(0);
     drop(1);
-    if (cs) (void)hipStreamDestroy(cs);
+    Retired r;
+    r.cs = cs;
+    retire(r, ls);
   }
 };
 
@@ -908,7 +1005,10 @@ struct Driver {
   std::vector<Job*> watched;
   double* pinned = nullptr;
   size_t pinned_n = 0;
+  double unconv_seen = 0.0;  // member-steps cut by the cap, summed over the watched jobs at the last poll
+  Driver() { reap_retired(); }
   ~Driver() {
+    drain();  // no copy into the pinned buffer may outlive it
     if (ev) (void)hipEventDestroy(ev);
     if (pinned) (void)hipHostFree(pinned);
   }
@@ -938,11 +1038,20 @@ struct Driver {
   }
   void absorb(size_t n) {
     int mx = 0;
-    for (size_t q = 0; q < n; q += STATS_STRIDE) mx = std::max(mx, (int)std::ceil(pinned[q + ST_RECENT]));
+    double unconv = 0.0;
+    for (size_t q = 0; q < n; q += STATS_STRIDE) {
+      mx = std::max(mx, (int)std::ceil(pinned[q + ST_RECENT]));
+      unconv += pinned[q + ST_UNCONV];
+    }
     // ST_RECENT decays by one cycle per 16 steps: the cap follows what the members needed
-    // lately (start-up transients fade), one cycle of headroom above it; a member that hits
-    // the cap reports cap cycles, so the next poll raises it
+    // lately (start-up transients fade), one cycle of headroom above it. A member that
+    // converges within the cap at every step does the same arithmetic whatever the cap (it
+    // skips the passes after its own convergence), so only a member that the cap cuts off
+    // depends on its batch; such steps are counted (ST_UNCONV), reported per call and per
+    // request, and lift the cap to its maximum until the next poll.
     cap = std::min(cap_max, std::max(2, mx + 1));
+    if (unconv > unconv_seen) cap = cap_max;
+    unconv_seen = unconv;
   }
   int start_async(const std::vector<Job*>& J, hipStream_t s) {
     size_t n = 0;
@@ -1001,9 +1110,13 @@ struct Driver {
         HIP_OK(hipGraphInstantiate(&G.x[par], g, nullptr, nullptr, 0));
         G.key[par] = key;
       }
+      G.ls = s;  // a Driver replays on one stream; retired executables wait on it
       HIP_OK(hipGraphLaunch(G.x[par], s));
     } else {
-      rc = batch_step<TT>(J, s, cap, sampled ? tm : nullptr);
+      // a job's first step runs with the largest cap, whatever the batch needed lately (the step
+      // that switches its forcing on can need more passes than any step before it): a request
+      // that joins a running batch starts like a forward of its own
+      rc = batch_step<TT>(J, s, fresh ? std::max(cap, cap_max) : cap, sampled ? tm : nullptr);
       if (rc) return rc;
     }
     for (Job* j : J) {
@@ -1467,6 +1580,7 @@ int envar_forward_batch(envar_job* jobs_in, int32_t njobs, void* stream) {
     rc = make_job(P, q.state_dev, q.controls_dev, q.n_rows, q.horizon, q.ws_dev, q.ws_bytes, jobs[k]);
     if (rc) return rc;
     outs[k].J = q.J_dev;
+    outs[k].fields = q.fields_dev;
     graphs = graphs && !(P.p.flags & ENVAR_FLAG_NO_GRAPHS);
   }
   int rc = prec ? run_batch<float>(jobs, outs, s, nullptr, graphs) : run_batch<double>(jobs, outs, s, nullptr, graphs);
@@ -2430,7 +2544,7 @@ struct Request {
   ReqLayout L{};
   size_t off = 0;
   Job job;
-  double* J_pinned = nullptr;
+  double* J_pinned = nullptr;  // host staging: J [n], then stats [n][STATS_STRIDE], then max |div| [n]
   hipEvent_t done_ev = nullptr;
   std::vector<double> J;
   envar_request_stats st{};
@@ -2484,9 +2598,16 @@ struct Server {
           continue;
         }
       }
+      bool dev_err = false;
       for (Request* r : admitted) {
         char* base = pool + r->off;
-        (void)hipMemcpyAsync(base + r->L.ctrl, r->controls.data(), r->controls.size() * 8, hipMemcpyHostToDevice, s);
+        const hipError_t e =
+            hipMemcpyAsync(base + r->L.ctrl, r->controls.data(), r->controls.size() * 8, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+          device_error(r, "control upload", e);
+          dev_err = true;
+          break;
+        }
         r->job.ws = base + r->L.ws;
         r->job.ctrl = (const double*)(base + r->L.ctrl);
         if (tune_job<TT>(r->job, s) != ENVAR_OK) apply_choice(r->job, TileChoice());
@@ -2495,6 +2616,7 @@ struct Server {
         if (D.cap == 0) D.cap = D.cap_max;
         ++D.epoch;
       }
+      if (dev_err) break;
       if (!running.empty()) {
         std::vector<Job*> jobs;
         int left = 1 << 30;
@@ -2517,8 +2639,21 @@ struct Server {
           if (r->job.step >= r->job.horizon) {
             double* Jd = (double*)(pool + r->off + r->L.J);
             finish_job(r->job, Jd, nullptr, false, s);
-            (void)hipMemcpyAsync(r->J_pinned, Jd, (size_t)r->n * 8, hipMemcpyDeviceToHost, s);
-            (void)hipEventRecord(r->done_ev, s);
+            const size_t n = (size_t)r->n;
+            hipError_t e = hipMemcpyAsync(r->J_pinned, Jd, n * 8, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+              e = hipMemcpyAsync(r->J_pinned + n, r->job.w_<double>(r->job.w.stats), n * STATS_STRIDE * 8,
+                                 hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+              e = hipMemcpyAsync(r->J_pinned + n * (1 + STATS_STRIDE), r->job.w_<double>(r->job.w.divmax), n * 8,
+                                 hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipEventRecord(r->done_ev, s);
+            if (e != hipSuccess) {
+              running.erase(running.begin() + k);
+              device_error(r, "result download", e);
+              dev_err = true;
+              break;
+            }
             r->phase = 2;
             finishing.push_back(r);
             running.erase(running.begin() + k);
@@ -2528,21 +2663,41 @@ struct Server {
           }
         }
         if (changed) ++D.epoch;
+        if (dev_err) break;
       }
       // completions
       for (size_t k = 0; k < finishing.size();) {
         Request* r = finishing[k];
         hipError_t q = hipEventQuery(r->done_ev);
         if (q == hipErrorNotReady && running.empty()) q = hipEventSynchronize(r->done_ev);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+          finishing.erase(finishing.begin() + k);
+          device_error(r, "completion event", q);
+          dev_err = true;
+          break;
+        }
         if (q == hipSuccess) {
-          r->J.assign(r->J_pinned, r->J_pinned + r->n);
+          const size_t n = (size_t)r->n;
+          r->J.assign(r->J_pinned, r->J_pinned + n);
           bool finite = true;
           for (double x : r->J) finite = finite && std::isfinite(x);
+          double cyc = 0.0, steps = 0.0, unconv = 0.0, mdiv = 0.0;
+          for (size_t i = 0; i < n; ++i) {
+            const double* m = r->J_pinned + n + i * STATS_STRIDE;
+            cyc += m[ST_CYCLES];
+            steps += m[ST_STEPS];
+            unconv += m[ST_UNCONV];
+            const double d = r->J_pinned[n * (1 + STATS_STRIDE) + i];
+            mdiv = (d > mdiv || d != d) ? d : mdiv;
+          }
           std::lock_guard<std::mutex> lk(mu);
           r->st.done_s = now();
           r->st.latency_s = r->st.done_s - r->st.submit_s;
           r->st.queue_s = r->st.start_s - r->st.submit_s;
-          r->st.status = finite ? ENVAR_OK : ENVAR_EDIVERGED;
+          r->st.max_div = mdiv;
+          r->st.mean_cycles = steps > 0 ? cyc / steps : 0.0;
+          r->st.unconverged = (int)unconv;
+          r->st.status = !finite ? ENVAR_EDIVERGED : unconv > 0 ? ENVAR_EUNCONVERGED : ENVAR_OK;
           alloc.release(r->off, r->L.total);
           r->phase = 3;
           finishing.erase(finishing.begin() + k);
@@ -2551,9 +2706,27 @@ struct Server {
           ++k;
         }
       }
+      if (dev_err) break;
     }
     D.drain();
     (void)hipStreamSynchronize(s);
+    // the stream is drained and is destroyed before the Driver: no graph may wait on it later
+    D.G.destroy_drained();
+  }
+
+  // A HIP call of the worker failed: the request completes with ENVAR_EDEVICE and the
+  // server stops (pending and running requests then complete as cancelled).
+  void device_error(Request* r, const char* what, hipError_t e) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(mu);
+    err = buf;
+    r->st.status = ENVAR_EDEVICE;
+    r->st.done_s = now();
+    r->st.latency_s = r->st.done_s - r->st.submit_s;
+    r->phase = 3;
+    stop = true;
+    cv_done.notify_all();
   }
 };
 
@@ -2624,7 +2797,7 @@ int envar_submit(envar_server* srv, const envar_request* req, uint64_t* ticket) 
   r->job.nmem = r->n;
   r->job.horizon = r->horizon;
   r->st.cell_steps = (double)r->P.ncells * r->horizon * r->n;
-  if (hipHostMalloc((void**)&r->J_pinned, (size_t)r->n * 8, hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc((void**)&r->J_pinned, (size_t)r->n * (2 + STATS_STRIDE) * 8, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess) {
     if (r->J_pinned) (void)hipHostFree(r->J_pinned);
     delete r;
@@ -2668,13 +2841,23 @@ int envar_wait(envar_server* srv, uint64_t ticket, double timeout_s, double* J_h
   if (J_host) std::copy(r->J.begin(), r->J.end(), J_host);
   if (stats) *stats = r->st;
   const int status = r->st.status;
+  const int unconv = r->st.unconverged;
   S.table.erase(it);
   (void)hipHostFree(r->J_pinned);
   (void)hipEventDestroy(r->done_ev);
   delete r;
-  return status == ENVAR_EDIVERGED ? fail(ENVAR_EDIVERGED, "a cost of ticket %llu is non-finite",
-                                         (unsigned long long)ticket)
-                                   : ENVAR_OK;
+  const unsigned long long t = (unsigned long long)ticket;
+  switch (status) {
+    case ENVAR_OK:
+      return ENVAR_OK;
+    case ENVAR_EDIVERGED:
+      return fail(ENVAR_EDIVERGED, "a cost of ticket %llu is non-finite", t);
+    case ENVAR_EUNCONVERGED:
+      return fail(ENVAR_EUNCONVERGED, "ticket %llu: %d member-step(s) stopped at the pass cap before div_tol", t,
+                  unconv);
+    default:
+      return fail(status, "ticket %llu failed on the device: %s", t, S.err.c_str());
+  }
 }
 
 int envar_server_destroy(envar_server* srv) {

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libenvar.so")
 
-OK, EINVAL, ENOMEM, EDIVERGED, EDEVICE, EBUSY, ECANCELLED, ETIMEOUT = range(8)
+OK, EINVAL, ENOMEM, EDIVERGED, EDEVICE, EBUSY, ECANCELLED, ETIMEOUT, EUNCONVERGED = range(9)
 CAVITY, CHANNEL, CAVITY_PAPER = 0, 1, 2
 REGION_COLUMN, REGION_CAVITY, REGION_BOX = 0, 1, 2
 FP64, MIXED = 0, 1
@@ -79,7 +79,7 @@ class _Job(ctypes.Structure):
         ("problem", _Problem), ("state_dev", ctypes.c_void_p), ("controls_dev", ctypes.c_void_p),
         ("n_rows", ctypes.c_int32), ("horizon", ctypes.c_int32), ("m", ctypes.c_int64),
         ("ws_dev", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("J_dev", ctypes.c_void_p),
-        ("stats", ctypes.POINTER(Stats)),
+        ("stats", ctypes.POINTER(Stats)), ("fields_dev", ctypes.c_void_p),
     ]
 
 
@@ -97,7 +97,8 @@ class RequestStats(ctypes.Structure):
     """envar_request_stats: timings (seconds since the server started) and status of a served request."""
     _fields_ = [("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
                 ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double), ("cell_steps", ctypes.c_double),
-                ("status", ctypes.c_int32), ("peak_jobs", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("peak_jobs", ctypes.c_int32), ("max_div", ctypes.c_double),
+                ("mean_cycles", ctypes.c_double), ("unconverged", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -379,10 +380,11 @@ def forward(p, state, controls, horizon, ws=None, J=None, fields=False, stats=Tr
     return J, F, (st.as_dict() if st is not None else None)
 
 
-def forward_batch(jobs):
+def forward_batch(jobs, fields=False):
     """Uneven batch: jobs = [(problem, state, controls [n, m] device FP64, horizon)], up to 8.
 
-    Returns a list of (J tensor, stats dict) in job order.
+    Returns a list of (J tensor, stats dict) in job order, or of (J, stats, fields tensor) with
+    fields=True (each member's final u, v flattened as in `forward`; see `split_fields`).
     """
     import torch
 
@@ -393,7 +395,12 @@ def forward_batch(jobs):
         ws = _bytes_tensor(workspace_bytes(p, n))
         J = torch.empty(n, dtype=torch.float64, device=ctrl.device)
         st = Stats()
-        keep.append((ws, J, st))
+        F = None
+        if fields:
+            NX, NY = p.box_dims()
+            F = torch.empty((n, NY * (NX + 1) + (NY + 1) * NX), dtype=torch.float64, device=ctrl.device)
+            arr[k].fields_dev = F.data_ptr()
+        keep.append((ws, J, st, F))
         arr[k].problem = p.c()
         arr[k].state_dev = state.data_ptr()
         arr[k].controls_dev = ctrl.data_ptr()
@@ -404,7 +411,9 @@ def forward_batch(jobs):
     rc = lib().envar_forward_batch(arr, len(jobs), _stream())
     if rc != EDIVERGED:
         _check(rc)
-    return [(J, st.as_dict()) for (_, J, st) in keep]
+    if fields:
+        return [(J, st.as_dict(), F) for (_, J, st, F) in keep]
+    return [(J, st.as_dict()) for (_, J, st, _) in keep]
 
 
 def split_fields(p, F):
@@ -611,7 +620,7 @@ class Server:
         rc = lib().envar_wait(self.h, ticket, timeout, J.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
         if rc == ETIMEOUT:
             raise TimeoutError(lib().envar_last_error().decode())
-        if rc not in (OK, EDIVERGED):
+        if rc not in (OK, EDIVERGED, EUNCONVERGED):
             _check(rc)
         del self._keep[ticket]
         return J, st.as_dict()

@@ -24,10 +24,13 @@ def _run(rows, J, precision):
     return g.cpu().numpy()
 
 
-# n (or m when n > m) spans every Cholesky variant: one wave (<= 64), 64-column panels (<= 256),
-# 32-column panels (<= 448) and the unblocked global-memory kernel
+# n (or m when n > m) spans every Cholesky variant: four waves of 16 rows each (<= 64), 64-column
+# panels (<= 256), 32-column panels (<= 448) and the unblocked global-memory kernel. The four-wave
+# factor is hit at every wave boundary (16, 32, 48), with a partly filled fourth wave (49, 63) and
+# full (64).
 @pytest.mark.parametrize("n,m", [(8, 4096), (64, 5000), (17, 333), (130, 1024), (1, 50), (16, 8), (40, 33),
-                                 (256, 2048), (200, 100), (300, 1500), (500, 3000)])
+                                 (256, 2048), (200, 100), (300, 1500), (500, 3000),
+                                 (16, 700), (32, 700), (48, 700), (49, 700), (63, 700)])
 def test_gradient_fp64_matches_lstsq(n, m):
     rng = np.random.default_rng(n * 1000 + m)
     rows = rng.standard_normal((n + 1, m)) * 1e-2
