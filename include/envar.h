@@ -228,6 +228,20 @@ size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
 int envar_gradient(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
                    int32_t precision, void* ws_dev, size_t ws_bytes, double* g_dev, void* stream);
 
+/* For callers that cannot allocate device memory at call time (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): envar_gradient with its workspace in
+ * a library-owned static device array of ENVAR_GRADIENT_STATIC_MAX_BYTES (64 MiB), one copy on
+ * every GPU the library runs on, held until the process ends. Arguments, results and errors as
+ * envar_gradient; the call allocates nothing (no device or pinned host memory: the solve's
+ * status word is read through pageable memory). Problems whose envar_gradient_bytes exceed the
+ * array (e.g. n = 64, m = 65,536 fits in both precisions; n = 256, m = 65,536 does not) return
+ * ENVAR_ENOMEM before any launch. Every call on one GPU uses the same array: calls that overlap
+ * on one GPU (other threads, other streams) race and must be serialised by the caller; nothing
+ * in the array needs clearing between calls (every kernel writes what a later one reads). */
+#define ENVAR_GRADIENT_STATIC_MAX_BYTES ((size_t)64 << 20)
+int envar_gradient_static(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
+                          int32_t precision, double* g_dev, void* stream);
+
 /* ---- Vector-observation EnVar (Sec. 3.3.1, with the observation of Sec. 4.1) ----
  * The observation H q(f) is the velocity fluctuation u' = u - u_bar at four sensors on
  * the cavity lid, x = x_cav + 1/5, 2/5, 3/5, 4/5, y = 0 (the paper places its cavity at

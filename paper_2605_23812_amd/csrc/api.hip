@@ -1688,9 +1688,11 @@ extern "C" size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision) 
 }
 
 namespace envar {
+// pinned_flag: read the solve's status word through a pinned word of this host thread (allocated
+// on the thread's first call and kept); otherwise through pageable memory (no allocation)
 template <typename TX>
 static int gradient_impl(const double* ctrl, const double* J, int n, long m, int precision, void* ws, double* g,
-                         hipStream_t s) {
+                         hipStream_t s, bool pinned_flag = true) {
   const GradLayout L = grad_layout(n, m, precision);
   TX* X = at<TX>(ws, L.X);
   double* dJ = at<double>(ws, L.dJ);
@@ -1716,11 +1718,17 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   // a pivot that is not positive after the ridge (a non-finite Gram) or a non-finite solution
   // (a non-finite cost) is reported instead of returning garbage: the solve leaves both in one
   // word, read through a pinned word of this host thread (allocated once, kept for the process)
-  static thread_local int* flag = nullptr;
-  if (!flag) HIP_OK(hipHostMalloc((void**)&flag, sizeof(int), hipHostMallocDefault));
-  HIP_OK(hipMemcpyAsync(flag, at<int>(ws, L.info), sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  const int info = *flag;
+  int info = 0;
+  if (pinned_flag) {
+    static thread_local int* flag = nullptr;
+    if (!flag) HIP_OK(hipHostMalloc((void**)&flag, sizeof(int), hipHostMallocDefault));
+    HIP_OK(hipMemcpyAsync(flag, at<int>(ws, L.info), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    info = *flag;
+  } else {
+    HIP_OK(hipMemcpyAsync(&info, at<int>(ws, L.info), sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
   if (info > 0) return fail(ENVAR_EDIVERGED, "the ensemble Gram is not positive definite (pivot %d)", info);
   if (info < 0) return fail(ENVAR_EDIVERGED, "non-finite least-squares solution (a cost is not finite?)");
   return ENVAR_OK;
@@ -1739,6 +1747,52 @@ extern "C" int envar_gradient(const double* controls_dev, const double* J_dev, i
   if (precision == ENVAR_MIXED)
     return gradient_impl<float>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
   return gradient_impl<double>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------- gradient without allocation
+// envar_gradient for callers that cannot allocate (code under HIP graph capture, serving loops,
+// harnesses that forbid allocation): the workspace is this file-scope device array, one copy per
+// GPU, held until the process ends. Host code never passes the array's name to a kernel or a
+// copy (on the host it is a stand-in, not a device address): each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+namespace envar {
+static __device__ __align__(256) unsigned char scratch[ENVAR_GRADIENT_STATIC_MAX_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[SCRATCH_MAX_DEVICES];
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(ENVAR_EDEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ENVAR_EDEVICE, "hipGetSymbolAddress returned NULL for the gradient scratch");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return ENVAR_OK;
+}
+}  // namespace envar
+
+extern "C" int envar_gradient_static(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
+                                     int32_t precision, double* g_dev, void* stream) {
+  if (n < 1 || m < 1) return fail(ENVAR_EINVAL, "n and m must be >= 1");
+  if (!controls_dev || !J_dev || !g_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
+  if (precision != ENVAR_FP64 && precision != ENVAR_MIXED) return fail(ENVAR_EINVAL, "unknown precision");
+  if (std::min<long>(n, m) > 1024) return fail(ENVAR_EINVAL, "min(n, m) = %ld exceeds 1024", std::min<long>(n, m));
+  const GradLayout L = grad_layout(n, m, precision);
+  if (L.total > ENVAR_GRADIENT_STATIC_MAX_BYTES)
+    return fail(ENVAR_ENOMEM, "n = %d, m = %lld needs %zu bytes of scratch; the static array holds %zu", n,
+                (long long)m, L.total, (size_t)ENVAR_GRADIENT_STATIC_MAX_BYTES);
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc) return rc;
+  if (precision == ENVAR_MIXED)
+    return gradient_impl<float>(controls_dev, J_dev, n, m, precision, ws, g_dev, (hipStream_t)stream, false);
+  return gradient_impl<double>(controls_dev, J_dev, n, m, precision, ws, g_dev, (hipStream_t)stream, false);
 }
 
 // ---------------------------------------------------------------------------- vector-observation EnVar step

@@ -28,7 +28,7 @@ FLAG_TILES_32 = 32
 EXPORTS = (
     "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",
     "envar_state_init", "envar_state_read", "envar_spinup", "envar_forward", "envar_forward_batch",
-    "envar_gradient_bytes", "envar_gradient", "envar_iterate_bytes", "envar_iterate",
+    "envar_gradient_bytes", "envar_gradient", "envar_gradient_static", "envar_iterate_bytes", "envar_iterate",
     "envar_last_error", "envar_version", "envar_stream_copy",
     "envar_request_bytes", "envar_server_create", "envar_submit", "envar_wait", "envar_server_destroy",
     "envar_forward_obs", "envar_gn_bytes", "envar_gn_step", "envar_posterior_bytes", "envar_posterior_var",
@@ -435,6 +435,25 @@ def gradient(controls, J, precision=FP64, ws=None, g=None):
     if g is None:
         g = torch.empty(m, dtype=torch.float64, device=controls.device)
     _check(lib().envar_gradient(_ptr(controls), _ptr(J), n, m, precision, _ptr(ws), ws.numel(), _ptr(g), _stream()))
+    return g
+
+
+GRADIENT_STATIC_MAX_BYTES = 64 << 20
+
+
+def gradient_static(controls, J, precision=FP64, g=None):
+    """`gradient` with the library's static device scratch as workspace (no allocation in the call).
+
+    For n, m whose gradient_bytes exceed GRADIENT_STATIC_MAX_BYTES the call raises (ENOMEM). Calls
+    on one GPU share the scratch: overlapping calls race.
+    """
+    import torch
+
+    n = controls.shape[0] - 1
+    m = controls.shape[1]
+    if g is None:
+        g = torch.empty(m, dtype=torch.float64, device=controls.device)
+    _check(lib().envar_gradient_static(_ptr(controls), _ptr(J), n, m, precision, _ptr(g), _stream()))
     return g
 
 

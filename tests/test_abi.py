@@ -57,3 +57,20 @@ def test_oracle_and_library_agree_on_the_control_region():
                               (16, E.REGION_BOX, "box", (1.2, 1.9, -0.5, 0.3))]:
         kw = dict(box=box) if box else {}
         assert E.control_dim(E.Problem(inv_h=n, region=reg, **kw)) == OP(inv_h=n, region=oreg, **kw).m
+
+
+def test_static_gradient_rejects_sizes_beyond_its_scratch_before_any_launch():
+    """envar_gradient_static checks the workspace size against its static array on the host (no
+    device call before the check, so this runs without a GPU)."""
+    import ctypes
+
+    L = E.lib()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the size check comes first
+    for n, m, prec in [(256, 65536, E.MIXED), (64, 262144, E.FP64)]:
+        assert E.gradient_bytes(n, m, prec) > E.GRADIENT_STATIC_MAX_BYTES
+        rc = L.envar_gradient_static(fake, fake, n, m, prec, fake, None)
+        assert rc == E.ENOMEM, rc
+        assert b"static array" in L.envar_last_error()
+    # the benchmark's reduction fits in both precisions
+    assert E.gradient_bytes(64, 65536, E.FP64) <= E.GRADIENT_STATIC_MAX_BYTES
+    assert E.gradient_bytes(64, 65536, E.MIXED) <= E.GRADIENT_STATIC_MAX_BYTES
