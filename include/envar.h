@@ -109,8 +109,15 @@ enum {
   ENVAR_FLAG_NO_TUNE = 4,   /* 8-row step tiles, 16-row multigrid tiles */
   ENVAR_FLAG_TILES_8 = 8,   /* 8 rows everywhere */
   ENVAR_FLAG_TILES_16 = 16, /* 16 rows everywhere (step tiles only where the rows align) */
-  ENVAR_FLAG_TILES_32 = 32  /* 32-row multigrid tiles where the cavity rows take whole tiles
+  ENVAR_FLAG_TILES_32 = 32, /* 32-row multigrid tiles where the cavity rows take whole tiles
                                (16 elsewhere), 16-row step tiles where the rows align */
+  /* By default the members of a forward (or of a batch) advance in two lanes: member groups of
+   * about equal work on two streams (the call's stream and one the library keeps per host
+   * thread), each with its own step graphs and cycle cap, so that one group's latency-bound
+   * phases overlap with the other's bandwidth-bound kernels. The call stays ordered on its
+   * stream (the lanes fork from it and join back). Results do not depend on the lanes. This
+   * flag runs every member on the call's stream. */
+  ENVAR_FLAG_ONE_LANE = 64
 };
 
 /* Per-call statistics (filled only when a non-NULL pointer is passed; then the

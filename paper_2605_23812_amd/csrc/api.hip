@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <cmath>
@@ -256,52 +257,68 @@ struct WS {
   size_t total;
 };
 
-static WS make_ws(const Plan& P, int nmem) {
-  WS w;
+// `stride` (optional) receives each buffer's bytes per member: every buffer is member-major, so
+// the members [a, b) of a workspace are a workspace of their own at offsets + a * stride.
+static WS make_ws(const Plan& P, int nmem, WS* stride = nullptr) {
+  WS w{}, st{};
   size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t at = o;
-    o = align256(o + bytes);
-    return at;
+  auto take = [&](size_t& field, size_t& sfield, size_t per_member) {
+    field = o;
+    sfield = per_member;
+    o = align256(o + (size_t)nmem * per_member);
   };
-  const long pl = P.lev[0].plane();
+  const size_t pl = (size_t)P.lev[0].plane();
   const size_t tsz = 8;  // tendency storage (FP64 in both precisions)
   const size_t vsz = P.mixed ? 4 : 8;  // V-cycle storage
-  w.u = take(nmem * pl * 8);
-  w.v = take(nmem * pl * 8);
-  w.us = take(nmem * pl * 8);   // u*, v* of even steps
-  w.vs = take(nmem * pl * 8);
-  w.us2 = take(nmem * pl * 8);  // u*, v* of odd steps (the fused predictor reads the other parity)
-  w.vs2 = take(nmem * pl * 8);
-  w.tuA = take(nmem * pl * tsz);
-  w.tvA = take(nmem * pl * tsz);
-  w.tuB = take(nmem * pl * tsz);
-  w.tvB = take(nmem * pl * tsz);
-  w.phiA = take(nmem * pl * 8);
-  w.phiB = P.mixed ? 0 : take(nmem * pl * 8);
-  w.phiC = take(nmem * pl * 8);  // previous pressure / next warm start
-  w.phiQ = take(nmem * pl * 8);  // pressure two steps back (quadratic warm start)
+  take(w.u, st.u, pl * 8);
+  take(w.v, st.v, pl * 8);
+  take(w.us, st.us, pl * 8);    // u*, v* of even steps
+  take(w.vs, st.vs, pl * 8);
+  take(w.us2, st.us2, pl * 8);  // u*, v* of odd steps (the fused predictor reads the other parity)
+  take(w.vs2, st.vs2, pl * 8);
+  take(w.tuA, st.tuA, pl * tsz);
+  take(w.tvA, st.tvA, pl * tsz);
+  take(w.tuB, st.tuB, pl * tsz);
+  take(w.tvB, st.tvB, pl * tsz);
+  take(w.phiA, st.phiA, pl * 8);
+  if (!P.mixed) take(w.phiB, st.phiB, pl * 8);
+  take(w.phiC, st.phiC, pl * 8);  // previous pressure / next warm start
+  take(w.phiQ, st.phiQ, pl * 8);  // pressure two steps back (quadratic warm start)
   // FP64: pressure three steps back (cubic warm start: 2.09 -> 1.78 V-cycles per step at the
   // benchmark shape); mixed precision keeps the quadratic one (1.30 refinement passes per step
   // against 1.46 with the cubic)
-  w.phiR = P.mixed ? 0 : take(nmem * pl * 8);
-  w.b0 = take(nmem * pl * 8);
-  w.e0 = P.mixed ? take(nmem * pl * 4) : 0;
-  w.r0 = P.mixed ? take(nmem * pl * 4) : 0;
-  for (int l = 1; l <= P.nlev_grid; ++l) {
-    const long lp = P.lev[l].plane();
-    w.lphiA[l] = take(nmem * lp * vsz);
-    w.lphiB[l] = (l < P.nlev_grid) ? take(nmem * lp * vsz) : 0;
-    w.lb[l] = take(nmem * lp * vsz);
+  if (!P.mixed) take(w.phiR, st.phiR, pl * 8);
+  take(w.b0, st.b0, pl * 8);
+  if (P.mixed) {
+    take(w.e0, st.e0, pl * 4);
+    take(w.r0, st.r0, pl * 4);
   }
-  w.s1u = take(nmem * P.cplane * 8);
-  w.s1v = take(nmem * P.cplane * 8);
-  w.s2part = take((size_t)nmem * P.st_tiles * 8);
-  w.norms = take((size_t)nmem * P.norm_slots * 8);
-  w.stats = take((size_t)nmem * STATS_STRIDE * 8);
-  w.divmax = take((size_t)nmem * 8);
+  for (int l = 1; l <= P.nlev_grid; ++l) {
+    const size_t lp = (size_t)P.lev[l].plane();
+    take(w.lphiA[l], st.lphiA[l], lp * vsz);
+    if (l < P.nlev_grid) take(w.lphiB[l], st.lphiB[l], lp * vsz);
+    take(w.lb[l], st.lb[l], lp * vsz);
+  }
+  take(w.s1u, st.s1u, (size_t)P.cplane * 8);
+  take(w.s1v, st.s1v, (size_t)P.cplane * 8);
+  take(w.s2part, st.s2part, (size_t)P.st_tiles * 8);
+  take(w.norms, st.norms, (size_t)P.norm_slots * 8);
+  take(w.stats, st.stats, (size_t)STATS_STRIDE * 8);
+  take(w.divmax, st.divmax, 8);
   w.total = o;
+  if (stride) *stride = st;
   return w;
+}
+
+// the workspace of members [a, a + k) of `w`: every buffer offset moved by a members
+static WS slice_ws(const WS& w, const WS& stride, int a) {
+  static_assert(sizeof(WS) % sizeof(size_t) == 0, "WS holds offsets only");
+  WS out = w;
+  size_t* d = (size_t*)&out;
+  const size_t* sd = (const size_t*)&stride;
+  constexpr size_t nf = sizeof(WS) / sizeof(size_t) - 1;  // every field but `total` (the last)
+  for (size_t f = 0; f < nf; ++f) d[f] += (size_t)a * sd[f];
+  return out;
 }
 
 // dense inverse of the coarsest operator (Gauss-Jordan with partial pivoting)
@@ -370,6 +387,7 @@ struct Timer {
   std::vector<hipEvent_t> ev;  // [sample][TM_N][2]
   std::vector<unsigned char> rec;  // [sample][TM_N] both edges recorded
   int samples = 0;
+  int members = 0;  // members of the timed launches (the first lane's)
   int cur = -1;  // sample index of the current step, -1 = not sampled
   int begin_step(int s, int steps) {
     cur = -1;
@@ -1022,6 +1040,10 @@ struct Driver {
     return ENVAR_OK;
   }
   int absorb_now(const std::vector<Job*>& J, hipStream_t s) {
+    // a poll started before the job set changed would later be absorbed over the old job count
+    // (dropping the new jobs from the cap) and may still be copying into the buffer that is
+    // resized below: wait for it and let this synchronous snapshot supersede it
+    drain();
     size_t n = 0;
     for (Job* j : J) n += (size_t)j->nmem * STATS_STRIDE;
     int rc = ensure_pinned(n);
@@ -1440,48 +1462,193 @@ static void put_rows(const Job& j, envar_stats* st) {
   for (int l = 0; l < 4; ++l) st->rows_mg[l] = l < j.P.nlev_grid ? j.rows_mg[l] : 0;
 }
 
-// Integrate every job to its own horizon; jobs leave the batch as they finish.
-template <typename TT>
-static int run_batch(std::vector<Job>& jobs, const std::vector<JobOut>& outs, hipStream_t s, Timer* tm, bool graphs) {
-  int cap_max = 0;
-  for (Job& j : jobs) {
-    const int rc = tune_job<TT>(j, s);
-    if (rc) return rc;
-    init_members<TT>(j, s);
-    cap_max = std::max(cap_max, j.P.cap_max);
-  }
-  Driver D;
-  D.cap = D.cap_max = cap_max;
-  std::vector<Job*> active;
-  std::vector<int> which;
+// ---------------------------------------------------------------------------- lanes
+// The members of a batch advance in lanes: member groups on separate streams, each with its own
+// step graphs and cycle cap. Members are independent over the horizon, so one lane's
+// latency-bound phases (the coarse multigrid levels, launches of passes its members skip, the
+// gaps between graph nodes) overlap with another lane's bandwidth-bound kernels. A lane runs
+// member slices of the batch's jobs: jobs are split into contiguous member ranges of about equal
+// work and the slices dealt to the least loaded lane, largest first. Results do not depend on the
+// split (per-member convergence; every kernel is per member).
+constexpr int LANES_DEFAULT = 2;
+
+struct Unit {
+  int job, a, b;  // members [a, b) of jobs[job]
+  double work;    // fluid cells x members x steps
+};
+
+static std::vector<std::vector<Unit>> make_lanes(const std::vector<Job>& jobs, int nlanes) {
+  double W = 0.0;
+  std::vector<Unit> units;
+  for (const Job& j : jobs) W += (double)j.P.ncells * j.nmem * j.horizon;
+  const double target = W / std::max(1, nlanes);
   for (size_t k = 0; k < jobs.size(); ++k) {
-    active.push_back(&jobs[k]);
-    which.push_back((int)k);
-  }
-  while (!active.empty()) {
-    int left = 1 << 30, longest = 0;
-    for (Job* j : active) {
-      left = std::min(left, j->horizon - j->step);
-      longest = std::max(longest, j->horizon);
+    const Job& j = jobs[k];
+    const double wj = (double)j.P.ncells * j.nmem * j.horizon;
+    int parts = (int)std::lround(wj / std::max(target, 1.0));
+    parts = std::max(1, std::min(parts, std::min(j.nmem, nlanes)));
+    for (int q = 0; q < parts; ++q) {
+      const int a = (int)((long)j.nmem * q / parts), b = (int)((long)j.nmem * (q + 1) / parts);
+      units.push_back({(int)k, a, b, (double)j.P.ncells * (b - a) * j.horizon});
     }
-    if (tm && tm->begin_step(active[0]->step, longest)) return fail(ENVAR_EDEVICE, "hipEventCreate failed");
-    int rc = D.step<TT>(active, s, tm, left, graphs);
-    if (rc) return rc;
-    bool changed = false;
-    for (size_t k = 0; k < active.size();) {
-      if (active[k]->step >= active[k]->horizon) {
-        const JobOut& o = outs[which[k]];
-        finish_job(*active[k], o.J, o.fields, o.spinup_store, s);
-        active.erase(active.begin() + k);
-        which.erase(which.begin() + k);
-        changed = true;
+  }
+  std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.work > y.work; });
+  const int L = std::max(1, std::min(nlanes, (int)units.size()));
+  std::vector<std::vector<Unit>> lanes(L);
+  std::vector<double> load(L, 0.0);
+  for (const Unit& u : units) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lanes[l].push_back(u);
+    load[l] += u.work;
+  }
+  return lanes;
+}
+
+// members [a, b) of job j (their control rows, sensor series and workspace slices)
+static Job slice_job(const Job& j, const WS& stride, int a, int b) {
+  Job s = j;
+  s.w = slice_ws(j.w, stride, a);
+  s.nmem = b - a;
+  if (j.ctrl) s.ctrl = j.ctrl + (size_t)a * j.P.m;
+  if (j.obs) s.obs = j.obs + (size_t)a * OBS_CHANNELS * j.obs_K;
+  return s;
+}
+
+// Streams and events of the lanes beyond the first (which runs on the call's stream): created
+// once per host thread at default priority and kept for the process.
+struct LaneRes {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  int ensure(int nstreams, int nevents) {
+    while ((int)streams.size() < nstreams) {
+      hipStream_t q = nullptr;
+      HIP_OK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+      streams.push_back(q);
+    }
+    while ((int)events.size() < nevents) {
+      hipEvent_t e = nullptr;
+      HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      events.push_back(e);
+    }
+    return ENVAR_OK;
+  }
+};
+static thread_local LaneRes t_lanes;
+
+// `dst` waits for everything queued so far on `src`
+static int stream_after(hipStream_t dst, hipStream_t src, hipEvent_t e) {
+  HIP_OK(hipEventRecord(e, src));
+  HIP_OK(hipStreamWaitEvent(dst, e, 0));
+  return ENVAR_OK;
+}
+
+// Integrate every job to its own horizon; jobs leave their lane as they finish. Kernel timing
+// (tm) samples the first lane; a sampled step runs with the other lanes held, so that its
+// kernels are timed alone.
+template <typename TT>
+static int run_batch(std::vector<Job>& jobs, const std::vector<JobOut>& outs, hipStream_t s, Timer* tm, bool graphs,
+                     int nlanes = 1) {
+  const auto plan = make_lanes(jobs, nlanes);
+  const int L = (int)plan.size();
+  std::vector<std::vector<Job>> lj(L);
+  std::vector<std::vector<JobOut>> lo(L);
+  int cap_max = 0;
+  for (int l = 0; l < L; ++l)
+    for (const Unit& u : plan[l]) {
+      const Job& j = jobs[u.job];
+      JobOut o = outs[u.job];
+      if (u.a == 0 && u.b == j.nmem) {
+        lj[l].push_back(j);
       } else {
-        ++k;
+        WS stride;
+        (void)make_ws(j.P, j.nmem, &stride);
+        lj[l].push_back(slice_job(j, stride, u.a, u.b));
+        const Geo& g = j.P.lev[0];
+        if (o.J) o.J += u.a;
+        if (o.fields) o.fields += (size_t)u.a * ((size_t)g.ny * (g.nx + 1) + (size_t)(g.ny + 1) * g.nx);
+        o.spinup_store = false;  // a spin-up has one member and is never split
+      }
+      lo[l].push_back(o);
+      cap_max = std::max(cap_max, j.P.cap_max);
+    }
+  for (int l = 0; l < L; ++l)
+    for (size_t k = 0; k < lj[l].size(); ++k) {
+      Job& j = lj[l][k];
+      const int rc = tune_job<TT>(j, s);
+      if (rc) return rc;
+      init_members<TT>(j, s);
+      const Unit& u = plan[l][k];
+      if (u.a == 0) {  // the job reports the tile heights of the slice that holds its first member
+        Job& whole = jobs[u.job];
+        whole.rows_pred = j.rows_pred;
+        whole.rows_proj = j.rows_proj;
+        std::copy(j.rows_mg, j.rows_mg + MAX_LEVELS, whole.rows_mg);
       }
     }
-    if (changed) ++D.epoch;
+  if (tm) {
+    tm->members = 0;
+    for (const Job& j : lj[0]) tm->members += j.nmem;
   }
-  D.drain();
+  std::vector<hipStream_t> st(L, s);
+  if (L > 1) {
+    int rc = t_lanes.ensure(L - 1, 2 * L + 2);
+    if (rc) return rc;
+    for (int l = 1; l < L; ++l) {
+      st[l] = t_lanes.streams[l - 1];
+      rc = stream_after(st[l], s, t_lanes.events[l]);  // fork: the lanes start after the set-up
+      if (rc) return rc;
+    }
+  }
+  std::vector<std::unique_ptr<Driver>> D(L);
+  std::vector<std::vector<Job*>> active(L);
+  std::vector<std::vector<int>> which(L);
+  for (int l = 0; l < L; ++l) {
+    D[l].reset(new Driver);
+    D[l]->cap = D[l]->cap_max = cap_max;
+    for (size_t k = 0; k < lj[l].size(); ++k) {
+      active[l].push_back(&lj[l][k]);
+      which[l].push_back((int)k);
+    }
+  }
+  int rc = ENVAR_OK;
+  for (bool any = true; any;) {
+    any = false;
+    for (int l = 0; l < L; ++l) {
+      std::vector<Job*>& A = active[l];
+      if (A.empty()) continue;
+      any = true;
+      int left = 1 << 30, longest = 0;
+      for (Job* j : A) {
+        left = std::min(left, j->horizon - j->step);
+        longest = std::max(longest, j->horizon);
+      }
+      Timer* lt = l == 0 ? tm : nullptr;
+      if (lt && lt->begin_step(A[0]->step, longest)) return fail(ENVAR_EDEVICE, "hipEventCreate failed");
+      const bool alone = lt && lt->cur >= 0 && L > 1;
+      if (alone)  // the sampled step starts after every other lane's queued work ...
+        for (int q = 1; q < L && !rc; ++q) rc = stream_after(st[0], st[q], t_lanes.events[L + q]);
+      if (!rc) rc = D[l]->step<TT>(A, st[l], lt, left, graphs);
+      if (alone)  // ... and the other lanes continue after it
+        for (int q = 1; q < L && !rc; ++q) rc = stream_after(st[q], st[0], t_lanes.events[0]);
+      if (rc) return rc;
+      bool changed = false;
+      for (size_t k = 0; k < A.size();) {
+        if (A[k]->step >= A[k]->horizon) {
+          const JobOut& o = lo[l][which[l][k]];
+          finish_job(*A[k], o.J, o.fields, o.spinup_store, st[l]);
+          A.erase(A.begin() + k);
+          which[l].erase(which[l].begin() + k);
+          changed = true;
+        } else {
+          ++k;
+        }
+      }
+      if (changed) ++D[l]->epoch;
+    }
+  }
+  for (int l = 1; l < L && !rc; ++l) rc = stream_after(s, st[l], t_lanes.events[L + l]);  // join
+  for (auto& d : D) d->drain();
+  if (rc) return rc;
   HIP_OK(hipGetLastError());
   return ENVAR_OK;
 }
@@ -1505,7 +1672,7 @@ static void fill_timer_stats(Timer& timer, envar_stats* stats, int n_rows) {
     *outs[t] = cnt ? 1e3 * sum / cnt : 0.0;
   }
   stats->timed_steps = timer.samples;
-  stats->timed_members = n_rows;
+  stats->timed_members = timer.members > 0 ? timer.members : n_rows;
   (void)hipGetLastError();  // the event queries leave no sticky error behind
 }
 
@@ -1542,8 +1709,9 @@ static int forward_impl(const Plan& P, const void* state_dev, const double* cont
   timer.on = stats != nullptr && (P.p.flags & ENVAR_FLAG_TIME_KERNELS);
   timer.every = std::max(1, (horizon - 1 + timer.max_samples - 1) / timer.max_samples);
   const bool graphs = !(P.p.flags & ENVAR_FLAG_NO_GRAPHS);
-  rc = P.mixed ? run_batch<float>(jobs, outs, s, timer.on ? &timer : nullptr, graphs)
-               : run_batch<double>(jobs, outs, s, timer.on ? &timer : nullptr, graphs);
+  const int nl = (P.p.flags & ENVAR_FLAG_ONE_LANE) ? 1 : LANES_DEFAULT;
+  rc = P.mixed ? run_batch<float>(jobs, outs, s, timer.on ? &timer : nullptr, graphs, nl)
+               : run_batch<double>(jobs, outs, s, timer.on ? &timer : nullptr, graphs, nl);
   if (rc) return rc;
   if (stats) {
     rc = collect_stats(P, jobs[0].w, ws_dev, n_rows, s, stats, J_dev);
@@ -1565,7 +1733,7 @@ int envar_forward_batch(envar_job* jobs_in, int32_t njobs, void* stream) {
   std::vector<Job> jobs(njobs);
   std::vector<JobOut> outs(njobs);
   int prec = -1;
-  bool graphs = true;
+  bool graphs = true, one_lane = false;
   for (int k = 0; k < njobs; ++k) {
     envar_job& q = jobs_in[k];
     Plan P;
@@ -1582,8 +1750,11 @@ int envar_forward_batch(envar_job* jobs_in, int32_t njobs, void* stream) {
     outs[k].J = q.J_dev;
     outs[k].fields = q.fields_dev;
     graphs = graphs && !(P.p.flags & ENVAR_FLAG_NO_GRAPHS);
+    one_lane = one_lane || (P.p.flags & ENVAR_FLAG_ONE_LANE);
   }
-  int rc = prec ? run_batch<float>(jobs, outs, s, nullptr, graphs) : run_batch<double>(jobs, outs, s, nullptr, graphs);
+  const int nl = one_lane ? 1 : LANES_DEFAULT;
+  int rc = prec ? run_batch<float>(jobs, outs, s, nullptr, graphs, nl)
+                : run_batch<double>(jobs, outs, s, nullptr, graphs, nl);
   if (rc) return rc;
   int diverged = 0;
   for (int k = 0; k < njobs; ++k)

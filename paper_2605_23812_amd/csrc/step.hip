@@ -639,12 +639,33 @@ __global__ void k_clear_flag(int* flag) { *flag = 0; }
 
 // Plain streaming copy (16-byte vectors, grid-stride): the measured HBM ceiling
 // and the reference that calibrates the memory-traffic counters.
-__global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+// Streaming copy: each thread keeps COPY_U independent 16-byte nontemporal loads in flight before
+// its stores (a one-load-per-iteration loop leaves the copy latency-bound); a workgroup covers
+// 256 x COPY_U consecutive 16-byte chunks per iteration, so every load and store is coalesced.
+typedef double copy_v2 __attribute__((ext_vector_type(2)));
+constexpr int COPY_U = 4;
+__global__ __launch_bounds__(256) void k_stream_copy(const copy_v2* __restrict__ src, copy_v2* __restrict__ dst,
                                                      long n) {
-  for (long k = blockIdx.x * 256L + threadIdx.x; k < n; k += (long)gridDim.x * 256L) dst[k] = src[k];
+  const long stride = (long)gridDim.x * 256 * COPY_U;
+  for (long base = (long)blockIdx.x * 256 * COPY_U + threadIdx.x; base < n; base += stride) {
+    copy_v2 r[COPY_U];
+#pragma unroll
+    for (int u = 0; u < COPY_U; ++u) {
+      const long k = base + (long)u * 256;
+      if (k < n) r[u] = __builtin_nontemporal_load(src + k);
+    }
+#pragma unroll
+    for (int u = 0; u < COPY_U; ++u) {
+      const long k = base + (long)u * 256;
+      if (k < n) __builtin_nontemporal_store(r[u], dst + k);
+    }
+  }
 }
 void launch_stream_copy(const void* src, void* dst, long n16, hipStream_t s) {
-  hipLaunchKernelGGL(k_stream_copy, dim3(256 * 64), dim3(256), 0, s, (const double2*)src, (double2*)dst, n16);
+  long blocks = (n16 + 256L * COPY_U - 1) / (256L * COPY_U);
+  if (blocks > 256L * 32) blocks = 256L * 32;  // 32 workgroups per CU, grid-stride beyond
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const copy_v2*)src, (copy_v2*)dst, n16);
 }
 
 // ---------------------------------------------------------------------------- launchers

@@ -24,6 +24,7 @@ FLAG_NO_TUNE = 4
 FLAG_TILES_8 = 8
 FLAG_TILES_16 = 16
 FLAG_TILES_32 = 32
+FLAG_ONE_LANE = 64
 
 EXPORTS = (
     "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",

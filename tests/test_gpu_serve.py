@@ -134,3 +134,35 @@ def test_served_requests_match_oracle(precision, tol):
         assert info["max_div"] <= 1.01 * (1e-12 if precision == E.FP64 else 1e-10)
         assert info["mean_cycles"] >= 1.0
         assert rel.max() <= tol
+
+
+@pytest.mark.parametrize("precision", [E.FP64, E.MIXED])
+def test_requests_admitted_mid_run_are_not_cut(precision):
+    """Requests whose strong forcing switches on when they are admitted, into a batch that has
+    been running for several cap polls (one every 16 steps) and needs few passes: the cap must
+    cover the newcomers' first steps (no member-step cut) and each equals its own forward."""
+    p_long = E.Problem(inv_h=32, Re=4000.0, precision=precision)
+    st = _state(32, 4000.0, 0)
+    m = E.control_dim(p_long)
+    long_rows = np.vstack([np.zeros(m), inputs.grf_perturbations(3, 32, 0.05, 5e-3, seed=40)])
+    late = []
+    for k in range(5):
+        rows = np.vstack([np.zeros(m), inputs.grf_perturbations(2, 32, 0.1, 0.5, seed=41 + k)])
+        late.append((E.Problem(inv_h=32, Re=4000.0, precision=precision), rows, 80))
+    srv = E.Server(1 << 30, max_jobs=8, precision=precision)
+    try:
+        tickets = [srv.submit(p_long, st, long_rows, 6000)]  # runs ~0.3 s: the others join it
+        for p, rows, h in late:
+            time.sleep(0.03)  # the running batch is some tens of steps further each time
+            tickets.append(srv.submit(p, st, rows, h))
+        results = [srv.wait(t, timeout=120.0) for t in tickets]
+    finally:
+        srv.close()
+    for (p, rows, h), (J, info) in zip([(p_long, long_rows, 6000)] + late, results):
+        print("mid-run admission", h, info["status"], info["unconverged"], info["mean_cycles"],
+              info["max_div"], info["peak_jobs"], flush=True)
+        assert info["status"] == E.OK and info["unconverged"] == 0
+        Js, _, _ = E.forward(p, st, torch.tensor(rows, device="cuda"), h)
+        torch.cuda.synchronize()
+        assert np.array_equal(J, Js.cpu().numpy())
+    assert max(r[1]["peak_jobs"] for r in results) >= 2
