@@ -527,6 +527,59 @@ def serving(torch, E, inputs, nreq, horizon_scale, div_tol, clients=4, think_s=0
     }
 
 
+def lyapunov(torch, E, inputs, n, Re, geometry, spin_units, window_units, every=20, eps=1e-10, seed=5):
+    """Leading Lyapunov exponent from twin FP64 runs: the unforced flow and the same flow forced by
+    eps times a unit-max GRF field (length 0.05), integrated together from a spun-up state; the
+    separation of their lid-sensor signals (8 channels, every `every` steps) grows like e^(lambda
+    t) until it saturates at the signal's own size. lambda is the least-squares slope of
+    log(separation) over the samples whose separation lies between 1e3 times its first value and
+    1e-2 of the signal's standard deviation."""
+    geo = E.CAVITY_PAPER if geometry == "paper" else E.CAVITY
+    p = E.Problem(inv_h=n, Re=Re, precision=E.FP64, geometry=geo)
+    dt = p.step_dt
+    u0, v0 = inputs.initial_field(n, amp=1e-3, seed=seed, geometry=geometry)
+    state = E.state_init(p, u0, v0)
+    t = time.time()
+    E.spinup(p, state, int(round(spin_units / dt)))
+    m = E.control_dim(p)
+    shape = (n + n // 2, n) if geometry == "paper" else None
+    pert = inputs.grf_perturbations(1, n, 0.05, 1.0, seed=seed + 1, shape=shape)[0]
+    rows = np.vstack([np.zeros(m), eps * pert / np.abs(pert).max()])
+    H = int(round(window_units / dt))
+    _, series, st = E.forward_obs(p, state, torch.tensor(rows, device="cuda"), H, every)
+    torch.cuda.synchronize()
+    secs = time.time() - t
+    S = series.cpu().numpy()
+    d = np.sqrt(((S[1] - S[0]) ** 2).sum(axis=0))
+    scale = float(np.sqrt(((S[0] - S[0].mean(axis=1, keepdims=True)) ** 2).sum(axis=0).mean()))
+    tt = (np.arange(S.shape[2]) + 1) * every * dt
+    d0 = float(d[:5].mean())
+    sel = (d > 1e3 * d0) & (d < 1e-2 * scale)
+    first = int(np.argmax(sel)) if sel.any() else 0
+    sat = np.nonzero(d >= 1e-2 * scale)[0]
+    last = int(sat[0]) if sat.size else d.size
+    idx = np.arange(first, last)
+    idx = idx[d[idx] > 1e3 * d0]
+    out = {"inv_h": n, "Re": Re, "geometry": geometry, "spinup_time_units": spin_units,
+           "window_time_units": window_units, "eps": eps, "samples": int(d.size), "seconds": round(secs, 1),
+           "separation_first": d0, "separation_last": float(d[-1]), "signal_std": scale,
+           "mean_vcycles": round(st["mean_cycles"], 3)}
+    if idx.size >= 10:
+        lam, c = np.polyfit(tt[idx], np.log(d[idx]), 1)
+        res = np.log(d[idx]) - (lam * tt[idx] + c)
+        out.update({"lambda": float(lam), "lyapunov_time": float(1.0 / lam) if lam > 0 else None,
+                    "fit_from_t": float(tt[idx[0]]), "fit_to_t": float(tt[idx[-1]]),
+                    "fit_rms_log_residual": float(np.sqrt(np.mean(res ** 2))),
+                    "saturated_at_t": float(tt[last]) if last < d.size else None})
+    else:
+        out.update({"lambda": None, "lyapunov_time": None,
+                    "note": "no exponential regime: the separation never grew 1e3-fold below saturation"})
+    # log-separation every ~2 time units, for the record
+    stride = max(1, int(round(2.0 / (every * dt))))
+    out["log10_separation_every_2_units"] = [round(float(np.log10(max(x, 1e-300))), 2) for x in d[::stride]]
+    return out
+
+
 def cpu_baseline(state_host, rows, steps, procs):
     """The oracle (plain FP64 numpy/scipy) on a bounded sample: every member for `steps` steps."""
     from oracle import envar as OE
@@ -599,6 +652,9 @@ def main():
     ap.add_argument("--no-gram", action="store_true")
     ap.add_argument("--anomaly-only", action="store_true",
                     help="run only the anomaly-reduction sweep and print it as one JSON line (for kernel traces)")
+    ap.add_argument("--lyapunov", action="store_true",
+                    help="only measure the leading Lyapunov exponent of the chaotic configurations (twin FP64 "
+                         "runs) and print them as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the ensemble members of one MI355X "
@@ -614,6 +670,15 @@ def main():
     torch.cuda.init()
     if args.anomaly_only:
         print(json.dumps({"anomaly_reduction": gram_sweep(torch, E)}), flush=True)
+        return
+    if args.lyapunov:
+        res = []
+        for cfg in ((256, 12000.0, "cavity", 20.0, 80.0), (128, 12000.0, "cavity", 20.0, 80.0),
+                    (64, 14000.0, "paper", 40.0, 150.0), (64, 12000.0, "cavity", 40.0, 150.0)):
+            r = lyapunov(torch, E, inputs, *cfg)
+            log("lyapunov", r)
+            res.append(r)
+        print(json.dumps({"lyapunov": res}), flush=True)
         return
     copy = measure_copy(torch, E, args.copy_bytes)
     copy_gbs = copy["GBs"]

@@ -39,7 +39,7 @@ constexpr double MG_OMEGA = 1.15;
 constexpr int COARSE_N = 16; // levels with inv_h <= 16 run inside one workgroup per member
 constexpr int MAX_LEVELS = 12;
 constexpr int MAX_COARSE_UNKNOWNS = 128;
-constexpr int COARSE_INV_MAX = 8192;  // LDS budget for the coarsest inverse (nc^2 doubles)
+constexpr int COARSE_INV_MAX = 8192;  // bound on the coarsest inverse (nc^2 doubles, read from global memory)
 
 struct Geo {
   int nx, ny;    // bounding box in cells

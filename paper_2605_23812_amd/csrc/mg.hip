@@ -572,11 +572,15 @@ __device__ __forceinline__ void lvl_prolong(double* p, const unsigned char* C, i
 
 // V-cycle over the three LDS levels with NS red-black sweeps per level and a
 // dense solve of the h = 1/4 operator through its inverse.
+// The dense solve gives eight threads (consecutive lanes) to each coarsest unknown q = tid / 8,
+// thread part = tid % 8 summing the terms r = part, part + 8, ...; its entries of the inverse are
+// loaded into registers at the start of the kernel, so their latency hides behind the sweeps.
+constexpr int COARSE_INV_PER_THREAD = (MAX_COARSE_UNKNOWNS + 7) / 8;
+
 template <typename T, bool ONE>
 __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> ms) {
   __shared__ double P0[CS0], B0[CS0], P1[CS1], B1[CS1], P2[CS2], B2[CS2];
   __shared__ unsigned char C0[CS0], C1[CS1], C2[CS2];
-  __shared__ double sinv[COARSE_INV_MAX];
   __shared__ double sbc[MAX_COARSE_UNKNOWNS];
   __shared__ double red[COARSE_THREADS / 64];
   int mem;
@@ -599,6 +603,15 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
   constexpr int RS = COARSE_THREADS / 64;
   constexpr int NL = CMAXNY0 / RS;
   const int ti = threadIdx.x & 63, tj = threadIdx.x >> 6;
+  // this thread's entries of the transposed inverse: ainv[r * nc + q] for r = part + 8 k
+  static_assert(MAX_COARSE_UNKNOWNS * 8 <= COARSE_THREADS, "dense solve needs 8 threads per unknown");
+  const int dq = threadIdx.x >> 3, dpart = threadIdx.x & 7;
+  double inv_r[COARSE_INV_PER_THREAD];
+#pragma unroll
+  for (int k = 0; k < COARSE_INV_PER_THREAD; ++k) {
+    const int r = dpart + 8 * k;
+    inv_r[k] = (dq < a.nc && r < a.nc) ? a.ainv[(long)r * a.nc + dq] : 0.0;
+  }
   {
     double vp[NL], vb[NL];
 #pragma unroll
@@ -611,9 +624,6 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
         if (a.warm) vp[k] = (double)gphi[g0.at(ti, j)];
       }
     }
-    // the transposed inverse of the coarsest operator, read once per workgroup
-    const int ninv = a.nc * a.nc;
-    for (int q = threadIdx.x; q < ninv; q += COARSE_THREADS) sinv[q] = a.ainv[q];
     for (int q = threadIdx.x; q < CS0; q += COARSE_THREADS) {
       P0[q] = 0.0;
       B0[q] = 0.0;
@@ -645,24 +655,25 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
   lvl_restrict<CNX0>(P0, B0, C0, g0.h, P1, B1, C1, ny1);
   for (int s = 0; s < a.nsweep_pre; ++s) lvl_sweep<CNX1>(P1, B1, C1, ny1, h21);
   lvl_restrict<CNX1>(P1, B1, C1, g1.h, P2, B2, C2, ny2);
-  // dense solve on the coarsest level: sinv holds the inverse transposed, thread q reads column q
+  // dense solve on the coarsest level through the inverse held in registers
   for (int q = threadIdx.x; q < a.nc; q += COARSE_THREADS) {
     const int c = a.aidx[q];
     sbc[q] = B2[cx<CNX2>(c % g2.nx, c / g2.nx)];
   }
   __syncthreads();
   {
-    // eight threads (consecutive lanes) per unknown, each summing every eighth term
-    static_assert(MAX_COARSE_UNKNOWNS * 8 <= COARSE_THREADS, "dense solve needs 8 threads per unknown");
-    const int q = threadIdx.x >> 3, part = threadIdx.x & 7;
+    // eight threads (consecutive lanes) per unknown, each summing every eighth term in order
     double s = 0.0;
-    if (q < a.nc)
-      for (int r = part; r < a.nc; r += 8) s += sinv[r * a.nc + q] * sbc[r];
+#pragma unroll
+    for (int k = 0; k < COARSE_INV_PER_THREAD; ++k) {
+      const int r = dpart + 8 * k;
+      if (dq < a.nc && r < a.nc) s += inv_r[k] * sbc[r];
+    }
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
     s += __shfl_xor(s, 4, 64);
-    if (q < a.nc && part == 0) {
-      const int c = a.aidx[q];
+    if (dq < a.nc && dpart == 0) {
+      const int c = a.aidx[dq];
       P2[cx<CNX2>(c % g2.nx, c / g2.nx)] = s;
     }
   }
