@@ -43,10 +43,12 @@ BYTES_PER_CELL = {
     # phi^{n-2}, phi^{n-3} in, guess and phi^{n-2} out (32) -> u*, v* (16) + T^n (16) + b (8);
     # FP64 jobs warm-start from one more pressure (cubic): phi^{n-4} in, phi^{n-3} out (+16)
     ("predictor", "fp64"): 166.4, ("predictor", "mixed"): 150.4,
-    # phi in/out (8 + 8) + b (8) + coarse rhs (8/4)              | mixed: phi64 (8) + b64 (8) -> r (4) + e (4) + coarse (1)
+    # phi in/out (8 + 8) + b (8) + coarse rhs (8/4)   | mixed, first pass: phi64 (8) + b64 (8) -> r (4) + e (4)
+    #                                                 + coarse (1)
     ("pre", "fp64"): 26.0, ("pre", "mixed"): 25.0,
-    # phi in/out (8 + 8) + b (8) + coarse correction (8/4)       | mixed: e (4) + r (4) + coarse (1) + phi64 in/out (16)
-    ("post", "fp64"): 26.0, ("post", "mixed"): 25.0,
+    # phi in/out (8 + 8) + b (8) + coarse correction (8/4)   | mixed: e (4) + r (4) + coarse (1) + phi64 in/out
+    #                                                 (16) -> r - L e (4)
+    ("post", "fp64"): 26.0, ("post", "mixed"): 29.0,
     # phi64 (8) + b64 (8) -> r32 (4)
     ("resid", "mixed"): 20.0,
     # u*, v* (16) + phi (8) -> u, v (16) + cost sums S1 in/out (32) + warm start: phi^{n-1} in / guess out (16)
@@ -154,12 +156,14 @@ def roofline(st, prec, ncells, copy_gbs=None):
     return out
 
 
-# bytes per cell-step of the whole step (ideal fusion): the fused predictor, one refinement pass
-# (finest pre and post 25 + 25 B, the coarser tiled levels ~22 B per cell of their level, 1/4 + 1/16
-# + ... of the fine cells) per pass, and the finest pre kernel of the convergence-check pass (25 B)
+# bytes per cell-step of the whole step (ideal fusion): the fused predictor and, per refinement
+# pass, the finest pre kernel (25 B in the first pass, which forms the FP64 residual; 9 B in later
+# ones, which start from the carried residual) and post kernel (29 B, which also updates the carried
+# residual and its norm) and the coarser tiled levels (~22 B per cell of their level, 1/4 + 1/16 +
+# ... of the fine cells); FP64: the predictor and 52 + 44/3 B per V-cycle
 def step_bytes(prec, cycles):
     if prec == "mixed":
-        return 150.4 + cycles * (50.0 + 22.0 / 3.0) + 25.0
+        return 150.4 + (25.0 + 29.0 + 22.0 / 3.0) + max(cycles - 1.0, 0.0) * (9.0 + 29.0 + 22.0 / 3.0)
     return 166.4 + cycles * (52.0 + 44.0 / 3.0)
 
 

@@ -251,7 +251,7 @@ static int make_plan(const envar_problem* pin, Plan& P) {
 
 // workspace layout of a forward over nmem members
 struct WS {
-  size_t u, v, us, vs, us2, vs2, tuA, tvA, tuB, tvB, phiA, phiB, phiC, phiQ, phiR, b0, e0, r0;
+  size_t u, v, us, vs, us2, vs2, tuA, tvA, tuB, tvB, phiA, phiB, phiC, phiQ, phiR, b0, e0, r0, r1;
   size_t lphiA[MAX_LEVELS], lphiB[MAX_LEVELS], lb[MAX_LEVELS];
   size_t s1u, s1v, s2part, norms, stats, divmax;
   size_t total;
@@ -291,7 +291,9 @@ static WS make_ws(const Plan& P, int nmem, WS* stride = nullptr) {
   take(w.b0, st.b0, pl * 8);
   if (P.mixed) {
     take(w.e0, st.e0, pl * 4);
+    // the residual carried across the refinement passes of a step (two planes, by pass parity)
     take(w.r0, st.r0, pl * 4);
+    take(w.r1, st.r1, pl * 4);
   }
   for (int l = 1; l <= P.nlev_grid; ++l) {
     const size_t lp = (size_t)P.lev[l].plane();
@@ -443,6 +445,8 @@ struct Job {
     return at<T>(ws, off);
   }
   double* phi(int k) const { return w_<double>(k ? w.phiC : w.phiA); }
+  // the residual carried after refinement pass k (pass k reads plane k - 1, writes plane k)
+  float* rplane(int k) const { return w_<float>((k & 1) ? w.r1 : w.r0); }
   double* ustar(int p) const { return w_<double>(p ? w.us2 : w.us); }
   double* vstar(int p) const { return w_<double>(p ? w.vs2 : w.vs); }
 };
@@ -585,11 +589,22 @@ static MGArgs<T> pre_args(const Job& j, int l, int k, int rows) {
     a.b = mixed ? nullptr : (const T*)j.w_<double>(w.b0);
     a.zero_guess = mixed ? 1 : 0;
     a.phi_out = mixed ? (T*)j.w_<float>(w.e0) : (T*)j.w_<double>(w.phiB);
-    if (mixed) {  // the residual of the FP64 pressure after pass k - 1 is formed in this launch
+    if (mixed && k <= 1) {  // first pass: the residual of the warm-started FP64 pressure is formed here
+      a.pre_mode = PRE_FIRST;
       a.phi64 = j.phi(cur);
       a.b64 = j.w_<double>(w.b0);
-      a.r_out = (T*)j.w_<float>(w.r0);
-      a.rslot = k - 1;
+      a.r_out = (T*)j.rplane(0);
+      a.rslot = 0;
+    } else if (mixed) {
+      // later passes: the residual carried from the previous pass's post kernel, re-formed from the
+      // FP64 pressure into the same plane while its norm exceeds 1e3 x the tolerance (so that the
+      // rounding of a large carried residual, relative 6e-8, never reaches the tolerance)
+      a.pre_mode = PRE_LATER;
+      a.b = (const T*)j.rplane(k - 1);
+      a.r_out = (T*)j.rplane(k - 1);
+      a.phi64 = j.phi(cur);
+      a.b64 = j.w_<double>(w.b0);
+      a.anchor = 1e3 * j.P.tol;
     }
   } else {
     a.phi_in = nullptr;
@@ -610,10 +625,11 @@ static MGArgs<T> post_args(const Job& j, int l, int k, int rows) {
   if (l == 0) {
     const int cur = j.step & 1;
     a.phi_in = mixed ? (const T*)j.w_<float>(w.e0) : (const T*)j.w_<double>(w.phiB);
-    a.b = mixed ? (const T*)j.w_<float>(w.r0) : (const T*)j.w_<double>(w.b0);
-    a.phi_out = mixed ? (T*)j.w_<float>(w.e0) : (T*)j.phi(cur);
+    a.b = mixed ? (const T*)j.rplane(k - 1) : (const T*)j.w_<double>(w.b0);
+    a.phi_out = mixed ? nullptr : (T*)j.phi(cur);
     a.add_to = mixed ? j.phi(cur) : nullptr;
-    a.write_norm = mixed ? 0 : 1;
+    if (mixed) a.r_out = (T*)j.rplane(k);  // phi64 += e, r - L e into plane k; a skipped member carries its norm
+    a.write_norm = 1;
   } else {
     a.phi_in = j.w_<T>(w.lphiB[l]);
     a.b = j.w_<T>(w.lb[l]);
@@ -735,7 +751,9 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
       grouped<MGArgs<T>>(
           Jk, [&](const Job& j) { return l < j.P.nlev_grid ? j.rows_mg[l] : 0; },
           [&](const Job& j, int rows) { return post_args<T>(j, l, k, rows); },
-          [&](const Multi<MGArgs<T>>& m) { launch_mg_post<T>(m, l == 0 && !mixed, st); });
+          [&](const Multi<MGArgs<T>>& m) {
+            launch_mg_post<T>(m, l > 0 ? POST_PLAIN : mixed ? POST_REFINE : POST_NORM, st);
+          });
       if (timed && l == 0) tm->mark(TM_POST, 1, st);
     }
     if (timed && !mixed) tm->mark(TM_CYCLE, 1, st);
@@ -758,7 +776,9 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
       if (!Jk.empty()) vcycle(k, Jk);
     }
   } else {
-    // slot k - 1 is written by pass k (its finest pre kernel), slot cap_j by the last residual
+    // slot 0 holds the initial residual (the first pass's finest pre kernel), slot k the residual
+    // after pass k (that pass's finest post kernel; for jobs without a tiled level, the standalone
+    // residual launches)
     resid(0, J, false);
     for (int k = 1; k <= cap; ++k) {
       const std::vector<Job*> Jk = in_pass(k);
@@ -767,8 +787,10 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
       resid(k, in_pass(k + 1), false);
       if (tm && k == k_timed) tm->mark(TM_CYCLE, 1, st);
     }
+    // the last pass's residual: tiled jobs carry it out of their finest post kernel; jobs whose
+    // finest level runs in the coarse kernel form it here
     if (tm) tm->mark(TM_RESID, 0, st);
-    resid(-1, J, true);
+    resid(-1, J, false);
     if (tm) tm->mark(TM_RESID, 1, st);
   }
 }
@@ -1437,7 +1459,7 @@ static int tune_job(Job& j, hipStream_t s) {
       const int rows = 8 << v;
       t[v] = timed([&] {
         launch_mg_pre<T>(one(pre_args<T>(j, l, k, rows)), s);
-        launch_mg_post<T>(one(post_args<T>(j, l, 0, rows)), l == 0 && !P.mixed, s);
+        launch_mg_post<T>(one(post_args<T>(j, l, 0, rows)), l > 0 ? POST_PLAIN : P.mixed ? POST_REFINE : POST_NORM, s);
       });
       if (t[v] < 0.97f * t[best]) best = v;  // a taller tile has to win by 3% (timing noise of short launches)
     }

@@ -145,6 +145,10 @@ struct InitArgs {
   double *s1u, *s1v, *s2part, *stats, *divmax;
 };
 
+// pre kernel at the finest level in mixed precision: the first pass forms the residual, later
+// passes carry it (re-forming it while it is large)
+enum { PRE_PLAIN = 0, PRE_FIRST = 1, PRE_LATER = 2 };
+
 // multigrid level arguments (T = arithmetic / storage type of the level)
 template <typename T>
 struct MGArgs {
@@ -162,14 +166,21 @@ struct MGArgs {
   T* bc;              // coarse right-hand side
   double* add_to;     // post, mixed: phi64 += phi instead of storing phi (NULL = store)
   int zero_guess;     // pre: start from phi = 0
-  // pre, mixed finest level (iterative refinement): the right-hand side is the
-  // FP64 residual b64 - L phi64, computed on the window; dt*max|r| of the tile
-  // goes to norms[rslot] (members with norms[rslot-1] <= tol exit at once)
-  // (also stored, as T, in r_out on the tile's cells for the post kernel)
+  // Mixed precision, finest level (iterative refinement of the FP64 pressure). The residual
+  // r = b64 - L phi64 is carried across the passes of a step in two T planes (pass k reads one
+  // as its right-hand side `b` and writes the other):
+  //  * the first pass's pre kernel forms r in FP64 on its window from phi64 and b64, stores it
+  //    (rounded to T) on its tile in r_out and puts dt*max|r| of the tile into norms[rslot] (slot 0);
+  //  * the post kernel adds its correction e to phi64 and stores r - L e, formed in FP64 (e is
+  //    exact on the tile and one ring around it), in r_out, with dt*max|r - L e| of the tile into
+  //    norms[k]. The rounding of the stored residual (relative 6e-8 of a residual near the
+  //    tolerance) stays far below the tolerance; the next step forms r afresh.
   const double* phi64;
   const double* b64;
   T* r_out;
   int rslot;
+  double anchor;      // later passes: re-form the residual when the previous norm exceeds this
+  int pre_mode;       // PRE_PLAIN | PRE_FIRST | PRE_LATER (selects the kernel instance)
   // convergence control: skip members whose previous cycle met tol
   double* norms;      // [nmem][norm_slots]
   int norm_slots;
@@ -251,8 +262,12 @@ void launch_sensors(const Multi<SensorArgs>& m, hipStream_t s);
 
 template <typename T>
 void launch_mg_pre(const Multi<MGArgs<T>>& m, hipStream_t s);
+// post kernel at the finest level: 0 plain, 1 the V-cycle's residual norm (FP64 cycles), 2 the
+// refinement update of phi64 and of the carried residual (mixed precision)
+enum { POST_PLAIN = 0, POST_NORM = 1, POST_REFINE = 2 };
+
 template <typename T>
-void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s);
+void launch_mg_post(const Multi<MGArgs<T>>& m, int mode, hipStream_t s);
 template <typename T>
 void launch_mg_coarse(const Multi<CoarseArgs>& m, hipStream_t s);
 void launch_resid64(const Multi<ResidArgs>& m, hipStream_t s);

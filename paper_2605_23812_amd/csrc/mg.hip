@@ -127,6 +127,12 @@ struct Items {
       __syncthreads();
     }
   }
+  // the same four neighbours summed in FP64
+  __device__ __forceinline__ double nbsum64(const T* sp, int c, int n) const {
+    const int l = left0[c] + 8 * n * W::QS;
+    const int m = l + 1 - ((c ^ r0) & 1);
+    return ((double)sp[l] + (double)sp[l + 1]) + ((double)sp[m - W::QS] + (double)sp[m + W::QS]);
+  }
   // h^2 r = h^2 b - (sum nb - d phi)
   __device__ __forceinline__ T resid_h2(const T* sp, int c, int n) const {
     return hb[c][n] - (nbsum(sp, c, n) - d[c][n] * sp[own0[c] + 8 * n * W::QS]);
@@ -182,12 +188,19 @@ __device__ __forceinline__ bool ref_skip(const MGArgs<T>& a, int mem, int tile) 
 }
 
 // ---------------------------------------------------------------------------- pre-smoothing + restriction
-template <typename T, int NS, bool REF, bool ONE, int TR>
+// REF: PRE_PLAIN; PRE_FIRST (mixed finest level, first pass: the FP64 residual r = b64 - L phi64 is
+// formed on the window, stored rounded to T in r_out, its norm into norms[rslot]); PRE_LATER (mixed
+// finest level, later passes: the right-hand side is the residual carried in `b` unless the
+// member's previous norm exceeds `anchor`, in which case it is formed afresh as in PRE_FIRST and
+// stored in r_out (the same plane), without a norm: a residual near the tolerance is carried, a
+// large one re-anchored, so the carried residual's rounding stays below anchor x 6e-8)
+template <typename T, int NS, int REF, bool ONE, int TR>
 __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
   typedef Win<T, TR> W;
   static_assert(2 * NS + 1 <= W::H, "window halo too small for the sweep count");
   static_assert(W::TH * 64 <= 2 * W::CS, "residual staging does not fit");
-  static_assert(!REF || sizeof(double) * 64 * W::LH <= sizeof(T) * 4 * W::CS, "FP64 window does not fit");
+  static_assert(REF == PRE_PLAIN || sizeof(double) * 64 * W::LH <= sizeof(T) * 4 * W::CS,
+                "FP64 window does not fit");
   __shared__ T spb[4 * W::CS];  // sp | sb; in refinement first the FP64 pressure window
   __shared__ unsigned char scode[2 * W::CS];
   __shared__ double red[4];
@@ -197,13 +210,15 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
   const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
   const int mem = item / a.ntiles, tile = item % a.ntiles;
-  if (REF ? ref_skip(a, mem, tile) : mg_skip(a, mem, tile)) return;
+  if (REF == PRE_FIRST ? ref_skip(a, mem, tile) : mg_skip(a, mem, tile)) return;
   int x0, y0;
   a.tiling.origin(tile, x0, y0);
   const int ox = x0 - W::H, oy = y0 - W::H;
   const long off = (long)mem * a.plane;
   const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (REF) {
+  const bool form = REF == PRE_FIRST ||
+                    (REF == PRE_LATER && a.norms[(long)mem * a.norm_slots + a.k - 1] > a.anchor);
+  if (form) {
     // r = b64 - L phi64 on the window (ring excluded), same arithmetic order as k_resid64
     double* const P64 = (double*)spb;
     double vp[W::NR], vb[W::NR];
@@ -262,7 +277,7 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
     mx = wave_max(mx);
     if ((threadIdx.x & 63) == 0) red[w] = mx;
     __syncthreads();  // every FP64 read is done before sp / sb overwrite the window
-    if (threadIdx.x == 0) {
+    if (REF == PRE_FIRST && threadIdx.x == 0) {
       double mm = red[0];
       for (int q = 1; q < 4; ++q) mm = (red[q] > mm || red[q] != red[q]) ? red[q] : mm;
       atomicMax((unsigned long long*)&a.norms[(long)mem * a.norm_slots + a.rslot], dbits(mm));
@@ -335,10 +350,13 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
 }
 
 // ---------------------------------------------------------------------------- prolongation + post-smoothing
-template <typename T, int NS, int NORM, bool ONE, int TR>
+// MODE: POST_PLAIN; POST_NORM (the residual norm of the V-cycle's own equation, FP64 cycles);
+// POST_REFINE (mixed finest level: phi64 += e and the carried FP64 residual r - L e on the tile)
+template <typename T, int NS, int MODE, bool ONE, int TR>
 __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
   typedef Win<T, TR> W;
-  static_assert(2 * NS + NORM <= W::H, "window halo too small for the sweep count");
+  // the norm and the refinement update need the smoothed values on the tile and one ring around it
+  static_assert(2 * NS + (MODE != POST_PLAIN ? 1 : 0) <= W::H, "window halo too small for the sweep count");
   constexpr int CW = 36, CH = W::LH / 2 + 3;
   __shared__ T sp[2 * W::CS];
   __shared__ T sb[2 * W::CS];
@@ -421,7 +439,35 @@ __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
   Items<T, TR> it;
   it.init(sb, scode, h2);
   for (int s = 0; s < NS; ++s) it.sweep(sp);
-  if (NORM && a.write_norm) {
+  if (MODE == POST_REFINE) {
+    // phi64 += e and r_out = r - L e (formed in FP64) on the tile's fluid cells; dt max|r - L e| -> norms[k]
+    const double inv_h2 = 1.0 / (g.h * g.h);
+    double m = 0.0;
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int n = 0; n < W::NIT; ++n) {
+        const int r = it.row(n), cl = it.col(c);
+        if (it.invd[c][n] != (T)0 && r >= W::H && r < W::H + W::TH && cl >= W::H && cl < W::H + W::TWI) {
+          const long at = off + g.at(ox + cl, oy + r);
+          const double e = (double)sp[it.own0[c] + 8 * n * W::QS];
+          const double rn = (double)a.b[at] - (it.nbsum64(sp, c, n) - (double)it.d[c][n] * e) * inv_h2;
+          a.r_out[at] = (T)rn;
+          a.add_to[at] += e;
+          const double rr = fabs(rn) * a.dt;
+          m = (rr > m || rr != rr) ? rr : m;
+        }
+      }
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mm = red[0];
+      for (int q = 1; q < 4; ++q) mm = (red[q] > mm || red[q] != red[q]) ? red[q] : mm;
+      atomicMax((unsigned long long*)&a.norms[(long)mem * a.norm_slots + a.k], dbits(mm));
+    }
+    return;
+  }
+  if (MODE == POST_NORM && a.write_norm) {
     double m = 0.0;
     const double sc = a.dt / (g.h * g.h);
     for (int c = 0; c < 2; ++c)
@@ -768,7 +814,7 @@ __global__ __launch_bounds__(256) void k_resid64(Multi<ResidArgs> ms) {
 }
 
 // ---------------------------------------------------------------------------- launchers
-template <typename T, bool REF, int TR>
+template <typename T, int REF, int TR>
 static void launch_mg_pre_(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.nseg == 1)
     hipLaunchKernelGGL((k_mg_pre<T, mg_ns<T>(), REF, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
@@ -776,7 +822,7 @@ static void launch_mg_pre_(const Multi<MGArgs<T>>& m, hipStream_t s) {
     hipLaunchKernelGGL((k_mg_pre<T, mg_ns<T>(), REF, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
 }
 // every segment of one launch shares the tile height (the host groups segments by it)
-template <typename T, bool REF>
+template <typename T, int REF>
 static void launch_mg_pre_rows(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.seg[0].trows == 8)
     launch_mg_pre_<T, REF, 8>(m, s);
@@ -787,41 +833,49 @@ static void launch_mg_pre_rows(const Multi<MGArgs<T>>& m, hipStream_t s) {
 }
 template <>
 void launch_mg_pre<double>(const Multi<MGArgs<double>>& m, hipStream_t s) {
-  launch_mg_pre_rows<double, false>(m, s);
+  launch_mg_pre_rows<double, PRE_PLAIN>(m, s);
 }
 template <>
 void launch_mg_pre<float>(const Multi<MGArgs<float>>& m, hipStream_t s) {
-  // every segment of a finest-level launch in mixed precision refines (one precision per batch)
-  if (m.seg[0].phi64)
-    launch_mg_pre_rows<float, true>(m, s);
+  // every segment of a finest-level launch in mixed precision refines (one precision per batch),
+  // and all of them are in the same pass
+  if (m.seg[0].pre_mode == PRE_FIRST)
+    launch_mg_pre_rows<float, PRE_FIRST>(m, s);
+  else if (m.seg[0].pre_mode == PRE_LATER)
+    launch_mg_pre_rows<float, PRE_LATER>(m, s);
   else
-    launch_mg_pre_rows<float, false>(m, s);
+    launch_mg_pre_rows<float, PRE_PLAIN>(m, s);
 }
-template <typename T, int NORM, int TR>
+template <typename T, int MODE, int TR>
 static void launch_mg_post_(const Multi<MGArgs<T>>& m, hipStream_t s) {
   if (m.nseg == 1)
-    hipLaunchKernelGGL((k_mg_post<T, mg_ns<T>(), NORM, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_post<T, mg_ns<T>(), MODE, true, TR>), dim3(m.total()), dim3(256), 0, s, m);
   else
-    hipLaunchKernelGGL((k_mg_post<T, mg_ns<T>(), NORM, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
+    hipLaunchKernelGGL((k_mg_post<T, mg_ns<T>(), MODE, false, TR>), dim3(m.total()), dim3(256), 0, s, m);
 }
-template <typename T>
-void launch_mg_post(const Multi<MGArgs<T>>& m, bool write_norm, hipStream_t s) {
+template <typename T, int MODE>
+static void launch_mg_post_rows(const Multi<MGArgs<T>>& m, hipStream_t s) {
   const int tr = m.seg[0].trows;
-  if (write_norm) {
-    if (tr == 8)
-      launch_mg_post_<T, 1, 8>(m, s);
-    else if (tr == 16)
-      launch_mg_post_<T, 1, 16>(m, s);
-    else
-      launch_mg_post_<T, 1, 32>(m, s);
-  } else {
-    if (tr == 8)
-      launch_mg_post_<T, 0, 8>(m, s);
-    else if (tr == 16)
-      launch_mg_post_<T, 0, 16>(m, s);
-    else
-      launch_mg_post_<T, 0, 32>(m, s);
-  }
+  if (tr == 8)
+    launch_mg_post_<T, MODE, 8>(m, s);
+  else if (tr == 16)
+    launch_mg_post_<T, MODE, 16>(m, s);
+  else
+    launch_mg_post_<T, MODE, 32>(m, s);
+}
+template <>
+void launch_mg_post<double>(const Multi<MGArgs<double>>& m, int mode, hipStream_t s) {
+  if (mode == POST_NORM)
+    launch_mg_post_rows<double, POST_NORM>(m, s);
+  else
+    launch_mg_post_rows<double, POST_PLAIN>(m, s);
+}
+template <>
+void launch_mg_post<float>(const Multi<MGArgs<float>>& m, int mode, hipStream_t s) {
+  if (mode == POST_REFINE)
+    launch_mg_post_rows<float, POST_REFINE>(m, s);
+  else
+    launch_mg_post_rows<float, POST_PLAIN>(m, s);
 }
 template <typename T>
 void launch_mg_coarse(const Multi<CoarseArgs>& m, hipStream_t s) {
@@ -837,8 +891,6 @@ void launch_resid64(const Multi<ResidArgs>& m, hipStream_t s) {
     hipLaunchKernelGGL(k_resid64<false>, dim3(m.total()), dim3(256), 0, s, m);
 }
 
-template void launch_mg_post<double>(const Multi<MGArgs<double>>&, bool, hipStream_t);
-template void launch_mg_post<float>(const Multi<MGArgs<float>>&, bool, hipStream_t);
 template void launch_mg_coarse<double>(const Multi<CoarseArgs>&, hipStream_t);
 template void launch_mg_coarse<float>(const Multi<CoarseArgs>&, hipStream_t);
 
