@@ -61,8 +61,10 @@ BYTES_PER_CELL = {
 # size), h=1/128, recorded with the kernel sources and launch shapes of the summaries in profiles/.
 # Set an entry to None when its kernel or its launch shape changes.
 MEASURED_TRAFFIC_PER_MEMBER_CELL = {
-    ("predictor", "mixed"): None,
-    ("pre", "mixed"): None,
+    # profiles/k_predictor_fused_h128_65members_mixed.md: 33-member launches (two lanes), 479.9 MB per
+    # launch (FETCH 279.4 + WRITE 200.4); the first refinement pass's finest pre kernel 73.9 MB
+    ("predictor", "mixed"): 177.5,
+    ("pre", "mixed"): 27.3,
     ("post", "mixed"): None,
     ("resid", "mixed"): None,
     ("predictor", "fp64"): None,
