@@ -9,7 +9,7 @@
 // v_mfma_f32_16x16x4f32 for FP32 operands) with a split over m and FP64
 // partials reduced in a fixed order (two levels). The n x n solve is an FP64
 // Cholesky in one workgroup (in the registers of four waves up to n = 64, in
-// 64-column panels up to n = 256); the projection g = X^T c is a
+// 32-column panels with MFMA trailing updates up to n = 256); the projection g = X^T c is a
 // bandwidth-bound GEMV with FP64 accumulation.
 #include "common.h"
 #include "kernels.h"
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(CHOL_BLK_NT) void k_chol_blocked(double* A, const d
   if (__syncthreads_or(nonfinite) && tid == 0 && *info == 0) *info = -1;
 }
 
-// ---------------------------------------------------------------------------- register Cholesky (n <= 64) and 64-column panels
+// ---------------------------------------------------------------------------- register Cholesky (n <= 64) and 32-column panels
 // Same system, (G + ridge I) x = rhs, as the kernels above, through the plain
 // factor G + ridge I = L L^T.
 //
@@ -413,42 +413,77 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// wave_chol64 factors a symmetric 64 x 64 block held one column per lane of one wave,
-// a[i] = A[i][lane], with no workgroup barrier, for the 64-column blocks of k_chol_p64. Step k
-// scales row k by 1 / sqrt(a_kk) (l_j = a_kj / sqrt(a_kk), lanes j > k), broadcasts it through
-// LDS, and every lane j > k subtracts l_i l_j from its entries i > k; lanes j <= k multiply by
-// zero instead of branching, so that a step is one basic block and the next pivot's chain
-// overlaps the updates. All 64 steps are unrolled (measured with the other phases of that
-// kernel: 415 us at n = 256 against 530 us for a loop over panels of eight). On return lane j
-// holds L[j][k] in a[k] for k < j, its pivot in a[j] and the trailing entries A^(j)[i][j] below
-// (i > j); rs = 1 / L[j][j] (rsqrt of the pivot) and sq = L[j][j] (pivot * rs). Returns
-// (wave-uniform) the first step whose pivot is not positive, plus one, or 0.
-__device__ __forceinline__ int wave_chol64(double (&a)[64], double& sq, double& rs, double* colk) {
-  const int lane = threadIdx.x & 63;
-  int bad = 0;
-  sq = 1.0;
-  rs = 1.0;
-  double piv = readlane_d(a[0], 0);
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    if (!(piv > 0.0) && bad == 0) bad = k + 1;
-    const double p = piv > 0.0 ? piv : 1e-300;
-    const double r = rsqrt(p);
-    double* const c = colk + (k & 1) * 64;  // two buffers: one wave sync per step
-    const double t = a[k] * r;
-    c[lane] = t;
-    wave_sync();
-    // lanes <= k multiply by zero instead of branching, so that a step is one basic block and
-    // the next pivot's chain overlaps this step's updates. That pivot is lane k + 1's own
-    // diagonal update (c[k + 1] is its t), bit for bit the value the loop below leaves.
-    const double tt = lane > k ? t : 0.0;
-    if (k + 1 < 64) piv = readlane_d(fma(-t, tt, a[k + 1]), k + 1);
-    sq = lane == k ? p * r : sq;
-    rs = lane == k ? r : rs;
-    a[k] = lane > k ? t : a[k];
-#pragma unroll
-    for (int i = k + 1; i < 64; ++i) a[i] = fma(-c[i], tt, a[i]);
+// lane src's value of v, for every lane (src may differ per lane)
+__device__ __forceinline__ double bperm_d(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// wave_chol32 factors a symmetric 32 x 32 block in one wave, with no barrier and no LDS: lane
+// (p, q) = (lane / 8, lane % 8) holds the entries (p + 8a, q + 8b) of the lower triangle in slot
+// e[a][b], b <= a (in the diagonal slots, the entries with p < q are upper and never used). Step
+// k: the lanes of column class k % 8 scale column k by r = 1 / sqrt(pivot) (the rows below k;
+// the pivot's own entry becomes pivot * r = sqrt(pivot)), every lane fetches the multipliers of
+// its four rows and four columns from those lanes (ds_bpermute, zero at rows <= k) and updates
+// the slots that can still hold trailing entries (both indices >= 8 (k / 8)). The next pivot is
+// formed from scalars read across lanes as soon as r is known, E(k+1, k+1) - (E(k+1, k) r)^2,
+// bit for bit the value the update leaves, so that the pivot chain does not wait for the
+// permutes: a step costs about one FP64 reciprocal square root and a few dependent operations.
+// The eight steps of a block of columns share their code (a rolled loop, the last one apart):
+// the kernel runs once per solve, and code that does not stay in the instruction cache is
+// fetched again for every panel. On return the slots hold L (lower entries); rsv[k] =
+// 1 / L[k][k] (written by lane 0). Returns (wave-uniform) the first step whose pivot is not
+// positive, plus one, or 0.
+// one step k = 8 KB + kq of wave_chol32; LAST: kq = 7, the next pivot lies in the next block
+template <int KB, bool LAST>
+__device__ __forceinline__ void wave_chol32_step(double (&e)[4][4], double* rsv, int kq, double& piv, int& bad) {
+  const int lane = threadIdx.x & 63, p = lane >> 3, q = lane & 7;
+  const int k = 8 * KB + kq;
+  if (!(piv > 0.0) && bad == 0) bad = k + 1;
+  const double pv = piv > 0.0 ? piv : 1e-300;
+  const double r = rsqrt(pv);
+  if (lane == 0) rsv[k] = r;
+  if constexpr (!LAST) {  // the next pivot, (k + 1, k + 1), in this block
+    const double l1 = readlane_d(e[KB][KB], (kq + 1) * 8 + kq) * r;
+    piv = fma(-l1, l1, readlane_d(e[KB][KB], (kq + 1) * 9));
+  } else if constexpr (KB < 3) {  // (8 KB + 8, 8 KB + 8): row class 0 of the next block
+    const double l1 = readlane_d(e[KB + 1][KB], 7) * r;
+    piv = fma(-l1, l1, readlane_d(e[KB + 1][KB + 1], 0));
   }
+  double lval[4];
+#pragma unroll
+  for (int a = KB; a < 4; ++a) {
+    const int i = p + 8 * a;
+    const double l = e[a][KB] * r;
+    lval[a] = (q == kq && i > k) ? l : 0.0;
+    e[a][KB] = q == kq ? (i > k ? l : (i == k ? pv * r : e[a][KB])) : e[a][KB];
+  }
+  double lr[4], lc[4];
+#pragma unroll
+  for (int a = KB; a < 4; ++a) {
+    lr[a] = bperm_d(lval[a], p * 8 + kq);
+    lc[a] = bperm_d(lval[a], q * 8 + kq);
+  }
+#pragma unroll
+  for (int a = KB; a < 4; ++a)
+#pragma unroll
+    for (int b = KB; b <= a; ++b) e[a][b] = fma(-lr[a], lc[b], e[a][b]);
+}
+template <int KB>
+__device__ __forceinline__ void wave_chol32_block(double (&e)[4][4], double* rsv, double& piv, int& bad) {
+#pragma unroll 1
+  for (int kq = 0; kq < 7; ++kq) wave_chol32_step<KB, false>(e, rsv, kq, piv, bad);
+  wave_chol32_step<KB, true>(e, rsv, 7, piv, bad);
+}
+__device__ __forceinline__ int wave_chol32(double (&e)[4][4], double* rsv) {
+  int bad = 0;
+  double piv = readlane_d(e[0][0], 0);
+  wave_chol32_block<0>(e, rsv, piv, bad);
+  wave_chol32_block<1>(e, rsv, piv, bad);
+  wave_chol32_block<2>(e, rsv, piv, bad);
+  wave_chol32_block<3>(e, rsv, piv, bad);
   return bad;
 }
 
@@ -544,205 +579,335 @@ __global__ __launch_bounds__(256) void k_chol_wave(const double* G, const double
   if (lane == 0) *info = first != 0 ? first : nonfinite ? -1 : 0;
 }
 
-// 64 < n <= CHOL_P64_MAX: right-looking in 64-column panels, the matrix in
-// global memory (L2 resident; lower triangle kept) and one workgroup. Per panel:
-// wave 0 factors the diagonal block (wave_chol64) and stores L11; every thread
-// takes one row of the panel below and solves L11 l^T = a^T right-looking (column
-// c final once scaled, then 63 - c independent updates) with L11 broadcast from
-// LDS; the panel, transposed in LDS, then takes the trailing lower triangle
-// A22 -= L21 L21^T in 4 x 4 register tiles. The solves are blocked the same way:
-// the diagonal blocks by wave 0 with the block in registers and the pivots and
-// running right-hand side read across lanes, the off-diagonal blocks as GEMVs by
-// all threads.
-constexpr int CHOL_P64_MAX = 256;
-constexpr int CHOL_P64_NT = 512;                 // eight waves: 256 VGPRs for wave 0's 64-double column
-constexpr int CHOL_P64_PR = CHOL_P64_MAX - 64;   // rows of the transposed panel
-constexpr int CHOL_P64_LDS = 64 * CHOL_P64_PR * (int)sizeof(double);  // dynamic part: the transposed panel
+// 64 < n <= CHOL_M32_MAX: right-looking in 32-column panels in one workgroup of four waves (one
+// per SIMD, so that each has the whole register file: 256 VGPRs and 256 AGPRs), with the
+// trailing matrix held, negated, in registers as MFMA accumulators. The system is padded to
+// n_p = 32 ceil(n / 32) with an identity block (its factor is the identity, its part of y and x
+// is zero), so every panel is full and every tile whole. G is read once, through a buffer
+// resource of n^2 doubles whose range check returns zero for a padded row of the lower triangle
+// (row >= n puts the offset row n + col past the end). The 16 x 16 tiles (ti, tj) of the lower
+// triangle below the first panel (2 <= tj <= ti < n_p / 16) are dealt in (tj, ti) order, tile q
+// to wave q mod 4 as its register slot q div 4; the tiles still trailing at panel p are those
+// with tj >= 2p + 2, a suffix q >= q0(p) of that order, so each panel's update is balanced over
+// the waves to within one tile. Each panel's 32 columns (all rows from its diagonal down) live
+// in an LDS buffer, two of them used in turn. Per panel p, three barriers (LDS only: the stores
+// of L to G are waited for once, before the backward solve):
+//   1. wave 0 factors the diagonal block L11 in registers (wave_chol32, the block spread over
+//      all 64 lanes) from the buffer, keeps it (column-major) in LDS with the pivots'
+//      reciprocals and stores it to G;
+//   2. one thread per row below solves L11 l^T = a^T right-looking with L11 broadcast from LDS
+//      (32 doubles in registers) and writes the row of L21 over its input in the buffer and to
+//      G; one more thread solves the right-hand side's block the same way (y's block: the
+//      forward solve L y = rhs rides along as one more row);
+//   3. the rows below take rhs_i -= l_i . y, and every wave adds L21 L21^T to its (negated)
+//      trailing tiles with v_mfma_f64_16x16x4f64 (A operand: L21 rows of tile row ti; B
+//      operand: L21 rows of tile row tj), then stores the tiles of the next panel's two tile
+//      columns, negated back, into the other buffer. Lane l supplies A[l%16][kk] and
+//      B[kk][l%16], kk = l/16; instruction s gives it the panel column c = 8 kk + s, so each
+//      lane reads eight consecutive doubles of one buffer row (four 16-byte LDS reads per
+//      operand); any assignment of the 32 columns to (kk, s) gives the same sum of products.
+// The backward solve L^T x = y runs block by block from the last, each block's rows of L staged
+// in LDS while the block before is solved: wave 0 the diagonal block (its columns in registers,
+// the running right-hand side read across lanes), then the rows above as a GEMV.
+// Scheduling notes, measured: the kernel runs once per solve, mostly straight-line code, and
+// code that does not stay in the instruction cache is fetched again for every panel, so it is
+// kept compact (one short block per register slot, the tile coordinates in an LDS table, the
+// diagonal factor's steps rolled within blocks of eight). Left to itself the scheduler issues
+// each LDS read at its first use and waits for it there (about 120 cycles a read); the reads of
+// a panel row's column, of the backward block and of the first panel are therefore issued
+// together ahead of their uses (scheduling barriers keep them there). At n = 256 the kernel
+// takes about 175 us (the 64-column kernel it replaced: 425 us), of which about 60 us are the
+// eight diagonal factors, each a chain of 32 FP64 reciprocal square roots.
+constexpr int CHOL_M32_MAX = 256;
+constexpr int CHOL_M32_NT = 256;
+constexpr int CHOL_M32_NW = CHOL_M32_NT / 64;
+constexpr int CHOL_M32_SLOTS = 27;  // ceil(105 / 4): the tiles below the first panel at n_p = 256
+constexpr int CHOL_M32_PS = 34;     // buffer row stride, doubles: 16-byte rows, 16 rows span all banks
+constexpr int CHOL_M32_R0 = CHOL_M32_MAX;       // rows of buffer 0 (the first panel: all rows)
+constexpr int CHOL_M32_R1 = CHOL_M32_MAX - 32;  // rows of buffer 1 (odd panels)
+constexpr int CHOL_M32_LDS = (CHOL_M32_R0 + CHOL_M32_R1) * CHOL_M32_PS * (int)sizeof(double);
+static_assert((CHOL_M32_MAX / 16 - 2) * (CHOL_M32_MAX / 16 - 1) / 2 <= CHOL_M32_SLOTS * CHOL_M32_NW, "slots");
+static_assert(CHOL_M32_NT > CHOL_M32_MAX - 32, "one thread per panel row and one for the right-hand side");
 
-__global__ __launch_bounds__(CHOL_P64_NT) void k_chol_p64(double* A, const double* rhs, int n, double* x, int* info,
+__device__ __forceinline__ double buf_load_d(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// workgroup barrier that orders LDS only (global stores stay in flight)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__global__ __launch_bounds__(CHOL_M32_NT) void k_chol_m32(double* A, const double* rhs, int n, double* x, int* info,
                                                       double ridge_rel) {
-  // the small buffers are static so that their constant offsets fold into the LDS
-  // instructions (offsets into the dynamic block are materialised one register each)
-  __shared__ double sL[64 * 65];  // L11, row stride 65
-  __shared__ double sR[64];       // 1 / L11[c][c]
-  __shared__ double colk[128];
-  __shared__ double sv[CHOL_P64_MAX];  // rhs -> y -> x
-  extern __shared__ double Pt[];       // Pt[c * PR + r] = L21[r][c]
-  constexpr int PR = CHOL_P64_PR;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ __align__(16) double sLc[32 * 32];  // sLc[c * 32 + k] = L11[k][c]
+  __shared__ double sR[32];        // 1 / L11[c][c]
+  __shared__ double sridge;
+  __shared__ double sv[CHOL_M32_MAX];                    // rhs -> y -> x (zero in the padding)
+  __shared__ int stab[CHOL_M32_NW * CHOL_M32_SLOTS];     // tile q: ti | tj << 8
+  extern __shared__ __align__(16) double Pbuf[];         // two panel buffers, row r = the panel's row k0 + r
+  constexpr int PS = CHOL_M32_PS;
+  typedef double __attribute__((ext_vector_type(4))) acc4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, kk = lane >> 4;
   const long ld = n;
-  if (wave == 0) {  // trace: strided partial sums, then a fixed shuffle tree
+  const int np = (n + 31) & ~31, T = np >> 4, ntile = (T - 2) * (T - 1) / 2;
+  const __amdgpu_buffer_rsrc_t gr = __builtin_amdgcn_make_buffer_rsrc(A, 0, n * n * (int)sizeof(double), 0x00020000);
+  if (tid < CHOL_M32_NW * CHOL_M32_SLOTS) {  // the tile order: column tj = 2, 3, ... of the tile grid
+    int q = tid, c = 2;
+    while (c < T && q >= T - c) {
+      q -= T - c;
+      ++c;
+    }
+    stab[tid] = (c + q) | (c << 8);
+  }
+  if (wave == 0) {  // trace: four clamped loads per lane, then a fixed shuffle tree
     double tr = 0.0;
-    for (int i = lane; i < n; i += 64) tr += A[i * ld + i];
+#pragma unroll
+    for (int q = 0; q < CHOL_M32_MAX / 64; ++q) {
+      const int i = lane + 64 * q, ic = min(i, n - 1);
+      const double d = buf_load_d(gr, ic * (n + 1) * (int)sizeof(double), 0);
+      tr += i < n ? d : 0.0;
+    }
     tr = wave_sum(tr);
     if (lane == 0) {
-      colk[0] = ridge_rel * tr / (double)n;
+      sridge = ridge_rel * tr / (double)n;
       *info = 0;
     }
   }
-  __syncthreads();
-  const double ridge = colk[0];
-  for (int i = tid; i < n; i += CHOL_P64_NT) A[i * ld + i] += ridge;
-  __threadfence_block();
-  __syncthreads();
-  for (int i = tid; i < n; i += CHOL_P64_NT) sv[i] = rhs[i];
-  for (int k0 = 0; k0 < n; k0 += 64) {
-    const int kw = min(64, n - k0), rows = n - k0 - kw;
-    double* const Ak = A + (long)k0 * ld + k0;
+  // the first panel into buffer 0 (lower triangle mirrored; padded rows load as zero), without
+  // the ridge (wave 0 adds it to the first diagonal block)
+  double* const B0 = Pbuf;
+  {
+    constexpr int Q = CHOL_M32_MAX * 32 / CHOL_M32_NT;
+    double g[Q];  // all loads in flight at once (an offset past n^2 reads zero)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + CHOL_M32_NT * q, i = e >> 5, j = e & 31;
+      g[q] = buf_load_d(gr, (max(i, j) * n + min(i, j)) * (int)sizeof(double), 0);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + CHOL_M32_NT * q, i = e >> 5, j = e & 31;
+      if (i < np) B0[i * PS + j] = g[q];
+    }
+  }
+  for (int i = tid; i < np; i += CHOL_M32_NT) sv[i] = i < n ? rhs[i] : 0.0;
+  lds_barrier();
+  // the trailing tiles, negated, into their registers, a group of slots at a time (all loads of a
+  // group in flight together; a slot without a tile reads past the end, zeros); the diagonal
+  // takes the ridge, and the padding's identity (its entries load as zero)
+  int loff[4];  // byte offset of this lane's entries within a tile
+#pragma unroll
+  for (int r = 0; r < 4; ++r) loff[r] = ((kk + 4 * r) * n + li) * (int)sizeof(double);
+  acc4 acc[CHOL_M32_SLOTS];
+  constexpr int GRP = 9;
+#pragma unroll
+  for (int g0 = 0; g0 < CHOL_M32_SLOTS; g0 += GRP) {
+#pragma unroll
+    for (int s = g0; s < g0 + GRP && s < CHOL_M32_SLOTS; ++s) {
+      const int q = CHOL_M32_NW * s + wave;
+      const int t = __builtin_amdgcn_readfirstlane(stab[q]), ti = t & 255, tj = t >> 8;
+      const int tb = q < ntile ? (16 * ti * n + 16 * tj) * (int)sizeof(double) : n * n * (int)sizeof(double);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[s][r] = buf_load_d(gr, tb + loff[r], 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const double ridge = sridge;
+#pragma unroll
+    for (int s = g0; s < g0 + GRP && s < CHOL_M32_SLOTS; ++s) {
+      const int q = CHOL_M32_NW * s + wave;
+      const int t = __builtin_amdgcn_readfirstlane(stab[q]), ti = t & 255, tj = t >> 8;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti + kk + 4 * r;
+        const bool dg = q < ntile && ti == tj && row == 16 * tj + li;
+        acc[s][r] = dg ? (row < n ? -(acc[s][r] + ridge) : -1.0) : -acc[s][r];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  int q0 = 0;  // the first tile of the order still trailing
+  for (int p = 0; 32 * p < np; ++p) {
+    const int k0 = 32 * p, R = np - k0;  // rows of this panel, its diagonal block included
+    double* const Bp = Pbuf + (p & 1) * CHOL_M32_R0 * PS;
+    double* const Bn = Pbuf + ((p + 1) & 1) * CHOL_M32_R0 * PS;
+    // 1. the diagonal block
     if (wave == 0) {
-      double a[64];
-      const int lc = min(lane, kw - 1);
+      // opaque per panel: otherwise the offsets below are hoisted out of the panel loop, and
+      // spilled
+      int pq = lane;
+      asm volatile("" : "+v"(pq));
+      const int pp = pq >> 3, qq = pq & 7;
+      double e[4][4];
 #pragma unroll
-      for (int i = 0; i < 64; ++i) {  // unconditional loads, masked arithmetically (as in k_chol_wave)
-        const int ic = min(i, kw - 1);
-        const double g = Ak[max(ic, lc) * ld + min(ic, lc)];
-        const bool in = i < kw && lane < kw;
-        a[i] = fma(g, in ? 1.0 : 0.0, (i == lane && !in) ? 1.0 : 0.0);
-      }
-      double sq, rs;
-      const int bad = wave_chol64(a, sq, rs, colk);
-      if (lane == 0 && bad != 0 && bad <= kw && *info == 0) *info = k0 + bad;
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int k = 0; k < 64; ++k) sL[lane * 65 + k] = k < lane ? a[k] : k == lane ? sq : 0.0;
-      sR[lane] = rs;
-      // row lane of L11 back to memory (lower triangle) from LDS, without per-element branches
-      // on the register array
-      wave_sync();
-      for (int e = lane; e < kw * kw; e += 64) {
-        const int i = e / kw, k = e - i * kw;
-        if (k <= i) Ak[i * ld + k] = sL[i * 65 + k];
-      }
+        for (int b = 0; b <= a; ++b) {
+          const int i = pp + 8 * a, j = qq + 8 * b;
+          e[a][b] = Bp[max(i, j) * PS + min(i, j)] + (p == 0 && i == j ? sridge : 0.0);
+        }
+      const int bad = wave_chol32(e, sR);
+      if (lane == 0 && bad != 0 && *info == 0) *info = k0 + bad;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          const int i = pp + 8 * a, j = qq + 8 * b;
+          if (i >= j) {
+            sLc[j * 32 + i] = e[a][b];
+            if (k0 + i < n) A[(k0 + i) * ld + k0 + j] = e[a][b];
+          }
+        }
     }
-    __syncthreads();
-    const int rows4 = (rows + 3) & ~3;
-    // a panel with rows below it is full (kw = 64); rows4 <= PR < CHOL_P64_NT: one row per thread
-    if (tid < rows4) {
-      const int r = tid;
-      double* const src = Ak + (long)(kw + r) * ld;
-      const double* const srow = Ak + (long)(kw + min(r, rows - 1)) * ld;
-      double ar[64];
-      const double keep = r < rows ? 1.0 : 0.0;
+    lds_barrier();
+    // 2. the rows below and the right-hand side's block. Column c's multipliers L11[k][c]
+    // (k > c, 16-byte reads) are all read before its updates, which then wait for each read in
+    // turn (LDS returns in order); left to itself the scheduler issues each read at its first use
+    // and waits for it there.
+    const int nrow = R - 32;
+    if (tid <= nrow) {
+      const bool isrhs = tid == nrow;
+      double ar[32];
+      const double* const src = Bp + (32 + min(tid, nrow - 1)) * PS;
 #pragma unroll
-      for (int c = 0; c < 64; ++c) ar[c] = srow[c] * keep;
-      // right-looking: column c is final once scaled, then leaves the 63 - c independent updates
-#pragma unroll
-      for (int c = 0; c < 64; ++c) {
-        ar[c] *= sR[c];
-#pragma unroll
-        for (int k = c + 1; k < 64; ++k) ar[k] = fma(-sL[k * 65 + c], ar[c], ar[k]);
-      }
-      if (r < rows) {
-#pragma unroll
-        for (int c = 0; c < 64; ++c) src[c] = ar[c];
+      for (int c = 0; c < 32; c += 2) {
+        const double2 g = nrow > 0 ? *(const double2*)(src + c) : make_double2(0.0, 0.0);
+        ar[c] = isrhs ? sv[k0 + c] : g.x;
+        ar[c + 1] = isrhs ? sv[k0 + c + 1] : g.y;
       }
 #pragma unroll
-      for (int c = 0; c < 64; ++c) Pt[c * PR + r] = ar[c];
-    }
-    __syncthreads();
-    const int T = rows4 >> 2, ntile = T * (T + 1) / 2;
-    double* const A22 = Ak + (long)kw * ld + kw;
-    for (int idx = tid; idx < ntile; idx += CHOL_P64_NT) {
-      int ti = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
-      while (ti * (ti + 1) / 2 > idx) --ti;
-      while ((ti + 1) * (ti + 2) / 2 <= idx) ++ti;
-      const int tj = idx - ti * (ti + 1) / 2;
-      double acc[4][4];
+      for (int c = 0; c < 32; ++c) {
+        // column c's multipliers, all reads issued before the updates that wait for them
+        double lv[32];
+        const double rc = sR[c];
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+        for (int k = (c + 1) & ~1; k < 32; k += 2) {
+          const double2 v = *(const double2*)(sLc + c * 32 + k);
+          lv[k] = v.x;
+          lv[k + 1] = v.y;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ar[c] *= rc;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-      const double* const pi = Pt + 4 * ti;
-      const double* const pj = Pt + 4 * tj;
-#pragma unroll 4
-      for (int c = 0; c < kw; ++c) {
-        const double2 i01 = *(const double2*)(pi + c * PR), i23 = *(const double2*)(pi + c * PR + 2);
-        const double2 j01 = *(const double2*)(pj + c * PR), j23 = *(const double2*)(pj + c * PR + 2);
-        const double li[4] = {i01.x, i01.y, i23.x, i23.y}, lj[4] = {j01.x, j01.y, j23.x, j23.y};
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[p][q] = fma(li[p], lj[q], acc[p][q]);
+        for (int k = c + 1; k < 32; ++k) ar[k] = fma(-lv[k], ar[c], ar[k]);
+        __builtin_amdgcn_sched_barrier(0);
       }
+      if (isrhs) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int i = 4 * ti + p;
+        for (int c = 0; c < 32; ++c) sv[k0 + c] = ar[c];
+      } else {
+        double* const dst = Bp + (32 + tid) * PS;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = 4 * tj + q;
-          if (i < rows && j <= i) A22[i * ld + j] -= acc[p][q];
+        for (int c = 0; c < 32; c += 2) *(double2*)(dst + c) = make_double2(ar[c], ar[c + 1]);
+        if (k0 + 32 + tid < n) {
+          double* const g = A + (long)(k0 + 32 + tid) * ld + k0;
+#pragma unroll
+          for (int c = 0; c < 32; ++c) g[c] = ar[c];
         }
       }
     }
-    __threadfence_block();
-    __syncthreads();
-  }
-  // L y = rhs
-  for (int k0 = 0; k0 < n; k0 += 64) {
-    const int kw = min(64, n - k0);
-    const double* const Ak = A + (long)k0 * ld + k0;
-    if (wave == 0) {
-      double a[64];
-      const int lc = min(lane, kw - 1);
-      // unmasked: only k < lane is used by a lane below kw; padding lanes start at zero and
-      // their broadcasts reach padding lanes only
+    lds_barrier();
+    // 3. the right-hand side below, then the trailing tiles
+    if (tid < nrow) {
+      double t = sv[k0 + 32 + tid];
+      const double* const row = Bp + (32 + tid) * PS;
 #pragma unroll
-      for (int k = 0; k < 64; ++k) a[k] = Ak[lc * ld + min(k, kw - 1)];
-      const double dg = Ak[lc * ld + lc], b = sv[k0 + lc];
-      const double rs = lane < kw ? 1.0 / dg : 1.0;
-      double v = lane < kw ? b : 0.0;
-#pragma unroll
-      for (int k = 0; k < 64; ++k) {
-        const double yk = readlane_d(v * rs, k);
-        if (lane == k)
-          v = yk;
-        else if (lane > k)
-          v = fma(-a[k], yk, v);
+      for (int c = 0; c < 32; c += 2) {
+        const double2 l = *(const double2*)(row + c);
+        t = fma(-l.x, sv[k0 + c], t);
+        t = fma(-l.y, sv[k0 + c + 1], t);
       }
-      if (lane < kw) sv[k0 + lane] = v;
+      sv[k0 + 32 + tid] = t;
     }
-    __syncthreads();
-    for (int i = k0 + kw + tid; i < n; i += CHOL_P64_NT) {
-      const double* const Li = A + (long)i * ld + k0;
-      double t = sv[i];
-      for (int c = 0; c < kw; ++c) t = fma(-Li[c], sv[k0 + c], t);
-      sv[i] = t;
+#pragma unroll
+    for (int s = 0; s < CHOL_M32_SLOTS; ++s) {
+      const int q = CHOL_M32_NW * s + wave;
+      if (q >= q0 && q < ntile) {  // wave-uniform
+        const int t = __builtin_amdgcn_readfirstlane(stab[q]), ti = t & 255, tj = t >> 8;
+        const double* const pa = Bp + (16 * (ti - 2 * p) + li) * PS + 8 * kk;
+        const double* const pb = Bp + (16 * (tj - 2 * p) + li) * PS + 8 * kk;
+        double2 va[4], vb[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          va[c] = *(const double2*)(pa + 2 * c);
+          vb[c] = *(const double2*)(pb + 2 * c);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[c].x, vb[c].x, acc[s], 0, 0, 0);
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[c].y, vb[c].y, acc[s], 0, 0, 0);
+        }
+        if (tj <= 2 * p + 3) {  // a tile of the next panel: into the other buffer
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            Bn[(16 * (ti - 2 * p - 2) + kk + 4 * r) * PS + 16 * (tj - 2 * p - 2) + li] = -acc[s][r];
+        }
+      }
     }
-    __syncthreads();
+    q0 += 2 * (T - 2 * p) - 5;  // the tiles of columns 2p + 2 and 2p + 3 leave the trailing matrix
+    lds_barrier();
   }
-  // L^T x = y
-  for (int k0 = ((n - 1) / 64) * 64; k0 >= 0; k0 -= 64) {
-    const int kw = min(64, n - k0);
-    const double* const Ak = A + (long)k0 * ld + k0;
+  __threadfence_block();  // L in G, visible to the whole workgroup
+  __syncthreads();
+  // L^T x = y, block by block from the last; each block's 32 rows of L are staged in LDS (one
+  // row per CHOL_M32_MAX doubles, thread t taking column t of every row) from registers that were
+  // loaded while the block before was being solved
+  double* const Lb = Pbuf;
+  constexpr int LS = CHOL_M32_MAX;
+  const int kl = ((n - 1) / 32) * 32, tc = min(tid, n - 1);
+  double lv[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c)
+    lv[c] = buf_load_d(gr, tc * (int)sizeof(double), (kl + min(c, n - 1 - kl)) * n * (int)sizeof(double));
+  for (int k0 = kl; k0 >= 0; k0 -= 32) {
+    const int kw = min(32, n - k0);
+#pragma unroll
+    for (int c = 0; c < 32; ++c) Lb[c * LS + tid] = lv[c];
+    lds_barrier();
+    if (k0 >= 32) {  // the next block's rows, in flight while this one is solved
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        lv[c] = buf_load_d(gr, tc * (int)sizeof(double), (k0 - 32 + c) * n * (int)sizeof(double));
+    }
     if (wave == 0) {
-      double a[64];
       const int lc = min(lane, kw - 1);
+      double a[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) a[k] = Lb[min(k, kw - 1) * LS + k0 + lc];
+      const double dg = Lb[lc * LS + k0 + lc], b = sv[k0 + lc];
+      __builtin_amdgcn_sched_barrier(0);
       // unmasked: a padding lane k >= kw keeps v = 0 (its updates are finite entries times
       // zero), so x_k = 0 and the clamped entries it meets change nothing
-#pragma unroll
-      for (int k = 0; k < 64; ++k) a[k] = Ak[min(k, kw - 1) * ld + lc];
-      const double dg = Ak[lc * ld + lc], b = sv[k0 + lc];
       const double rs = lane < kw ? 1.0 / dg : 1.0;
       double v = lane < kw ? b : 0.0;
 #pragma unroll
-      for (int k = 63; k >= 0; --k) {
+      for (int k = 31; k >= 0; --k) {
         const double xk = readlane_d(v * rs, k);
-        if (lane == k)
-          v = xk;
-        else if (lane < k)
-          v = fma(-a[k], xk, v);
+        v = lane == k ? xk : lane < k ? fma(-a[k], xk, v) : v;
       }
       if (lane < kw) sv[k0 + lane] = v;
     }
-    __syncthreads();
-    for (int i = tid; i < k0; i += CHOL_P64_NT) {
-      double t = sv[i];
-      for (int c = 0; c < kw; ++c) t = fma(-A[(long)(k0 + c) * ld + i], sv[k0 + c], t);
-      sv[i] = t;
+    lds_barrier();
+    if (tid < k0) {  // k0 < CHOL_M32_NT: one row of the system per thread
+      double l[32], xs[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) {
+        l[c] = Lb[c * LS + tid];
+        xs[c] = sv[k0 + c];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      double t = sv[tid];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) t = fma(c < kw ? -l[c] : 0.0, xs[c], t);
+      sv[tid] = t;
     }
-    __syncthreads();
+    lds_barrier();
   }
   bool nonfinite = false;
-  for (int i = tid; i < n; i += CHOL_P64_NT) {
+  for (int i = tid; i < n; i += CHOL_M32_NT) {
     x[i] = sv[i];
     nonfinite = nonfinite || !isfinite(sv[i]);
   }
@@ -811,15 +976,15 @@ int launch_chol_solve(double* G, const double* rhs, int n, double* x, double* wo
   if (n > CHOL_VEC_MAX) return -1;
   if (n <= 64) {
     hipLaunchKernelGGL(k_chol_wave, dim3(1), dim3(256), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
-  } else if (n <= CHOL_P64_MAX) {
+  } else if (n <= CHOL_M32_MAX) {
     static bool attr = false;
     if (!attr) {
-      if (hipFuncSetAttribute((const void*)k_chol_p64, hipFuncAttributeMaxDynamicSharedMemorySize, CHOL_P64_LDS) !=
+      if (hipFuncSetAttribute((const void*)k_chol_m32, hipFuncAttributeMaxDynamicSharedMemorySize, CHOL_M32_LDS) !=
           hipSuccess)
         return -2;
       attr = true;
     }
-    hipLaunchKernelGGL(k_chol_p64, dim3(1), dim3(CHOL_P64_NT), CHOL_P64_LDS, s, G, rhs, n, x, (int*)work, ridge_rel);
+    hipLaunchKernelGGL(k_chol_m32, dim3(1), dim3(CHOL_M32_NT), CHOL_M32_LDS, s, G, rhs, n, x, (int*)work, ridge_rel);
   } else if (n <= CHOL_BLK_MAX)
     hipLaunchKernelGGL(k_chol_blocked, dim3(1), dim3(CHOL_BLK_NT), 0, s, G, rhs, n, x, (int*)work, ridge_rel);
   else

@@ -24,8 +24,9 @@ def _run(rows, J, precision):
     return g.cpu().numpy()
 
 
-# n (or m when n > m) spans every Cholesky variant: four waves of 16 rows each (<= 64), 64-column
-# panels (<= 256), 32-column panels (<= 448) and the unblocked global-memory kernel. The four-wave
+# n (or m when n > m) spans every Cholesky variant: four waves of 16 rows each (<= 64), 32-column
+# panels with MFMA trailing updates (<= 256), 32-column panels on the vector units (<= 448) and the
+# unblocked global-memory kernel. The four-wave
 # factor is hit at every wave boundary (16, 32, 48), with a partly filled fourth wave (49, 63) and
 # full (64).
 @pytest.mark.parametrize("n,m", [(8, 4096), (64, 5000), (17, 333), (130, 1024), (1, 50), (16, 8), (40, 33),
@@ -42,10 +43,12 @@ def test_gradient_fp64_matches_lstsq(n, m):
     assert np.abs(g - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
-# the edges of the Cholesky variants (one wave <= 64 < 64-column blocks <= 256 < 32-column panels
-# <= 448 < unblocked) and the largest supported system, in the Gram (n <= m) and normal-equation
-# (n > m) forms
-@pytest.mark.parametrize("n,m", [(65, 200), (257, 600), (448, 900), (449, 900), (1024, 2048), (1100, 1024)])
+# the edges of the Cholesky variants (one wave <= 64 < MFMA panels <= 256 < vector panels <= 448 <
+# unblocked) and the largest supported system, in the Gram (n <= m) and normal-equation (n > m)
+# forms; inside the MFMA range, panel counts with a full last panel (96), one row past it (97) and
+# ragged trailing tiles (161, 223, 255)
+@pytest.mark.parametrize("n,m", [(65, 200), (96, 500), (97, 400), (161, 700), (223, 900), (255, 1000), (257, 600),
+                                 (448, 900), (449, 900), (1024, 2048), (1100, 1024)])
 def test_gradient_fp64_at_solver_size_edges(n, m):
     rng = np.random.default_rng(7 * n + m)
     rows = rng.standard_normal((n + 1, m)) * 1e-2
@@ -101,6 +104,24 @@ def test_gradient_with_repeated_members_is_minimum_norm(precision, tol):
     err = np.abs(g - ref).max() / np.abs(ref).max()
     print("repeated members", precision, err, flush=True)
     assert err <= tol
+
+
+def test_gradient_with_repeated_members_in_the_panel_range():
+    """Rank-deficient X at n = 150 (32-column MFMA panels): the minimum-norm solution."""
+    rng = np.random.default_rng(78)
+    n, m = 150, 4000
+    rows = rng.standard_normal((n + 1, m)) * 1e-2
+    for a, b in ((40, 3), (120, 77), (150, 149)):
+        rows[a] = rows[b]
+    J = rng.standard_normal(n + 1)
+    for a, b in ((40, 3), (120, 77), (150, 149)):
+        J[a] = J[b]
+    g = _run(rows, J, E.FP64)
+    X = rows[1:] - rows[0]
+    ref, *_ = np.linalg.lstsq(X, J[1:] - J[0], rcond=None)
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print("repeated members, n = 150", err, flush=True)
+    assert err <= 1e-8
 
 
 def test_gradient_reports_a_non_finite_cost():
