@@ -217,7 +217,7 @@ typedef struct {
  * non-finite). */
 int envar_forward_batch(envar_job* jobs, int32_t njobs, void* stream);
 
-/* Device bytes of the workspace of envar_gradient. */
+/* Device bytes of the workspace of envar_gradient (the same with or without ENVAR_GRADIENT_PINV). */
 size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
 
 /* Anomaly reduction {delta f_i, J_i} -> g (eq. gradient_EnVar, scalar-J form):
@@ -228,10 +228,18 @@ size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision);
  * The Gram X X^T runs on the matrix cores (FP64 MFMA, or FP32 MFMA with
  * precision = ENVAR_MIXED); the n x n solve is an FP64 Cholesky with a
  * relative ridge 1e-12 tr(G)/n (a rank-deficient X, e.g. repeated members, then gives the
- * minimum-norm solution up to that ridge). Synchronous (the solve is checked on the host).
- * Errors: EINVAL (n < 1, m < 1, min(n, m) > 1024), ENOMEM, EDIVERGED (a pivot not positive
- * after the ridge, or a non-finite solution, e.g. from a non-finite cost; g_dev is then
- * undefined), EDEVICE (a launch failed). */
+ * minimum-norm solution up to that ridge). When the factor fails (a pivot not positive after
+ * the ridge), the call does not give up: in mixed precision (n <= m) the system is formed
+ * again in FP64 from the control rows, the FP64 gradient's arithmetic; a factor that fails in
+ * FP64 is replaced by the eigen-pseudo-inverse of the Gram (cyclic Jacobi, eigenvalues at or
+ * below 1e-12 of the largest dropped; systems up to 512). precision | ENVAR_GRADIENT_PINV asks
+ * for the pseudo-inverse directly (in mixed precision over the FP64 Gram). Synchronous (the
+ * solve is checked on the host).
+ * Errors: EINVAL (n < 1, m < 1, min(n, m) > 1024, an unknown precision or flag), ENOMEM,
+ * EDIVERGED (a non-finite solution, e.g. from a non-finite cost; a failed factor with no
+ * fallback: mixed precision with n > m, or a system above 512; g_dev is then undefined),
+ * EDEVICE (a launch failed). */
+#define ENVAR_GRADIENT_PINV 16
 int envar_gradient(const double* controls_dev, const double* J_dev, int32_t n, int64_t m,
                    int32_t precision, void* ws_dev, size_t ws_bytes, double* g_dev, void* stream);
 

@@ -1836,10 +1836,12 @@ int envar_forward_obs(const envar_problem* p, const void* state_dev, const doubl
 // ---------------------------------------------------------------------------- gradient
 namespace envar {
 struct GradLayout {
-  size_t X, Xt, dJ, rhs, partial, tmp, G, c, info, total;
+  size_t X, Xt, dJ, rhs, partial, tmp, G, c, info, W, Wt, ev, jscr, total;
   int nsplit, dim;
   long kchunk;
 };
+constexpr int GRAD_PINV_MAX = 512;  // largest system the pseudo-inverse (one-workgroup Jacobi) takes
+constexpr double GRAD_PINV_RCOND = 1e-12;
 
 static GradLayout grad_layout(int n, long m, int precision) {
   GradLayout L{};
@@ -1869,6 +1871,13 @@ static GradLayout grad_layout(int n, long m, int precision) {
   L.G = take((size_t)L.dim * L.dim * 8);
   L.c = take((size_t)L.dim * 8);
   L.info = take(256);
+  if (L.dim <= GRAD_PINV_MAX) {  // the pseudo-inverse: eigenvectors, eigenvalues, Jacobi's matrices
+    const size_t d = (size_t)L.dim, ne = d + (d & 1);
+    L.W = take(d * d * 8);
+    L.Wt = take(d * d * 8);
+    L.ev = take(d * 8);
+    L.jscr = take(2 * ne * (ne + 1) * 8);
+  }
   L.total = o;
   return L;
 }
@@ -1877,7 +1886,7 @@ static GradLayout grad_layout(int n, long m, int precision) {
 
 extern "C" size_t envar_gradient_bytes(int32_t n, int64_t m, int32_t precision) {
   if (n < 1 || m < 1) return 0;
-  return grad_layout(n, m, precision).total;
+  return grad_layout(n, m, precision & ~ENVAR_GRADIENT_PINV).total;
 }
 
 namespace envar {
@@ -1886,44 +1895,107 @@ namespace envar {
 template <typename TX>
 static int gradient_impl(const double* ctrl, const double* J, int n, long m, int precision, void* ws, double* g,
                          hipStream_t s, bool pinned_flag = true) {
+  const bool pinv = (precision & ENVAR_GRADIENT_PINV) != 0;
+  precision &= ~ENVAR_GRADIENT_PINV;
   const GradLayout L = grad_layout(n, m, precision);
+  const bool tall = n <= m;
   TX* X = at<TX>(ws, L.X);
   double* dJ = at<double>(ws, L.dJ);
   double* G = at<double>(ws, L.G);
+  double* partial = at<double>(ws, L.partial);
+  double* rhs = at<double>(ws, L.rhs);
+  double* c = at<double>(ws, L.c);
+  int* info_dev = at<int>(ws, L.info);
+  // the solve's status word, read through a pinned word of this host thread (allocated once, kept
+  // for the process) or, for callers that cannot allocate, through pageable memory
+  auto read_info = [&](int& info) -> int {
+    if (pinned_flag) {
+      static thread_local int* flag = nullptr;
+      if (!flag) HIP_OK(hipHostMalloc((void**)&flag, sizeof(int), hipHostMallocDefault));
+      HIP_OK(hipMemcpyAsync(flag, info_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      info = *flag;
+    } else {
+      HIP_OK(hipMemcpyAsync(&info, info_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+    }
+    return ENVAR_OK;
+  };
   launch_anomaly<TX>(ctrl, J, n, m, X, dJ, s);
-  if (n <= m) {
-    launch_gram<TX>(X, n, m, m, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
-    launch_gram_reduce(at<double>(ws, L.partial), n, L.nsplit, at<double>(ws, L.tmp), G, s);
-    if (launch_chol_solve(G, dJ, n, at<double>(ws, L.c), at<double>(ws, L.info), s))
-      return fail(ENVAR_EDEVICE, "Cholesky launch failed (n = %d)", n);
-    launch_gemv_t<TX>(X, n, m, m, at<double>(ws, L.c), g, s);
+  if (tall) {
+    launch_gram<TX>(X, n, m, m, partial, L.nsplit, L.kchunk, s);
+    launch_gram_reduce(partial, n, L.nsplit, at<double>(ws, L.tmp), G, s);
+    if (!pinv) {
+      if (launch_chol_solve(G, dJ, n, c, (double*)info_dev, s)) return fail(ENVAR_EDEVICE, "Cholesky launch failed (n = %d)", n);
+      launch_gemv_t<TX>(X, n, m, m, c, g, s);
+    }
   } else {
     TX* Xt = at<TX>(ws, L.Xt);
     launch_transpose<TX>(X, n, m, Xt, s);
-    launch_gram<TX>(Xt, (int)m, n, n, at<double>(ws, L.partial), L.nsplit, L.kchunk, s);
-    launch_gram_reduce(at<double>(ws, L.partial), (int)m, L.nsplit, at<double>(ws, L.tmp), G, s);
-    double* rhs = at<double>(ws, L.rhs);
+    launch_gram<TX>(Xt, (int)m, n, n, partial, L.nsplit, L.kchunk, s);
+    launch_gram_reduce(partial, (int)m, L.nsplit, at<double>(ws, L.tmp), G, s);
     launch_gemv_t<TX>(X, n, m, m, dJ, rhs, s);
-    if (launch_chol_solve(G, rhs, (int)m, g, at<double>(ws, L.info), s))
+    if (!pinv && launch_chol_solve(G, rhs, (int)m, g, (double*)info_dev, s))
       return fail(ENVAR_EDEVICE, "Cholesky launch failed (m = %ld)", m);
   }
   HIP_OK(hipGetLastError());
-  // a pivot that is not positive after the ridge (a non-finite Gram) or a non-finite solution
-  // (a non-finite cost) is reported instead of returning garbage: the solve leaves both in one
-  // word, read through a pinned word of this host thread (allocated once, kept for the process)
   int info = 0;
-  if (pinned_flag) {
-    static thread_local int* flag = nullptr;
-    if (!flag) HIP_OK(hipHostMalloc((void**)&flag, sizeof(int), hipHostMallocDefault));
-    HIP_OK(hipMemcpyAsync(flag, at<int>(ws, L.info), sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    info = *flag;
-  } else {
-    HIP_OK(hipMemcpyAsync(&info, at<int>(ws, L.info), sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+  if (!pinv) {
+    // a pivot that is not positive after the ridge or a non-finite solution (a non-finite cost)
+    // is not returned as a gradient: the solve leaves both in one word
+    const int rc = read_info(info);
+    if (rc) return rc;
+    if (info < 0) return fail(ENVAR_EDIVERGED, "non-finite least-squares solution (a cost is not finite?)");
+    if (info == 0) return ENVAR_OK;
   }
-  if (info > 0) return fail(ENVAR_EDIVERGED, "the ensemble Gram is not positive definite (pivot %d)", info);
-  if (info < 0) return fail(ENVAR_EDIVERGED, "non-finite least-squares solution (a cost is not finite?)");
+  // A failed factor (or a requested pseudo-inverse). With FP32 anomalies, the Gram's rounding
+  // (about 1e-7 of its largest entries) can make the Gram of a nearly dependent ensemble
+  // indefinite; the system is then formed again in FP64 from the control rows, the anomalies
+  // taken on the fly, which is the FP64 gradient's own arithmetic. A factor that fails in FP64
+  // (or the pseudo-inverse asked for) goes to the eigen-pseudo-inverse of the Gram: its
+  // eigenvalues at or below 1e-12 of the largest dropped, the minimum-norm solution.
+  const bool fp32 = sizeof(TX) == sizeof(float);
+  if (fp32) {
+    if (!tall)
+      return fail(ENVAR_EDIVERGED, "the FP32 Gram of %d members over %ld controls is not positive definite (pivot %d); "
+                  "use ENVAR_FP64", n, m, info);
+    launch_gram_anom(ctrl, n, m, partial, L.nsplit, L.kchunk, s);
+    launch_gram_reduce(partial, n, L.nsplit, at<double>(ws, L.tmp), G, s);
+    if (!pinv) {
+      if (launch_chol_solve(G, dJ, n, c, (double*)info_dev, s)) return fail(ENVAR_EDEVICE, "Cholesky launch failed (n = %d)", n);
+      HIP_OK(hipGetLastError());
+      const int rc = read_info(info);
+      if (rc) return rc;
+      if (info < 0) return fail(ENVAR_EDIVERGED, "non-finite least-squares solution (a cost is not finite?)");
+      if (info == 0) {
+        launch_gemv_anom(ctrl, n, m, c, g, s);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(s));
+        return ENVAR_OK;
+      }
+    }
+  }
+  if (L.dim > GRAD_PINV_MAX)
+    return fail(ENVAR_EDIVERGED, "the ensemble Gram is not positive definite (pivot %d); the pseudo-inverse takes "
+                "systems up to %d", info, GRAD_PINV_MAX);
+  if (!pinv)  // the failed factor overwrote the Gram: reduce the partials again
+    launch_gram_reduce(partial, L.dim, L.nsplit, at<double>(ws, L.tmp), G, s);
+  double* W = at<double>(ws, L.W);
+  double* ev = at<double>(ws, L.ev);
+  if (launch_jacobi(G, L.dim, L.dim, ev, W, at<double>(ws, L.Wt), at<double>(ws, L.jscr), s))
+    return fail(ENVAR_EDEVICE, "Jacobi launch failed (n = %d)", L.dim);
+  if (launch_pinv_apply(W, ev, L.dim, tall ? dJ : rhs, tall ? c : g, GRAD_PINV_RCOND, info_dev, s))
+    return fail(ENVAR_EDEVICE, "pseudo-inverse launch failed (n = %d)", L.dim);
+  if (tall) {
+    if (fp32)
+      launch_gemv_anom(ctrl, n, m, c, g, s);
+    else
+      launch_gemv_t<TX>(X, n, m, m, c, g, s);
+  }
+  HIP_OK(hipGetLastError());
+  const int rc = read_info(info);
+  if (rc) return rc;
+  if (info != 0) return fail(ENVAR_EDIVERGED, "non-finite pseudo-inverse solution (a cost is not finite?)");
   return ENVAR_OK;
 }
 
@@ -1933,11 +2005,12 @@ extern "C" int envar_gradient(const double* controls_dev, const double* J_dev, i
                    void* ws_dev, size_t ws_bytes, double* g_dev, void* stream) {
   if (n < 1 || m < 1) return fail(ENVAR_EINVAL, "n and m must be >= 1");
   if (!controls_dev || !J_dev || !ws_dev || !g_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
-  if (precision != ENVAR_FP64 && precision != ENVAR_MIXED) return fail(ENVAR_EINVAL, "unknown precision");
+  const int base = precision & ~ENVAR_GRADIENT_PINV;
+  if (base != ENVAR_FP64 && base != ENVAR_MIXED) return fail(ENVAR_EINVAL, "unknown precision");
   if (std::min<long>(n, m) > 1024) return fail(ENVAR_EINVAL, "min(n, m) = %ld exceeds 1024", std::min<long>(n, m));
-  const GradLayout L = grad_layout(n, m, precision);
+  const GradLayout L = grad_layout(n, m, base);
   if (ws_bytes < L.total) return fail(ENVAR_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
-  if (precision == ENVAR_MIXED)
+  if (base == ENVAR_MIXED)
     return gradient_impl<float>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
   return gradient_impl<double>(controls_dev, J_dev, n, m, precision, ws_dev, g_dev, (hipStream_t)stream);
 }
@@ -1974,16 +2047,17 @@ extern "C" int envar_gradient_static(const double* controls_dev, const double* J
                                      int32_t precision, double* g_dev, void* stream) {
   if (n < 1 || m < 1) return fail(ENVAR_EINVAL, "n and m must be >= 1");
   if (!controls_dev || !J_dev || !g_dev) return fail(ENVAR_EINVAL, "NULL device pointer");
-  if (precision != ENVAR_FP64 && precision != ENVAR_MIXED) return fail(ENVAR_EINVAL, "unknown precision");
+  const int base = precision & ~ENVAR_GRADIENT_PINV;
+  if (base != ENVAR_FP64 && base != ENVAR_MIXED) return fail(ENVAR_EINVAL, "unknown precision");
   if (std::min<long>(n, m) > 1024) return fail(ENVAR_EINVAL, "min(n, m) = %ld exceeds 1024", std::min<long>(n, m));
-  const GradLayout L = grad_layout(n, m, precision);
+  const GradLayout L = grad_layout(n, m, base);
   if (L.total > ENVAR_GRADIENT_STATIC_MAX_BYTES)
     return fail(ENVAR_ENOMEM, "n = %d, m = %lld needs %zu bytes of scratch; the static array holds %zu", n,
                 (long long)m, L.total, (size_t)ENVAR_GRADIENT_STATIC_MAX_BYTES);
   void* ws = nullptr;
   const int rc = scratch_address(&ws);
   if (rc) return rc;
-  if (precision == ENVAR_MIXED)
+  if (base == ENVAR_MIXED)
     return gradient_impl<float>(controls_dev, J_dev, n, m, precision, ws, g_dev, (hipStream_t)stream, false);
   return gradient_impl<double>(controls_dev, J_dev, n, m, precision, ws, g_dev, (hipStream_t)stream, false);
 }

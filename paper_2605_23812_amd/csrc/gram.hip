@@ -71,9 +71,12 @@ struct Vec16<double> {
 // transposed as G[J][I]), so G is exactly symmetric. The X rows are fetched as 16-byte vectors into
 // registers one chunk ahead of the MFMA work on the chunk in LDS (a diagonal tile fetches its rows
 // once and uses them for both operands).
-template <typename TX>
+// ANOM: row r of X is formed on the fly as X[r] - X0 (the anomaly of a control row about the
+// centre row X0, the values k_anomaly would store), so that no copy of the anomalies is needed.
+template <typename TX, bool ANOM = false>
 __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, long m, long ldx,
-                                              double* __restrict__ partial, int nsplit, long kchunk, int nbt) {
+                                              double* __restrict__ partial, int nsplit, long kchunk, int nbt,
+                                              const TX* __restrict__ X0 = nullptr) {
   typedef typename MfmaAcc<TX>::V V;
   typedef typename Vec16<TX>::T VT;
   constexpr int KC = GRAM_KC, LDR = KC + 1;
@@ -100,8 +103,16 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
   VT ra[NV], rb[NV];
   auto load = [&](int row, long k) -> VT {
     VT v;
-    if (row < n && vec && k + VW <= kend) return *(const VT*)(X + (long)row * ldx + k);
-    for (int e = 0; e < VW; ++e) v[e] = (row < n && k + e < kend) ? X[(long)row * ldx + k + e] : (TX)0;
+    if (row < n && vec && k + VW <= kend) {
+      v = *(const VT*)(X + (long)row * ldx + k);
+      if constexpr (ANOM) v -= *(const VT*)(X0 + k);
+      return v;
+    }
+    for (int e = 0; e < VW; ++e) {
+      const bool in = row < n && k + e < kend;
+      v[e] = in ? X[(long)row * ldx + k + e] : (TX)0;
+      if constexpr (ANOM) v[e] = in ? v[e] - X0[k + e] : (TX)0;
+    }
     return v;
   };
   auto fetch = [&](long k0) {
@@ -916,17 +927,20 @@ __global__ __launch_bounds__(CHOL_M32_NT) void k_chol_m32(double* A, const doubl
 
 // ---------------------------------------------------------------------------- GEMVs
 // g[k] = sum_i X[i][k] c[i]: 64 columns per block, four row groups summed in order
-template <typename TX>
+// ANOM: X[i] - X0 on the fly, as in k_gram
+template <typename TX, bool ANOM = false>
 __global__ __launch_bounds__(256) void k_gemv_t(const TX* __restrict__ X, int n, long m, long ldx,
-                                                const double* __restrict__ c, double* __restrict__ g) {
+                                                const double* __restrict__ c, double* __restrict__ g,
+                                                const TX* __restrict__ X0 = nullptr) {
   __shared__ double part[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (long k0 = blockIdx.x * 64L; k0 < m; k0 += (long)gridDim.x * 64L) {
     const long k = k0 + tx;
     double s = 0.0;
     if (k < m) {
+      const TX x0 = ANOM ? X0[k] : (TX)0;
 #pragma unroll 4
-      for (int i = ty; i < n; i += 4) s += (double)X[(long)i * ldx + k] * c[i];
+      for (int i = ty; i < n; i += 4) s += (double)(ANOM ? X[(long)i * ldx + k] - x0 : X[(long)i * ldx + k]) * c[i];
     }
     part[ty][tx] = s;
     __syncthreads();
@@ -944,6 +958,37 @@ __global__ void k_transpose(const TX* X, int n, long m, TX* Xt) {
   }
 }
 
+// ---------------------------------------------------------------------------- pseudo-inverse solve
+// out = W diag(1 / lambda_k, lambda_k > rcond lambda_0; else 0) W^T rhs for the eigenpairs of a
+// symmetric n x n matrix (W[i][k]: component i of eigenvector k, eigenvalues in decreasing order,
+// so lambda_0 is the largest), n <= 512, one workgroup: the eigenvalue cut of a pseudo-inverse.
+// Each sum runs in index order. *info: 0, or -1 for a non-finite result or a largest eigenvalue
+// that is not positive and finite.
+__global__ __launch_bounds__(512) void k_pinv_apply(const double* __restrict__ W, const double* __restrict__ ev,
+                                                    int n, const double* __restrict__ rhs, double* __restrict__ out,
+                                                    double rcond, int* __restrict__ info) {
+  __shared__ double t[512];
+  const int tid = threadIdx.x;
+  const double l0 = ev[0];
+  const bool ok0 = l0 > 0.0 && isfinite(l0);
+  if (tid < n) {
+    const double lk = ev[tid];
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) sum = fma(W[(long)i * n + tid], rhs[i], sum);
+    t[tid] = (ok0 && lk > rcond * l0) ? sum / lk : 0.0;
+  }
+  __syncthreads();
+  bool bad = !ok0;
+  if (tid < n) {
+    double sum = 0.0;
+    for (int k = 0; k < n; ++k) sum = fma(W[(long)tid * n + k], t[k], sum);
+    out[tid] = sum;
+    bad = bad || !isfinite(sum);
+  }
+  const int anybad = __syncthreads_or(bad);
+  if (tid == 0) *info = anybad ? -1 : 0;
+}
+
 // ---------------------------------------------------------------------------- launchers
 template <typename TX>
 void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, double* dJ, hipStream_t s) {
@@ -956,6 +1001,22 @@ void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nspl
   const int nbt = (n + 63) / 64;
   hipLaunchKernelGGL(k_gram<TX>, dim3(nsplit * nbt * (nbt + 1) / 2), dim3(256), 0, s, X, n, m, ldx, partial, nsplit,
                      kchunk, nbt);
+}
+void launch_gram_anom(const double* ctrl, int n, long m, double* partial, int nsplit, long kchunk, hipStream_t s) {
+  const int nbt = (n + 63) / 64;
+  hipLaunchKernelGGL((k_gram<double, true>), dim3(nsplit * nbt * (nbt + 1) / 2), dim3(256), 0, s, ctrl + m, n, m, m,
+                     partial, nsplit, kchunk, nbt, ctrl);
+}
+void launch_gemv_anom(const double* ctrl, int n, long m, const double* c, double* g, hipStream_t s) {
+  long bx = (m + 63) / 64;
+  if (bx > 8192) bx = 8192;
+  hipLaunchKernelGGL((k_gemv_t<double, true>), dim3((unsigned)bx), dim3(256), 0, s, ctrl + m, n, m, m, c, g, ctrl);
+}
+int launch_pinv_apply(const double* W, const double* ev, int n, const double* rhs, double* out, double rcond,
+                      int* info, hipStream_t s) {
+  if (n > 512) return -1;
+  hipLaunchKernelGGL(k_pinv_apply, dim3(1), dim3(512), 0, s, W, ev, n, rhs, out, rcond, info);
+  return 0;
 }
 int gram_reduce_groups(int nsplit) { return (nsplit + GRAM_REDUCE_GROUP - 1) / GRAM_REDUCE_GROUP; }
 void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, double* G, hipStream_t s) {

@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDIVERGED, EDEVICE, EBUSY, ECANCELLED, ETIMEOUT, EUNCONVERGE
 CAVITY, CHANNEL, CAVITY_PAPER = 0, 1, 2
 REGION_COLUMN, REGION_CAVITY, REGION_BOX = 0, 1, 2
 FP64, MIXED = 0, 1
+GRADIENT_PINV = 16  # or-ed into a gradient's precision: solve by the eigen-pseudo-inverse directly
 FLAG_TIME_KERNELS = 1
 FLAG_NO_GRAPHS = 2
 FLAG_NO_TUNE = 4
@@ -426,7 +427,10 @@ def split_fields(p, F):
 
 
 def gradient(controls, J, precision=FP64, ws=None, g=None):
-    """g [m] = X^+ dJ for rows 1..n of controls [n+1, m] against row 0."""
+    """g [m] = X^+ dJ for rows 1..n of controls [n+1, m] against row 0.
+
+    precision: FP64 or MIXED, optionally | GRADIENT_PINV (the eigen-pseudo-inverse instead of the
+    ridged Cholesky; a failed Cholesky falls back to it by itself)."""
     import torch
 
     n = controls.shape[0] - 1

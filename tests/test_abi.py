@@ -74,3 +74,20 @@ def test_static_gradient_rejects_sizes_beyond_its_scratch_before_any_launch():
     # the benchmark's reduction fits in both precisions
     assert E.gradient_bytes(64, 65536, E.FP64) <= E.GRADIENT_STATIC_MAX_BYTES
     assert E.gradient_bytes(64, 65536, E.MIXED) <= E.GRADIENT_STATIC_MAX_BYTES
+
+
+def test_gradient_flags_are_checked_before_any_launch():
+    """The pseudo-inverse flag leaves the workspace size as it is; an unknown precision or flag is
+    refused on the host (no device call before the check, so this runs without a GPU)."""
+    import ctypes
+
+    L = E.lib()
+    for prec in (E.FP64, E.MIXED):
+        assert E.gradient_bytes(40, 500, prec | E.GRADIENT_PINV) == E.gradient_bytes(40, 500, prec)
+    fake = ctypes.c_void_p(256)  # never dereferenced: the precision check comes first
+    for bad in (2, E.GRADIENT_PINV | 2, 32):
+        rc = L.envar_gradient(fake, fake, 40, 500, bad, fake, 1 << 30, fake, None)
+        assert rc == E.EINVAL, (bad, rc)
+        assert b"unknown precision" in L.envar_last_error()
+        rc = L.envar_gradient_static(fake, fake, 40, 500, bad, fake, None)
+        assert rc == E.EINVAL, (bad, rc)

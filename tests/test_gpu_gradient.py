@@ -124,6 +124,67 @@ def test_gradient_with_repeated_members_in_the_panel_range():
     assert err <= 1e-8
 
 
+def test_mixed_gradient_of_a_nearly_dependent_ensemble_is_the_fp64_gradient():
+    """Eight pairs of members that differ by 1e-5 of their perturbation: the FP32 Gram's rounding
+    (about 1e-7 of its largest entries) swamps the pairs' small eigenvalues (about 1e-10 of the
+    largest), so the FP32 factor fails; the call then forms the system again in FP64 from the
+    control rows, which is the FP64 gradient's own arithmetic: the results agree to the bit."""
+    rng = np.random.default_rng(79)
+    n, m = 48, 6000
+    rows = rng.standard_normal((n + 1, m)) * 1e-2
+    for a in range(8):
+        i, j = 1 + 2 * a, 2 + 2 * a
+        rows[j] = rows[i] + 1e-5 * (rows[i] - rows[0]) * rng.standard_normal(m)
+    J = rng.standard_normal(n + 1)
+    g64 = _run(rows, J, E.FP64)
+    gmx = _run(rows, J, E.MIXED)
+    # the FP64 gradient is the ridged solution X^T (G + 1e-12 tr(G)/n I)^-1 dJ (the pairs'
+    # eigenvalues are about 100 times the ridge, so it moves them by about 1%): checked against
+    # numpy to the conditioning of G + ridge (about 1e10)
+    X = rows[1:] - rows[0]
+    G = X @ X.T
+    ref = X.T @ np.linalg.solve(G + 1e-12 * np.trace(G) / n * np.eye(n), J[1:] - J[0])
+    err = np.abs(g64 - ref).max() / np.abs(ref).max()
+    print("nearly dependent: FP64 vs numpy (ridged)", err, " mixed vs FP64 max |diff|", np.abs(gmx - g64).max(),
+          flush=True)
+    assert err <= 1e-5
+    assert np.array_equal(gmx, g64)
+
+
+@pytest.mark.parametrize("n,m", [(40, 500), (150, 4000), (200, 100)])
+def test_pseudo_inverse_gradient_matches_lstsq(n, m):
+    """precision | GRADIENT_PINV: the eigen-pseudo-inverse of the Gram (Jacobi), in FP64, for the
+    Gram (n <= m) and normal-equation (n > m) forms; mixed precision with the flag runs on the FP64
+    Gram and gives the same bits."""
+    rng = np.random.default_rng(11 * n + m)
+    rows = rng.standard_normal((n + 1, m)) * 1e-2
+    J = rng.standard_normal(n + 1)
+    g = _run(rows, J, E.FP64 | E.GRADIENT_PINV)
+    X = rows[1:] - rows[0]
+    ref, *_ = np.linalg.lstsq(X, J[1:] - J[0], rcond=None)
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print("pseudo-inverse gradient", n, m, err, flush=True)
+    assert err <= 1e-9
+    if n <= m:
+        assert np.array_equal(_run(rows, J, E.MIXED | E.GRADIENT_PINV), g)
+
+
+def test_pseudo_inverse_gradient_with_repeated_members_is_minimum_norm():
+    rng = np.random.default_rng(80)
+    n, m = 100, 3000
+    rows = rng.standard_normal((n + 1, m)) * 1e-2
+    J = rng.standard_normal(n + 1)
+    for a, b in ((40, 3), (70, 12), (99, 98)):
+        rows[a] = rows[b]
+        J[a] = J[b]
+    g = _run(rows, J, E.FP64 | E.GRADIENT_PINV)
+    X = rows[1:] - rows[0]
+    ref, *_ = np.linalg.lstsq(X, J[1:] - J[0], rcond=None)
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    print("pseudo-inverse, repeated members", err, flush=True)
+    assert err <= 1e-9
+
+
 def test_gradient_reports_a_non_finite_cost():
     rng = np.random.default_rng(5)
     rows = rng.standard_normal((9, 500)) * 1e-2
