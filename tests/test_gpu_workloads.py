@@ -7,8 +7,9 @@
   Gram) every J within 1e-4 and the gradient's cosine with the oracle's at
   least 0.999.
 * The h = 1/128 launch configuration of the benchmark (65 members, m = 65,536)
-  on a short horizon: sampled members against the oracle one by one (FP64:
-  1e-10; mixed: 1e-4), the rest checked by properties (finite, converged).
+  over 48 steps, with the step graphs replaying and with eager launches:
+  sampled members against the oracle one by one (FP64: 1e-10; mixed: 1e-4),
+  the rest checked by properties (finite, converged).
 * envar_iterate against the oracle's fixed-ensemble Armijo descent.
 """
 import numpy as np
@@ -79,10 +80,13 @@ def test_h32_workload_mixed_precision_against_oracle():
     assert st["unconverged"] == 0 and st["max_div"] <= 1.01e-10
 
 
+@pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("precision,tol", [(E.FP64, 1e-10), (E.MIXED, 1e-4)])
-def test_h128_bench_configuration_sampled_members(precision, tol):
-    n, horizon = 128, 4
-    p = E.Problem(inv_h=n, Re=7500.0, precision=precision)
+def test_h128_bench_configuration_sampled_members(precision, tol, graphs):
+    """48 steps, so that the captured step graphs replay (a graph is used while at least 16 steps
+    remain), and the same with every launch eager."""
+    n, horizon = 128, 48
+    p = E.Problem(inv_h=n, Re=7500.0, precision=precision, flags=0 if graphs else E.FLAG_NO_GRAPHS)
     op = OE.Problem(inv_h=n, Re=7500.0)
     u0, v0 = inputs.initial_field(n, amp=1e-3)
     base = OE.spinup(op, OE.initial_state(op, u0, v0), 12)
