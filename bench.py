@@ -67,7 +67,9 @@ MEASURED_TRAFFIC_PER_MEMBER_CELL = {
     ("pre", "mixed"): 27.3,
     ("post", "mixed"): None,
     ("resid", "mixed"): None,
-    ("predictor", "fp64"): None,
+    # profiles/k_predictor_fused_h128_65members_fp64.md: the cubic-warm-start FP64 predictor, 33-member
+    # launches (two lanes), 523.7 MB per launch (FETCH 301.7 + WRITE 221.9)
+    ("predictor", "fp64"): 193.7,
     ("pre", "fp64"): None,
     ("post", "fp64"): None,
 }
