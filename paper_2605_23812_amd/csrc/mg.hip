@@ -440,23 +440,31 @@ __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
   it.init(sb, scode, h2);
   for (int s = 0; s < NS; ++s) it.sweep(sp);
   if (MODE == POST_REFINE) {
-    // phi64 += e and r_out = r - L e (formed in FP64) on the tile's fluid cells; dt max|r - L e| -> norms[k]
+    // phi64 += e and r_out = r - L e (formed in FP64) on the tile's fluid cells; dt max|r - L e| -> norms[k].
+    // Walked in the window layout (a wave's lanes on consecutive columns of one row), so that the FP32
+    // residual and the FP64 pressure are read and written in whole rows; the sum of the four
+    // neighbours runs in the same order as Items::nbsum64.
     const double inv_h2 = 1.0 / (g.h * g.h);
     double m = 0.0;
-    for (int c = 0; c < 2; ++c)
+    const int i = ox + col;
+    if (col >= W::H && col < W::H + W::TWI) {
 #pragma unroll
-      for (int n = 0; n < W::NIT; ++n) {
-        const int r = it.row(n), cl = it.col(c);
-        if (it.invd[c][n] != (T)0 && r >= W::H && r < W::H + W::TH && cl >= W::H && cl < W::H + W::TWI) {
-          const long at = off + g.at(ox + cl, oy + r);
-          const double e = (double)sp[it.own0[c] + 8 * n * W::QS];
-          const double rn = (double)a.b[at] - (it.nbsum64(sp, c, n) - (double)it.d[c][n] * e) * inv_h2;
+      for (int q = 0; q < W::NR; ++q) {
+        const int r = w + 4 * q;
+        const int x = W::idx(r, col);
+        if (r >= W::H && r < W::H + W::TH && scode[x]) {
+          const long at = off + g.at(i, oy + r);
+          const double e = (double)sp[x];
+          const double nb = ((double)sp[W::idx(r, col - 1)] + (double)sp[W::idx(r, col + 1)]) +
+                            ((double)sp[W::idx(r - 1, col)] + (double)sp[W::idx(r + 1, col)]);
+          const double rn = (double)L.vb[q] - (nb - (double)scode[x] * e) * inv_h2;
           a.r_out[at] = (T)rn;
           a.add_to[at] += e;
           const double rr = fabs(rn) * a.dt;
           m = (rr > m || rr != rr) ? rr : m;
         }
       }
+    }
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) red[w] = m;
     __syncthreads();
