@@ -490,6 +490,8 @@ def serving(torch, E, inputs, nreq, horizon_scale, div_tol, clients=4, think_s=0
                     p = E.Problem(inv_h=r["n"], Re=r["Re"], precision=precision, div_tol=div_tol)
                     t = srv.submit(p, states[(r["n"], r["Re"])], r["rows"], r["horizon"])
                     results[k] = srv.wait(t, timeout=900.0)
+                    log(f"  serving {'mixed' if precision == E.MIXED else 'fp64'}: request {k} done "
+                        f"(latency {results[k][1]['latency_s']:.2f} s, {time.time() - t0:.1f} s in)")
             except Exception as e:  # reported below
                 errors.append(repr(e))
         try:
@@ -658,6 +660,8 @@ def main():
     ap.add_argument("--iterate-horizon", type=int, default=1000, help="window of the FP64 descent (0: skip)")
     ap.add_argument("--iterate-iters", type=int, default=10)
     ap.add_argument("--no-gram", action="store_true")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving comparison and print it as one JSON line")
     ap.add_argument("--anomaly-only", action="store_true",
                     help="run only the anomaly-reduction sweep and print it as one JSON line (for kernel traces)")
     ap.add_argument("--lyapunov", action="store_true",
@@ -678,6 +682,10 @@ def main():
     torch.cuda.init()
     if args.anomaly_only:
         print(json.dumps({"anomaly_reduction": gram_sweep(torch, E)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serving(torch, E, inputs, args.serve_requests, args.serve_horizon_scale,
+                                             DIV_TOL)}), flush=True)
         return
     if args.lyapunov:
         res = []
