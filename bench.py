@@ -241,8 +241,14 @@ def config2_iterate(torch, E, inputs, state, ctrl, horizon, iters, div_tol):
     E.iterate(p, state, f.clone(), pert, 20, iters=1)  # tune and warm at this shape
     torch.cuda.synchronize()
     t = time.time()
-    recs = E.iterate(p, state, f, pert, horizon, iters=iters, search_every=1)
-    torch.cuda.synchronize()
+    recs = []
+    for it in range(iters):  # one call per iteration, so that a long window logs its progress
+        r = E.iterate(p, state, f, pert, horizon, iters=1, search_every=1)
+        torch.cuda.synchronize()
+        recs += r
+        log(f"  config-2 iteration {it}: {r[-1] if r else None} ({time.time() - t:.1f} s in)")
+        if not r or not (r[-1]["alpha"] > 0.0):  # the line search found no decrease: the descent ends
+            break
     dt = time.time() - t
     cells = E.cell_count(p)
     return {"inv_h": INV_H, "members": pert.shape[0], "horizon": horizon, "iterations": len(recs),
