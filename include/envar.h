@@ -117,7 +117,17 @@ enum {
    * phases overlap with the other's bandwidth-bound kernels. The call stays ordered on its
    * stream (the lanes fork from it and join back). Results do not depend on the lanes. This
    * flag runs every member on the call's stream. */
-  ENVAR_FLAG_ONE_LANE = 64
+  ENVAR_FLAG_ONE_LANE = 64,
+  /* Pressure passes. A step launches its first passes (V-cycles in FP64, refinement passes in
+   * MIXED) level by level, as many as the members needed lately (at least two); the passes
+   * beyond, up to max_cycles, run in one launch that gives each member a workgroup of its own and
+   * goes through the same per-tile arithmetic, so a member that needs more passes than its batch
+   * has lately needed gets them at the cost of one launch per step when no member does. This
+   * holds for jobs with 32 <= inv_h <= 256; other batches keep one extra level-by-level pass of
+   * headroom. Results do not depend on either choice. */
+  ENVAR_FLAG_NO_TAIL = 128,      /* one pass of headroom instead of the per-member launch */
+  ENVAR_FLAG_SHORT_GRAPH = 256   /* one level-by-level pass per step, every later one in the
+                                    per-member launch (for comparisons; much slower) */
 };
 
 /* Per-call statistics (filled only when a non-NULL pointer is passed; then the

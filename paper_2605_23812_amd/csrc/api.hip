@@ -716,8 +716,30 @@ static void grouped(const std::vector<Job*>& J, RowsOf rows_of, Make make, Launc
 // sized by it).
 static int job_cap(const Job& j, int cap) { return std::min(cap, j.P.cap_max); }
 
+// A job whose passes beyond the step's cap can run in the tail kernel (one workgroup per member).
+static bool tail_fits(const Job& j) { return j.P.nlev_grid >= 1 && j.P.nlev_grid <= TAIL_MAX_LEV; }
+
+template <typename T>
+static TailArgs<T> tail_args(const Job& j, int k0, int k1) {
+  TailArgs<T> t{};
+  t.nlev = j.P.nlev_grid;
+  t.k0 = k0;
+  t.k1 = k1;
+  t.mixed = j.P.mixed;
+  for (int l = 0; l < t.nlev; ++l) {
+    t.pre[l] = pre_args<T>(j, l, k0, TAIL_ROWS);
+    t.post[l] = post_args<T>(j, l, k0, TAIL_ROWS);
+  }
+  t.coarse = coarse_args<T>(j, k0);
+  if (j.P.mixed) {
+    t.rpl[0] = (T*)j.rplane(0);
+    t.rpl[1] = (T*)j.rplane(1);
+  }
+  return t;
+}
+
 template <typename TT>
-static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
+static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, bool tail, Timer* tm) {
   typedef TT T;  // V-cycle type
   const bool mixed = J[0]->P.mixed;
   const int k_timed = mixed ? 1 : 0;
@@ -793,11 +815,19 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
     resid(-1, J, false);
     if (tm) tm->mark(TM_RESID, 1, st);
   }
+  // the passes beyond the cap, up to each job's own max_cycles, for the members that need them
+  // (mixed: passes cap + 1 .. max_cycles; FP64: V-cycles cap .. max_cycles - 1)
+  if (tail)
+    for (Job* j : J) {
+      const int c = job_cap(*j, cap);
+      const int k0 = mixed ? c + 1 : c, k1 = mixed ? j->P.cap_max : j->P.cap_max - 1;
+      if (k0 <= k1) launch_mg_tail<T>(tail_args<T>(*j, k0, k1), j->nmem, st);
+    }
 }
 
 // One time step of every job of the batch (each at its own step index).
 template <typename TT>
-static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer* tm) {
+static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, bool tail, Timer* tm) {
   // the first step of a job starts from u^n; later steps fuse the previous step's projection
   if (tm) tm->mark(TM_PRED, 0, st);
   for (const bool fused : {false, true})
@@ -806,7 +836,7 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer
         [&](const Job& j, int rows) { return pred_args(j, rows, fused); },
         [&](const Multi<PredArgs<double>>& m) { launch_predictor<double>(m, st); });
   if (tm) tm->mark(TM_PRED, 1, st);
-  batch_pressure<TT>(J, st, cap, tm);
+  batch_pressure<TT>(J, st, cap, tail, tm);
   {
     auto m = seg_begin<SensorArgs>();
     for (Job* j : J) {
@@ -839,7 +869,7 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, Timer
       BookArgs bk{};
       bk.nmem = j->nmem;
       bk.norm_slots = j->P.norm_slots;
-      bk.cap = job_cap(*j, cap);
+      bk.cap = tail ? j->P.cap_max : job_cap(*j, cap);  // the tail fills every slot
       bk.slot_base = j->P.mixed ? 1 : 0;
       bk.tol = j->P.tol;
       bk.norms = j->w_<double>(j->w.norms);
@@ -1037,6 +1067,8 @@ struct StepGraphs {
 struct Driver {
   int cap = 0;
   int cap_max = 0;
+  bool tail = false;         // passes beyond the cap run in the per-member tail kernel
+  bool short_graph = false;  // cap pinned to one pass (the tail runs the rest)
   long epoch = 0;  // bumps whenever the job set changes
   StepGraphs G;
   hipEvent_t ev = nullptr;
@@ -1088,13 +1120,16 @@ struct Driver {
       unconv += pinned[q + ST_UNCONV];
     }
     // ST_RECENT decays by one cycle per 16 steps: the cap follows what the members needed
-    // lately (start-up transients fade), one cycle of headroom above it. A member that
-    // converges within the cap at every step does the same arithmetic whatever the cap (it
-    // skips the passes after its own convergence), so only a member that the cap cuts off
+    // lately (start-up transients fade). With the tail kernel the passes beyond the cap still
+    // run, per member, up to its max_cycles, so the cap only decides which passes are level
+    // launches; without it the cap keeps one cycle of headroom above the recent need. A member
+    // that converges within its passes at every step does the same arithmetic whatever the cap
+    // (it skips the passes after its own convergence), so only a member that the cap cuts off
     // depends on its batch; such steps are counted (ST_UNCONV), reported per call and per
     // request, and lift the cap to its maximum until the next poll.
-    cap = std::min(cap_max, std::max(2, mx + 1));
-    if (unconv > unconv_seen) cap = cap_max;
+    cap = std::min(cap_max, std::max(2, tail ? mx : mx + 1));
+    if (short_graph && tail) cap = std::min(cap_max, 1);
+    if (!tail && unconv > unconv_seen) cap = cap_max;  // with the tail a cut happens only at max_cycles
     unconv_seen = unconv;
   }
   int start_async(const std::vector<Job*>& J, hipStream_t s) {
@@ -1132,7 +1167,13 @@ struct Driver {
   template <typename TT>
   int step(std::vector<Job*>& J, hipStream_t s, Timer* tm, int steps_left_min, bool use_graphs) {
     bool fresh = false;
-    for (Job* j : J) fresh = fresh || j->step == 0;
+    tail = true;
+    short_graph = false;
+    for (Job* j : J) {
+      fresh = fresh || j->step == 0;
+      tail = tail && tail_fits(*j) && !(j->P.p.flags & ENVAR_FLAG_NO_TAIL);
+      short_graph = short_graph || (j->P.p.flags & ENVAR_FLAG_SHORT_GRAPH);
+    }
     const bool sampled = tm && tm->cur >= 0;
     const int par = J[0]->step & 1;
     int rc;
@@ -1142,7 +1183,7 @@ struct Driver {
         G.drop(par);
         if (!G.cs) HIP_OK(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
         HIP_OK(hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal));
-        rc = batch_step<TT>(J, G.cs, cap, nullptr);
+        rc = batch_step<TT>(J, G.cs, cap, tail, nullptr);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(G.cs, &g);
         if (rc) {
@@ -1160,7 +1201,7 @@ struct Driver {
       // a job's first step runs with the largest cap, whatever the batch needed lately (the step
       // that switches its forcing on can need more passes than any step before it): a request
       // that joins a running batch starts like a forward of its own
-      rc = batch_step<TT>(J, s, fresh ? std::max(cap, cap_max) : cap, sampled ? tm : nullptr);
+      rc = batch_step<TT>(J, s, fresh ? std::max(cap, cap_max) : cap, tail, sampled ? tm : nullptr);
       if (rc) return rc;
     }
     for (Job* j : J) {

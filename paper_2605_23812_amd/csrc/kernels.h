@@ -272,6 +272,25 @@ template <typename T>
 void launch_mg_coarse(const Multi<CoarseArgs>& m, hipStream_t s);
 void launch_resid64(const Multi<ResidArgs>& m, hipStream_t s);
 
+// The passes of a step beyond those launched level by level (the "tail"): one workgroup per
+// member runs passes k0..k1 in order while the member's previous norm exceeds the tolerance, each
+// phase over the member's tiles in turn with the tile bodies of the level kernels (16-row tiles)
+// and the LDS levels on 256 threads, so a pass gives bitwise the result of its level launches.
+// A member that has converged carries its norm through slots k..k1 and leaves at once, so the
+// tail costs one launch when no member needs it. Jobs with 1 to TAIL_MAX_LEV tiled levels.
+constexpr int TAIL_MAX_LEV = 4;
+constexpr int TAIL_ROWS = 16;
+template <typename T>
+struct TailArgs {
+  MGArgs<T> pre[TAIL_MAX_LEV];   // pass-independent fields; `k` (and, mixed, the finest level's
+  MGArgs<T> post[TAIL_MAX_LEV];  // residual planes) are set per pass
+  CoarseArgs coarse;
+  T* rpl[2];  // mixed: the finest level's residual planes by pass parity (pass k reads k - 1, writes k)
+  int nlev, k0, k1, mixed;
+};
+template <typename T>
+void launch_mg_tail(const TailArgs<T>& a, int nmem, hipStream_t s);
+
 // anomaly reduction
 struct GramPlan {
   int n;          // rows of X (Gram is n x n)

@@ -143,20 +143,20 @@ struct Items {
 };
 
 // window load shared by pre and post: phi (+ correction), b and the diagonal codes
-template <typename T, int TR>
+template <typename T, int TR, typename E = T>
 struct WinLoad {
   typedef Win<T, TR> W;
-  T vp[W::NR], vb[W::NR];
+  E vp[W::NR], vb[W::NR];
   unsigned char vc[W::NR];
-  __device__ __forceinline__ void fetch(const Geo& g, const unsigned char* code, const T* phi, const T* b, long off,
+  __device__ __forceinline__ void fetch(const Geo& g, const unsigned char* code, const E* phi, const E* b, long off,
                                         int ox, int oy) {
     const int col = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = ox + col;
 #pragma unroll
     for (int m = 0; m < W::NR; ++m) {
       const int r = w + 4 * m, j = oy + r;
-      vp[m] = (T)0;
-      vb[m] = (T)0;
+      vp[m] = (E)0;
+      vb[m] = (E)0;
       vc[m] = 0;
       if (r < W::LH && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
         const long at = g.at(i, j);
@@ -169,8 +169,8 @@ struct WinLoad {
 #pragma unroll
     for (int m = 0; m < W::NR; ++m)
       if (!vc[m]) {
-        vp[m] = (T)0;
-        vb[m] = (T)0;
+        vp[m] = (E)0;
+        vb[m] = (E)0;
       }
   }
 };
@@ -194,22 +194,28 @@ __device__ __forceinline__ bool ref_skip(const MGArgs<T>& a, int mem, int tile) 
 // member's previous norm exceeds `anchor`, in which case it is formed afresh as in PRE_FIRST and
 // stored in r_out (the same plane), without a norm: a residual near the tolerance is carried, a
 // large one re-anchored, so the carried residual's rounding stays below anchor x 6e-8)
-template <typename T, int NS, int REF, bool ONE, int TR>
-__global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
+// LDS of one pre tile: sp | sb (in refinement first the FP64 pressure window), diagonal codes
+template <typename T, int TR>
+struct PreLds {
+  T spb[4 * Win<T, TR>::CS];
+  unsigned char scode[2 * Win<T, TR>::CS];
+  double red[4];
+};
+
+// One (member, tile) of the pre kernel; the tail kernel runs the same body over a member's tiles.
+template <typename T, int NS, int REF, int TR>
+__device__ __forceinline__ void mg_pre_tile(const MGArgs<T>& a, int mem, int tile, PreLds<T, TR>& S) {
   typedef Win<T, TR> W;
   static_assert(2 * NS + 1 <= W::H, "window halo too small for the sweep count");
   static_assert(W::TH * 64 <= 2 * W::CS, "residual staging does not fit");
   static_assert(REF == PRE_PLAIN || sizeof(double) * 64 * W::LH <= sizeof(T) * 4 * W::CS,
                 "FP64 window does not fit");
-  __shared__ T spb[4 * W::CS];  // sp | sb; in refinement first the FP64 pressure window
-  __shared__ unsigned char scode[2 * W::CS];
-  __shared__ double red[4];
+  T* const spb = S.spb;
+  unsigned char* const scode = S.scode;
+  double* const red = S.red;
   T* const sp = spb;
   T* const sb = spb + 2 * W::CS;
-  int item;
-  const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
   const Geo& g = a.g;
-  const int mem = item / a.ntiles, tile = item % a.ntiles;
   if (REF == PRE_FIRST ? ref_skip(a, mem, tile) : mg_skip(a, mem, tile)) return;
   int x0, y0;
   a.tiling.origin(tile, x0, y0);
@@ -221,22 +227,12 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
   if (form) {
     // r = b64 - L phi64 on the window (ring excluded), same arithmetic order as k_resid64
     double* const P64 = (double*)spb;
-    double vp[W::NR], vb[W::NR];
-    unsigned char vc[W::NR];
+    WinLoad<T, TR, double> L64;
+    L64.fetch(g, a.code, a.phi64, a.b64, off, ox, oy);
+    double (&vp)[W::NR] = L64.vp;
+    double (&vb)[W::NR] = L64.vb;
+    unsigned char (&vc)[W::NR] = L64.vc;
     const int i = ox + col;
-#pragma unroll
-    for (int m = 0; m < W::NR; ++m) {
-      const int r = w + 4 * m, j = oy + r;
-      vp[m] = 0.0;
-      vb[m] = 0.0;
-      vc[m] = 0;
-      if (r < W::LH && i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
-        const long at = g.at(i, j);
-        vc[m] = a.code[at];
-        vb[m] = a.b64[off + at];
-        vp[m] = a.phi64[off + at];
-      }
-    }
 #pragma unroll
     for (int m = 0; m < W::NR; ++m) {
       const int r = w + 4 * m;
@@ -349,26 +345,44 @@ __global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
   }
 }
 
+template <typename T, int NS, int REF, bool ONE, int TR>
+__global__ __launch_bounds__(256) void k_mg_pre(Multi<MGArgs<T>> ms) {
+  __shared__ PreLds<T, TR> S;
+  int item;
+  const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
+  mg_pre_tile<T, NS, REF, TR>(a, item / a.ntiles, item % a.ntiles, S);
+}
+
 // ---------------------------------------------------------------------------- prolongation + post-smoothing
 // MODE: POST_PLAIN; POST_NORM (the residual norm of the V-cycle's own equation, FP64 cycles);
 // POST_REFINE (mixed finest level: phi64 += e and the carried FP64 residual r - L e on the tile)
-template <typename T, int NS, int MODE, bool ONE, int TR>
-__global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
+// LDS of one post tile: the window (phi, b, codes) and the coarse correction window
+template <typename T, int TR>
+struct PostLds {
+  static constexpr int CW = 36, CH = Win<T, TR>::LH / 2 + 3;
+  T sp[2 * Win<T, TR>::CS];
+  T sb[2 * Win<T, TR>::CS];
+  unsigned char scode[2 * Win<T, TR>::CS];
+  T scw[CH * CW];
+  unsigned char sccode[CH * CW];
+  double red[4];
+};
+
+// One (member, tile) of the post kernel; the tail kernel runs the same body over a member's tiles.
+template <typename T, int NS, int MODE, int TR>
+__device__ __forceinline__ void mg_post_tile(const MGArgs<T>& a, int mem, int tile, PostLds<T, TR>& S) {
   typedef Win<T, TR> W;
   // the norm and the refinement update need the smoothed values on the tile and one ring around it
   static_assert(2 * NS + (MODE != POST_PLAIN ? 1 : 0) <= W::H, "window halo too small for the sweep count");
-  constexpr int CW = 36, CH = W::LH / 2 + 3;
-  __shared__ T sp[2 * W::CS];
-  __shared__ T sb[2 * W::CS];
-  __shared__ unsigned char scode[2 * W::CS];
-  __shared__ T scw[CH * CW];
-  __shared__ unsigned char sccode[CH * CW];
-  __shared__ double red[4];
-  int item;
-  const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
+  constexpr int CW = PostLds<T, TR>::CW, CH = PostLds<T, TR>::CH;
+  T* const sp = S.sp;
+  T* const sb = S.sb;
+  unsigned char* const scode = S.scode;
+  T* const scw = S.scw;
+  unsigned char* const sccode = S.sccode;
+  double* const red = S.red;
   const Geo& g = a.g;
   const Geo& gc = a.gc;
-  const int mem = item / a.ntiles, tile = item % a.ntiles;
   if (mg_skip(a, mem, tile)) return;
   int x0, y0;
   a.tiling.origin(tile, x0, y0);
@@ -515,6 +529,14 @@ __global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
   }
 }
 
+template <typename T, int NS, int MODE, bool ONE, int TR>
+__global__ __launch_bounds__(256) void k_mg_post(Multi<MGArgs<T>> ms) {
+  __shared__ PostLds<T, TR> S;
+  int item;
+  const MGArgs<T>& a = ms.template pick<ONE>(xcd_remap(blockIdx.x, gridDim.x), item);
+  mg_post_tile<T, NS, MODE, TR>(a, item / a.ntiles, item % a.ntiles, S);
+}
+
 // ---------------------------------------------------------------------------- coarse levels in LDS
 // The levels inv_h = 16, 8, 4 of one member run in one workgroup, every level
 // resident in LDS as a padded array: NX x ny cells plus a ring of ghost cells,
@@ -534,25 +556,25 @@ __device__ __forceinline__ int cx(int i, int j) {
 }
 
 // diagonal codes of one level (ghost ring included)
-template <int NX>
+template <int NX, int NTH>
 __device__ __forceinline__ void lvl_codes(unsigned char* C, const Geo& g) {
   const int n = (g.ny + 2) * (NX + 2);
-  for (int q = threadIdx.x; q < n; q += COARSE_THREADS) {
+  for (int q = threadIdx.x; q < n; q += NTH) {
     const int jj = q / (NX + 2), i = q - jj * (NX + 2) - 1, j = jj - 1;
     C[q] = g.fluid(i, j) ? (unsigned char)g.diag_count(i, j) : (unsigned char)0;
   }
 }
 
 // one red-black Gauss-Seidel sweep (same operand order as the tiled kernels)
-template <int NX>
+template <int NX, int NTH>
 __device__ __forceinline__ void lvl_sweep(double* p, const double* b, const unsigned char* C, int ny, double h2) {
   constexpr int HX = NX / 2, P = NX + 2;
-  constexpr int K = (HX * (CMAXNY0 * NX / CNX0) + COARSE_THREADS - 1) / COARSE_THREADS;
+  constexpr int K = (HX * (CMAXNY0 * NX / CNX0) + NTH - 1) / NTH;
   const int n = HX * ny;
   for (int c = 0; c < 2; ++c) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int q = threadIdx.x + k * COARSE_THREADS;
+      const int q = threadIdx.x + k * NTH;
       if (q >= n) break;
       const int j = q / HX, i = 2 * (q % HX) + ((c ^ j) & 1);
       const int x = cx<NX>(i, j);
@@ -584,12 +606,12 @@ __device__ __forceinline__ double lvl_resid(const double* p, const double* b, co
 
 // residual of the fine level restricted (mean of the four children) into the
 // coarse right-hand side; zero coarse guess
-template <int NX>
+template <int NX, int NTH>
 __device__ __forceinline__ void lvl_restrict(const double* p, const double* b, const unsigned char* C, double h,
                                              double* pc, double* bc, const unsigned char* Cc, int nyc) {
   constexpr int NXC = NX / 2;
   const double inv_h2 = 1.0 / (h * h);
-  for (int q = threadIdx.x; q < NXC * nyc; q += COARSE_THREADS) {
+  for (int q = threadIdx.x; q < NXC * nyc; q += NTH) {
     const int J = q / NXC, I = q % NXC;
     const int xc = cx<NXC>(I, J);
     double rs = 0.0;
@@ -604,11 +626,11 @@ __device__ __forceinline__ void lvl_restrict(const double* p, const double* b, c
 
 // bilinear prolongation of the coarse correction (Neumann mirror at walls,
 // sign flip across the outflow face) added to the fine level
-template <int NX>
+template <int NX, int NTH>
 __device__ __forceinline__ void lvl_prolong(double* p, const unsigned char* C, int ny, const double* pc,
                                             const unsigned char* Cc) {
   constexpr int NXC = NX / 2;
-  for (int q = threadIdx.x; q < NX * ny; q += COARSE_THREADS) {
+  for (int q = threadIdx.x; q < NX * ny; q += NTH) {
     const int j = q / NX, i = q % NX;
     const int x = cx<NX>(i, j);
     if (!C[x]) continue;
@@ -626,19 +648,35 @@ __device__ __forceinline__ void lvl_prolong(double* p, const unsigned char* C, i
 
 // V-cycle over the three LDS levels with NS red-black sweeps per level and a
 // dense solve of the h = 1/4 operator through its inverse.
-// The dense solve gives eight threads (consecutive lanes) to each coarsest unknown q = tid / 8,
-// thread part = tid % 8 summing the terms r = part, part + 8, ...; its entries of the inverse are
-// loaded into registers at the start of the kernel, so their latency hides behind the sweeps.
+// The dense solve gives eight threads (consecutive lanes) to each coarsest unknown q, thread
+// part = tid % 8 summing the terms r = part, part + 8, ... in order; with 1024 threads every
+// unknown has its eight threads at once and their entries of the inverse are loaded into registers
+// at the start, so that their latency hides behind the sweeps; with fewer threads (the tail kernel)
+// the unknowns take several rounds with the same sums.
 constexpr int COARSE_INV_PER_THREAD = (MAX_COARSE_UNKNOWNS + 7) / 8;
 
-template <typename T, bool ONE>
-__global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> ms) {
-  __shared__ double P0[CS0], B0[CS0], P1[CS1], B1[CS1], P2[CS2], B2[CS2];
-  __shared__ unsigned char C0[CS0], C1[CS1], C2[CS2];
-  __shared__ double sbc[MAX_COARSE_UNKNOWNS];
-  __shared__ double red[COARSE_THREADS / 64];
-  int mem;
-  const CoarseArgs& a = ms.template pick<ONE>(blockIdx.x, mem);
+template <int NTH>
+struct CoarseLds {
+  double P0[CS0], B0[CS0], P1[CS1], B1[CS1], P2[CS2], B2[CS2];
+  double sbc[MAX_COARSE_UNKNOWNS];
+  double red[NTH / 64];
+  unsigned char C0[CS0], C1[CS1], C2[CS2];
+};
+
+// The LDS levels of one member on NTH threads (the arithmetic does not depend on NTH).
+template <typename T, int NTH>
+__device__ __forceinline__ void mg_coarse_member(const CoarseArgs& a, int mem, CoarseLds<NTH>& S) {
+  double* const P0 = S.P0;
+  double* const B0 = S.B0;
+  double* const P1 = S.P1;
+  double* const B1 = S.B1;
+  double* const P2 = S.P2;
+  double* const B2 = S.B2;
+  unsigned char* const C0 = S.C0;
+  unsigned char* const C1 = S.C1;
+  unsigned char* const C2 = S.C2;
+  double* const sbc = S.sbc;
+  double* const red = S.red;
   if (a.k > 0 && a.norms != nullptr) {
     const double prev = a.norms[(long)mem * a.norm_slots + a.k - 1];
     if (prev <= a.tol) {
@@ -653,18 +691,22 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
   const long off = (long)mem * a.plane;
   const T* gphi = (const T*)a.phi + off;
   const T* gb = (const T*)a.b + off;
-  // thread t owns the top-level cells (t & 63, (t >> 6) + 16 k)
-  constexpr int RS = COARSE_THREADS / 64;
+  // thread t owns the top-level cells (t & 63, (t >> 6) + RS k)
+  constexpr int RS = NTH / 64;
   constexpr int NL = CMAXNY0 / RS;
   const int ti = threadIdx.x & 63, tj = threadIdx.x >> 6;
-  // this thread's entries of the transposed inverse: ainv[r * nc + q] for r = part + 8 k
-  static_assert(MAX_COARSE_UNKNOWNS * 8 <= COARSE_THREADS, "dense solve needs 8 threads per unknown");
-  const int dq = threadIdx.x >> 3, dpart = threadIdx.x & 7;
-  double inv_r[COARSE_INV_PER_THREAD];
+  static_assert((MAX_COARSE_UNKNOWNS * 8) % NTH == 0, "dense solve needs whole rounds of 8 threads per unknown");
+  constexpr int DROUNDS = MAX_COARSE_UNKNOWNS * 8 / NTH;
+  const int dpart = threadIdx.x & 7;
+  // one round: this thread's entries of the transposed inverse, ainv[r * nc + q] for r = part + 8 k
+  double inv_r[DROUNDS == 1 ? COARSE_INV_PER_THREAD : 1];
+  if (DROUNDS == 1) {
+    const int dq = threadIdx.x >> 3;
 #pragma unroll
-  for (int k = 0; k < COARSE_INV_PER_THREAD; ++k) {
-    const int r = dpart + 8 * k;
-    inv_r[k] = (dq < a.nc && r < a.nc) ? a.ainv[(long)r * a.nc + dq] : 0.0;
+    for (int k = 0; k < COARSE_INV_PER_THREAD; ++k) {
+      const int r = dpart + 8 * k;
+      inv_r[k] = (dq < a.nc && r < a.nc) ? a.ainv[(long)r * a.nc + dq] : 0.0;
+    }
   }
   {
     double vp[NL], vb[NL];
@@ -678,21 +720,21 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
         if (a.warm) vp[k] = (double)gphi[g0.at(ti, j)];
       }
     }
-    for (int q = threadIdx.x; q < CS0; q += COARSE_THREADS) {
+    for (int q = threadIdx.x; q < CS0; q += NTH) {
       P0[q] = 0.0;
       B0[q] = 0.0;
     }
-    for (int q = threadIdx.x; q < CS1; q += COARSE_THREADS) {
+    for (int q = threadIdx.x; q < CS1; q += NTH) {
       P1[q] = 0.0;
       B1[q] = 0.0;
     }
-    for (int q = threadIdx.x; q < CS2; q += COARSE_THREADS) {
+    for (int q = threadIdx.x; q < CS2; q += NTH) {
       P2[q] = 0.0;
       B2[q] = 0.0;
     }
-    lvl_codes<CNX0>(C0, g0);
-    lvl_codes<CNX1>(C1, g1);
-    lvl_codes<CNX2>(C2, g2);
+    lvl_codes<CNX0, NTH>(C0, g0);
+    lvl_codes<CNX1, NTH>(C1, g1);
+    lvl_codes<CNX2, NTH>(C2, g2);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
@@ -705,23 +747,25 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
   }
   __syncthreads();
   const double h20 = g0.h * g0.h, h21 = g1.h * g1.h;
-  for (int s = 0; s < a.nsweep_pre; ++s) lvl_sweep<CNX0>(P0, B0, C0, ny0, h20);
-  lvl_restrict<CNX0>(P0, B0, C0, g0.h, P1, B1, C1, ny1);
-  for (int s = 0; s < a.nsweep_pre; ++s) lvl_sweep<CNX1>(P1, B1, C1, ny1, h21);
-  lvl_restrict<CNX1>(P1, B1, C1, g1.h, P2, B2, C2, ny2);
-  // dense solve on the coarsest level through the inverse held in registers
-  for (int q = threadIdx.x; q < a.nc; q += COARSE_THREADS) {
+  for (int s = 0; s < a.nsweep_pre; ++s) lvl_sweep<CNX0, NTH>(P0, B0, C0, ny0, h20);
+  lvl_restrict<CNX0, NTH>(P0, B0, C0, g0.h, P1, B1, C1, ny1);
+  for (int s = 0; s < a.nsweep_pre; ++s) lvl_sweep<CNX1, NTH>(P1, B1, C1, ny1, h21);
+  lvl_restrict<CNX1, NTH>(P1, B1, C1, g1.h, P2, B2, C2, ny2);
+  // dense solve on the coarsest level through the inverse
+  for (int q = threadIdx.x; q < a.nc; q += NTH) {
     const int c = a.aidx[q];
     sbc[q] = B2[cx<CNX2>(c % g2.nx, c / g2.nx)];
   }
   __syncthreads();
-  {
+#pragma unroll 1
+  for (int rd = 0; rd < DROUNDS; ++rd) {
     // eight threads (consecutive lanes) per unknown, each summing every eighth term in order
+    const int dq = (threadIdx.x >> 3) + rd * (NTH / 8);
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < COARSE_INV_PER_THREAD; ++k) {
       const int r = dpart + 8 * k;
-      if (dq < a.nc && r < a.nc) s += inv_r[k] * sbc[r];
+      if (dq < a.nc && r < a.nc) s += (DROUNDS == 1 ? inv_r[k] : a.ainv[(long)r * a.nc + dq]) * sbc[r];
     }
     s += __shfl_xor(s, 1, 64);
     s += __shfl_xor(s, 2, 64);
@@ -732,10 +776,10 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
     }
   }
   __syncthreads();
-  lvl_prolong<CNX1>(P1, C1, ny1, P2, C2);
-  for (int s = 0; s < a.nsweep_post; ++s) lvl_sweep<CNX1>(P1, B1, C1, ny1, h21);
-  lvl_prolong<CNX0>(P0, C0, ny0, P1, C1);
-  for (int s = 0; s < a.nsweep_post; ++s) lvl_sweep<CNX0>(P0, B0, C0, ny0, h20);
+  lvl_prolong<CNX1, NTH>(P1, C1, ny1, P2, C2);
+  for (int s = 0; s < a.nsweep_post; ++s) lvl_sweep<CNX1, NTH>(P1, B1, C1, ny1, h21);
+  lvl_prolong<CNX0, NTH>(P0, C0, ny0, P1, C1);
+  for (int s = 0; s < a.nsweep_post; ++s) lvl_sweep<CNX0, NTH>(P0, B0, C0, ny0, h20);
   if (a.write_norm) {
     const double inv_h2 = 1.0 / h20;
     double m = 0.0;
@@ -755,7 +799,7 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
     __syncthreads();
     if (threadIdx.x == 0) {
       double mm = red[0];
-      for (int w = 1; w < COARSE_THREADS / 64; ++w) mm = (red[w] > mm || red[w] != red[w]) ? red[w] : mm;
+      for (int w = 1; w < NTH / 64; ++w) mm = (red[w] > mm || red[w] != red[w]) ? red[w] : mm;
       a.norms[(long)mem * a.norm_slots + a.k] = mm;
     }
   }
@@ -772,6 +816,89 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
       wphi[g0.at(ti, j)] = (T)P0[x];
   }
 }
+
+template <typename T, bool ONE>
+__global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> ms) {
+  __shared__ CoarseLds<COARSE_THREADS> S;
+  int mem;
+  const CoarseArgs& a = ms.template pick<ONE>(blockIdx.x, mem);
+  mg_coarse_member<T, COARSE_THREADS>(a, mem, S);
+}
+
+// ---------------------------------------------------------------------------- tail passes
+// Passes k0..k1 of one member per workgroup (256 threads): the level phases in the order of the
+// level launches (pre on every tiled level, the LDS levels, post back up), each phase over the
+// member's tiles in turn through the same tile bodies, with a barrier between tiles (the LDS is
+// reused) and between phases (the next phase reads what this one wrote; a phase never reads what
+// it writes, so the order of its tiles does not matter). The norm of the previous pass decides,
+// as in the level kernels: a converged member carries it into the remaining slots and leaves.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_tail(TailArgs<T> ta) {
+  constexpr int NS = mg_ns<T>();
+  constexpr bool MIXED = sizeof(T) == sizeof(float);
+  __shared__ union {
+    PreLds<T, TAIL_ROWS> pre;
+    PostLds<T, TAIL_ROWS> post;
+    CoarseLds<256> coarse;
+  } S;
+  const int mem = blockIdx.x;
+  const int L = ta.nlev;
+  double* const nr = ta.pre[0].norms + (long)mem * ta.pre[0].norm_slots;
+  const double tol = ta.pre[0].tol;
+  for (int k = ta.k0; k <= ta.k1; ++k) {
+    const double prev = __hip_atomic_load(nr + k - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev <= tol) {
+      for (int q = k + (int)threadIdx.x; q <= ta.k1; q += 256) nr[q] = prev;
+      return;
+    }
+    for (int l = 0; l < L; ++l) {
+      MGArgs<T> a = ta.pre[l];
+      a.k = k;
+      if (MIXED && l == 0) {
+        a.b = ta.rpl[(k - 1) & 1];
+        a.r_out = ta.rpl[(k - 1) & 1];
+      }
+      for (int t = 0; t < a.ntiles; ++t) {
+        if (MIXED && l == 0)
+          mg_pre_tile<T, NS, PRE_LATER, TAIL_ROWS>(a, mem, t, S.pre);
+        else
+          mg_pre_tile<T, NS, PRE_PLAIN, TAIL_ROWS>(a, mem, t, S.pre);
+        __syncthreads();
+      }
+    }
+    {
+      CoarseArgs c = ta.coarse;
+      c.k = k;
+      mg_coarse_member<T, 256>(c, mem, S.coarse);
+      __syncthreads();
+    }
+    for (int l = L - 1; l >= 0; --l) {
+      MGArgs<T> a = ta.post[l];
+      a.k = k;
+      if (MIXED && l == 0) {
+        a.b = ta.rpl[(k - 1) & 1];
+        a.r_out = ta.rpl[k & 1];
+      }
+      for (int t = 0; t < a.ntiles; ++t) {
+        if (l > 0)
+          mg_post_tile<T, NS, POST_PLAIN, TAIL_ROWS>(a, mem, t, S.post);
+        else if (MIXED)
+          mg_post_tile<T, NS, POST_REFINE, TAIL_ROWS>(a, mem, t, S.post);
+        else
+          mg_post_tile<T, NS, POST_NORM, TAIL_ROWS>(a, mem, t, S.post);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+static_assert(sizeof(TailArgs<double>) <= 4096, "tail arguments exceed the kernel argument space");
+template <typename T>
+void launch_mg_tail(const TailArgs<T>& a, int nmem, hipStream_t s) {
+  hipLaunchKernelGGL((k_mg_tail<T>), dim3(nmem), dim3(256), 0, s, a);
+}
+template void launch_mg_tail<float>(const TailArgs<float>&, int, hipStream_t);
+template void launch_mg_tail<double>(const TailArgs<double>&, int, hipStream_t);
 
 // ---------------------------------------------------------------------------- FP64 residual (refinement)
 template <bool ONE>

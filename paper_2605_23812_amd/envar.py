@@ -26,6 +26,8 @@ FLAG_TILES_8 = 8
 FLAG_TILES_16 = 16
 FLAG_TILES_32 = 32
 FLAG_ONE_LANE = 64
+FLAG_NO_TAIL = 128      # passes beyond the cap as one level-by-level headroom pass, not the per-member launch
+FLAG_SHORT_GRAPH = 256  # one level-by-level pass per step, the rest in the per-member launch (comparisons)
 
 EXPORTS = (
     "envar_control_dim", "envar_cell_count", "envar_state_bytes", "envar_workspace_bytes",
