@@ -738,8 +738,23 @@ static TailArgs<T> tail_args(const Job& j, int k0, int k1) {
   return t;
 }
 
+// the step record of a job's members (the tail fills every norm slot up to max_cycles)
+static BookArgs book_args(const Job& j, int cap, bool tail) {
+  BookArgs bk{};
+  bk.nmem = j.nmem;
+  bk.norm_slots = j.P.norm_slots;
+  bk.cap = tail ? j.P.cap_max : job_cap(j, cap);
+  bk.slot_base = j.P.mixed ? 1 : 0;
+  bk.tol = j.P.tol;
+  bk.norms = j.w_<double>(j.w.norms);
+  bk.stats = j.w_<double>(j.w.stats);
+  return bk;
+}
+
+// Returns whether the tail launches wrote every job's step record (then no bookkeeping launch is
+// needed): when every job has a tail launch this step and `book` is set.
 template <typename TT>
-static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, bool tail, Timer* tm) {
+static bool batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, bool tail, bool book, Timer* tm) {
   typedef TT T;  // V-cycle type
   const bool mixed = J[0]->P.mixed;
   const int k_timed = mixed ? 1 : 0;
@@ -817,12 +832,24 @@ static void batch_pressure(const std::vector<Job*>& J, hipStream_t st, int cap, 
   }
   // the passes beyond the cap, up to each job's own max_cycles, for the members that need them
   // (mixed: passes cap + 1 .. max_cycles; FP64: V-cycles cap .. max_cycles - 1)
-  if (tail)
-    for (Job* j : J) {
-      const int c = job_cap(*j, cap);
-      const int k0 = mixed ? c + 1 : c, k1 = mixed ? j->P.cap_max : j->P.cap_max - 1;
-      if (k0 <= k1) launch_mg_tail<T>(tail_args<T>(*j, k0, k1), j->nmem, st);
+  if (!tail) return false;
+  bool booked = book;
+  for (Job* j : J) {
+    const int c = job_cap(*j, cap);
+    booked = booked && (mixed ? c + 1 : c) <= (mixed ? j->P.cap_max : j->P.cap_max - 1);
+  }
+  for (Job* j : J) {
+    const int c = job_cap(*j, cap);
+    const int k0 = mixed ? c + 1 : c, k1 = mixed ? j->P.cap_max : j->P.cap_max - 1;
+    if (k0 > k1) continue;
+    TailArgs<T> ta = tail_args<T>(*j, k0, k1);
+    if (booked) {
+      ta.book = book_args(*j, cap, true);
+      ta.book_member = 1;
     }
+    launch_mg_tail<T>(ta, j->nmem, st);
+  }
+  return booked;
 }
 
 // One time step of every job of the batch (each at its own step index).
@@ -836,7 +863,11 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, bool 
         [&](const Job& j, int rows) { return pred_args(j, rows, fused); },
         [&](const Multi<PredArgs<double>>& m) { launch_predictor<double>(m, st); });
   if (tm) tm->mark(TM_PRED, 1, st);
-  batch_pressure<TT>(J, st, cap, tail, tm);
+  // sensors read the step counter that the record advances, so a batch with sensors keeps the
+  // bookkeeping launch after them
+  bool any_obs = false;
+  for (const Job* j : J) any_obs = any_obs || j->obs != nullptr;
+  const bool booked = batch_pressure<TT>(J, st, cap, tail, !any_obs, tm);
   {
     auto m = seg_begin<SensorArgs>();
     for (Job* j : J) {
@@ -863,17 +894,10 @@ static int batch_step(const std::vector<Job*>& J, hipStream_t st, int cap, bool 
     }
     if (m.nseg) launch_sensors(m, st);
   }
-  {
+  if (!booked) {
     auto m = seg_begin<BookArgs>();
     for (Job* j : J) {
-      BookArgs bk{};
-      bk.nmem = j->nmem;
-      bk.norm_slots = j->P.norm_slots;
-      bk.cap = tail ? j->P.cap_max : job_cap(*j, cap);  // the tail fills every slot
-      bk.slot_base = j->P.mixed ? 1 : 0;
-      bk.tol = j->P.tol;
-      bk.norms = j->w_<double>(j->w.norms);
-      bk.stats = j->w_<double>(j->w.stats);
+      const BookArgs bk = book_args(*j, cap, tail);
       seg_add(m, bk, (j->nmem + 63) / 64);
     }
     launch_step_book(m, st);

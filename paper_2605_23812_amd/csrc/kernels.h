@@ -120,6 +120,29 @@ struct BookArgs {
   double* stats;
 };
 
+// One member's step record: norms[mem][k] holds dt*max|r| after cycle k and a skipped cycle
+// carries the previous value, so the first slot at or below tol ends the solve. Records the
+// cycles run, the final residual and whether the tolerance was met.
+__device__ __forceinline__ void step_book_member(const BookArgs& a, int mem) {
+  const double* nr = a.norms + (long)mem * a.norm_slots;
+  const int filled = a.cap + a.slot_base;
+  int used = filled;
+  for (int k = 0; k < filled; ++k)
+    if (nr[k] <= a.tol) {
+      used = k + 1;
+      break;
+    }
+  const double last = nr[used - 1];
+  const int cycles = used - a.slot_base;
+  double* st = a.stats + (long)mem * STATS_STRIDE;
+  st[ST_CYCLES] += (double)cycles;
+  st[ST_MAXCYC] = fmax(st[ST_MAXCYC], (double)cycles);
+  if (!(last <= a.tol)) st[ST_UNCONV] += 1.0;
+  st[ST_MAXRES] = (last > st[ST_MAXRES] || last != last) ? last : st[ST_MAXRES];
+  st[ST_STEPS] += 1.0;
+  st[ST_RECENT] = fmax((double)cycles, st[ST_RECENT] - 1.0 / 16.0);
+}
+
 struct FinalArgs {
   Geo g;
   int nmem, ntiles;
@@ -287,6 +310,8 @@ struct TailArgs {
   CoarseArgs coarse;
   T* rpl[2];  // mixed: the finest level's residual planes by pass parity (pass k reads k - 1, writes k)
   int nlev, k0, k1, mixed;
+  BookArgs book;  // the step record of each member, written at the end (book_member), when set
+  int book_member;
 };
 template <typename T>
 void launch_mg_tail(const TailArgs<T>& a, int nmem, hipStream_t s);

@@ -831,7 +831,8 @@ __global__ __launch_bounds__(COARSE_THREADS) void k_mg_coarse(Multi<CoarseArgs> 
 // member's tiles in turn through the same tile bodies, with a barrier between tiles (the LDS is
 // reused) and between phases (the next phase reads what this one wrote; a phase never reads what
 // it writes, so the order of its tiles does not matter). The norm of the previous pass decides,
-// as in the level kernels: a converged member carries it into the remaining slots and leaves.
+// as in the level kernels: a converged member carries it into the remaining slots and stops. With
+// `book_member` the workgroup then writes its member's step record (the bookkeeping launch's work).
 template <typename T>
 __global__ __launch_bounds__(256) void k_mg_tail(TailArgs<T> ta) {
   constexpr int NS = mg_ns<T>();
@@ -849,7 +850,7 @@ __global__ __launch_bounds__(256) void k_mg_tail(TailArgs<T> ta) {
     const double prev = __hip_atomic_load(nr + k - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev <= tol) {
       for (int q = k + (int)threadIdx.x; q <= ta.k1; q += 256) nr[q] = prev;
-      return;
+      break;
     }
     for (int l = 0; l < L; ++l) {
       MGArgs<T> a = ta.pre[l];
@@ -889,6 +890,10 @@ __global__ __launch_bounds__(256) void k_mg_tail(TailArgs<T> ta) {
         __syncthreads();
       }
     }
+  }
+  if (ta.book_member) {
+    __syncthreads();  // every norm slot of the step is written
+    if (threadIdx.x == 0) step_book_member(ta.book, mem);
   }
 }
 

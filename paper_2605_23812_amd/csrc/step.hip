@@ -492,31 +492,13 @@ __global__ void k_sensors(Multi<SensorArgs> ms) {
 }
 
 // ---------------------------------------------------------------------------- per-step bookkeeping
-// norms[mem][k] holds dt*max|r| after cycle k; a skipped cycle carries the
-// previous value, so the first slot at or below tol ends the solve. Records
-// the cycles run, the final residual and whether the tolerance was met.
+// One thread per member (step_book_member).
 __global__ void k_step_book(Multi<BookArgs> ms) {
   int blk;
   const BookArgs& a = ms.template pick<false>(blockIdx.x, blk);
   const int mem = blk * blockDim.x + threadIdx.x;
   if (mem >= a.nmem) return;
-  const double* nr = a.norms + (long)mem * a.norm_slots;
-  const int filled = a.cap + a.slot_base;
-  int used = filled;
-  for (int k = 0; k < filled; ++k)
-    if (nr[k] <= a.tol) {
-      used = k + 1;
-      break;
-    }
-  const double last = nr[used - 1];
-  const int cycles = used - a.slot_base;
-  double* st = a.stats + (long)mem * STATS_STRIDE;
-  st[ST_CYCLES] += (double)cycles;
-  st[ST_MAXCYC] = fmax(st[ST_MAXCYC], (double)cycles);
-  if (!(last <= a.tol)) st[ST_UNCONV] += 1.0;
-  st[ST_MAXRES] = (last > st[ST_MAXRES] || last != last) ? last : st[ST_MAXRES];
-  st[ST_STEPS] += 1.0;
-  st[ST_RECENT] = fmax((double)cycles, st[ST_RECENT] - 1.0 / 16.0);
+  step_book_member(a, mem);
 }
 
 // ---------------------------------------------------------------------------- J finalisation
