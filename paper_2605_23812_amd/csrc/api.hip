@@ -1904,6 +1904,10 @@ struct GradLayout {
   size_t X, Xt, dJ, rhs, partial, tmp, G, c, info, W, Wt, ev, jscr, total;
   int nsplit, dim;
   long kchunk;
+  // the split of an FP64 Gram (the FP64 path's own, which the mixed path's FP64 re-solve takes so
+  // that it forms bitwise the FP64 path's Gram)
+  int nsplit64;
+  long kchunk64;
 };
 constexpr int GRAD_PINV_MAX = 512;  // largest system the pseudo-inverse (one-workgroup Jacobi) takes
 constexpr double GRAD_PINV_RCOND = 1e-12;
@@ -1914,13 +1918,10 @@ static GradLayout grad_layout(int n, long m, int precision) {
   const bool tall = n <= m;
   L.dim = tall ? n : (int)m;
   const long klen = tall ? m : n;  // contraction length
-  // split the contraction so that >= ~512 workgroups run, chunks multiple of 32
-  const int nbt = (L.dim + 63) / 64;
-  long want = std::max(1L, 512L / (nbt * nbt));
-  long chunk = (klen + want - 1) / want;
-  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
-  L.kchunk = chunk;
-  L.nsplit = (int)((klen + chunk - 1) / chunk);
+  gram_split(L.dim, klen, (int)xs, L.nsplit, L.kchunk);
+  gram_split(L.dim, klen, 8, L.nsplit64, L.kchunk64);
+  const size_t nsp = (size_t)std::max(L.nsplit, L.nsplit64);
+  const size_t ngr = (size_t)std::max(gram_reduce_groups(L.nsplit), gram_reduce_groups(L.nsplit64));
   size_t o = 0;
   auto take = [&](size_t b) {
     size_t a = o;
@@ -1931,8 +1932,8 @@ static GradLayout grad_layout(int n, long m, int precision) {
   L.Xt = tall ? 0 : take((size_t)n * m * xs);
   L.dJ = take((size_t)n * 8);
   L.rhs = take((size_t)L.dim * 8);
-  L.partial = take((size_t)L.nsplit * L.dim * L.dim * 8);
-  L.tmp = take((size_t)gram_reduce_groups(L.nsplit) * L.dim * L.dim * 8);
+  L.partial = take(nsp * L.dim * L.dim * 8);
+  L.tmp = take(ngr * L.dim * L.dim * 8);
   L.G = take((size_t)L.dim * L.dim * 8);
   L.c = take((size_t)L.dim * 8);
   L.info = take(256);
@@ -2024,8 +2025,8 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
     if (!tall)
       return fail(ENVAR_EDIVERGED, "the FP32 Gram of %d members over %ld controls is not positive definite (pivot %d); "
                   "use ENVAR_FP64", n, m, info);
-    launch_gram_anom(ctrl, n, m, partial, L.nsplit, L.kchunk, s);
-    launch_gram_reduce(partial, n, L.nsplit, at<double>(ws, L.tmp), G, s);
+    launch_gram_anom(ctrl, n, m, partial, L.nsplit64, L.kchunk64, s);
+    launch_gram_reduce(partial, n, L.nsplit64, at<double>(ws, L.tmp), G, s);
     if (!pinv) {
       if (launch_chol_solve(G, dJ, n, c, (double*)info_dev, s)) return fail(ENVAR_EDEVICE, "Cholesky launch failed (n = %d)", n);
       HIP_OK(hipGetLastError());
@@ -2043,8 +2044,8 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   if (L.dim > GRAD_PINV_MAX)
     return fail(ENVAR_EDIVERGED, "the ensemble Gram is not positive definite (pivot %d); the pseudo-inverse takes "
                 "systems up to %d", info, GRAD_PINV_MAX);
-  if (!pinv)  // the failed factor overwrote the Gram: reduce the partials again
-    launch_gram_reduce(partial, L.dim, L.nsplit, at<double>(ws, L.tmp), G, s);
+  if (!pinv)  // the failed factor overwrote the Gram: reduce the partials (of an FP64 Gram) again
+    launch_gram_reduce(partial, L.dim, L.nsplit64, at<double>(ws, L.tmp), G, s);
   double* W = at<double>(ws, L.W);
   double* ev = at<double>(ws, L.ev);
   if (launch_jacobi(G, L.dim, L.dim, ev, W, at<double>(ws, L.Wt), at<double>(ws, L.jscr), s))
@@ -2137,12 +2138,7 @@ struct GNLayout {
 
 static GNLayout gn_layout(int n, long n_obs) {
   GNLayout L{};
-  const int nbt = (n + 63) / 64;
-  long want = std::max(1L, 512L / (nbt * nbt));
-  long chunk = (n_obs + want - 1) / want;
-  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
-  L.kchunk = chunk;
-  L.nsplit = (int)((n_obs + chunk - 1) / chunk);
+  gram_split(n, n_obs, 8, L.nsplit, L.kchunk);
   size_t o = 0;
   auto take = [&](size_t b) {
     size_t a = o;
@@ -2493,12 +2489,7 @@ struct EigLayout {
 static EigLayout eig_layout(const EigSetup& S) {
   EigLayout L{};
   const int b = S.b, n2 = 2 * b;
-  const int nbt = (n2 + 63) / 64;
-  long want = std::max(1L, 512L / (nbt * nbt));
-  long chunk = (S.M + want - 1) / want;
-  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
-  L.kchunk = chunk;
-  L.nsplit = (int)((S.M + chunk - 1) / chunk);
+  gram_split(n2, S.M, 8, L.nsplit, L.kchunk);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t a = o;

@@ -67,24 +67,31 @@ struct Vec16<double> {
   typedef double __attribute__((ext_vector_type(2))) T;
 };
 
-// Only the tile pairs bi <= bj are computed; an off-diagonal tile is written twice (as G[I][J] and
+// Only the block pairs bi <= bj are computed; an off-diagonal block is written twice (as G[I][J] and
 // transposed as G[J][I]), so G is exactly symmetric. The X rows are fetched as 16-byte vectors into
-// registers one chunk ahead of the MFMA work on the chunk in LDS (a diagonal tile fetches its rows
+// registers one chunk ahead of the MFMA work on the chunk in LDS (a diagonal block fetches its rows
 // once and uses them for both operands).
+// BS: rows of a block, 64 or 128. Wave w owns the BS / 4 rows from I0 + w BS / 4 (BS / 64 row tiles
+// of 16) against the BS / 16 column tiles of the J block; at each step of 4 along the contraction it
+// reads its A fragments and the B fragments once and issues every tile's MFMA. 128-row blocks read
+// each X row for fewer block pairs (at n = 256: two row blocks, three pairs, against four and ten).
 // ANOM: row r of X is formed on the fly as X[r] - X0 (the anomaly of a control row about the
 // centre row X0, the values k_anomaly would store), so that no copy of the anomalies is needed.
-template <typename TX, bool ANOM = false>
+template <typename TX, bool ANOM = false, int BS = 64>
 __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, long m, long ldx,
                                               double* __restrict__ partial, int nsplit, long kchunk, int nbt,
                                               const TX* __restrict__ X0 = nullptr) {
   typedef typename MfmaAcc<TX>::V V;
   typedef typename Vec16<TX>::T VT;
+  static_assert(BS == 64 || BS == 128, "64- or 128-row blocks");
   constexpr int KC = GRAM_KC, LDR = KC + 1;
   constexpr int VW = 16 / sizeof(TX);      // elements per vector
   constexpr int VPR = KC / VW;             // vectors per row and chunk
-  constexpr int NV = 64 * VPR / 256;       // vectors per thread and operand
-  __shared__ TX sa[64 * LDR];
-  __shared__ TX sb[64 * LDR];
+  constexpr int NV = BS * VPR / 256;       // vectors per thread and operand
+  constexpr int RT = BS / 64;              // 16-row tiles per wave
+  constexpr int CT = BS / 16;              // 16-column tiles
+  __shared__ TX sa[BS * LDR];
+  __shared__ TX sb[BS * LDR];
   const int split = blockIdx.x % nsplit;
   int pair = blockIdx.x / nsplit;
   int bi = 0;
@@ -94,7 +101,7 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
   }
   const int bj = bi + pair;
   const bool diag = bi == bj;
-  const int I0 = bi * 64, J0 = bj * 64;
+  const int I0 = bi * BS, J0 = bj * BS;
   const long kbeg = (long)split * kchunk;
   long kend = kbeg + kchunk;
   if (kend > m) kend = m;
@@ -123,8 +130,11 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
       if (!diag) rb[v] = load(J0 + r, k0 + c);
     }
   };
-  V acc[4];
-  for (int t = 0; t < 4; ++t) acc[t] = V{0, 0, 0, 0};
+  V acc[RT][CT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = V{0, 0, 0, 0};
   if (kbeg < kend) fetch(kbeg);
   for (long k0 = kbeg; k0 < kend; k0 += KC) {
 #pragma unroll
@@ -139,27 +149,52 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
     __syncthreads();
     if (k0 + KC < kend) fetch(k0 + KC);  // the next chunk's loads overlap this chunk's MFMA work
     const TX* sB = diag ? sa : sb;
-    const int row = 16 * wave + lane % 16;
     for (int kk = 0; kk < KC; kk += 4) {
-      const TX a = sa[row * LDR + kk + lane / 16];
-      for (int t = 0; t < 4; ++t) {
-        const TX b = sB[(16 * t + lane % 16) * LDR + kk + lane / 16];
-        acc[t] = MfmaAcc<TX>::mma(a, b, acc[t]);
-      }
+      TX a[RT], b[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a[rt] = sa[(16 * (wave * RT + rt) + lane % 16) * LDR + kk + lane / 16];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) b[ct] = sB[(16 * ct + lane % 16) * LDR + kk + lane / 16];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = MfmaAcc<TX>::mma(a[rt], b[ct], acc[rt][ct]);
     }
     __syncthreads();
   }
   double* P = partial + (long)split * n * n;
-  for (int t = 0; t < 4; ++t) {
-    const int j = J0 + 16 * t + lane % 16;
-    for (int r = 0; r < 4; ++r) {
-      const int i = I0 + 16 * wave + MfmaAcc<TX>::row(lane, r);
-      if (i < n && j < n) {
-        P[(long)i * n + j] = (double)acc[t][r];
-        if (!diag) P[(long)j * n + i] = (double)acc[t][r];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int j = J0 + 16 * ct + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I0 + 16 * (wave * RT + rt) + MfmaAcc<TX>::row(lane, r);
+        if (i < n && j < n) {
+          P[(long)i * n + j] = (double)acc[rt][ct][r];
+          if (!diag) P[(long)j * n + i] = (double)acc[rt][ct][r];
+        }
       }
     }
-  }
+}
+
+// Rows of a Gram block: 128 for an FP64 Gram above n = 64 (three block pairs at n = 256 instead of
+// ten, and each pair's MFMA work per loaded row doubles), else 64 (the FP32 Gram measured faster
+// with 64-row blocks: 91.8 against 109 us at n = 256, m = 65,536).
+int gram_block_rows(int n, int elem_bytes) { return n > 64 && elem_bytes == 8 ? 128 : 64; }
+
+// Split of the contraction (chunks a multiple of 32, at least 64 columns). 64-row blocks: about
+// 512 / nbt^2 splits. 128-row blocks hold one workgroup per CU (their registers), so the grid stays
+// at or below 256 workgroups: a 257th would run alone after the rest.
+void gram_split(int n, long klen, int elem_bytes, int& nsplit, long& kchunk) {
+  const int bs = gram_block_rows(n, elem_bytes);
+  const long nbt = (n + bs - 1) / bs;
+  const long want = bs == 128 ? std::max(1L, 256L / (nbt * (nbt + 1) / 2)) : std::max(1L, 512L / (nbt * nbt));
+  long chunk = (klen + want - 1) / want;
+  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
+  kchunk = chunk;
+  nsplit = (int)((klen + chunk - 1) / chunk);
 }
 
 // Fixed-order reduction of the split-K partials in two levels: groups of
@@ -998,14 +1033,24 @@ void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, d
 }
 template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s) {
-  const int nbt = (n + 63) / 64;
-  hipLaunchKernelGGL(k_gram<TX>, dim3(nsplit * nbt * (nbt + 1) / 2), dim3(256), 0, s, X, n, m, ldx, partial, nsplit,
-                     kchunk, nbt);
+  const int bs = gram_block_rows(n, (int)sizeof(TX)), nbt = (n + bs - 1) / bs;
+  const dim3 grid(nsplit * nbt * (nbt + 1) / 2);
+  if (bs == 128)
+    hipLaunchKernelGGL((k_gram<TX, false, 128>), grid, dim3(256), 0, s, X, n, m, ldx, partial, nsplit, kchunk, nbt,
+                       nullptr);
+  else
+    hipLaunchKernelGGL((k_gram<TX, false, 64>), grid, dim3(256), 0, s, X, n, m, ldx, partial, nsplit, kchunk, nbt,
+                       nullptr);
 }
 void launch_gram_anom(const double* ctrl, int n, long m, double* partial, int nsplit, long kchunk, hipStream_t s) {
-  const int nbt = (n + 63) / 64;
-  hipLaunchKernelGGL((k_gram<double, true>), dim3(nsplit * nbt * (nbt + 1) / 2), dim3(256), 0, s, ctrl + m, n, m, m,
-                     partial, nsplit, kchunk, nbt, ctrl);
+  const int bs = gram_block_rows(n, 8), nbt = (n + bs - 1) / bs;
+  const dim3 grid(nsplit * nbt * (nbt + 1) / 2);
+  if (bs == 128)
+    hipLaunchKernelGGL((k_gram<double, true, 128>), grid, dim3(256), 0, s, ctrl + m, n, m, m, partial, nsplit, kchunk,
+                       nbt, ctrl);
+  else
+    hipLaunchKernelGGL((k_gram<double, true, 64>), grid, dim3(256), 0, s, ctrl + m, n, m, m, partial, nsplit, kchunk,
+                       nbt, ctrl);
 }
 void launch_gemv_anom(const double* ctrl, int n, long m, const double* c, double* g, hipStream_t s) {
   long bx = (m + 63) / 64;
