@@ -53,7 +53,7 @@ struct MfmaAcc<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
 
-constexpr int GRAM_KC = 32;
+constexpr int GRAM_KC = 64;  // contraction columns per LDS chunk
 constexpr int GRAM_REDUCE_GROUP = 32;  // splits summed per group in the first reduction level
 
 template <typename TX>
@@ -184,15 +184,16 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
 // with 64-row blocks: 91.8 against 109 us at n = 256, m = 65,536).
 int gram_block_rows(int n, int elem_bytes) { return n > 64 && elem_bytes == 8 ? 128 : 64; }
 
-// Split of the contraction (chunks a multiple of 32, at least 64 columns). 64-row blocks: about
+// Split of the contraction (at least one LDS chunk of columns). 64-row blocks: about
 // 512 / nbt^2 splits. 128-row blocks hold one workgroup per CU (their registers), so the grid stays
-// at or below 256 workgroups: a 257th would run alone after the rest.
+// at or below 256 workgroups: a 257th would run alone after the rest. A split is a whole number of
+// LDS chunks, so that no MFMA work runs on zero padding inside the contraction.
 void gram_split(int n, long klen, int elem_bytes, int& nsplit, long& kchunk) {
   const int bs = gram_block_rows(n, elem_bytes);
   const long nbt = (n + bs - 1) / bs;
   const long want = bs == 128 ? std::max(1L, 256L / (nbt * (nbt + 1) / 2)) : std::max(1L, 512L / (nbt * nbt));
   long chunk = (klen + want - 1) / want;
-  chunk = std::max(64L, ((chunk + 31) / 32) * 32);
+  chunk = std::max((long)GRAM_KC, ((chunk + GRAM_KC - 1) / GRAM_KC) * GRAM_KC);  // whole LDS chunks
   kchunk = chunk;
   nsplit = (int)((klen + chunk - 1) / chunk);
 }

@@ -321,7 +321,7 @@ struct GramPlan {
   int n;          // rows of X (Gram is n x n)
   long m;         // contraction length
   int nsplit;     // split-K partials
-  long kchunk;    // columns per split (multiple of 16)
+  long kchunk;    // columns per split (a whole number of the Gram kernel's LDS chunks)
 };
 template <typename TX>
 void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, double* dJ, hipStream_t s);
