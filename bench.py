@@ -30,11 +30,12 @@ ELL, SIGMA = 0.05, 5e-3
 DIV_TOL = 1e-10      # divergence bound of the headline and of every baseline it is compared with
 DIV_TOL_REF = 1e-12  # the FP64 accuracy reference
 
-# the survey's algorithmic bytes per cell-step (ideal fusion, section 8(d) of the design notes):
+# the minimal-fusion byte model per cell-step (every field moved once per step, the tendency
+# history and forcing once, halos from cache; no warm-start history):
 # fused predictor + projection + cost 59 + 80 (mixed) / 78 + 80 (FP64), each refinement pass 133 B
 # (mixed), each FP64 V-cycle 187 B
-SURVEY_PRED_PROJ = {"mixed": 139.0, "fp64": 158.0}
-SURVEY_PER_CYCLE = {"mixed": 133.0, "fp64": 187.0}
+MINIMAL_PRED_PROJ = {"mixed": 139.0, "fp64": 158.0}
+MINIMAL_PER_CYCLE = {"mixed": 133.0, "fp64": 187.0}
 
 # algorithmic bytes per fluid cell and launch (ideal fusion, halos re-read from cache)
 BYTES_PER_CELL = {
@@ -152,11 +153,11 @@ def roofline(st, prec, ncells, copy_gbs=None):
         "per_step_us": {k: round(v, 1) for k, v in per_step.items()},
         "per_kernel_algorithmic_GBs": per_kernel,
     }
-    if name == "predictor":  # the survey's bytes for the same launch (predictor + projection + cost)
-        sb = SURVEY_PRED_PROJ[prec] * ncells * members
-        out["survey_bytes_per_member_cell"] = SURVEY_PRED_PROJ[prec]
-        out["survey_achieved"] = round(sb / (avg_us * 1e-6) / 1e9, 1)
-        out["survey_frac"] = round(sb / (avg_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+    if name == "predictor":  # the minimal model's bytes for the same launch (predictor + projection + cost)
+        sb = MINIMAL_PRED_PROJ[prec] * ncells * members
+        out["minimal_bytes_per_member_cell"] = MINIMAL_PRED_PROJ[prec]
+        out["minimal_achieved"] = round(sb / (avg_us * 1e-6) / 1e9, 1)
+        out["minimal_frac"] = round(sb / (avg_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
     return out
 
 
@@ -174,10 +175,10 @@ def step_bytes(prec, cycles):
 def step_roofline(value, prec, cycles, copy_gbs):
     b = step_bytes(prec, cycles)
     at_peak = PEAK_HBM_GBS * 1e9 / b
-    sb = SURVEY_PRED_PROJ[prec] + SURVEY_PER_CYCLE[prec] * cycles
+    sb = MINIMAL_PRED_PROJ[prec] + MINIMAL_PER_CYCLE[prec] * cycles
     return {"bytes_per_cell_step": round(b, 1), "cell_steps_per_s_at_peak": round(at_peak, 1),
             "frac": round(value / at_peak, 4),
-            "survey_bytes_per_cell_step": round(sb, 1), "survey_frac": round(value * sb / (PEAK_HBM_GBS * 1e9), 4),
+            "minimal_bytes_per_cell_step": round(sb, 1), "minimal_frac": round(value * sb / (PEAK_HBM_GBS * 1e9), 4),
             "frac_of_measured_copy": round(value / (copy_gbs * 1e9 / b), 4) if copy_gbs else None}
 
 
