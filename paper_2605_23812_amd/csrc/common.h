@@ -33,9 +33,13 @@ __host__ __device__ constexpr int mg_h() { return 2 * mg_ns<T>() + 1; }
 // multigrid tile width: the window is one wave wide
 template <typename T>
 __host__ __device__ constexpr int mg_tw() { return 64 - 2 * mg_h<T>(); }
-// over-relaxation of the red-black sweeps on the tiled levels: measured at h = 1/128 (65 members),
-// FP64 V-cycles per step 3.04 (omega = 1) -> 2.06 (1.15) -> 3.05 (1.3); the LDS levels keep 1
-constexpr double MG_OMEGA = 1.15;
+// relaxation of the red-black sweeps on the tiled levels, by the V-cycle's element type, measured at
+// h = 1/128 with 65 members (the LDS levels keep 1):
+//  * FP64 V(2,2): V-cycles per step 3.04 (omega = 1) -> 2.06 (1.15) -> 3.05 (1.3);
+//  * FP32 V(1,1) inside FP64 refinement, 6,000 steps: refinement passes per step 1.398 (0.9),
+//    1.381 (0.95), 1.363 (1), 1.369 (1.05), 1.510 (1.15), 1.619 (1.25); cell-steps/s best at 1.
+template <typename T>
+__host__ __device__ constexpr double mg_omega() { return sizeof(T) == sizeof(float) ? 1.0 : 1.15; }
 constexpr int COARSE_N = 16; // levels with inv_h <= 16 run inside one workgroup per member
 constexpr int MAX_LEVELS = 12;
 constexpr int MAX_COARSE_UNKNOWNS = 128;

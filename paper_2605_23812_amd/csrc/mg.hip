@@ -6,7 +6,7 @@
 //
 // Per fine level and V-cycle two launches, both over (member, 64-wide tile of 8, 16 or 32 rows):
 //   pre : load phi, b with a halo of 2 NS + 1 into LDS, NS red-black
-//         Gauss-Seidel sweeps over-relaxed by MG_OMEGA (temporal blocking: a sweep invalidates two
+//         Gauss-Seidel sweeps relaxed by mg_omega (temporal blocking: a sweep invalidates two
 //         halo rings), residual r = b - L phi, restriction b_c = mean of the
 //         four children; writes phi and b_c.
 //   post: load phi, b with a halo of 2 NS (+1), add the bilinearly
@@ -122,7 +122,7 @@ struct Items {
       for (int n = 0; n < W::NIT; ++n)
         if (invd[c][n] != (T)0) {
           T* const o = sp + own0[c] + 8 * n * W::QS;
-          *o += (T)MG_OMEGA * ((nbsum(sp, c, n) - hb[c][n]) * invd[c][n] - *o);
+          *o += (T)mg_omega<T>() * ((nbsum(sp, c, n) - hb[c][n]) * invd[c][n] - *o);
         }
       __syncthreads();
     }
