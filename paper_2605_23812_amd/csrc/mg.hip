@@ -848,7 +848,9 @@ __global__ __launch_bounds__(256) void k_mg_tail(TailArgs<T> ta) {
   const double tol = ta.pre[0].tol;
   for (int k = ta.k0; k <= ta.k1; ++k) {
     const double prev = __hip_atomic_load(nr + k - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev <= tol) {
+    // a converged member, or one whose residual is not a number (no pass can change that; its
+    // record is the same: no slot at or below the tolerance)
+    if (prev <= tol || prev != prev) {
       for (int q = k + (int)threadIdx.x; q <= ta.k1; q += 256) nr[q] = prev;
       break;
     }

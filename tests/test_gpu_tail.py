@@ -102,3 +102,27 @@ def test_tail_heavy_forward_matches_oracle():
               flush=True)
         assert rel.max() <= tol
         assert st["unconverged"] == 0 and st["max_cycles_used"] >= 2
+
+
+def test_tail_stops_on_a_non_finite_member():
+    """A member whose forcing holds a NaN has a NaN residual from its first solve on. The tail stops
+    on it (no pass can change that) instead of running every pass up to max_cycles, and the three
+    schedules still agree: the other members' costs bit for bit, the NaN member's cost not finite,
+    each of its steps counted as not converged."""
+    p, state, ctrl = _setup(64, "cavity", E.MIXED, 4, seed=5)
+    bad = ctrl.clone()
+    bad[2, 100] = float("nan")
+    keep = [0, 1, 3]
+    ref = None
+    for flags in (E.FLAG_NO_TAIL, 0, E.FLAG_SHORT_GRAPH):
+        q = dataclasses.replace(p, flags=flags)
+        J, _, st = E.forward(q, state, bad, 30)
+        torch.cuda.synchronize()
+        J = J.cpu().numpy()
+        print("non-finite member: flags", flags, "J", J, "unconverged", st["unconverged"], "diverged",
+              st["diverged"], flush=True)
+        assert np.isnan(J[2]) and np.all(np.isfinite(J[keep]))
+        assert st["diverged"] == 1 and st["unconverged"] == 30
+        if ref is None:
+            ref = J
+        assert np.array_equal(J[keep], ref[keep])
