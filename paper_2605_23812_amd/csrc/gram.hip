@@ -179,19 +179,23 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
     }
 }
 
-// Rows of a Gram block: 128 for an FP64 Gram above n = 64 (three block pairs at n = 256 instead of
-// ten, and each pair's MFMA work per loaded row doubles), else 64 (the FP32 Gram measured faster
-// with 64-row blocks: 91.8 against 109 us at n = 256, m = 65,536).
-int gram_block_rows(int n, int elem_bytes) { return n > 64 && elem_bytes == 8 ? 128 : 64; }
+// Rows of a Gram block: 128 above n = 64 (three block pairs at n = 256 instead of ten, and each
+// pair's MFMA work per loaded row doubles), else 64.
+int gram_block_rows(int n, int elem_bytes) {
+  (void)elem_bytes;
+  return n > 64 ? 128 : 64;
+}
 
 // Split of the contraction (at least one LDS chunk of columns). 64-row blocks: about
-// 512 / nbt^2 splits. 128-row blocks hold one workgroup per CU (their registers), so the grid stays
-// at or below 256 workgroups: a 257th would run alone after the rest. A split is a whole number of
-// LDS chunks, so that no MFMA work runs on zero padding inside the contraction.
+// 512 / nbt^2 splits. 128-row blocks: the registers of the FP64 kernel hold one workgroup per CU,
+// those of the FP32 kernel two, so the grid stays at or below 256 or 512 workgroups (one more would
+// run alone after the rest). A split is a whole number of LDS chunks, so that no MFMA work runs on
+// zero padding inside the contraction.
 void gram_split(int n, long klen, int elem_bytes, int& nsplit, long& kchunk) {
   const int bs = gram_block_rows(n, elem_bytes);
   const long nbt = (n + bs - 1) / bs;
-  const long want = bs == 128 ? std::max(1L, 256L / (nbt * (nbt + 1) / 2)) : std::max(1L, 512L / (nbt * nbt));
+  const long slots = elem_bytes == 8 ? 256L : 512L;
+  const long want = bs == 128 ? std::max(1L, slots / (nbt * (nbt + 1) / 2)) : std::max(1L, 512L / (nbt * nbt));
   long chunk = (klen + want - 1) / want;
   chunk = std::max((long)GRAM_KC, ((chunk + GRAM_KC - 1) / GRAM_KC) * GRAM_KC);  // whole LDS chunks
   kchunk = chunk;
