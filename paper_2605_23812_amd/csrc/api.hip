@@ -2583,8 +2583,14 @@ extern "C" int envar_eigen_ensemble(const envar_problem* p, int32_t N, const env
     launch_gram<double>(Q, rows, M, M, d(L.partial), L.nsplit, L.kchunk, s);
     launch_gram_reduce(d(L.partial), rows, L.nsplit, d(L.tmp), G2, s);
   };
+  // One Jacobi sweep per iteration: the next block spans B Q whatever rotation W the Ritz step
+  // applies, so the subspace iteration is unchanged; the basis carries the rotations over from one
+  // iteration to the next, and the residual test (every kept |B u - theta u| from the rotated
+  // blocks) only passes once that basis diagonalises the Ritz matrix. Measured at h = 1/128: the
+  // same iteration counts (69 for 20 members, 39 for 64) and eigenvalues within 1e-15 relative as
+  // with sweeps until convergence, in 15 against 20 ms and 41 against 78 ms.
   auto jacobi = [&](const double* A, double* ev, double* Wc, double* Wr) -> int {
-    if (launch_jacobi(A, b, b, ev, Wc, Wr, d(L.jac), s)) return fail(ENVAR_EDEVICE, "Jacobi launch failed");
+    if (launch_jacobi(A, b, b, ev, Wc, Wr, d(L.jac), s, 1)) return fail(ENVAR_EDEVICE, "Jacobi launch failed");
     return ENVAR_OK;
   };
   auto chol_inv = [&](const double* G, double* Li) -> int {

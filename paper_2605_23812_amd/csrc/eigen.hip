@@ -512,7 +512,7 @@ size_t jacobi_scratch_doubles(int n) {
   return ne <= JAC_LDS_MAX ? 0 : 2 * (size_t)ne * (ne + 1);
 }
 int launch_jacobi(const double* A, int lda, int n, double* evals, double* W, double* Wt, double* scratch,
-                  hipStream_t s) {
+                  hipStream_t s, int max_sweeps) {
   if (n < 1 || n > JAC_MAX) return -1;
   const int ne = n + (n & 1);
   const size_t dyn = ne <= JAC_LDS_MAX ? 2 * (size_t)ne * (ne + 1) * sizeof(double) : 0;
@@ -523,7 +523,7 @@ int launch_jacobi(const double* A, int lda, int n, double* evals, double* W, dou
       return -2;
     attr = true;
   }
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), dyn, s, A, lda, n, 40, evals, W, Wt, scratch);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), dyn, s, A, lda, n, max_sweeps, evals, W, Wt, scratch);
   return 0;
 }
 int launch_chol_inv(const double* G, int n, double* Linv, double* scratch, hipStream_t s) {

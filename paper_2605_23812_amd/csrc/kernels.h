@@ -358,7 +358,7 @@ void launch_dgemm(int M, int N, int K, const double* A, long lda, long sA, const
                   double* C, long ldc, long sC, int batch, const double* S, long lds, hipStream_t s);
 size_t jacobi_scratch_doubles(int n);
 int launch_jacobi(const double* A, int lda, int n, double* evals, double* W, double* Wt, double* scratch,
-                  hipStream_t s);
+                  hipStream_t s, int max_sweeps = 40);
 int launch_chol_inv(const double* G, int n, double* Linv, double* scratch, hipStream_t s);
 void launch_small_gemm(int n, const double* A, int ta, const double* B, int tb, const double* d, double* C,
                        hipStream_t s);
