@@ -181,10 +181,7 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
 
 // Rows of a Gram block: 128 above n = 64 (three block pairs at n = 256 instead of ten, and each
 // pair's MFMA work per loaded row doubles), else 64.
-int gram_block_rows(int n, int elem_bytes) {
-  (void)elem_bytes;
-  return n > 64 ? 128 : 64;
-}
+int gram_block_rows(int n) { return n > 64 ? 128 : 64; }
 
 // Split of the contraction (at least one LDS chunk of columns). 64-row blocks: about
 // 512 / nbt^2 splits. 128-row blocks: the registers of the FP64 kernel hold one workgroup per CU,
@@ -192,7 +189,7 @@ int gram_block_rows(int n, int elem_bytes) {
 // run alone after the rest). A split is a whole number of LDS chunks, so that no MFMA work runs on
 // zero padding inside the contraction.
 void gram_split(int n, long klen, int elem_bytes, int& nsplit, long& kchunk) {
-  const int bs = gram_block_rows(n, elem_bytes);
+  const int bs = gram_block_rows(n);
   const long nbt = (n + bs - 1) / bs;
   const long slots = elem_bytes == 8 ? 256L : 512L;
   const long want = bs == 128 ? std::max(1L, slots / (nbt * (nbt + 1) / 2)) : std::max(1L, 512L / (nbt * nbt));
@@ -1038,7 +1035,7 @@ void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, d
 }
 template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s) {
-  const int bs = gram_block_rows(n, (int)sizeof(TX)), nbt = (n + bs - 1) / bs;
+  const int bs = gram_block_rows(n), nbt = (n + bs - 1) / bs;
   const dim3 grid(nsplit * nbt * (nbt + 1) / 2);
   if (bs == 128)
     hipLaunchKernelGGL((k_gram<TX, false, 128>), grid, dim3(256), 0, s, X, n, m, ldx, partial, nsplit, kchunk, nbt,
@@ -1048,7 +1045,7 @@ void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nspl
                        nullptr);
 }
 void launch_gram_anom(const double* ctrl, int n, long m, double* partial, int nsplit, long kchunk, hipStream_t s) {
-  const int bs = gram_block_rows(n, 8), nbt = (n + bs - 1) / bs;
+  const int bs = gram_block_rows(n), nbt = (n + bs - 1) / bs;
   const dim3 grid(nsplit * nbt * (nbt + 1) / 2);
   if (bs == 128)
     hipLaunchKernelGGL((k_gram<double, true, 128>), grid, dim3(256), 0, s, ctrl + m, n, m, m, partial, nsplit, kchunk,

@@ -327,9 +327,9 @@ template <typename TX>
 void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, double* dJ, hipStream_t s);
 template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s);
-// the Gram's block rows (64 or 128) and the split of its contraction of length klen that every caller
-// sizes its partials by (nsplit x n x n doubles)
-int gram_block_rows(int n, int elem_bytes);
+// the Gram's block rows (64 or 128) and the split of its contraction of length klen (elements of
+// elem_bytes) that every caller sizes its partials by (nsplit x n x n doubles)
+int gram_block_rows(int n);
 void gram_split(int n, long klen, int elem_bytes, int& nsplit, long& kchunk);
 int gram_reduce_groups(int nsplit);
 void launch_gram_reduce(const double* partial, int n, int nsplit, double* tmp, double* G, hipStream_t s);
