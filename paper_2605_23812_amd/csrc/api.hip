@@ -1987,13 +1987,28 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
     }
     return ENVAR_OK;
   };
-  launch_anomaly<TX>(ctrl, J, n, m, X, dJ, s);
+  // FP64 rows over at least as many controls as members: the Gram and the final product form the
+  // anomalies from the control rows where they read them (the values k_anomaly would store, so the
+  // result is the same bit for bit), which saves writing X and reading it back. The Gram's vector
+  // loads then read the rows themselves: 16-byte aligned rows (or an odd m, read element by element).
+  const bool fp32 = sizeof(TX) == sizeof(float);
+  const bool onfly = !fp32 && tall && ((uintptr_t)ctrl % 16 == 0 || m % 2 == 1);
+  if (onfly)
+    launch_cost_anomaly(J, n, dJ, s);
+  else
+    launch_anomaly<TX>(ctrl, J, n, m, X, dJ, s);
   if (tall) {
-    launch_gram<TX>(X, n, m, m, partial, L.nsplit, L.kchunk, s);
+    if (onfly)
+      launch_gram_anom(ctrl, n, m, partial, L.nsplit, L.kchunk, s);
+    else
+      launch_gram<TX>(X, n, m, m, partial, L.nsplit, L.kchunk, s);
     launch_gram_reduce(partial, n, L.nsplit, at<double>(ws, L.tmp), G, s);
     if (!pinv) {
       if (launch_chol_solve(G, dJ, n, c, (double*)info_dev, s)) return fail(ENVAR_EDEVICE, "Cholesky launch failed (n = %d)", n);
-      launch_gemv_t<TX>(X, n, m, m, c, g, s);
+      if (onfly)
+        launch_gemv_anom(ctrl, n, m, c, g, s);
+      else
+        launch_gemv_t<TX>(X, n, m, m, c, g, s);
     }
   } else {
     TX* Xt = at<TX>(ws, L.Xt);
@@ -2020,7 +2035,6 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   // taken on the fly, which is the FP64 gradient's own arithmetic. A factor that fails in FP64
   // (or the pseudo-inverse asked for) goes to the eigen-pseudo-inverse of the Gram: its
   // eigenvalues at or below 1e-12 of the largest dropped, the minimum-norm solution.
-  const bool fp32 = sizeof(TX) == sizeof(float);
   if (fp32) {
     if (!tall)
       return fail(ENVAR_EDIVERGED, "the FP32 Gram of %d members over %ld controls is not positive definite (pivot %d); "
@@ -2053,7 +2067,7 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   if (launch_pinv_apply(W, ev, L.dim, tall ? dJ : rhs, tall ? c : g, GRAD_PINV_RCOND, info_dev, s))
     return fail(ENVAR_EDEVICE, "pseudo-inverse launch failed (n = %d)", L.dim);
   if (tall) {
-    if (fp32)
+    if (fp32 || onfly)
       launch_gemv_anom(ctrl, n, m, c, g, s);
     else
       launch_gemv_t<TX>(X, n, m, m, c, g, s);

@@ -25,6 +25,12 @@ __global__ void k_anomaly(const double* ctrl, const double* J, int n, long m, TX
   if (blockIdx.x == 0 && threadIdx.x == 0) dJ[i] = J[i + 1] - J[0];
 }
 
+// the cost anomalies dJ_i = J_{i+1} - J_0 alone, for a solve whose Gram and final product form the
+// control anomalies where they read them
+__global__ void k_cost_anomaly(const double* J, int n, double* dJ) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dJ[i] = J[i + 1] - J[0];
+}
+
 // ---------------------------------------------------------------------------- Gram on MFMA
 // One workgroup (4 waves) computes a 64 x 64 block G[I0:I0+64, J0:J0+64] of
 // one split's partial sum over columns [kbeg, kend). X rows are staged through
@@ -105,29 +111,36 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
   const long kbeg = (long)split * kchunk;
   long kend = kbeg + kchunk;
   if (kend > m) kend = m;
-  const bool vec = ldx % VW == 0;
+  // 16-byte vector loads need 16-byte aligned rows (control rows passed by the caller may not be)
+  const bool vec = ldx % VW == 0 && (((uintptr_t)X | (uintptr_t)(ANOM ? X0 : X)) % 16) == 0;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   VT ra[NV], rb[NV];
+  // the raw row values (0 outside the rows and the chunk); ANOM subtracts the centre row when the
+  // chunk goes to LDS, so that the loads stay in flight during the MFMA work on the previous chunk
   auto load = [&](int row, long k) -> VT {
+    if (row < n && vec && k + VW <= kend) return *(const VT*)(X + (long)row * ldx + k);
     VT v;
-    if (row < n && vec && k + VW <= kend) {
-      v = *(const VT*)(X + (long)row * ldx + k);
-      if constexpr (ANOM) v -= *(const VT*)(X0 + k);
-      return v;
-    }
-    for (int e = 0; e < VW; ++e) {
-      const bool in = row < n && k + e < kend;
-      v[e] = in ? X[(long)row * ldx + k + e] : (TX)0;
-      if constexpr (ANOM) v[e] = in ? v[e] - X0[k + e] : (TX)0;
-    }
+    for (int e = 0; e < VW; ++e) v[e] = row < n && k + e < kend ? X[(long)row * ldx + k + e] : (TX)0;
     return v;
   };
+  // every vector of a thread covers the same columns of the chunk (256 is a multiple of VPR), so
+  // one vector of the centre row serves all of them
+  static_assert(256 % VPR == 0, "a thread's vectors share their columns");
+  const int cth = (threadIdx.x % VPR) * VW;
+  VT z{};
   auto fetch = [&](long k0) {
+    if constexpr (ANOM) {
+      const long k = k0 + cth;
+      if (vec && k + VW <= kend)
+        z = *(const VT*)(X0 + k);
+      else
+        for (int e = 0; e < VW; ++e) z[e] = k + e < kend ? X0[k + e] : (TX)0;
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int q = threadIdx.x + 256 * v, r = q / VPR, c = (q % VPR) * VW;
-      ra[v] = load(I0 + r, k0 + c);
-      if (!diag) rb[v] = load(J0 + r, k0 + c);
+      const int r = (threadIdx.x + 256 * v) / VPR;
+      ra[v] = load(I0 + r, k0 + cth);
+      if (!diag) rb[v] = load(J0 + r, k0 + cth);
     }
   };
   V acc[RT][CT];
@@ -139,11 +152,16 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int n, l
   for (long k0 = kbeg; k0 < kend; k0 += KC) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int q = threadIdx.x + 256 * v, r = q / VPR, c = (q % VPR) * VW;
+      const int r = (threadIdx.x + 256 * v) / VPR;
+      VT xa = ra[v], xb = rb[v];
+      if constexpr (ANOM) {
+        if (I0 + r < n) xa -= z;
+        if (!diag && J0 + r < n) xb -= z;
+      }
 #pragma unroll
       for (int e = 0; e < VW; ++e) {
-        sa[r * LDR + c + e] = ra[v][e];
-        if (!diag) sb[r * LDR + c + e] = rb[v][e];
+        sa[r * LDR + cth + e] = xa[e];
+        if (!diag) sb[r * LDR + cth + e] = xb[e];
       }
     }
     __syncthreads();
@@ -1032,6 +1050,9 @@ void launch_anomaly(const double* ctrl, const double* J, int n, long m, TX* X, d
   int bx = (int)((m + 255) / 256);
   if (bx > 256) bx = 256;
   hipLaunchKernelGGL(k_anomaly<TX>, dim3(bx, n), dim3(256), 0, s, ctrl, J, n, m, X, dJ);
+}
+void launch_cost_anomaly(const double* J, int n, double* dJ, hipStream_t s) {
+  hipLaunchKernelGGL(k_cost_anomaly, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, J, n, dJ);
 }
 template <typename TX>
 void launch_gram(const TX* X, int n, long m, long ldx, double* partial, int nsplit, long kchunk, hipStream_t s) {

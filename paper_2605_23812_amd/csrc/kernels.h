@@ -383,6 +383,7 @@ void launch_gemv_t(const TX* X, int n, long m, long ldx, const double* c, double
 // FP64 Gram partials and g = X^T c with the anomalies X_i = ctrl[i + 1] - ctrl[0] formed on the
 // fly from the n + 1 control rows (no stored copy of X)
 void launch_gram_anom(const double* ctrl, int n, long m, double* partial, int nsplit, long kchunk, hipStream_t s);
+void launch_cost_anomaly(const double* J, int n, double* dJ, hipStream_t s);
 void launch_gemv_anom(const double* ctrl, int n, long m, const double* c, double* g, hipStream_t s);
 // out = pinv(A) rhs from A's eigenpairs (launch_jacobi's evals and W), eigenvalues at or below
 // rcond times the largest dropped; n <= 512 (else -1); *info = 0, or -1 for a non-finite result

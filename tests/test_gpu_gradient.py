@@ -5,7 +5,8 @@ seeded rows (FP64 MFMA: 1e-10 relative; FP32 MFMA: cosine >= 0.999999), for
 n <= m (Gram path) and n > m (normal-equation path), at the size edges of the
 Cholesky variants and at the largest supported system (1024), the closed form of
 an antithetic quadratic cost, repeated members (rank-deficient X: the
-minimum-norm solution) and a non-finite cost (reported, not returned).
+minimum-norm solution) and a non-finite cost (reported, not returned); FP64 anomalies formed where
+they are read against stored ones, bit for bit.
 """
 import numpy as np
 import pytest
@@ -59,6 +60,35 @@ def test_gradient_fp64_at_solver_size_edges(n, m):
     err = np.abs(g - ref).max() / np.abs(ref).max()
     print("fp64 gradient at size edge", n, m, err, flush=True)
     assert err <= 1e-9
+
+
+# An FP64 gradient over at least as many controls as members forms the anomalies where the Gram and
+# the final product read them; control rows that are not 16-byte aligned (a view one element into
+# a buffer) take the stored anomalies instead. The two must agree bit for bit (the same differences,
+# summed in the same order), with the Cholesky solve and the pseudo-inverse, and match lstsq.
+# 64- and 128-row Gram blocks, a partial last block, an odd m (element loads).
+@pytest.mark.parametrize("n,m", [(8, 4096), (64, 5000), (130, 1024), (256, 2048), (17, 333)])
+def test_gradient_fp64_onfly_anomalies_match_stored(n, m):
+    rng = np.random.default_rng(11 * n + m)
+    rows = rng.standard_normal((n + 1, m)) * 1e-2
+    J = rng.standard_normal(n + 1)
+    a = torch.tensor(rows, dtype=torch.float64, device="cuda")
+    buf = torch.zeros((n + 1) * m + 1, dtype=torch.float64, device="cuda")
+    b = buf[1:].view(n + 1, m)
+    b.copy_(a)
+    assert a.data_ptr() % 16 == 0 and b.data_ptr() % 16 == 8
+    j = torch.tensor(J, dtype=torch.float64, device="cuda")
+    X = rows[1:] - rows[0]
+    ref, *_ = np.linalg.lstsq(X, J[1:] - J[0], rcond=None)
+    for precision in (E.FP64, E.FP64 | E.GRADIENT_PINV):
+        ga = E.gradient(a, j, precision)
+        gb = E.gradient(b, j, precision)
+        torch.cuda.synchronize()
+        ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
+        err = np.abs(ga - ref).max() / np.abs(ref).max()
+        print("fp64 gradient, anomalies on the fly against stored:", n, m, precision, "lstsq", err, flush=True)
+        assert np.array_equal(ga, gb)
+        assert err <= 1e-9
 
 
 @pytest.mark.parametrize("n,m", [(8, 4096), (64, 65536), (256, 65536)])
