@@ -67,7 +67,7 @@ def test_gradient_fp64_at_solver_size_edges(n, m):
 # a buffer) take the stored anomalies instead. The two must agree bit for bit (the same differences,
 # summed in the same order), with the Cholesky solve and the pseudo-inverse, and match lstsq.
 # 64- and 128-row Gram blocks, a partial last block, an odd m (element loads).
-@pytest.mark.parametrize("n,m", [(8, 4096), (64, 5000), (130, 1024), (256, 2048), (17, 333)])
+@pytest.mark.parametrize("n,m", [(8, 4096), (64, 5000), (130, 1024), (256, 2048), (17, 333), (17, 334)])
 def test_gradient_fp64_onfly_anomalies_match_stored(n, m):
     rng = np.random.default_rng(11 * n + m)
     rows = rng.standard_normal((n + 1, m)) * 1e-2
