@@ -1928,7 +1928,9 @@ static GradLayout grad_layout(int n, long m, int precision) {
     o = align256(o + b);
     return a;
   };
-  L.X = take((size_t)n * m * xs);
+  // FP64 with n <= m stores no anomalies: the Gram and the final product form them from the
+  // control rows (L.X is then not used)
+  L.X = precision == ENVAR_FP64 && tall ? 0 : take((size_t)n * m * xs);
   L.Xt = tall ? 0 : take((size_t)n * m * xs);
   L.dJ = take((size_t)n * 8);
   L.rhs = take((size_t)L.dim * 8);
@@ -1989,10 +1991,10 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   };
   // FP64 rows over at least as many controls as members: the Gram and the final product form the
   // anomalies from the control rows where they read them (the values k_anomaly would store, so the
-  // result is the same bit for bit), which saves writing X and reading it back. The Gram's vector
-  // loads then read the rows themselves: 16-byte aligned rows (or an odd m, read element by element).
+  // result is the same bit for bit), which saves writing X, reading it back and its workspace.
+  // Control rows that are not 16-byte aligned are read element by element.
   const bool fp32 = sizeof(TX) == sizeof(float);
-  const bool onfly = !fp32 && tall && ((uintptr_t)ctrl % 16 == 0 || m % 2 == 1);
+  const bool onfly = !fp32 && tall;
   if (onfly)
     launch_cost_anomaly(J, n, dJ, s);
   else

@@ -37,7 +37,9 @@ def test_sizes_and_control_dims():
     w9 = E.workspace_bytes(p, 9)
     assert w1 > 0 and abs((w9 - w1) - 8 * (w2 - w1)) < 8 * 4096
     assert E.workspace_bytes(E.Problem(inv_h=32, precision=E.MIXED), 9) < w9
-    assert E.gradient_bytes(8, 4096) > 8 * 4096 * 8
+    # mixed precision stores the FP32 anomalies; FP64 with n <= m forms them where they are read
+    assert E.gradient_bytes(8, 4096, E.MIXED) > 8 * 4096 * 4
+    assert 0 < E.gradient_bytes(8, 4096) < 8 * 4096 * 8
     assert E.state_bytes(p) > 5 * 129 * 65 * 8
 
 
@@ -66,7 +68,7 @@ def test_static_gradient_rejects_sizes_beyond_its_scratch_before_any_launch():
 
     L = E.lib()
     fake = ctypes.c_void_p(256)  # never dereferenced: the size check comes first
-    for n, m, prec in [(256, 65536, E.MIXED), (64, 262144, E.FP64)]:
+    for n, m, prec in [(256, 65536, E.MIXED), (1024, 65536, E.FP64), (1100, 1024, E.FP64)]:
         assert E.gradient_bytes(n, m, prec) > E.GRADIENT_STATIC_MAX_BYTES
         rc = L.envar_gradient_static(fake, fake, n, m, prec, fake, None)
         assert rc == E.ENOMEM, rc

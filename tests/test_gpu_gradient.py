@@ -6,7 +6,7 @@ n <= m (Gram path) and n > m (normal-equation path), at the size edges of the
 Cholesky variants and at the largest supported system (1024), the closed form of
 an antithetic quadratic cost, repeated members (rank-deficient X: the
 minimum-norm solution) and a non-finite cost (reported, not returned); FP64 anomalies formed where
-they are read against stored ones, bit for bit.
+they are read, from aligned and unaligned control rows, bit for bit.
 """
 import numpy as np
 import pytest
@@ -63,12 +63,12 @@ def test_gradient_fp64_at_solver_size_edges(n, m):
 
 
 # An FP64 gradient over at least as many controls as members forms the anomalies where the Gram and
-# the final product read them; control rows that are not 16-byte aligned (a view one element into
-# a buffer) take the stored anomalies instead. The two must agree bit for bit (the same differences,
-# summed in the same order), with the Cholesky solve and the pseudo-inverse, and match lstsq.
-# 64- and 128-row Gram blocks, a partial last block, an odd m (element loads).
+# the final product read them, with 16-byte loads from aligned control rows and element loads from
+# rows that are not (a view one element into a buffer). The two must agree bit for bit (the same
+# differences, summed in the same order), with the Cholesky solve and the pseudo-inverse, and match
+# lstsq. 64- and 128-row Gram blocks, a partial last block, an odd m (element loads either way).
 @pytest.mark.parametrize("n,m", [(8, 4096), (64, 5000), (130, 1024), (256, 2048), (17, 333), (17, 334)])
-def test_gradient_fp64_onfly_anomalies_match_stored(n, m):
+def test_gradient_fp64_onfly_anomalies_aligned_and_not(n, m):
     rng = np.random.default_rng(11 * n + m)
     rows = rng.standard_normal((n + 1, m)) * 1e-2
     J = rng.standard_normal(n + 1)
@@ -86,7 +86,7 @@ def test_gradient_fp64_onfly_anomalies_match_stored(n, m):
         torch.cuda.synchronize()
         ga, gb = ga.cpu().numpy(), gb.cpu().numpy()
         err = np.abs(ga - ref).max() / np.abs(ref).max()
-        print("fp64 gradient, anomalies on the fly against stored:", n, m, precision, "lstsq", err, flush=True)
+        print("fp64 gradient, aligned against unaligned control rows:", n, m, precision, "lstsq", err, flush=True)
         assert np.array_equal(ga, gb)
         assert err <= 1e-9
 
