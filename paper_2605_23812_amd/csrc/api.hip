@@ -1967,7 +1967,13 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
   precision &= ~ENVAR_GRADIENT_PINV;
   const GradLayout L = grad_layout(n, m, precision);
   const bool tall = n <= m;
-  TX* X = at<TX>(ws, L.X);
+  // FP64 rows over at least as many controls as members: the Gram and the final product form the
+  // anomalies from the control rows where they read them (the values k_anomaly would store, so the
+  // result is the same bit for bit), which saves writing X, reading it back and its workspace.
+  // Control rows that are not 16-byte aligned are read element by element.
+  const bool fp32 = sizeof(TX) == sizeof(float);
+  const bool onfly = !fp32 && tall;
+  TX* X = onfly ? nullptr : at<TX>(ws, L.X);  // the workspace holds no X then
   double* dJ = at<double>(ws, L.dJ);
   double* G = at<double>(ws, L.G);
   double* partial = at<double>(ws, L.partial);
@@ -1989,12 +1995,6 @@ static int gradient_impl(const double* ctrl, const double* J, int n, long m, int
     }
     return ENVAR_OK;
   };
-  // FP64 rows over at least as many controls as members: the Gram and the final product form the
-  // anomalies from the control rows where they read them (the values k_anomaly would store, so the
-  // result is the same bit for bit), which saves writing X, reading it back and its workspace.
-  // Control rows that are not 16-byte aligned are read element by element.
-  const bool fp32 = sizeof(TX) == sizeof(float);
-  const bool onfly = !fp32 && tall;
   if (onfly)
     launch_cost_anomaly(J, n, dJ, s);
   else
