@@ -2840,21 +2840,30 @@ extern "C" int envar_iterate(const envar_problem* p, const void* state_dev, doub
     if (search) {
       double a = ls->alpha0 > 0 ? ls->alpha0 : pmax / std::max(gmax, 1e-300);
       bool ok = false;
-      for (int t = 0; t < trials; ++t) {
-        // trial row: f - a g, evaluated as a one-member forward into rows[0]
-        hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, s, f_dev, perturb_dev, 0, (long)m, (double*)nullptr, a,
-                           (const double*)g, rows);
-        rc = forward_impl(P, state_dev, rows, 1, horizon, fws, fbytes, Jd, nullptr, nullptr, s, false);
+      // Backtracking: the first trial alone (it is usually accepted); when it is not, the next
+      // ones together, up to n + 1 trial rows f - a g per batched forward. Each member's cost is
+      // that of its own forward, so the first acceptable trial in order is the one that trying
+      // them one after another accepts, at the same step.
+      std::vector<double> Jt((size_t)n + 1);
+      for (int t = 0; t < trials && !ok;) {
+        const int nb = t == 0 ? 1 : std::min(trials - t, n + 1);
+        double at_ = a;
+        for (int q = 0; q < nb; ++q, at_ *= shrink)
+          hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, s, f_dev, perturb_dev, 0, (long)m, (double*)nullptr,
+                             at_, (const double*)g, rows + (long)q * m);
+        rc = forward_impl(P, state_dev, rows, nb, horizon, fws, fbytes, Jd, nullptr, nullptr, s, false);
         if (rc) return rc;
-        double Jt = 0.0;
-        HIP_OK(hipMemcpyAsync(&Jt, Jd, 8, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(Jt.data(), Jd, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
-        if (Jt <= J0 - c1 * a * gg) {
-          ok = true;
-          rec.J_trial = Jt;
-          break;
+        for (int q = 0; q < nb; ++q) {
+          if (Jt[q] <= J0 - c1 * a * gg) {
+            ok = true;
+            rec.J_trial = Jt[q];
+            break;
+          }
+          a *= shrink;
         }
-        a *= shrink;
+        t += nb;
       }
       if (!ok) {
         if (records) records[it] = rec;

@@ -132,6 +132,36 @@ def test_iterate_matches_oracle_descent():
     assert recs[0]["J_trial"] < recs[0]["J0"]
 
 
+@pytest.mark.parametrize("N", [6, 2])
+def test_iterate_backtracking_matches_oracle(N):
+    """A first trial step 64 times the default, so that the Armijo search backtracks several times
+    (Fig. envar_loop, Sec. 3.3.3). The trials after the first run together, up to N + 1 of them per
+    batched forward (N = 2: batches of 1, 3, 3 and 1 trial rows); the step and the cost accepted
+    must be those of the oracle's search, which tries one step after another."""
+    n, horizon = 16, 12
+    p = E.Problem(inv_h=n, Re=1000.0)
+    op = OE.Problem(inv_h=n, Re=1000.0)
+    u0, v0 = inputs.initial_field(n, amp=1e-2, seed=4)
+    base = OE.spinup(op, OE.initial_state(op, u0, v0), 30)
+    pert = inputs.grf_perturbations(N, n, 0.1, 1e-5, seed=8)
+    f0 = np.zeros(op.m)
+    rows = np.vstack([f0, f0 + pert])
+    g = OE.gradient(rows, OE.forward(op, base, rows, horizon))
+    a0 = 64.0 * np.abs(pert).max() / np.abs(g).max()
+    hist = OE.iterate(op, base, f0, pert, horizon, iters=1, alpha0=a0)
+    state = E.state_init(p, base.u, base.v, base.Tu_prev, base.Tv_prev)
+    f = torch.tensor(f0, device="cuda")
+    recs = E.iterate(p, state, f, torch.tensor(pert, device="cuda"), horizon, iters=1, alpha0=a0)
+    torch.cuda.synchronize()
+    _say("backtracking: N", N, "a0", a0, "gpu", recs, "oracle", [(h["alpha"], h["J_new"]) for h in hist])
+    h, r = hist[0], recs[0]
+    assert 0.0 < h["alpha"] < a0  # backtracked, and found a step
+    assert r["alpha"] == h["alpha"]  # the same trial of the same sequence a0, a0 / 2, ...
+    assert abs(r["J_trial"] - h["J_new"]) <= 1e-9 * abs(h["J_new"])
+    fo = h["f"]
+    assert np.abs(f.cpu().numpy() - fo).max() <= 1e-6 * np.abs(fo).max()
+
+
 def test_iterate_h32_workload_matches_oracle_descent():
     """Fig. envar_loop on the h = 1/32 workload's grid and ensemble (centre + 8 GRF members, length
     0.1, std 1e-2), three iterations over a 40-step horizon from a seeded non-zero forcing (std 0.5,
