@@ -2840,13 +2840,13 @@ extern "C" int envar_iterate(const envar_problem* p, const void* state_dev, doub
     if (search) {
       double a = ls->alpha0 > 0 ? ls->alpha0 : pmax / std::max(gmax, 1e-300);
       bool ok = false;
-      // Backtracking: the first trial alone (it is usually accepted); when it is not, the next
-      // ones together, up to n + 1 trial rows f - a g per batched forward. Each member's cost is
-      // that of its own forward, so the first acceptable trial in order is the one that trying
-      // them one after another accepts, at the same step.
+      // Backtracking with the trial rows f - a g, a = a0, a0 shrink, ..., up to n + 1 of them per
+      // batched forward (a forward of a few rows takes about as long as one: a single member
+      // leaves most of the GPU idle). Each member's cost is that of its own forward, so the first
+      // acceptable trial in order is the one that trying them one after another accepts.
       std::vector<double> Jt((size_t)n + 1);
       for (int t = 0; t < trials && !ok;) {
-        const int nb = t == 0 ? 1 : std::min(trials - t, n + 1);
+        const int nb = std::min(trials - t, n + 1);
         double at_ = a;
         for (int q = 0; q < nb; ++q, at_ *= shrink)
           hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, s, f_dev, perturb_dev, 0, (long)m, (double*)nullptr,

@@ -135,9 +135,9 @@ def test_iterate_matches_oracle_descent():
 @pytest.mark.parametrize("N", [6, 2])
 def test_iterate_backtracking_matches_oracle(N):
     """A first trial step 64 times the default, so that the Armijo search backtracks several times
-    (Fig. envar_loop, Sec. 3.3.3). The trials after the first run together, up to N + 1 of them per
-    batched forward (N = 2: batches of 1, 3, 3 and 1 trial rows); the step and the cost accepted
-    must be those of the oracle's search, which tries one step after another."""
+    (Fig. envar_loop, Sec. 3.3.3). The trials run together, up to N + 1 of them per batched forward
+    (N = 6: 7 and 1 trial rows; N = 2: 3, 3 and 2); the step and the cost accepted must be those
+    of the oracle's search, which tries one step after another."""
     n, horizon = 16, 12
     p = E.Problem(inv_h=n, Re=1000.0)
     op = OE.Problem(inv_h=n, Re=1000.0)
